@@ -1,0 +1,218 @@
+"""Plain FP64 CPU oracle for the recursive regularised LB-MHD step.
+
+TEST INFRASTRUCTURE ONLY: this package may be imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the CPU-baseline leg of ``bench.py``.  The
+product path (the HIP library and its binding) never imports or calls it, and
+the two share no code.
+
+The arithmetic lives in ``rrmhd_oracle.c`` (plain C, FP64, OpenMP over rows);
+this module only compiles it with gcc and marshals numpy arrays through ctypes.
+Every function cites the passage of the paper it follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rrmhd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FEQ_ALGORITHM = 0  # equilibrium of the algorithm (Maxwell stress at 2nd order)
+FEQ_SERIES_FULL = 1  # full Hermite series incl. the u.M cross terms (ablation)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp",
+               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_init.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.orc_step_count.restype = ctypes.c_long
+        L.orc_step_count.argtypes = [ctypes.c_void_p]
+        L.orc_moments.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc_diagnostics.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_invariants.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_current_vorticity.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_get_state.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_set_state.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_hermite.restype = ctypes.c_double
+        L.orc_hermite.argtypes = [ctypes.c_int, _ip, ctypes.c_int]
+        L.orc_node_equilibrium.argtypes = [ctypes.c_double, _dp, _dp,
+                                           ctypes.c_int, _dp, _dp]
+        L.orc_node_feq_series.argtypes = [ctypes.c_double, _dp, _dp,
+                                          ctypes.c_int, _dp]
+        L.orc_node_collide.argtypes = [_dp, _dp, ctypes.c_double,
+                                       ctypes.c_double, _dp, ctypes.c_int,
+                                       _dp, _dp, _dp]
+        L.orc_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's grid loops use."""
+    return int(lib().orc_threads())
+
+
+def hermite(n: int, idx, i: int) -> float:
+    """Hermite tensor component H^(n)_{i, idx} from its definition."""
+    arr = (ctypes.c_int * max(n, 1))(*idx)
+    return float(lib().orc_hermite(n, arr, i))
+
+
+def node_equilibrium(rho, u, b, option=FEQ_ALGORITHM):
+    """(f_eq[9], g_eq[10]) of one node; g_eq is ordered [j][component]."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    feq = np.zeros(9)
+    geq = np.zeros(10)
+    lib().orc_node_equilibrium(float(rho), _ptr(u), _ptr(b), option,
+                               _ptr(feq), _ptr(geq))
+    return feq, geq
+
+
+def node_feq_series(rho, u, b, full=False):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    feq = np.zeros(9)
+    lib().orc_node_feq_series(float(rho), _ptr(u), _ptr(b), int(bool(full)),
+                              _ptr(feq))
+    return feq
+
+
+def node_collide(f, g, omega, omega_m, G=(0.0, 0.0), option=FEQ_ALGORITHM):
+    """Collide one node.  Returns (f*[9], g*[10], aux dict)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(10)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    fs = np.zeros(9)
+    gs = np.zeros(10)
+    aux = np.zeros(63)
+    lib().orc_node_collide(_ptr(f), _ptr(g), float(omega), float(omega_m),
+                           _ptr(G), option, _ptr(fs), _ptr(gs), _ptr(aux))
+    names = [("rho", 1), ("u", 2), ("b", 2), ("a1", 2), ("a2", 4), ("a3", 8),
+             ("a4", 16), ("feq", 9), ("geq", 10), ("fneq_reg", 9)]
+    d, k = {}, 0
+    for nm, sz in names:
+        d[nm] = aux[k:k + sz].copy() if sz > 1 else float(aux[k])
+        k += sz
+    d["a2"] = d["a2"].reshape(2, 2)
+    d["a3"] = d["a3"].reshape(2, 2, 2)
+    d["a4"] = d["a4"].reshape(2, 2, 2, 2)
+    return fs, gs, d
+
+
+class Oracle:
+    """FP64 grid solver: state = pre-collision populations.
+
+    ``walls`` puts half-way bounce-back walls at y = -1/2 and ny - 1/2 (x stays
+    periodic); ``force`` is the body force per unit mass; ``b_wall`` is the
+    field the magnetic anti-bounce-back imposes at the walls.
+    """
+
+    def __init__(self, nx, ny, tau_f, tau_m, walls=False, force=(0.0, 0.0),
+                 b_wall=(0.0, 0.0), option=FEQ_ALGORITHM):
+        self.nx, self.ny = int(nx), int(ny)
+        self._h = lib().orc_create(self.nx, self.ny, float(tau_f),
+                                   float(tau_m), int(bool(walls)),
+                                   float(force[0]), float(force[1]),
+                                   float(b_wall[0]), float(b_wall[1]),
+                                   int(option))
+        if not self._h:
+            raise ValueError("oracle: invalid grid or relaxation times")
+
+    def close(self):
+        if self._h:
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, u, b):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        assert u.shape == (2, self.ny, self.nx) and b.shape == u.shape
+        lib().orc_init(self._h, _ptr(u), _ptr(b))
+
+    def step(self, n=1):
+        lib().orc_step(self._h, int(n))
+
+    @property
+    def step_count(self):
+        return int(lib().orc_step_count(self._h))
+
+    def moments(self):
+        rho = np.zeros((self.ny, self.nx))
+        u = np.zeros((2, self.ny, self.nx))
+        b = np.zeros((2, self.ny, self.nx))
+        lib().orc_moments(self._h, _ptr(rho), _ptr(u), _ptr(b))
+        return rho, u, b
+
+    def diagnostics(self):
+        out = np.zeros(3)
+        lib().orc_diagnostics(self._h, _ptr(out))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def invariants(self):
+        out = np.zeros(5)
+        lib().orc_invariants(self._h, _ptr(out))
+        return out
+
+    def current_vorticity(self):
+        jz = np.zeros((self.ny, self.nx))
+        wz = np.zeros((self.ny, self.nx))
+        lib().orc_current_vorticity(self._h, _ptr(jz), _ptr(wz))
+        return jz, wz
+
+    def get_state(self):
+        f = np.zeros((9, self.ny, self.nx))
+        g = np.zeros((5, 2, self.ny, self.nx))
+        lib().orc_get_state(self._h, _ptr(f), _ptr(g))
+        return f, g
+
+    def set_state(self, f, g):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        assert g.shape == (5, 2, self.ny, self.nx)
+        lib().orc_set_state(self._h, _ptr(f), _ptr(g))
