@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Throughput of the fused RR-MHD step on one MI355X.
+
+Workload: decaying 2D MHD turbulence on an 8192^2 periodic grid (random-phase
+stream and flux functions, E(k) ~ k^4 exp(-2 (k/4)^2), rms u = b = 0.04),
+tau_f = tau_m = 0.51, FP32 arithmetic, populations stored as FP32 offsets
+f - w (``--storage f16`` for the FP16-offset codec).  A step is one fused
+stream-and-collide launch over all 67,108,864 nodes; inputs are resident in
+HBM before timing starts.
+
+Prints one JSON line.  MLUPS = nodes x steps / seconds / 1e6.  The roofline
+object prices the step kernel's algorithmic traffic (19 reads + 19 writes
+per node: 152 B in FP32 storage, 76 B in FP16) per launch against 8 TB/s.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_NODE = {"f32": 152, "f16": 76}
+KERNEL_SOURCES = ["paper_2602_14667_amd/csrc/rr_node.h",
+                  "paper_2602_14667_amd/csrc/rr_kernels.hip"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, n):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when absent or taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{storage}_{n}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(n_sample=2048, steps=6):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import oracle
+    from paper_2602_14667_amd import inputs
+    u, b = inputs.turbulence(n_sample, 0.04)
+    o = oracle.Oracle(n_sample, n_sample, 0.51, 0.51)
+    o.init(u, b)
+    o.step(1)  # warm-up
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * n_sample * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n_sample}^2 of the same turbulence field, {steps} "
+                      f"steps after 1 warm-up step, FP64, OpenMP rows",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--tau", type=float, default=0.51)
+    ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for "
+              f"--gpus {args.gpus}); the domain-decomposed multi-GPU path is "
+              "a design, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_14667_amd import inputs, rrmhd
+
+    torch.cuda.set_device(0)
+    n = args.n
+    u, b = inputs.turbulence(n, 0.04)
+    ud = torch.from_numpy(u).cuda()
+    bd = torch.from_numpy(b).cuda()
+    del u, b
+    s = rrmhd.Solver(n, n, args.tau, args.tau, storage=args.storage)
+    s.init(ud, bd)
+    del ud, bd
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    s.step(args.steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_launches = e0.elapsed_time(e1)
+    ek, em, dv = s.diagnostics()
+    s.close()
+
+    nodes = n * n
+    sec = ms_launches / 1e3
+    mlups = nodes * args.steps / sec / 1e6
+    per_launch = sec / args.steps
+    bpn = BYTES_PER_NODE[args.storage]
+    achieved = bpn * nodes / per_launch / 1e9
+    traffic = measured_traffic(args.storage, n)
+    out = {
+        "metric": "MLUPS & % HBM roofline (fused RR-MHD step)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * per_launch, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"decaying 2D MHD turbulence {n}x{n} periodic, "
+                               "random-phase psi/A, rms u=b=0.04",
+                   "nodes": nodes, "tau_f": args.tau, "tau_m": args.tau,
+                   "storage": f"{args.storage}-shifted (f - w)",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic},
+        "wall_s_timed": round(wall, 4),
+        "diagnostics_after": {"E_kin": ek, "E_mag": em, "max_div_b": dv},
+        "kernel_hash": kernel_hash(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/*
+ * rrmhd.h -- C-ABI of the MI355X (gfx950) library for the recursive
+ * regularised lattice Boltzmann method for 2D incompressible MHD
+ * (De Rosis, arXiv 2602.14667).
+ *
+ * The library advances a D2Q9 fluid population set (fourth-order Hermite
+ * equilibrium carrying the Maxwell stress, recursive regularisation of the
+ * non-equilibrium part) and a D2Q5 vector magnetic population set (BGK) by
+ * one fused stream-and-collide kernel per time step, following the six
+ * per-node tasks of the paper's "Algorithm of computation" (Sec. II.B).
+ *
+ * Conventions shared by every call
+ *  - Units are lattice units (dx = dt = 1).
+ *  - Field arrays are C-contiguous FP64 in DEVICE memory: a scalar field is
+ *    [ny][nx] (x fastest), a vector field is [2][ny][nx] (component, y, x).
+ *  - The library owns the population buffers.  The caller owns every I/O
+ *    array and keeps it alive until the handle's stream has reached the call.
+ *  - Calls are stream-ordered on the handle's HIP stream and return before
+ *    the GPU work ends, except where a call says it synchronises.
+ *  - Every call returns RRMHD_OK (0) or a negative code; no exception or
+ *    abort crosses the ABI.  On failure an output handle is set to NULL;
+ *    other failures leave the handle valid.  rrmhd_strerror gives the text,
+ *    rrmhd_last_error_detail the HIP message of the last device error.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef RRMHD_H
+#define RRMHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RRMHD_OK = 0,
+  RRMHD_EINVAL = -1,     /* bad argument: tau <= 1/2, size < 1, bad enum... */
+  RRMHD_ENOMEM = -2,     /* device allocation failed */
+  RRMHD_EDEVICE = -3,    /* a HIP call failed */
+  RRMHD_ENONFINITE = -4, /* a diagnostic came out NaN or infinite */
+  RRMHD_ESTATE = -5      /* e.g. rrmhd_step before rrmhd_init */
+};
+
+/* Population storage.  Both store f_i - w_i for the fluid populations and
+ * g_j for the magnetic ones, times the codec scale; arithmetic is FP32. */
+enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1 };
+
+/* Boundary kinds.  PERIODIC: doubly periodic.  WALLS_Y: periodic in x,
+ * walls half-way at y = -1/2 and y = ny - 1/2 (half-way bounce-back for f,
+ * anti-bounce-back imposing b_wall for g). */
+enum { RRMHD_BC_PERIODIC = 0, RRMHD_BC_WALLS_Y = 1 };
+
+typedef struct {
+  int32_t nx, ny;    /* nodes in x and y, >= 1 (ny >= 2 with walls) */
+  int32_t storage;   /* RRMHD_STORE_* */
+  float codec_scale; /* power-of-two storage scale S; 0 selects 1 */
+} rrmhd_grid;
+
+typedef struct {
+  int32_t kind;     /* RRMHD_BC_* */
+  double force[2];  /* body force per unit mass G (F = rho G), Guo-type */
+  double b_wall[2]; /* wall field imposed by the magnetic anti-bounce-back */
+} rrmhd_bc;
+
+typedef struct rrmhd rrmhd;
+
+/* Create a solver on the current HIP device.  tau_f and tau_m are the fluid
+ * and magnetic relaxation times (omega = 1/tau_f, omega_m = 1/tau_m in the
+ * collision of algorithm task 5), both > 1/2 and finite.  bc may be NULL
+ * (periodic, no force).  hip_stream may be NULL (the null stream) or a
+ * hipStream_t such as torch's current stream.  Allocates the two population
+ * buffers (19 planes each) and a diagnostics workspace. */
+int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
+                 const rrmhd_bc *bc, void *hip_stream, rrmhd **out);
+
+/* Initial state from the macroscopic fields of Sec. III: rho = 1 and the
+ * populations at their equilibria f_eq(1, u, b), g_eq(u, b) (algorithm task
+ * 2), so rrmhd_moments right after init returns (1, u, b).  u and b are
+ * device [2][ny][nx] FP64.  Resets the step counter. */
+int rrmhd_init(rrmhd *h, const double *u, const double *b);
+
+/* Advance n >= 0 time steps.  One step is tasks 1-6 of the algorithm at every
+ * node: moments, equilibria, non-equilibrium Hermite coefficients with the
+ * recursive third/fourth orders, regularised reconstruction, collision and
+ * streaming (done as a pull, fused into one kernel).  Asynchronous. */
+int rrmhd_step(rrmhd *h, int64_t n);
+
+/* Pre-collision macroscopic fields of the current state (task 1): rho
+ * [ny][nx], u and b [2][ny][nx], FP64 device arrays; any may be NULL.  With a
+ * body force u includes half the force impulse.  Asynchronous. */
+int rrmhd_moments(rrmhd *h, double *rho, double *u, double *b);
+
+/* Host scalars: E_kin = sum |u|^2 / (2 nx ny), E_mag = sum |b|^2 / (2 nx ny)
+ * (the averaged energies of Sec. III.B with the integral as a node sum) and
+ * max |div b| with the isotropic lattice gradient of Sec. III (interior rows
+ * only with walls).  Accumulated in FP64 on the GPU with a fixed reduction
+ * order.  Synchronises the stream.  Returns RRMHD_ENONFINITE, with the
+ * outputs set to NaN, if any result is not finite.  Any pointer may be NULL. */
+int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag,
+                      double *max_div_b);
+
+/* Host out[5] = mass sum rho, momentum sum_i c_i f_i (x, y), total field
+ * sum b (x, y), FP64, over the current state.  Synchronises the stream. */
+int rrmhd_invariants(rrmhd *h, double out[5]);
+
+/* Steps taken since rrmhd_init (host value, no synchronisation). */
+int rrmhd_step_count(const rrmhd *h, int64_t *out);
+
+/* Raw stored state for checkpoint/resume: 19 planes of nx*ny elements of
+ * the storage type (4 bytes for F32, 2 for F16) in the order f_0..f_8,
+ * g_0x, g_0y, ..., g_4x, g_4y, each plane [ny][nx].  These are the
+ * post-collision values of the last step at their source nodes (the pull
+ * layout), not the pre-collision populations.  `bytes` must be at least
+ * rrmhd_state_bytes().  dst/src are device pointers.  Asynchronous. */
+int64_t rrmhd_state_bytes(const rrmhd *h);
+int rrmhd_save_state(rrmhd *h, void *dst, int64_t bytes);
+int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes,
+                     int64_t step_count);
+
+/* Stream used by the handle; NULL is the null stream. */
+int rrmhd_set_stream(rrmhd *h, void *hip_stream);
+
+int rrmhd_destroy(rrmhd *h);
+
+const char *rrmhd_strerror(int code);
+const char *rrmhd_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RRMHD_H */

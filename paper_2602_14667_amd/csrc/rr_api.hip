@@ -1,0 +1,259 @@
+// rr_api.hip -- host runtime behind the C-ABI declared in include/rrmhd.h:
+// handle, A/B population buffers, stream ordering, error mapping.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/rrmhd.h"
+#include "rr_kernels.h"
+
+namespace {
+
+thread_local char g_detail[512] = "";
+
+int dev_err(hipError_t e, const char *what) {
+  std::snprintf(g_detail, sizeof g_detail, "%s: %s", what, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? RRMHD_ENOMEM : RRMHD_EDEVICE;
+}
+
+#define HIP_OR_RETURN(expr)                          \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return dev_err(e_, #expr); \
+  } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct rrmhd {
+  rr::Domain D{};
+  int storage = 0;
+  int64_t elem = 4;  // bytes per stored value
+  double tau_f = 0, tau_m = 0;
+  rrmhd_bc bc{};
+  hipStream_t stream = nullptr;
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t steps = 0;
+  bool ready = false;
+  rr::LaunchShape shape{};
+  void *diag_work = nullptr;
+  double *diag_out = nullptr;   // device, 8 doubles
+  double *diag_host = nullptr;  // pinned, 8 doubles
+};
+
+extern "C" {
+
+const char *rrmhd_strerror(int code) {
+  switch (code) {
+    case RRMHD_OK: return "ok";
+    case RRMHD_EINVAL: return "invalid argument";
+    case RRMHD_ENOMEM: return "out of device memory";
+    case RRMHD_EDEVICE: return "HIP device error";
+    case RRMHD_ENONFINITE: return "non-finite diagnostic";
+    case RRMHD_ESTATE: return "invalid state (not initialised)";
+    default: return "unknown error";
+  }
+}
+
+const char *rrmhd_last_error_detail(void) { return g_detail; }
+
+int rrmhd_destroy(rrmhd *h) {
+  if (!h) return RRMHD_OK;
+  int rc = RRMHD_OK;
+  if (h->stream || h->buf[0]) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = dev_err(e, "hipStreamSynchronize");
+  }
+  for (void *&p : h->buf)
+    if (p) (void)hipFree(p), p = nullptr;
+  if (h->diag_work) (void)hipFree(h->diag_work);
+  if (h->diag_out) (void)hipFree(h->diag_out);
+  if (h->diag_host) (void)hipHostFree(h->diag_host);
+  delete h;
+  return rc;
+}
+
+int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
+                 const rrmhd_bc *bc, void *hip_stream, rrmhd **out) {
+  if (!out) return RRMHD_EINVAL;
+  *out = nullptr;
+  if (!grid) return RRMHD_EINVAL;
+  if (grid->nx < 1 || grid->ny < 1) return RRMHD_EINVAL;
+  if (grid->storage != RRMHD_STORE_F32 && grid->storage != RRMHD_STORE_F16)
+    return RRMHD_EINVAL;
+  if (!(std::isfinite(tau_f) && std::isfinite(tau_m)) || tau_f <= 0.5 || tau_m <= 0.5)
+    return RRMHD_EINVAL;
+  rrmhd_bc b{};
+  b.kind = RRMHD_BC_PERIODIC;
+  if (bc) b = *bc;
+  if (b.kind != RRMHD_BC_PERIODIC && b.kind != RRMHD_BC_WALLS_Y) return RRMHD_EINVAL;
+  if (b.kind == RRMHD_BC_WALLS_Y && grid->ny < 2) return RRMHD_EINVAL;
+  for (int k = 0; k < 2; ++k)
+    if (!finite_pos(b.force[k]) || !finite_pos(b.b_wall[k])) return RRMHD_EINVAL;
+  const int64_t N = (int64_t)grid->nx * grid->ny;
+  if (N > ((int64_t)1 << 31) - 1) return RRMHD_EINVAL;  // in-plane offsets are int32
+  float S = grid->codec_scale;
+  if (S == 0.0f) S = 1.0f;
+  int ex = 0;
+  if (!(S > 0.0f) || std::frexp(S, &ex) != 0.5f) return RRMHD_EINVAL;  // power of two
+
+  rrmhd *h = new (std::nothrow) rrmhd();
+  if (!h) return RRMHD_ENOMEM;
+  h->storage = grid->storage;
+  h->elem = grid->storage == RRMHD_STORE_F16 ? 2 : 4;
+  h->tau_f = tau_f;
+  h->tau_m = tau_m;
+  h->bc = b;
+  h->stream = (hipStream_t)hip_stream;
+  rr::Domain &D = h->D;
+  D.nx = grid->nx;
+  D.ny = grid->ny;
+  // planes start on 256-byte boundaries
+  const int64_t align = 256 / h->elem;
+  D.plane = (N + align - 1) / align * align;
+  D.walls = b.kind == RRMHD_BC_WALLS_Y;
+  const double om = 1.0 / tau_f, omm = 1.0 / tau_m;
+  D.om_c = (float)(1.0 - om);
+  D.omm_c = (float)(1.0 - omm);
+  D.src_c = (float)(1.0 - 0.5 * om);
+  D.Gx = (float)b.force[0];
+  D.Gy = (float)b.force[1];
+  D.bw2x = (float)(b.b_wall[0] / 3.0);
+  D.bw2y = (float)(b.b_wall[1] / 3.0);
+  D.s = grid->storage == RRMHD_STORE_F16 ? S : 1.0f;
+  D.inv_s = 1.0f / D.s;
+  h->shape = rr::default_shape(D);
+
+  const size_t bytes = (size_t)D.plane * rr::kStatePlanes * h->elem;
+  int rc = RRMHD_OK;
+  for (int k = 0; k < 2 && rc == RRMHD_OK; ++k) {
+    hipError_t e = hipMalloc(&h->buf[k], bytes);
+    if (e != hipSuccess) rc = dev_err(e, "hipMalloc(populations)");
+  }
+  if (rc == RRMHD_OK) {
+    hipError_t e = hipMalloc((void **)&h->diag_out, 8 * sizeof(double));
+    if (e != hipSuccess) rc = dev_err(e, "hipMalloc(diag)");
+  }
+  if (rc == RRMHD_OK) {
+    hipError_t e = hipHostMalloc((void **)&h->diag_host, 8 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) rc = dev_err(e, "hipHostMalloc(diag)");
+  }
+  if (rc != RRMHD_OK) {
+    rrmhd_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return RRMHD_OK;
+}
+
+int rrmhd_set_stream(rrmhd *h, void *hip_stream) {
+  if (!h) return RRMHD_EINVAL;
+  h->stream = (hipStream_t)hip_stream;
+  return RRMHD_OK;
+}
+
+int rrmhd_init(rrmhd *h, const double *u, const double *b) {
+  if (!h || !u || !b) return RRMHD_EINVAL;
+  HIP_OR_RETURN(rr::launch_init(h->storage, h->D, u, b, h->bc.b_wall[0],
+                                h->bc.b_wall[1], h->buf[0], h->stream));
+  h->cur = 0;
+  h->steps = 0;
+  h->ready = true;
+  return RRMHD_OK;
+}
+
+int rrmhd_step(rrmhd *h, int64_t n) {
+  if (!h || n < 0) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  for (int64_t k = 0; k < n; ++k) {
+    HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur],
+                                  h->buf[h->cur ^ 1], h->shape, h->stream));
+    h->cur ^= 1;
+    h->steps++;
+  }
+  return RRMHD_OK;
+}
+
+int rrmhd_moments(rrmhd *h, double *rho, double *u, double *b) {
+  if (!h) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  if (!rho && !u && !b) return RRMHD_OK;
+  HIP_OR_RETURN(rr::launch_moments(h->storage, h->D, h->buf[h->cur], rho, u, b,
+                                   h->stream));
+  return RRMHD_OK;
+}
+
+static int run_diag(rrmhd *h) {
+  if (!h->diag_work) {
+    HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
+  }
+  HIP_OR_RETURN(rr::launch_diagnostics(h->storage, h->D, h->buf[h->cur],
+                                       h->diag_work, h->diag_out, h->stream));
+  HIP_OR_RETURN(hipMemcpyAsync(h->diag_host, h->diag_out, 8 * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_RETURN(hipStreamSynchronize(h->stream));
+  return RRMHD_OK;
+}
+
+int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag, double *max_div_b) {
+  if (!h) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  int rc = run_diag(h);
+  if (rc != RRMHD_OK) return rc;
+  const double *r = h->diag_host;
+  const bool bad = !(std::isfinite(r[0]) && std::isfinite(r[1]) && std::isfinite(r[2]));
+  const double nan = std::nan("");
+  if (E_kin) *E_kin = bad ? nan : r[0];
+  if (E_mag) *E_mag = bad ? nan : r[1];
+  if (max_div_b) *max_div_b = bad ? nan : r[2];
+  return bad ? RRMHD_ENONFINITE : RRMHD_OK;
+}
+
+int rrmhd_invariants(rrmhd *h, double out[5]) {
+  if (!h || !out) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  int rc = run_diag(h);
+  if (rc != RRMHD_OK) return rc;
+  for (int k = 0; k < 5; ++k) out[k] = h->diag_host[3 + k];
+  return RRMHD_OK;
+}
+
+int rrmhd_step_count(const rrmhd *h, int64_t *out) {
+  if (!h || !out) return RRMHD_EINVAL;
+  *out = h->steps;
+  return RRMHD_OK;
+}
+
+int64_t rrmhd_state_bytes(const rrmhd *h) {
+  if (!h) return RRMHD_EINVAL;
+  return (int64_t)h->D.nx * h->D.ny * rr::kStatePlanes * h->elem;
+}
+
+int rrmhd_save_state(rrmhd *h, void *dst, int64_t bytes) {
+  if (!h || !dst || bytes < rrmhd_state_bytes(h)) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
+  const size_t pitch = (size_t)h->D.plane * h->elem;
+  HIP_OR_RETURN(hipMemcpy2DAsync(dst, row, h->buf[h->cur], pitch, row, rr::kStatePlanes,
+                                 hipMemcpyDeviceToDevice, h->stream));
+  return RRMHD_OK;
+}
+
+int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes, int64_t step_count) {
+  if (!h || !src || bytes < rrmhd_state_bytes(h) || step_count < 0) return RRMHD_EINVAL;
+  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
+  const size_t pitch = (size_t)h->D.plane * h->elem;
+  HIP_OR_RETURN(hipMemcpy2DAsync(h->buf[0], pitch, src, row, row, rr::kStatePlanes,
+                                 hipMemcpyDeviceToDevice, h->stream));
+  h->cur = 0;
+  h->steps = step_count;
+  h->ready = true;
+  return RRMHD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// rr_kernels.h -- launch interfaces of the single-domain kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rr {
+
+enum Storage { kF32 = 0, kF16 = 1 };
+constexpr int kStatePlanes = 19;  // 9 fluid + 5 x 2 magnetic planes
+
+// Geometry and physics of one domain, as the kernels see it.
+struct Domain {
+  int nx, ny;
+  int64_t plane;  // elements between consecutive planes of one buffer
+  int walls;      // 0 periodic, 1 walls in y
+  float om_c, omm_c, src_c;
+  float Gx, Gy;
+  float bw2x, bw2y;  // 2 psi_j b_wall for j = 1..4 (psi = 1/6): b_wall / 3
+  float s, inv_s;    // storage scale (F16)
+};
+
+struct LaunchShape {
+  int bx, by;  // threads per block in x and y
+  int ry;      // rows per thread (block covers by * ry rows)
+  int xcd;     // 1: XCD-aware block order
+};
+
+hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
+                       const LaunchShape &L, hipStream_t st);
+hipError_t launch_init(int storage, const Domain &D, const double *u,
+                       const double *b, double bwx, double bwy, void *dst,
+                       hipStream_t st);
+hipError_t launch_moments(int storage, const Domain &D, const void *src,
+                          double *rho, double *u, double *b, hipStream_t st);
+// Diagnostics: out_dev[8] = {E_kin, E_mag, max|div b|, mass, j_x, j_y, b_x,
+// b_y}.  work must hold diag_work_bytes(D) bytes.
+size_t diag_work_bytes(const Domain &D);
+hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
+                              void *work, double *out_dev, hipStream_t st);
+
+LaunchShape default_shape(const Domain &D);
+
+}  // namespace rr

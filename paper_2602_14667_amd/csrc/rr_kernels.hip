@@ -1,0 +1,519 @@
+// rr_kernels.hip -- single-domain kernels: the fused stream-and-collide step,
+// equilibrium initialisation, moments and FP64 diagnostics.
+//
+// Layout in HBM: structure of arrays, 19 planes per buffer (f_0..f_8, then
+// g_0x, g_0y, ..., g_4x, g_4y), each plane [ny][nx] with x fastest and
+// `plane` elements between plane starts.  Two buffers (A/B) alternate: a
+// step pulls from one and writes the other.  A stored value is the
+// post-collision population of the previous step at its source node, so the
+// pull f_i(x) = f*_i(x - c_i) is task 6 of the algorithm fused into the
+// loads of the next step.
+#include "rr_kernels.h"
+#include "rr_node.h"
+
+namespace rr {
+
+// ---------------------------------------------------------------------------
+// Pull addressing (task 6).  For a node (x, y) the population i comes from
+// (x - c_ix, y - c_iy), periodic in x, periodic or walled in y.  With walls,
+// a population whose source lies beyond a wall is the node's own
+// post-collision population in the opposite direction (half-way
+// bounce-back); for the magnetic populations the anti-bounce-back adds the
+// wall term: g_j = -g*_opp(j) + 2 psi_j b_wall.
+// ---------------------------------------------------------------------------
+struct Rows {
+  int xm, xp;        // x - 1, x + 1 (periodic)
+  int rm, r0, rp;    // row offsets of y - 1, y, y + 1
+  bool lo, hi;       // wall below (y == 0) / above (y == ny - 1)
+};
+
+template <bool WALLS>
+__device__ __forceinline__ Rows rows_of(const Domain &D, int x, int y) {
+  Rows R;
+  R.xm = x == 0 ? D.nx - 1 : x - 1;
+  R.xp = x == D.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? D.ny - 1 : y - 1;
+  const int yp = y == D.ny - 1 ? 0 : y + 1;
+  R.rm = ym * D.nx;
+  R.r0 = y * D.nx;
+  R.rp = yp * D.nx;
+  R.lo = WALLS && y == 0;
+  R.hi = WALLS && y == D.ny - 1;
+  return R;
+}
+
+// Load population i (decoded, f - w) of node x through the pull.
+template <class C, bool WALLS, int I>
+__device__ __forceinline__ float pull_f(const Domain &D,
+                                        const typename C::T *__restrict__ s,
+                                        const Rows &R, int x) {
+  constexpr int CX = cx(I), CY = cy(I);
+  const int sx = CX == 0 ? x : (CX > 0 ? R.xm : R.xp);
+  int off = (CY == 0 ? R.r0 : (CY > 0 ? R.rm : R.rp)) + sx;
+  int plane = I;
+  if constexpr (WALLS && CY != 0) {
+    const bool wall = CY > 0 ? R.lo : R.hi;
+    if (wall) {
+      plane = opp_f(I);
+      off = R.r0 + x;
+    }
+  }
+  return C::dec(s[(int64_t)plane * D.plane + off], D.inv_s);
+}
+
+template <class C, bool WALLS, int J>
+__device__ __forceinline__ void pull_g(const Domain &D,
+                                       const typename C::T *__restrict__ s,
+                                       const Rows &R, int x, float &gx,
+                                       float &gy) {
+  constexpr int EX = ex(J), EY = ey(J);
+  const int sx = EX == 0 ? x : (EX > 0 ? R.xm : R.xp);
+  int off = (EY == 0 ? R.r0 : (EY > 0 ? R.rm : R.rp)) + sx;
+  int j = J;
+  bool wall = false;
+  if constexpr (WALLS && EY != 0) {
+    wall = EY > 0 ? R.lo : R.hi;
+    if (wall) {
+      j = opp_g(J);
+      off = R.r0 + x;
+    }
+  }
+  gx = C::dec(s[(int64_t)gplane(j, 0) * D.plane + off], D.inv_s);
+  gy = C::dec(s[(int64_t)gplane(j, 1) * D.plane + off], D.inv_s);
+  if constexpr (WALLS && EY != 0) {
+    if (wall) {
+      gx = D.bw2x - gx;
+      gy = D.bw2y - gy;
+    }
+  }
+}
+
+template <class C, bool WALLS>
+__device__ __forceinline__ void pull_node(const Domain &D,
+                                          const typename C::T *__restrict__ s,
+                                          int x, int y, float (&d)[kQ],
+                                          float (&g)[2 * kQm]) {
+  const Rows R = rows_of<WALLS>(D, x, y);
+  d[0] = pull_f<C, WALLS, 0>(D, s, R, x);
+  d[1] = pull_f<C, WALLS, 1>(D, s, R, x);
+  d[2] = pull_f<C, WALLS, 2>(D, s, R, x);
+  d[3] = pull_f<C, WALLS, 3>(D, s, R, x);
+  d[4] = pull_f<C, WALLS, 4>(D, s, R, x);
+  d[5] = pull_f<C, WALLS, 5>(D, s, R, x);
+  d[6] = pull_f<C, WALLS, 6>(D, s, R, x);
+  d[7] = pull_f<C, WALLS, 7>(D, s, R, x);
+  d[8] = pull_f<C, WALLS, 8>(D, s, R, x);
+  pull_g<C, WALLS, 0>(D, s, R, x, g[0], g[1]);
+  pull_g<C, WALLS, 1>(D, s, R, x, g[2], g[3]);
+  pull_g<C, WALLS, 2>(D, s, R, x, g[4], g[5]);
+  pull_g<C, WALLS, 3>(D, s, R, x, g[6], g[7]);
+  pull_g<C, WALLS, 4>(D, s, R, x, g[8], g[9]);
+}
+
+// Block order: hardware hands consecutive workgroups to the eight XCDs in
+// turn.  Renumbering so that each XCD receives a contiguous run of tiles
+// keeps the cache lines shared by neighbouring tiles (the +-1 pull offsets)
+// inside one L2.
+__device__ __forceinline__ int xcd_remap(int L, int n) {
+  const int q = n >> 3, r = n & 7, k = L & 7, m = L >> 3;
+  return k < r ? k * (q + 1) + m : r * (q + 1) + (k - r) * q + m;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step: pull (task 6 of the previous step), tasks 1-5, local store.
+// 1-D grid of tiles; a tile is blockDim.x nodes of ry consecutive rows,
+// blockDim.y tiles high.
+// ---------------------------------------------------------------------------
+template <class C, bool WALLS, bool FORCED>
+__global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
+                                              int xcd,
+                                              const typename C::T *__restrict__ src,
+                                              typename C::T *__restrict__ dst) {
+  const int ntiles = gridDim.x;
+  const int L = xcd ? xcd_remap(blockIdx.x, ntiles) : (int)blockIdx.x;
+  const int tx = L % tiles_x, ty = L / tiles_x;
+  const int x = tx * blockDim.x + threadIdx.x;
+  const int y0 = (ty * blockDim.y + threadIdx.y) * ry;
+  if (x >= D.nx) return;
+  CollideParams P;
+  P.om_c = D.om_c;
+  P.omm_c = D.omm_c;
+  P.Gx = D.Gx;
+  P.Gy = D.Gy;
+  P.src_c = D.src_c;
+  for (int r = 0; r < ry; ++r) {
+    const int y = y0 + r;
+    if (y >= D.ny) return;
+    float d[kQ], g[2 * kQm];
+    pull_node<C, WALLS>(D, src, x, y, d, g);
+    collide<FORCED>(d, g, P);
+    const int o = y * D.nx + x;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) dst[(int64_t)i * D.plane + o] = C::enc(d[i], D.s);
+#pragma unroll
+    for (int k = 0; k < 2 * kQm; ++k)
+      dst[(int64_t)(kQ + k) * D.plane + o] = C::enc(g[k], D.s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation at equilibrium (rho = 1), written for the pull layout: the
+// value stored in plane p at node n is read by node n + c_p as population p,
+// or, beyond a wall, by n itself as the opposite population.  It is set so
+// that the first pull yields exactly f_eq(1, u, b), g_eq(u, b) everywhere.
+// FP64 arithmetic, rounded once to the storage type.
+// ---------------------------------------------------------------------------
+__device__ double feq_dev_d(int i, double ux, double uy, double bx, double by) {
+  // D1Q3 factors minus one, times the weight split w_i = wx * wy
+  const int cxi = cx(i), cyi = cy(i);
+  const double ax = cxi == 0 ? -1.5 * ux * ux : 3.0 * cxi * ux + 3.0 * ux * ux;
+  const double ay = cyi == 0 ? -1.5 * uy * uy : 3.0 * cyi * uy + 3.0 * uy * uy;
+  const double c2 = (double)(cxi * cxi + cyi * cyi);
+  const double cb = cxi * bx + cyi * by;
+  const double q = 0.5 * (bx * bx + by * by) * c2 - cb * cb;
+  const double w = (i == 0) ? 16.0 / 36.0 : ((i & 1) ? 1.0 / 36.0 : 4.0 / 36.0);
+  return w * (ax + ay + ax * ay + 4.5 * q);
+}
+
+__device__ void geq_d(int j, double ux, double uy, double bx, double by,
+                      double &gx, double &gy) {
+  const double E = ux * by - uy * bx;
+  const double psi = j == 0 ? 1.0 / 3.0 : 1.0 / 6.0;
+  gx = psi * (bx - 3.0 * ey(j) * E);
+  gy = psi * (by + 3.0 * ex(j) * E);
+}
+
+template <class C>
+__global__ void k_init(Domain D, const double *__restrict__ u,
+                       const double *__restrict__ b, double bwx, double bwy,
+                       typename C::T *__restrict__ dst) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= D.nx) return;
+  const int64_t N = (int64_t)D.nx * D.ny;
+  const int o = y * D.nx + x;
+  auto fld = [&](const double *a, int comp, int xx, int yy) {
+    return a[comp * N + (int64_t)yy * D.nx + xx];
+  };
+  for (int i = 0; i < kQ; ++i) {
+    int tx = x + cx(i), ty = y + cy(i);
+    tx = tx < 0 ? tx + D.nx : (tx >= D.nx ? tx - D.nx : tx);
+    double v;
+    if (D.walls && (ty < 0 || ty >= D.ny)) {
+      v = feq_dev_d(opp_f(i), fld(u, 0, x, y), fld(u, 1, x, y), fld(b, 0, x, y),
+                    fld(b, 1, x, y));
+    } else {
+      ty = ty < 0 ? ty + D.ny : (ty >= D.ny ? ty - D.ny : ty);
+      v = feq_dev_d(i, fld(u, 0, tx, ty), fld(u, 1, tx, ty), fld(b, 0, tx, ty),
+                    fld(b, 1, tx, ty));
+    }
+    dst[(int64_t)i * D.plane + o] = C::enc((float)v, D.s);
+  }
+  for (int j = 0; j < kQm; ++j) {
+    int tx = x + ex(j), ty = y + ey(j);
+    tx = tx < 0 ? tx + D.nx : (tx >= D.nx ? tx - D.nx : tx);
+    double gx, gy;
+    if (D.walls && (ty < 0 || ty >= D.ny)) {
+      const int o2 = opp_g(j);
+      geq_d(o2, fld(u, 0, x, y), fld(u, 1, x, y), fld(b, 0, x, y),
+            fld(b, 1, x, y), gx, gy);
+      // stored so that -stored + 2 psi b_wall = g_eq
+      gx = bwx / 3.0 - gx;
+      gy = bwy / 3.0 - gy;
+    } else {
+      ty = ty < 0 ? ty + D.ny : (ty >= D.ny ? ty - D.ny : ty);
+      geq_d(j, fld(u, 0, tx, ty), fld(u, 1, tx, ty), fld(b, 0, tx, ty),
+            fld(b, 1, tx, ty), gx, gy);
+    }
+    dst[(int64_t)gplane(j, 0) * D.plane + o] = C::enc((float)gx, D.s);
+    dst[(int64_t)gplane(j, 1) * D.plane + o] = C::enc((float)gy, D.s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moments (task 1) of the current state in FP64.
+// ---------------------------------------------------------------------------
+struct MomD {
+  double rho, jx, jy, ux, uy, bx, by;
+};
+
+template <class C, bool WALLS>
+__device__ __forceinline__ MomD moments_d(const Domain &D,
+                                          const typename C::T *__restrict__ s,
+                                          int x, int y) {
+  float d[kQ], g[2 * kQm];
+  pull_node<C, WALLS>(D, s, x, y, d, g);
+  MomD m;
+  double dr = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    dr += (double)d[i];
+    jx += (double)cx(i) * d[i];
+    jy += (double)cy(i) * d[i];
+  }
+  m.rho = 1.0 + dr;
+  m.jx = jx;
+  m.jy = jy;
+  m.ux = (jx + 0.5 * m.rho * (double)D.Gx) / m.rho;
+  m.uy = (jy + 0.5 * m.rho * (double)D.Gy) / m.rho;
+  double bx = 0.0, by = 0.0;
+#pragma unroll
+  for (int j = 0; j < kQm; ++j) {
+    bx += (double)g[2 * j];
+    by += (double)g[2 * j + 1];
+  }
+  m.bx = bx;
+  m.by = by;
+  return m;
+}
+
+template <class C, bool WALLS>
+__global__ void k_moments(Domain D, const typename C::T *__restrict__ src,
+                          double *__restrict__ rho, double *__restrict__ u,
+                          double *__restrict__ b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= D.nx) return;
+  const MomD m = moments_d<C, WALLS>(D, src, x, y);
+  const int64_t N = (int64_t)D.nx * D.ny, o = (int64_t)y * D.nx + x;
+  if (rho) rho[o] = m.rho;
+  if (u) {
+    u[o] = m.ux;
+    u[N + o] = m.uy;
+  }
+  if (b) {
+    b[o] = m.bx;
+    b[N + o] = m.by;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: FP64 sums with a fixed reduction tree (deterministic for a
+// given grid), max |div b| with the isotropic gradient
+// d_a phi = 3 sum_i w_i phi(x + c_i) c_ia.
+// ---------------------------------------------------------------------------
+constexpr int kDiagBlock = 256;
+constexpr int kDiagGrid = 1024;
+constexpr int kSums = 7;  // |u|^2, |b|^2, rho, j_x, j_y, b_x, b_y
+
+__device__ __forceinline__ double nanmax(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+
+// Sum (or NaN-propagating max) over a 256-thread block; result in thread 0.
+template <bool MAX>
+__device__ double block_reduce(double v, double *lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    v = MAX ? nanmax(v, o) : v + o;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    r = lds[0];
+    for (int w = 1; w < kDiagBlock / 64; ++w) r = MAX ? nanmax(r, lds[w]) : r + lds[w];
+  }
+  return r;
+}
+
+template <class C, bool WALLS>
+__global__ __launch_bounds__(kDiagBlock) void k_diag_sums(
+    Domain D, const typename C::T *__restrict__ src, double *__restrict__ bpl,
+    double *__restrict__ part) {
+  __shared__ double lds[kDiagBlock / 64];
+  const int64_t N = (int64_t)D.nx * D.ny;
+  double acc[kSums] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t n = (int64_t)blockIdx.x * kDiagBlock + threadIdx.x; n < N;
+       n += (int64_t)gridDim.x * kDiagBlock) {
+    const int y = (int)(n / D.nx), x = (int)(n - (int64_t)y * D.nx);
+    const MomD m = moments_d<C, WALLS>(D, src, x, y);
+    acc[0] += m.ux * m.ux + m.uy * m.uy;
+    acc[1] += m.bx * m.bx + m.by * m.by;
+    acc[2] += m.rho;
+    acc[3] += m.jx;
+    acc[4] += m.jy;
+    acc[5] += m.bx;
+    acc[6] += m.by;
+    bpl[n] = m.bx;
+    bpl[N + n] = m.by;
+  }
+  for (int k = 0; k < kSums; ++k) {
+    const double r = block_reduce<false>(acc[k], lds);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kSums + k] = r;
+  }
+}
+
+__global__ __launch_bounds__(kDiagBlock) void k_diag_divb(Domain D,
+                                                          const double *__restrict__ bpl,
+                                                          double *__restrict__ part) {
+  __shared__ double lds[kDiagBlock / 64];
+  const int64_t N = (int64_t)D.nx * D.ny;
+  const int ylo = D.walls ? 1 : 0, yhi = D.walls ? D.ny - 1 : D.ny;
+  double mx = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * kDiagBlock + threadIdx.x; n < N;
+       n += (int64_t)gridDim.x * kDiagBlock) {
+    const int y = (int)(n / D.nx), x = (int)(n - (int64_t)y * D.nx);
+    if (y < ylo || y >= yhi) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+      int xx = x + cx(i), yy = y + cy(i);
+      xx = xx < 0 ? xx + D.nx : (xx >= D.nx ? xx - D.nx : xx);
+      yy = yy < 0 ? yy + D.ny : (yy >= D.ny ? yy - D.ny : yy);
+      const int64_t o = (int64_t)yy * D.nx + xx;
+      const double w = (i & 1) ? 1.0 / 36.0 : 1.0 / 9.0;
+      s += w * (cx(i) * bpl[o] + cy(i) * bpl[N + o]);
+    }
+    const double dv = fabs(3.0 * s);
+    mx = nanmax(mx, dv);
+  }
+  const double r = block_reduce<true>(mx, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kDiagBlock) void k_diag_final(
+    const double *__restrict__ part_s, int nb_s, const double *__restrict__ part_m,
+    int nb_m, double inv_n2, double *__restrict__ out) {
+  __shared__ double lds[kDiagBlock / 64];
+  for (int k = 0; k < kSums; ++k) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb_s; i += kDiagBlock) v += part_s[(int64_t)i * kSums + k];
+    const double r = block_reduce<false>(v, lds);
+    if (threadIdx.x == 0) {
+      if (k == 0) out[0] = r * inv_n2;
+      else if (k == 1) out[1] = r * inv_n2;
+      else out[k + 1] = r;
+    }
+  }
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb_m; i += kDiagBlock) m = nanmax(m, part_m[i]);
+  const double r = block_reduce<true>(m, lds);
+  if (threadIdx.x == 0) out[2] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+LaunchShape default_shape(const Domain &D) {
+  LaunchShape L;
+  if (D.nx >= 256) {
+    L.bx = 256;
+    L.by = 1;
+  } else {
+    L.bx = ((D.nx + 63) / 64) * 64;
+    L.by = 256 / L.bx;
+  }
+  L.ry = 1;
+  L.xcd = 1;
+  return L;
+}
+
+template <class C>
+static hipError_t step_t(const Domain &D, const void *src, void *dst,
+                         const LaunchShape &L, hipStream_t st) {
+  const int tiles_x = (D.nx + L.bx - 1) / L.bx;
+  const int rows_per_tile = L.by * L.ry;
+  const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
+  const dim3 grid(tiles_x * tiles_y), block(L.bx, L.by);
+  const bool forced = D.Gx != 0.0f || D.Gy != 0.0f;
+  auto s = (const typename C::T *)src;
+  auto d = (typename C::T *)dst;
+  if (D.walls) {
+    if (forced)
+      hipLaunchKernelGGL((k_step<C, true, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    else
+      hipLaunchKernelGGL((k_step<C, true, false>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  } else {
+    if (forced)
+      hipLaunchKernelGGL((k_step<C, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    else
+      hipLaunchKernelGGL((k_step<C, false, false>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
+                       const LaunchShape &L, hipStream_t st) {
+  if (L.bx <= 0 || L.by <= 0 || L.bx * L.by > 256 || L.ry <= 0) return hipErrorInvalidValue;
+  return storage == kF16 ? step_t<CodecF16>(D, src, dst, L, st)
+                         : step_t<CodecF32>(D, src, dst, L, st);
+}
+
+hipError_t launch_init(int storage, const Domain &D, const double *u,
+                       const double *b, double bwx, double bwy, void *dst,
+                       hipStream_t st) {
+  const dim3 block(64), grid((D.nx + 63) / 64, D.ny);
+  if (storage == kF16)
+    hipLaunchKernelGGL(k_init<CodecF16>, grid, block, 0, st, D, u, b, bwx, bwy,
+                       (__half *)dst);
+  else
+    hipLaunchKernelGGL(k_init<CodecF32>, grid, block, 0, st, D, u, b, bwx, bwy,
+                       (float *)dst);
+  return hipGetLastError();
+}
+
+template <class C>
+static void moments_t(const Domain &D, const void *src, double *rho, double *u,
+                      double *b, hipStream_t st) {
+  const dim3 block(64), grid((D.nx + 63) / 64, D.ny);
+  auto s = (const typename C::T *)src;
+  if (D.walls)
+    hipLaunchKernelGGL((k_moments<C, true>), grid, block, 0, st, D, s, rho, u, b);
+  else
+    hipLaunchKernelGGL((k_moments<C, false>), grid, block, 0, st, D, s, rho, u, b);
+}
+
+hipError_t launch_moments(int storage, const Domain &D, const void *src,
+                          double *rho, double *u, double *b, hipStream_t st) {
+  if (storage == kF16)
+    moments_t<CodecF16>(D, src, rho, u, b, st);
+  else
+    moments_t<CodecF32>(D, src, rho, u, b, st);
+  return hipGetLastError();
+}
+
+static int diag_grid(const Domain &D) {
+  const int64_t N = (int64_t)D.nx * D.ny;
+  const int64_t need = (N + kDiagBlock - 1) / kDiagBlock;
+  return (int)(need < kDiagGrid ? need : kDiagGrid);
+}
+
+size_t diag_work_bytes(const Domain &D) {
+  const int64_t N = (int64_t)D.nx * D.ny;
+  return sizeof(double) * (size_t)(2 * N + kDiagGrid * kSums + kDiagGrid);
+}
+
+template <class C>
+static void diag_t(const Domain &D, const void *src, double *bpl, double *ps,
+                   double *pm, int nb, hipStream_t st) {
+  auto s = (const typename C::T *)src;
+  if (D.walls)
+    hipLaunchKernelGGL((k_diag_sums<C, true>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
+  else
+    hipLaunchKernelGGL((k_diag_sums<C, false>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
+}
+
+hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
+                              void *work, double *out_dev, hipStream_t st) {
+  const int64_t N = (int64_t)D.nx * D.ny;
+  double *bpl = (double *)work;
+  double *ps = bpl + 2 * N;
+  double *pm = ps + kDiagGrid * kSums;
+  const int nb = diag_grid(D);
+  if (storage == kF16)
+    diag_t<CodecF16>(D, src, bpl, ps, pm, nb, st);
+  else
+    diag_t<CodecF32>(D, src, bpl, ps, pm, nb, st);
+  hipLaunchKernelGGL(k_diag_divb, dim3(nb), dim3(kDiagBlock), 0, st, D, bpl, pm);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, st, ps, nb, pm, nb,
+                     1.0 / (2.0 * (double)N), out_dev);
+  return hipGetLastError();
+}
+
+}  // namespace rr

@@ -1,0 +1,275 @@
+// rr_node.h -- per-node arithmetic of the recursive regularised LB-MHD step
+// on gfx950: the collision of one node (algorithm tasks 1-5 of Sec. II.B),
+// the storage codecs and the pull addressing of task 6.  Every kernel that
+// advances populations (single domain, batched ensemble) goes through these
+// functions, so all variants round identically.
+//
+// Floating-point contract: the library is compiled with -ffp-contract=off;
+// every fused multiply-add below is written as fmaf() on purpose, so the
+// rounding does not depend on the surrounding code.
+//
+// Arithmetic is FP32 on deviations d_i = f_i - w_i.  Constants that are not
+// exactly representable (w_i, 1/3, 1/6) never enter as rounded multipliers:
+// the equilibrium and regularised parts are formed as w_i * [bracket] where
+// the bracket uses only exact constants (3, 4.5, 1.5, 2.25, 9), and w_i is
+// applied as a quotient by 36/W_i in {2.25, 9, 36} with one Newton/FMA
+// correction, so a rounding error never repeats with the same sign every
+// step.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rr {
+
+// ---- Sec. II.A lattices -------------------------------------------------
+// D2Q9 velocities in Latt's ordering: c_x = [0,-1,-1,-1,0,1,1,1,0],
+// c_y = [0,1,0,-1,-1,-1,0,1,1]; weights 4/9 (rest), 1/36 (diagonals,
+// odd i), 1/9 (axes, even i > 0).  D2Q5: e_x = [0,-1,0,1,0],
+// e_y = [0,0,-1,0,1], weights 1/3 and 1/6.
+constexpr int kQ = 9;
+constexpr int kQm = 5;
+constexpr int kPlanes = kQ + 2 * kQm;  // f_0..f_8, then g_jx, g_jy pairs
+
+__host__ __device__ constexpr int cx(int i) {
+  return (i >= 1 && i <= 3) ? -1 : ((i >= 5 && i <= 7) ? 1 : 0);
+}
+__host__ __device__ constexpr int cy(int i) {
+  return (i == 1 || i == 7 || i == 8) ? 1 : ((i >= 3 && i <= 5) ? -1 : 0);
+}
+__host__ __device__ constexpr int ex(int j) {
+  return j == 1 ? -1 : (j == 3 ? 1 : 0);
+}
+__host__ __device__ constexpr int ey(int j) {
+  return j == 2 ? -1 : (j == 4 ? 1 : 0);
+}
+// 36 / W_i: the divisor that applies w_i = W_i / 36.
+__host__ __device__ constexpr float wdiv(int i) {
+  return i == 0 ? 2.25f : ((i & 1) ? 36.0f : 9.0f);
+}
+__host__ __device__ constexpr int opp_f(int i) { return i == 0 ? 0 : ((i + 3) & 7) + 1; }
+__host__ __device__ constexpr int opp_g(int j) { return j == 0 ? 0 : ((j + 1) & 3) + 1; }
+__host__ __device__ constexpr int gplane(int j, int comp) { return kQ + 2 * j + comp; }
+
+// a / d for an exactly representable constant d with rd = RN(1/d): the
+// product a*rd is corrected by one FMA residual step (Markstein), which
+// returns the correctly rounded quotient for normal operands.
+__device__ __forceinline__ float qdiv(float a, float d, float rd) {
+  float q = a * rd;
+  float e = fmaf(-q, d, a);
+  return fmaf(e, rd, q);
+}
+
+// a / b for a runtime divisor b near 1 (the density): hardware reciprocal
+// estimate refined by the same residual step.
+__device__ __forceinline__ float rdiv(float a, float b, float rb) {
+  float q = a * rb;
+  float e = fmaf(-q, b, a);
+  return fmaf(e, rb, q);
+}
+
+// ---- storage codecs ------------------------------------------------------
+// Stored value for the fluid plane i: S (f_i - w_i); for a magnetic plane:
+// S g.  F32 keeps S = 1.  F16 converts with round-to-nearest-even.
+struct CodecF32 {
+  using T = float;
+  __device__ __forceinline__ static float dec(T v, float) { return v; }
+  __device__ __forceinline__ static T enc(float v, float) { return v; }
+};
+struct CodecF16 {
+  using T = __half;
+  __device__ __forceinline__ static float dec(T v, float inv_s) {
+    return __half2float(v) * inv_s;
+  }
+  __device__ __forceinline__ static T enc(float v, float s) {
+    return __float2half_rn(v * s);
+  }
+};
+
+// ---- parameters of the collision ------------------------------------------
+struct CollideParams {
+  float om_c;   // 1 - omega,   omega   = 1 / tau_f
+  float omm_c;  // 1 - omega_m, omega_m = 1 / tau_m
+  float Gx, Gy;  // body force per unit mass (zero in the paper's method)
+  float src_c;   // 1 - omega / 2 (forcing source factor)
+};
+
+struct Acoef {
+  float xx, xy, yy, xxy, xyy, xxyy;
+};
+
+// Regularised non-equilibrium bracket for velocity (CX, CY), times (1-omega)
+// already folded into A (Eq. fineq_reg restricted to the D2Q9-supported
+// components): with h = 3 c^2 - 1,
+//   R = 1.5 (hx Axx + hy Ayy) + 9 cx cy Axy
+//     + 4.5 (cy hx Axxy + cx hy Axyy) + 2.25 hx hy Axxyy,
+// so that f_neq,reg,i = w_i R.
+template <int CX, int CY>
+__device__ __forceinline__ float reg_bracket(const Acoef &A) {
+  constexpr float hx = CX ? 2.0f : -1.0f;
+  constexpr float hy = CY ? 2.0f : -1.0f;
+  float r = 1.5f * fmaf(hx, A.xx, hy * A.yy);
+  if constexpr (CX != 0 && CY != 0) r = fmaf(9.0f * CX * CY, A.xy, r);
+  if constexpr (CY != 0) r = fmaf(4.5f * CY * hx, A.xxy, r);
+  if constexpr (CX != 0) r = fmaf(4.5f * CX * hy, A.xyy, r);
+  return fmaf(2.25f * hx * hy, A.xxyy, r);
+}
+
+struct EqTerms {
+  float dr, rho;
+  float ex0, exp, exm, ey0, eyp, eym;  // D1Q3 factors minus one
+  float mq;                            // 4.5 M_xx
+  float mxy;                           // 9 b_x b_y
+};
+
+// Equilibrium bracket: f_eq,i - w_i = w_i B with
+//   B = rho (1 + e_x)(1 + e_y) - 1 + 4.5 [|b|^2 |c|^2 / 2 - (c.b)^2],
+// where (1 + e) is the D1Q3 factor 1 - 1.5 u^2 (c = 0) or 1 +- 3u + 3u^2
+// (c = +-1).  The product equals the fourth-order Hermite equilibrium of
+// algorithm task 2 at b = 0 term by term, including its u_x^2 u_y^2 term
+// with the coefficient 1/(4 c_s^8).
+template <int CX, int CY>
+__device__ __forceinline__ float eq_bracket(const EqTerms &E) {
+  const float exv = CX == 0 ? E.ex0 : (CX > 0 ? E.exp : E.exm);
+  const float eyv = CY == 0 ? E.ey0 : (CY > 0 ? E.eyp : E.eym);
+  float s = fmaf(exv, eyv, exv + eyv);
+  float B = fmaf(E.rho, s, E.dr);
+  if constexpr (CX != 0 && CY == 0) B = B + E.mq;
+  if constexpr (CX == 0 && CY != 0) B = B - E.mq;
+  if constexpr (CX != 0 && CY != 0) B = fmaf(-(float)(CX * CY), E.mxy, B);
+  return B;
+}
+
+struct ForceTerms {
+  float a1c;     // (1 - omega) * 3   applied to c.a1, a1 = -F/2
+  float a1x, a1y;
+  float sc;      // 1 - omega / 2
+  float Fx, Fy, ux, uy;
+};
+
+// Forcing additions to the bracket (project reading; see the oracle):
+// (1 - omega) 3 c.a1 + (1 - omega/2) [3 c.F + 3 (hx u_x F_x + hy u_y F_y)
+// + 9 cx cy (u_x F_y + u_y F_x)].
+template <int CX, int CY>
+__device__ __forceinline__ float force_bracket(const ForceTerms &T) {
+  constexpr float hx = CX ? 2.0f : -1.0f;
+  constexpr float hy = CY ? 2.0f : -1.0f;
+  float ca1 = 0.0f, cF = 0.0f;
+  if constexpr (CX != 0) { ca1 = CX * T.a1x; cF = CX * T.Fx; }
+  if constexpr (CY != 0) { ca1 = ca1 + CY * T.a1y; cF = cF + CY * T.Fy; }
+  float s = 3.0f * fmaf(hx * T.ux, T.Fx, hy * T.uy * T.Fy) + 3.0f * cF;
+  if constexpr (CX != 0 && CY != 0)
+    s = fmaf(9.0f * CX * CY, fmaf(T.ux, T.Fy, T.uy * T.Fx), s);
+  return fmaf(T.a1c, ca1, T.sc * s);
+}
+
+template <int I, bool FORCED>
+__device__ __forceinline__ float post_f(const EqTerms &E, const Acoef &A,
+                                        const ForceTerms &T) {
+  constexpr int CX = cx(I), CY = cy(I);
+  float v = eq_bracket<CX, CY>(E) + reg_bracket<CX, CY>(A);
+  if constexpr (FORCED) v = v + force_bracket<CX, CY>(T);
+  return qdiv(v, wdiv(I), 1.0f / wdiv(I));
+}
+
+// One collision (algorithm tasks 1-5) in place.  d[i] = f_i - w_i on entry,
+// f*_i - w_i on exit; g[2j + c] = g_j,c before and after.
+template <bool FORCED>
+__device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
+                                        const CollideParams &P) {
+  // task 1: macroscopic variables
+  const float dr = ((d[0] + d[2]) + (d[4] + d[6])) +
+                   (((d[1] + d[3]) + (d[5] + d[7])) + d[8]);
+  const float rho = 1.0f + dr;
+  const float jx = ((d[5] + d[6]) + d[7]) - ((d[1] + d[2]) + d[3]);
+  const float jy = ((d[1] + d[7]) + d[8]) - ((d[3] + d[4]) + d[5]);
+  const float rr = __builtin_amdgcn_rcpf(rho);
+  float ux = rdiv(jx, rho, rr);
+  float uy = rdiv(jy, rho, rr);
+  if constexpr (FORCED) {
+    ux = fmaf(0.5f, P.Gx, ux);
+    uy = fmaf(0.5f, P.Gy, uy);
+  }
+  const float bx = ((g[0] + g[2]) + (g[4] + g[6])) + g[8];
+  const float by = ((g[1] + g[3]) + (g[5] + g[7])) + g[9];
+
+  // task 3 (needs only the Hermite moments of f_eq, which are exact):
+  // a_ab = sum_i H_ab,i (f_i - f_eq,i) = P_ab - c_s^2 dr delta_ab
+  //        - rho u_a u_b - M_ab, with P_ab = sum_i c_a c_b d_i.
+  const float pxx = ((d[1] + d[2]) + d[3]) + ((d[5] + d[6]) + d[7]);
+  const float pyy = ((d[1] + d[3]) + (d[5] + d[7])) + (d[4] + d[8]);
+  const float pxy = (d[3] + d[7]) - (d[1] + d[5]);
+  const float dr3 = qdiv(dr, 3.0f, 1.0f / 3.0f);
+  const float bxx = bx * bx, byy = by * by, bxy = bx * by;
+  const float mxx = 0.5f * (byy - bxx);  // M_xx = -M_yy; M_xy = -b_x b_y
+  const float rux = rho * ux, ruy = rho * uy;
+  Acoef A;
+  float axx = fmaf(-rux, ux, pxx - dr3) - mxx;
+  float ayy = fmaf(-ruy, uy, pyy - dr3) + mxx;
+  float axy = fmaf(-rux, uy, pxy) + bxy;
+  // recursion for the third and fourth orders (D2Q9-supported components)
+  const float axxy = fmaf(2.0f * ux, axy, uy * axx);
+  const float axyy = fmaf(2.0f * uy, axy, ux * ayy);
+  const float axxyy =
+      fmaf(ux * ux, ayy, fmaf(uy * uy, axx, (4.0f * ux) * (uy * axy)));
+  A.xx = P.om_c * axx;
+  A.yy = P.om_c * ayy;
+  A.xy = P.om_c * axy;
+  A.xxy = P.om_c * axxy;
+  A.xyy = P.om_c * axyy;
+  A.xxyy = P.om_c * axxyy;
+
+  // task 2: equilibrium factors
+  EqTerms E;
+  E.dr = dr;
+  E.rho = rho;
+  const float ux2 = ux * ux, uy2 = uy * uy;
+  E.ex0 = -1.5f * ux2;
+  E.exp = fmaf(3.0f, ux, 3.0f * ux2);
+  E.exm = fmaf(-3.0f, ux, 3.0f * ux2);
+  E.ey0 = -1.5f * uy2;
+  E.eyp = fmaf(3.0f, uy, 3.0f * uy2);
+  E.eym = fmaf(-3.0f, uy, 3.0f * uy2);
+  E.mq = 4.5f * mxx;
+  E.mxy = 9.0f * bxy;
+
+  ForceTerms T{};
+  if constexpr (FORCED) {
+    const float Fx = rho * P.Gx, Fy = rho * P.Gy;
+    T.a1c = 3.0f * P.om_c;
+    T.a1x = -0.5f * Fx;
+    T.a1y = -0.5f * Fy;
+    T.sc = P.src_c;
+    T.Fx = Fx;
+    T.Fy = Fy;
+    T.ux = ux;
+    T.uy = uy;
+  }
+
+  // tasks 4-5: regularised reconstruction and collision, per velocity
+  d[0] = post_f<0, FORCED>(E, A, T);
+  d[1] = post_f<1, FORCED>(E, A, T);
+  d[2] = post_f<2, FORCED>(E, A, T);
+  d[3] = post_f<3, FORCED>(E, A, T);
+  d[4] = post_f<4, FORCED>(E, A, T);
+  d[5] = post_f<5, FORCED>(E, A, T);
+  d[6] = post_f<6, FORCED>(E, A, T);
+  d[7] = post_f<7, FORCED>(E, A, T);
+  d[8] = post_f<8, FORCED>(E, A, T);
+
+  // magnetic BGK: g_eq,j = psi_j [b + e_j.(u b - b u) / c_s^2], i.e. with
+  // E = u_x b_y - u_y b_x: g_eq,j = psi_j (b_x - 3 e_jy E, b_y + 3 e_jx E).
+  const float Ez3 = 3.0f * fmaf(ux, by, -uy * bx);
+  const float bx3 = qdiv(bx, 3.0f, 1.0f / 3.0f);
+  const float by3 = qdiv(by, 3.0f, 1.0f / 3.0f);
+  const float bx6 = 0.5f * bx3, by6 = 0.5f * by3;  // exact halving
+  const float q1y = qdiv(by - Ez3, 6.0f, 1.0f / 6.0f);
+  const float q2x = qdiv(bx + Ez3, 6.0f, 1.0f / 6.0f);
+  const float q3y = qdiv(by + Ez3, 6.0f, 1.0f / 6.0f);
+  const float q4x = qdiv(bx - Ez3, 6.0f, 1.0f / 6.0f);
+  const float geq[2 * kQm] = {bx3, by3, bx6, q1y, q2x, by6, bx6, q3y, q4x, by6};
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k) g[k] = fmaf(P.omm_c, g[k] - geq[k], geq[k]);
+}
+
+}  // namespace rr

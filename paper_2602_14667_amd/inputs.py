@@ -111,22 +111,28 @@ def _turb_modes(seed: int):
 
 
 def _field_from_stream(n: int, seed: int):
-    """(d_y psi, -d_x psi) on an n x n grid for the drawn stream function."""
+    """(d_y psi, -d_x psi) on an n x n grid for the drawn stream function.
+
+    The field has only |kappa_x|, |kappa_y| <= TURB_KMAX modes, so it is
+    synthesised separably: v(y, x) = Re[Ey C Ex^T] with Ey[y, ky] =
+    exp(i ky 2 pi y / n), which costs O(n^2 K) instead of a full n x n FFT.
+    """
     kx, ky, c = _turb_modes(seed)
     K = TURB_KMAX
     keep = (np.abs(kx) < n / 2.0) & (np.abs(ky) < n / 2.0)
-    spec_x = np.zeros((n, n), dtype=np.complex128)
-    spec_y = np.zeros((n, n), dtype=np.complex128)
-    iy = np.mod(ky[keep], n)
-    ix = np.mod(kx[keep], n)
-    np.add.at(spec_x, (iy, ix), (1j * ky * c)[keep])
-    np.add.at(spec_y, (iy, ix), (-1j * kx * c)[keep])
-    vx = np.real(np.fft.ifft2(spec_x)) * n * n
-    vy = np.real(np.fft.ifft2(spec_y)) * n * n
+    c = np.where(keep, c, 0.0)
+    k1 = np.arange(-K, K + 1)
+    ph = np.exp(1j * 2.0 * np.pi * np.outer(np.arange(n), k1) / n)  # [n, 2K+1]
+    pr, pi = np.ascontiguousarray(ph.real), np.ascontiguousarray(ph.imag)
+    out = []
+    for spec in (1j * ky * c, -1j * kx * c):  # rows: ky, cols: kx
+        t = spec @ ph.T                        # [2K+1 (ky), n (x)]
+        v = pr @ np.ascontiguousarray(t.real)  # Re[Ey t]
+        v -= pi @ np.ascontiguousarray(t.imag)
+        out.append(v)
     # vector rms from Parseval in kappa space (identical on every grid)
-    ms = float(np.sum(np.abs(c[keep]) ** 2 * (kx[keep] ** 2 + ky[keep] ** 2)))
-    del K
-    return np.stack([vx, vy]), math.sqrt(ms)
+    ms = float(np.sum(np.abs(c) ** 2 * (kx ** 2 + ky ** 2)))
+    return np.stack(out), math.sqrt(ms)
 
 
 def turbulence(n: int, rms: float = 0.04, seed_psi: int = 1,
@@ -140,6 +146,29 @@ def turbulence(n: int, rms: float = 0.04, seed_psi: int = 1,
     b, sb = _field_from_stream(n, seed_a)
     return (np.ascontiguousarray(u * (rms / su)),
             np.ascontiguousarray(b * (rms / sb)))
+
+
+def random_modes(nx: int, ny: int, amp: float, seed: int, kmax: int = 3):
+    """Smooth periodic test fields on a rectangular grid: each component of u
+    and b is a sum of Fourier modes |k| <= kmax with counter-based random
+    coefficients, scaled to max |component| ~ amp.  Returns u, b [2][ny][nx].
+    """
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    fields = []
+    stream = 20
+    for _ in range(4):
+        f = np.zeros((ny, nx))
+        for kx_ in range(-kmax, kmax + 1):
+            for ky_ in range(0, kmax + 1):
+                r = counter_uniform(seed, stream, np.arange(2))
+                stream += 1
+                f += (r[0] - 0.5) * np.cos(2 * np.pi * (kx_ * x / nx + ky_ * y / ny)
+                                           + 2 * np.pi * r[1])
+        m = np.abs(f).max()
+        fields.append(f * (amp / m if m > 0 else 0.0))
+    u = np.stack(fields[:2])
+    b = np.stack(fields[2:])
+    return np.ascontiguousarray(u), np.ascontiguousarray(b)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,224 @@
+"""ctypes binding of ``librrmhd.so`` (declared in include/rrmhd.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (FP64 CUDA/HIP tensors) and the stream.  The
+library is loaded on first use; if it is missing the binding raises, there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librrmhd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+STORE_F32, STORE_F16 = 0, 1
+BC_PERIODIC, BC_WALLS_Y = 0, 1
+
+EXPORTED = [
+    "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
+    "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
+    "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
+    "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
+    "rrmhd_last_error_detail",
+]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("codec_scale", ctypes.c_float)]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("force", ctypes.c_double * 2),
+                ("b_wall", ctypes.c_double * 2)]
+
+
+class RRMHDError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        L = lib()
+        msg = L.rrmhd_strerror(code).decode()
+        det = L.rrmhd_last_error_detail().decode()
+        super().__init__(f"{where}: {msg} ({code})" + (f" [{det}]" if det and
+                                                      code == EDEVICE else ""))
+
+
+_lib = None
+
+
+def lib():
+    """Load librrmhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library not built: {LIB_PATH} is missing "
+                "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+        L.rrmhd_create.argtypes = [ctypes.POINTER(Grid), ctypes.c_double,
+                                   ctypes.c_double, ctypes.POINTER(BC), vp,
+                                   ctypes.POINTER(vp)]
+        L.rrmhd_init.argtypes = [vp, dp, dp]
+        L.rrmhd_step.argtypes = [vp, i64]
+        L.rrmhd_moments.argtypes = [vp, dp, dp, dp]
+        L.rrmhd_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.rrmhd_invariants.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.rrmhd_step_count.argtypes = [vp, ctypes.POINTER(i64)]
+        L.rrmhd_state_bytes.argtypes = [vp]
+        L.rrmhd_state_bytes.restype = i64
+        L.rrmhd_save_state.argtypes = [vp, vp, i64]
+        L.rrmhd_load_state.argtypes = [vp, vp, i64, i64]
+        L.rrmhd_set_stream.argtypes = [vp, vp]
+        L.rrmhd_destroy.argtypes = [vp]
+        L.rrmhd_strerror.argtypes = [ctypes.c_int]
+        L.rrmhd_strerror.restype = ctypes.c_char_p
+        L.rrmhd_last_error_detail.argtypes = []
+        L.rrmhd_last_error_detail.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("rrmhd_strerror", "rrmhd_last_error_detail",
+                            "rrmhd_state_bytes"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise RRMHDError(rc, where)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t, shape, name):
+    import torch
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor "
+                         f"of shape {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One lattice on the current device.
+
+    storage: "f32" or "f16" (populations stored as offsets f - w).
+    walls: half-way bounce-back walls in y (periodic x); force: body force
+    per unit mass; b_wall: field imposed by the magnetic walls.
+    """
+
+    def __init__(self, nx, ny, tau_f, tau_m, storage="f32", walls=False,
+                 force=(0.0, 0.0), b_wall=(0.0, 0.0), codec_scale=0.0,
+                 stream=None):
+        L = lib()
+        self.nx, self.ny = int(nx), int(ny)
+        self.storage = storage
+        self._stream = stream
+        g = Grid(self.nx, self.ny, STORE_F16 if storage == "f16" else STORE_F32,
+                 float(codec_scale))
+        bc = BC(BC_WALLS_Y if walls else BC_PERIODIC,
+                (ctypes.c_double * 2)(*force), (ctypes.c_double * 2)(*b_wall))
+        h = ctypes.c_void_p()
+        _check(L.rrmhd_create(ctypes.byref(g), float(tau_f), float(tau_m),
+                              ctypes.byref(bc), _stream_handle(stream),
+                              ctypes.byref(h)), "rrmhd_create")
+        self._h = h
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().rrmhd_destroy(self._h), "rrmhd_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls ---------------------------------------------------------------
+    def init(self, u, b):
+        shp = (2, self.ny, self.nx)
+        _check(lib().rrmhd_init(self._h, _dev_f64(u, shp, "u"),
+                                _dev_f64(b, shp, "b")), "rrmhd_init")
+
+    def step(self, n=1):
+        _check(lib().rrmhd_step(self._h, int(n)), "rrmhd_step")
+
+    def moments(self, rho=None, u=None, b=None):
+        """Fill (or allocate) FP64 device tensors rho, u, b."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if rho is None:
+            rho = torch.empty((self.ny, self.nx), dtype=torch.float64, device=dev)
+        if u is None:
+            u = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=dev)
+        if b is None:
+            b = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=dev)
+        _check(lib().rrmhd_moments(
+            self._h, _dev_f64(rho, (self.ny, self.nx), "rho"),
+            _dev_f64(u, (2, self.ny, self.nx), "u"),
+            _dev_f64(b, (2, self.ny, self.nx), "b")), "rrmhd_moments")
+        return rho, u, b
+
+    def diagnostics(self, allow_nonfinite=False):
+        ek, em, dv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().rrmhd_diagnostics(self._h, ctypes.byref(ek),
+                                     ctypes.byref(em), ctypes.byref(dv))
+        if not (allow_nonfinite and rc == ENONFINITE):
+            _check(rc, "rrmhd_diagnostics")
+        return ek.value, em.value, dv.value
+
+    def diagnostics_rc(self):
+        ek, em, dv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().rrmhd_diagnostics(self._h, ctypes.byref(ek),
+                                     ctypes.byref(em), ctypes.byref(dv))
+        return rc, (ek.value, em.value, dv.value)
+
+    def invariants(self):
+        out = (ctypes.c_double * 5)()
+        _check(lib().rrmhd_invariants(self._h, out), "rrmhd_invariants")
+        return list(out)
+
+    @property
+    def step_count(self):
+        v = ctypes.c_int64()
+        _check(lib().rrmhd_step_count(self._h, ctypes.byref(v)),
+               "rrmhd_step_count")
+        return v.value
+
+    def state_bytes(self):
+        return int(lib().rrmhd_state_bytes(self._h))
+
+    def save_state(self, dst):
+        _check(lib().rrmhd_save_state(self._h, ctypes.c_void_p(dst.data_ptr()),
+                                      dst.numel() * dst.element_size()),
+               "rrmhd_save_state")
+
+    def load_state(self, src, step_count):
+        _check(lib().rrmhd_load_state(self._h, ctypes.c_void_p(src.data_ptr()),
+                                      src.numel() * src.element_size(),
+                                      int(step_count)), "rrmhd_load_state")
+
+    def set_stream(self, stream):
+        self._stream = stream
+        _check(lib().rrmhd_set_stream(self._h, _stream_handle(stream)),
+               "rrmhd_set_stream")

