@@ -117,6 +117,14 @@ int rrmhd_save_state(rrmhd *h, void *dst, int64_t bytes);
 int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes,
                      int64_t step_count);
 
+/* Launch shape of the step kernel (the tuning knob of the autotuner; the
+ * default is picked from the grid).  bx x by threads per workgroup
+ * (bx * by <= 256, bx >= 1, by >= 1), ry consecutive rows per thread (>= 1),
+ * xcd = 1 renumbers workgroups so each XCD gets contiguous tiles, nt = 1
+ * writes populations with non-temporal stores.  Results do not depend on
+ * the shape (bitwise).  Host-side only. */
+int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
+
 /* Stream used by the handle; NULL is the null stream. */
 int rrmhd_set_stream(rrmhd *h, void *hip_stream);
 

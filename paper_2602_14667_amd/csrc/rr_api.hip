@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -113,9 +114,16 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   rr::Domain &D = h->D;
   D.nx = grid->nx;
   D.ny = grid->ny;
-  // planes start on 256-byte boundaries
+  // planes start on 256-byte boundaries; an optional extra gap between
+  // planes (RRMHD_PLANE_PAD_BYTES, a multiple of 256) staggers the plane
+  // starts across HBM channels
   const int64_t align = 256 / h->elem;
-  D.plane = (N + align - 1) / align * align;
+  int64_t pad = 0;
+  if (const char *e = std::getenv("RRMHD_PLANE_PAD_BYTES")) {
+    long long v = std::atoll(e);
+    if (v > 0 && v % 256 == 0) pad = v / h->elem;
+  }
+  D.plane = (N + align - 1) / align * align + pad;
   D.walls = b.kind == RRMHD_BC_WALLS_Y;
   const double om = 1.0 / tau_f, omm = 1.0 / tau_m;
   D.om_c = (float)(1.0 - om);
@@ -148,6 +156,16 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
     return rc;
   }
   *out = h;
+  return RRMHD_OK;
+}
+
+int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
+  if (!h || bx < 1 || by < 1 || bx * by > 256 || ry < 1) return RRMHD_EINVAL;
+  h->shape.bx = bx;
+  h->shape.by = by;
+  h->shape.ry = ry;
+  h->shape.xcd = xcd ? 1 : 0;
+  h->shape.nt = nt ? 1 : 0;
   return RRMHD_OK;
 }
 

@@ -23,6 +23,7 @@ struct LaunchShape {
   int bx, by;  // threads per block in x and y
   int ry;      // rows per thread (block covers by * ry rows)
   int xcd;     // 1: XCD-aware block order
+  int nt;      // 1: non-temporal stores of the new populations
 };
 
 hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,

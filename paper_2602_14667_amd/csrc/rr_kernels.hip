@@ -110,6 +110,51 @@ __device__ __forceinline__ void pull_node(const Domain &D,
   pull_g<C, WALLS, 4>(D, s, R, x, g[8], g[9]);
 }
 
+// Periodic fast path: every plane base is wave-uniform (scalar registers)
+// and the in-plane position is a 32-bit byte offset, so each access is one
+// global load/store with a scalar base and a 32-bit vector offset.
+template <class T>
+__device__ __forceinline__ const T *plane_ptr(const T *__restrict__ s, int p,
+                                              int64_t plane) {
+  return s + (int64_t)p * plane;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_at(const T *__restrict__ base, uint32_t byte_off) {
+  return *(const T *)((const char *)base + byte_off);
+}
+
+template <class T, bool NT>
+__device__ __forceinline__ void st_at(T *__restrict__ base, uint32_t byte_off, T v) {
+  T *p = (T *)((char *)base + byte_off);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <class C, int I>
+__device__ __forceinline__ float pull_f_per(const Domain &D,
+                                            const typename C::T *__restrict__ s,
+                                            uint32_t bm, uint32_t b0, uint32_t bp,
+                                            uint32_t xm, uint32_t x0, uint32_t xp) {
+  constexpr int CX = cx(I), CY = cy(I);
+  const uint32_t row = CY == 0 ? b0 : (CY > 0 ? bm : bp);
+  const uint32_t col = CX == 0 ? x0 : (CX > 0 ? xm : xp);
+  return C::dec(ld_at(plane_ptr(s, I, D.plane), row + col), D.inv_s);
+}
+
+template <class C, int J, int COMP>
+__device__ __forceinline__ float pull_g_per(const Domain &D,
+                                            const typename C::T *__restrict__ s,
+                                            uint32_t bm, uint32_t b0, uint32_t bp,
+                                            uint32_t xm, uint32_t x0, uint32_t xp) {
+  constexpr int EX = ex(J), EY = ey(J);
+  const uint32_t row = EY == 0 ? b0 : (EY > 0 ? bm : bp);
+  const uint32_t col = EX == 0 ? x0 : (EX > 0 ? xm : xp);
+  return C::dec(ld_at(plane_ptr(s, gplane(J, COMP), D.plane), row + col), D.inv_s);
+}
+
 // Block order: hardware hands consecutive workgroups to the eight XCDs in
 // turn.  Renumbering so that each XCD receives a contiguous run of tiles
 // keeps the cache lines shared by neighbouring tiles (the +-1 pull offsets)
@@ -124,11 +169,12 @@ __device__ __forceinline__ int xcd_remap(int L, int n) {
 // 1-D grid of tiles; a tile is blockDim.x nodes of ry consecutive rows,
 // blockDim.y tiles high.
 // ---------------------------------------------------------------------------
-template <class C, bool WALLS, bool FORCED>
+template <class C, bool WALLS, bool FORCED, bool NT>
 __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
                                               int xcd,
                                               const typename C::T *__restrict__ src,
                                               typename C::T *__restrict__ dst) {
+  using T = typename C::T;
   const int ntiles = gridDim.x;
   const int L = xcd ? xcd_remap(blockIdx.x, ntiles) : (int)blockIdx.x;
   const int tx = L % tiles_x, ty = L / tiles_x;
@@ -141,18 +187,49 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
+  constexpr uint32_t E = sizeof(T);
+  const uint32_t xm = (x == 0 ? D.nx - 1 : x - 1) * E;
+  const uint32_t xp = (x == D.nx - 1 ? 0 : x + 1) * E;
+  const uint32_t x0 = x * E;
+  const uint32_t pitch = D.nx * E;
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
     float d[kQ], g[2 * kQm];
-    pull_node<C, WALLS>(D, src, x, y, d, g);
+    if constexpr (WALLS) {
+      pull_node<C, true>(D, src, x, y, d, g);
+    } else {
+      const uint32_t b0 = y * pitch;
+      const uint32_t bm = (y == 0 ? D.ny - 1 : y - 1) * pitch;
+      const uint32_t bp = (y == D.ny - 1 ? 0 : y + 1) * pitch;
+      d[0] = pull_f_per<C, 0>(D, src, bm, b0, bp, xm, x0, xp);
+      d[1] = pull_f_per<C, 1>(D, src, bm, b0, bp, xm, x0, xp);
+      d[2] = pull_f_per<C, 2>(D, src, bm, b0, bp, xm, x0, xp);
+      d[3] = pull_f_per<C, 3>(D, src, bm, b0, bp, xm, x0, xp);
+      d[4] = pull_f_per<C, 4>(D, src, bm, b0, bp, xm, x0, xp);
+      d[5] = pull_f_per<C, 5>(D, src, bm, b0, bp, xm, x0, xp);
+      d[6] = pull_f_per<C, 6>(D, src, bm, b0, bp, xm, x0, xp);
+      d[7] = pull_f_per<C, 7>(D, src, bm, b0, bp, xm, x0, xp);
+      d[8] = pull_f_per<C, 8>(D, src, bm, b0, bp, xm, x0, xp);
+      g[0] = pull_g_per<C, 0, 0>(D, src, bm, b0, bp, xm, x0, xp);
+      g[1] = pull_g_per<C, 0, 1>(D, src, bm, b0, bp, xm, x0, xp);
+      g[2] = pull_g_per<C, 1, 0>(D, src, bm, b0, bp, xm, x0, xp);
+      g[3] = pull_g_per<C, 1, 1>(D, src, bm, b0, bp, xm, x0, xp);
+      g[4] = pull_g_per<C, 2, 0>(D, src, bm, b0, bp, xm, x0, xp);
+      g[5] = pull_g_per<C, 2, 1>(D, src, bm, b0, bp, xm, x0, xp);
+      g[6] = pull_g_per<C, 3, 0>(D, src, bm, b0, bp, xm, x0, xp);
+      g[7] = pull_g_per<C, 3, 1>(D, src, bm, b0, bp, xm, x0, xp);
+      g[8] = pull_g_per<C, 4, 0>(D, src, bm, b0, bp, xm, x0, xp);
+      g[9] = pull_g_per<C, 4, 1>(D, src, bm, b0, bp, xm, x0, xp);
+    }
     collide<FORCED>(d, g, P);
-    const int o = y * D.nx + x;
+    const uint32_t o = y * pitch + x0;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) dst[(int64_t)i * D.plane + o] = C::enc(d[i], D.s);
+    for (int i = 0; i < kQ; ++i)
+      st_at<T, NT>(dst + (int64_t)i * D.plane, o, C::enc(d[i], D.s));
 #pragma unroll
     for (int k = 0; k < 2 * kQm; ++k)
-      dst[(int64_t)(kQ + k) * D.plane + o] = C::enc(g[k], D.s);
+      st_at<T, NT>(dst + (int64_t)(kQ + k) * D.plane, o, C::enc(g[k], D.s));
   }
 }
 
@@ -411,12 +488,13 @@ LaunchShape default_shape(const Domain &D) {
   }
   L.ry = 1;
   L.xcd = 1;
+  L.nt = 0;
   return L;
 }
 
-template <class C>
-static hipError_t step_t(const Domain &D, const void *src, void *dst,
-                         const LaunchShape &L, hipStream_t st) {
+template <class C, bool NT>
+static void step_nt(const Domain &D, const void *src, void *dst, const LaunchShape &L,
+                    hipStream_t st) {
   const int tiles_x = (D.nx + L.bx - 1) / L.bx;
   const int rows_per_tile = L.by * L.ry;
   const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
@@ -426,21 +504,33 @@ static hipError_t step_t(const Domain &D, const void *src, void *dst,
   auto d = (typename C::T *)dst;
   if (D.walls) {
     if (forced)
-      hipLaunchKernelGGL((k_step<C, true, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      hipLaunchKernelGGL((k_step<C, true, true, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
     else
-      hipLaunchKernelGGL((k_step<C, true, false>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      hipLaunchKernelGGL((k_step<C, true, false, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
   } else {
     if (forced)
-      hipLaunchKernelGGL((k_step<C, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      hipLaunchKernelGGL((k_step<C, false, true, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
     else
-      hipLaunchKernelGGL((k_step<C, false, false>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      hipLaunchKernelGGL((k_step<C, false, false, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
   }
+}
+
+template <class C>
+static hipError_t step_t(const Domain &D, const void *src, void *dst,
+                         const LaunchShape &L, hipStream_t st) {
+  if (L.nt)
+    step_nt<C, true>(D, src, dst, L, st);
+  else
+    step_nt<C, false>(D, src, dst, L, st);
   return hipGetLastError();
 }
 
 hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
                        const LaunchShape &L, hipStream_t st) {
   if (L.bx <= 0 || L.by <= 0 || L.bx * L.by > 256 || L.ry <= 0) return hipErrorInvalidValue;
+  // byte offsets inside one plane are 32-bit
+  if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
+    return hipErrorInvalidValue;
   return storage == kF16 ? step_t<CodecF16>(D, src, dst, L, st)
                          : step_t<CodecF32>(D, src, dst, L, st);
 }
@@ -451,7 +541,7 @@ hipError_t launch_init(int storage, const Domain &D, const double *u,
   const dim3 block(64), grid((D.nx + 63) / 64, D.ny);
   if (storage == kF16)
     hipLaunchKernelGGL(k_init<CodecF16>, grid, block, 0, st, D, u, b, bwx, bwy,
-                       (__half *)dst);
+                       (uint16_t *)dst);
   else
     hipLaunchKernelGGL(k_init<CodecF32>, grid, block, 0, st, D, u, b, bwx, bwy,
                        (float *)dst);

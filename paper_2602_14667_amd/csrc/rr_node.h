@@ -77,12 +77,12 @@ struct CodecF32 {
   __device__ __forceinline__ static T enc(float v, float) { return v; }
 };
 struct CodecF16 {
-  using T = __half;
+  using T = uint16_t;  // IEEE binary16 bit pattern
   __device__ __forceinline__ static float dec(T v, float inv_s) {
-    return __half2float(v) * inv_s;
+    return __half2float(__ushort_as_half(v)) * inv_s;
   }
   __device__ __forceinline__ static T enc(float v, float s) {
-    return __float2half_rn(v * s);
+    return __half_as_ushort(__float2half_rn(v * s));
   }
 };
 

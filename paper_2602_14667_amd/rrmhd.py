@@ -21,7 +21,7 @@ EXPORTED = [
     "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
     "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
-    "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
+    "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail",
 ]
 
@@ -75,6 +75,8 @@ def lib():
         L.rrmhd_save_state.argtypes = [vp, vp, i64]
         L.rrmhd_load_state.argtypes = [vp, vp, i64, i64]
         L.rrmhd_set_stream.argtypes = [vp, vp]
+        ci = ctypes.c_int
+        L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
         L.rrmhd_destroy.argtypes = [vp]
         L.rrmhd_strerror.argtypes = [ctypes.c_int]
         L.rrmhd_strerror.restype = ctypes.c_char_p
@@ -217,6 +219,10 @@ class Solver:
         _check(lib().rrmhd_load_state(self._h, ctypes.c_void_p(src.data_ptr()),
                                       src.numel() * src.element_size(),
                                       int(step_count)), "rrmhd_load_state")
+
+    def set_launch(self, bx, by, ry=1, xcd=1, nt=0):
+        _check(lib().rrmhd_set_launch(self._h, int(bx), int(by), int(ry),
+                                      int(xcd), int(nt)), "rrmhd_set_launch")
 
     def set_stream(self, stream):
         self._stream = stream
