@@ -49,7 +49,7 @@ def measured_traffic(storage, n):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(n_sample=2048, steps=6):
+def cpu_baseline(n_sample=2048, steps=60):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
     from paper_2602_14667_amd import inputs
@@ -67,15 +67,40 @@ def cpu_baseline(n_sample=2048, steps=6):
             "seconds": dt}
 
 
+def copy_reference(torch, rrmhd, args):
+    """Plain streaming copy of a known byte count (bandwidth reference and
+    calibration of memory-traffic counters)."""
+    nb = args.copy_bytes
+    a = torch.zeros(nb // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(max(args.warmup, 1)):
+        rrmhd.bandwidth_probe(c, a)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        rrmhd.bandwidth_probe(c, a)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    print(json.dumps({"mode": "copy", "bytes_read": nb, "bytes_written": nb,
+                      "ms_per_copy": ms, "GBs": 2 * nb / ms / 1e6}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tau", type=float, default=0.51)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["step", "copy"], default="step",
+                    help="copy: time the plain device-copy reference instead")
+    ap.add_argument("--copy-bytes", type=int, default=4 << 30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for "
@@ -87,12 +112,16 @@ def main():
     from paper_2602_14667_amd import inputs, rrmhd
 
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        copy_reference(torch, rrmhd, args)
+        return
     n = args.n
     u, b = inputs.turbulence(n, 0.04)
     ud = torch.from_numpy(u).cuda()
     bd = torch.from_numpy(b).cuda()
     del u, b
     s = rrmhd.Solver(n, n, args.tau, args.tau, storage=args.storage)
+    launch = "library default (f32: 128x2, f16: 256x1 threads; NT stores)"
     s.init(ud, bd)
     del ud, bd
     s.step(args.warmup)
@@ -134,6 +163,7 @@ def main():
                                "random-phase psi/A, rms u=b=0.04",
                    "nodes": nodes, "tau_f": args.tau, "tau_m": args.tau,
                    "storage": f"{args.storage}-shifted (f - w)",
+                   "launch": launch,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -120,8 +120,9 @@ int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes,
 /* Launch shape of the step kernel (the tuning knob of the autotuner; the
  * default is picked from the grid).  bx x by threads per workgroup
  * (bx * by <= 256, bx >= 1, by >= 1), ry consecutive rows per thread (>= 1),
- * xcd = 1 renumbers workgroups so each XCD gets contiguous tiles, nt = 1
- * writes populations with non-temporal stores.  Results do not depend on
+ * xcd = 1 renumbers workgroups so each XCD gets contiguous tiles; nt bit 0
+ * writes populations with non-temporal stores, bit 1 reads them with
+ * non-temporal loads (periodic grids).  Results do not depend on
  * the shape (bitwise).  Host-side only. */
 int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 
@@ -129,6 +130,13 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 int rrmhd_set_stream(rrmhd *h, void *hip_stream);
 
 int rrmhd_destroy(rrmhd *h);
+
+/* Measurement helper, not part of the method: copies `bytes` (a multiple of
+ * 16, both pointers 16-byte aligned, device memory) with a plain streaming
+ * kernel on hip_stream.  Used as the measured device-bandwidth reference
+ * and to calibrate memory-traffic counters against a known byte count. */
+int rrmhd_bandwidth_probe(void *dst, const void *src, int64_t bytes,
+                          void *hip_stream);
 
 const char *rrmhd_strerror(int code);
 const char *rrmhd_last_error_detail(void);

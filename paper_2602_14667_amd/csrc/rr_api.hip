@@ -118,10 +118,10 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   // planes (RRMHD_PLANE_PAD_BYTES, a multiple of 256) staggers the plane
   // starts across HBM channels
   const int64_t align = 256 / h->elem;
-  int64_t pad = 0;
+  int64_t pad = 256 / h->elem;  // measured best default: 256 B between planes
   if (const char *e = std::getenv("RRMHD_PLANE_PAD_BYTES")) {
     long long v = std::atoll(e);
-    if (v > 0 && v % 256 == 0) pad = v / h->elem;
+    if (v >= 0 && v % 256 == 0) pad = v / h->elem;
   }
   D.plane = (N + align - 1) / align * align + pad;
   D.walls = b.kind == RRMHD_BC_WALLS_Y;
@@ -135,6 +135,7 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   D.bw2y = (float)(b.b_wall[1] / 3.0);
   D.s = grid->storage == RRMHD_STORE_F16 ? S : 1.0f;
   D.inv_s = 1.0f / D.s;
+  D.elem = (int)h->elem;
   h->shape = rr::default_shape(D);
 
   const size_t bytes = (size_t)D.plane * rr::kStatePlanes * h->elem;
@@ -165,7 +166,7 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
   h->shape.by = by;
   h->shape.ry = ry;
   h->shape.xcd = xcd ? 1 : 0;
-  h->shape.nt = nt ? 1 : 0;
+  h->shape.nt = nt & 3;
   return RRMHD_OK;
 }
 

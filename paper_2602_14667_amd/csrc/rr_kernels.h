@@ -17,13 +17,14 @@ struct Domain {
   float Gx, Gy;
   float bw2x, bw2y;  // 2 psi_j b_wall for j = 1..4 (psi = 1/6): b_wall / 3
   float s, inv_s;    // storage scale (F16)
+  int elem;          // bytes per stored value (4 or 2)
 };
 
 struct LaunchShape {
   int bx, by;  // threads per block in x and y
   int ry;      // rows per thread (block covers by * ry rows)
   int xcd;     // 1: XCD-aware block order
-  int nt;      // 1: non-temporal stores of the new populations
+  int nt;      // bit 0: non-temporal stores, bit 1: non-temporal loads
 };
 
 hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,

@@ -269,7 +269,13 @@ __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
   const float q4x = qdiv(bx - Ez3, 6.0f, 1.0f / 6.0f);
   const float geq[2 * kQm] = {bx3, by3, bx6, q1y, q2x, by6, bx6, q3y, q4x, by6};
 #pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k) g[k] = fmaf(P.omm_c, g[k] - geq[k], geq[k]);
+  for (int k = 2; k < 2 * kQm; ++k) g[k] = fmaf(P.omm_c, g[k] - geq[k], geq[k]);
+  // The collision leaves b = sum_j g_j unchanged (sum_j g_eq,j = b), so the
+  // rest population is taken from that identity: g*_0 = b - sum_{j>0} g*_j.
+  // Each node then conserves its field exactly up to one rounding per step
+  // instead of accumulating the roundings of five relaxations.
+  g[0] = bx - ((g[2] + g[4]) + (g[6] + g[8]));
+  g[1] = by - ((g[3] + g[5]) + (g[7] + g[9]));
 }
 
 }  // namespace rr

@@ -22,7 +22,7 @@ EXPORTED = [
     "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
     "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
-    "rrmhd_last_error_detail",
+    "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
         ci = ctypes.c_int
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
         L.rrmhd_destroy.argtypes = [vp]
+        L.rrmhd_bandwidth_probe.argtypes = [vp, vp, i64, vp]
         L.rrmhd_strerror.argtypes = [ctypes.c_int]
         L.rrmhd_strerror.restype = ctypes.c_char_p
         L.rrmhd_last_error_detail.argtypes = []
@@ -228,3 +229,13 @@ class Solver:
         self._stream = stream
         _check(lib().rrmhd_set_stream(self._h, _stream_handle(stream)),
                "rrmhd_set_stream")
+
+
+def bandwidth_probe(dst, src, stream=None):
+    """Plain device copy of src into dst (torch tensors, equal byte sizes)."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nb
+    _check(lib().rrmhd_bandwidth_probe(ctypes.c_void_p(dst.data_ptr()),
+                                       ctypes.c_void_p(src.data_ptr()), nb,
+                                       _stream_handle(stream)),
+           "rrmhd_bandwidth_probe")
