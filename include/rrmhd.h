@@ -120,7 +120,8 @@ int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes,
 /* Launch shape of the step kernel (the tuning knob of the autotuner; the
  * default is picked from the grid).  bx x by threads per workgroup
  * (bx * by <= 256, bx >= 1, by >= 1), ry consecutive rows per thread (>= 1),
- * xcd = 1 renumbers workgroups so each XCD gets contiguous tiles; nt bit 0
+ * xcd = 1 renumbers workgroups so each XCD gets one contiguous run of tiles,
+ * xcd = 2 so each XCD gets 8 neighbouring tiles out of every 64; nt bit 0
  * writes populations with non-temporal stores, bit 1 reads them with
  * non-temporal loads (periodic grids).  Results do not depend on
  * the shape (bitwise).  Host-side only. */
@@ -130,6 +131,61 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 int rrmhd_set_stream(rrmhd *h, void *hip_stream);
 
 int rrmhd_destroy(rrmhd *h);
+
+/* ---- Batched ensemble --------------------------------------------------
+ * Many independent doubly periodic domains of uneven sizes and relaxation
+ * times, all advanced together: one persistent kernel launch per time step
+ * strides over a flat list of 256-thread tiles covering every domain (the
+ * same per-node update as rrmhd_step, so each domain evolves bitwise as a
+ * standalone handle would).  With a graph chunk set, runs of that many steps
+ * are captured once into a hipGraph and replayed.  One storage type for the
+ * whole ensemble.  Domain indices run 0..n-1; field arrays follow the
+ * single-domain conventions for the domain's own nx, ny. */
+typedef struct rrmhd_batch rrmhd_batch;
+
+/* grids[d] gives nx, ny of domain d (storage/codec_scale fields ignored; the
+ * storage argument applies to all); tau_f[d], tau_m[d] > 1/2 (host arrays).
+ * Allocates both population buffers for all domains. */
+int rrmhd_batch_create(int n, const rrmhd_grid *grids, const double *tau_f,
+                       const double *tau_m, int storage, void *hip_stream,
+                       rrmhd_batch **out);
+/* Equilibrium initial state of domain d (as rrmhd_init). */
+int rrmhd_batch_init(rrmhd_batch *b, int d, const double *u, const double *bf);
+/* Advance every domain n steps (all domains must have been initialised). */
+int rrmhd_batch_step(rrmhd_batch *b, int64_t n);
+/* Steps per captured hipGraph (0: plain launches, the default). */
+int rrmhd_batch_set_graph_chunk(rrmhd_batch *b, int chunk);
+/* Tile width bx (a divisor of 256, tile = bx x 256/bx) for domain d, or for
+ * all domains when d = -1 (0 keeps it); persistent workgroup count grid (0
+ * keeps it); nt = 1/0 non-temporal stores (-1 keeps it).  Results do not
+ * depend on these (bitwise). */
+int rrmhd_batch_set_shape(rrmhd_batch *b, int d, int bx, int grid, int nt);
+int rrmhd_batch_moments(rrmhd_batch *b, int d, double *rho, double *u,
+                        double *bf);
+/* As rrmhd_diagnostics for domain d (synchronises). */
+int rrmhd_batch_diagnostics(rrmhd_batch *b, int d, double *E_kin,
+                            double *E_mag, double *max_div_b);
+/* Total nodes, steps taken, tiles in the work list, persistent grid size. */
+int rrmhd_batch_info(const rrmhd_batch *b, int64_t *nodes, int64_t *steps,
+                     int *ntiles, int *grid);
+int rrmhd_batch_destroy(rrmhd_batch *b);
+const char *rrmhd_batch_last_error_detail(void);
+
+/* ---- Autotuner -----------------------------------------------------------
+ * Times candidate launch shapes of the step kernel on the handle's own grid
+ * (trials steps each, best of three repetitions, HIP events) and installs
+ * the fastest.  The handle's state and step count are preserved (a handle
+ * that was never initialised is timed on the rest state and stays
+ * uninitialised).  cache_path (may be NULL) names a JSON file of earlier
+ * results keyed by device architecture, grid size and storage; a cached
+ * entry is installed without timing, and new results are added to it.
+ * Outputs (may be NULL): the chosen bx, by, xcd and its time per step. */
+int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
+                   int *out_by, int *out_xcd, double *out_ms);
+/* Ensemble version: a tile width for every distinct domain size (timed on a
+ * standalone grid of that size) and then the persistent workgroup count
+ * (timed on the ensemble, state preserved); same cache file. */
+int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials);
 
 /* Measurement helper, not part of the method: copies `bytes` (a multiple of
  * 16, both pointers 16-byte aligned, device memory) with a plain streaming

@@ -9,6 +9,7 @@
 #include <new>
 
 #include "../../include/rrmhd.h"
+#include "rr_internal.h"
 #include "rr_kernels.h"
 
 namespace {
@@ -165,7 +166,7 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
   h->shape.bx = bx;
   h->shape.by = by;
   h->shape.ry = ry;
-  h->shape.xcd = xcd ? 1 : 0;
+  h->shape.xcd = (xcd >= 0 && xcd <= 2) ? xcd : 0;
   h->shape.nt = nt & 3;
   return RRMHD_OK;
 }
@@ -273,6 +274,21 @@ int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes, int64_t step_coun
   h->steps = step_count;
   h->ready = true;
   return RRMHD_OK;
+}
+
+int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage, hipStream_t *stream,
+                   int *ready) {
+  if (!h) return RRMHD_EINVAL;
+  if (nx) *nx = h->D.nx;
+  if (ny) *ny = h->D.ny;
+  if (storage) *storage = h->storage;
+  if (stream) *stream = h->stream;
+  if (ready) *ready = h->ready ? 1 : 0;
+  return RRMHD_OK;
+}
+
+void rr_handle_set_ready(rrmhd *h, int ready) {
+  if (h) h->ready = ready != 0;
 }
 
 }  // extern "C"

@@ -1,0 +1,23 @@
+// rr_internal.h -- hooks between the host-side translation units of the
+// library (not exported: hidden visibility).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rrmhd.h"
+
+#define RR_HIDDEN __attribute__((visibility("hidden")))
+
+extern "C" {
+// single domain: geometry, storage, stream and whether a state is present
+RR_HIDDEN int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage,
+                             hipStream_t *stream, int *ready);
+RR_HIDDEN void rr_handle_set_ready(rrmhd *h, int ready);
+// batch: domain sizes (arrays may be NULL to query n and storage)
+RR_HIDDEN int rr_batch_domains(const rrmhd_batch *b, int *n, int *storage, int *nx,
+                               int *ny);
+// batch: copy of the whole current state / restore it (frees the copy)
+RR_HIDDEN int rr_batch_save(rrmhd_batch *b, void **copy);
+RR_HIDDEN int rr_batch_restore(rrmhd_batch *b, void *copy, int64_t steps);
+RR_HIDDEN hipStream_t rr_batch_stream(const rrmhd_batch *b);
+}

@@ -10,6 +10,7 @@
 // loads of the next step.
 #include "rr_kernels.h"
 #include "rr_node.h"
+#include "rr_pull.h"
 
 namespace rr {
 
@@ -110,56 +111,6 @@ __device__ __forceinline__ void pull_node(const Domain &D,
   pull_g<C, WALLS, 4>(D, s, R, x, g[8], g[9]);
 }
 
-// Periodic fast path: every plane base is wave-uniform (scalar registers)
-// and the in-plane position is a 32-bit byte offset, so each access is one
-// global load/store with a scalar base and a 32-bit vector offset.
-template <class T>
-__device__ __forceinline__ const T *plane_ptr(const T *__restrict__ s, int p,
-                                              int64_t plane) {
-  return s + (int64_t)p * plane;
-}
-
-template <class T, bool NT = false>
-__device__ __forceinline__ T ld_at(const T *__restrict__ base, uint32_t byte_off) {
-  const T *p = (const T *)((const char *)base + byte_off);
-  if constexpr (NT)
-    return __builtin_nontemporal_load(p);
-  else
-    return *p;
-}
-
-template <class T, bool NT>
-__device__ __forceinline__ void st_at(T *__restrict__ base, uint32_t byte_off, T v) {
-  T *p = (T *)((char *)base + byte_off);
-  if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
-}
-
-template <class C, int I, bool NTL>
-__device__ __forceinline__ float pull_f_per(const Domain &D,
-                                            const typename C::T *__restrict__ s,
-                                            uint32_t bm, uint32_t b0, uint32_t bp,
-                                            uint32_t xm, uint32_t x0, uint32_t xp) {
-  constexpr int CX = cx(I), CY = cy(I);
-  const uint32_t row = CY == 0 ? b0 : (CY > 0 ? bm : bp);
-  const uint32_t col = CX == 0 ? x0 : (CX > 0 ? xm : xp);
-  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(s, I, D.plane), row + col), D.inv_s);
-}
-
-template <class C, int J, int COMP, bool NTL>
-__device__ __forceinline__ float pull_g_per(const Domain &D,
-                                            const typename C::T *__restrict__ s,
-                                            uint32_t bm, uint32_t b0, uint32_t bp,
-                                            uint32_t xm, uint32_t x0, uint32_t xp) {
-  constexpr int EX = ex(J), EY = ey(J);
-  const uint32_t row = EY == 0 ? b0 : (EY > 0 ? bm : bp);
-  const uint32_t col = EX == 0 ? x0 : (EX > 0 ? xm : xp);
-  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(s, gplane(J, COMP), D.plane), row + col),
-                D.inv_s);
-}
-
 // Block order: hardware hands consecutive workgroups to the eight XCDs in
 // turn.  Renumbering so that each XCD receives a contiguous run of tiles
 // keeps the cache lines shared by neighbouring tiles (the +-1 pull offsets)
@@ -167,6 +118,16 @@ __device__ __forceinline__ float pull_g_per(const Domain &D,
 __device__ __forceinline__ int xcd_remap(int L, int n) {
   const int q = n >> 3, r = n & 7, k = L & 7, m = L >> 3;
   return k < r ? k * (q + 1) + m : r * (q + 1) + (k - r) * q + m;
+}
+
+// Local variant: within each run of 64 consecutive workgroups, XCD k
+// (workgroups L with L % 8 == k) takes 8 neighbouring tiles, so 7 of every 8
+// tile boundaries stay inside one L2 while all XCDs still sweep the same
+// region of memory together.
+__device__ __forceinline__ int xcd_local(int L, int n) {
+  const int g = L >> 6, j = L & 63;
+  if ((g + 1) * 64 > n) return L;
+  return (g << 6) + ((j & 7) << 3) + (j >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -179,9 +140,9 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
                                               int xcd,
                                               const typename C::T *__restrict__ src,
                                               typename C::T *__restrict__ dst) {
-  using T = typename C::T;
   const int ntiles = gridDim.x;
-  const int L = xcd ? xcd_remap(blockIdx.x, ntiles) : (int)blockIdx.x;
+  const int L = xcd == 1 ? xcd_remap(blockIdx.x, ntiles)
+                         : (xcd == 2 ? xcd_local(blockIdx.x, ntiles) : (int)blockIdx.x);
   const int tx = L % tiles_x, ty = L / tiles_x;
   const int x = tx * blockDim.x + threadIdx.x;
   const int y0 = (ty * blockDim.y + threadIdx.y) * ry;
@@ -192,49 +153,23 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
-  constexpr uint32_t E = sizeof(T);
-  const uint32_t xm = (x == 0 ? D.nx - 1 : x - 1) * E;
-  const uint32_t xp = (x == D.nx - 1 ? 0 : x + 1) * E;
-  const uint32_t x0 = x * E;
-  const uint32_t pitch = D.nx * E;
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
-    float d[kQ], g[2 * kQm];
     if constexpr (WALLS) {
+      float d[kQ], g[2 * kQm];
       pull_node<C, true>(D, src, x, y, d, g);
+      collide<FORCED>(d, g, P);
+      const int o = y * D.nx + x;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) dst[(int64_t)i * D.plane + o] = C::enc(d[i], D.s);
+#pragma unroll
+      for (int k = 0; k < 2 * kQm; ++k)
+        dst[(int64_t)(kQ + k) * D.plane + o] = C::enc(g[k], D.s);
     } else {
-      const uint32_t b0 = y * pitch;
-      const uint32_t bm = (y == 0 ? D.ny - 1 : y - 1) * pitch;
-      const uint32_t bp = (y == D.ny - 1 ? 0 : y + 1) * pitch;
-      d[0] = pull_f_per<C, 0, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[1] = pull_f_per<C, 1, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[2] = pull_f_per<C, 2, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[3] = pull_f_per<C, 3, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[4] = pull_f_per<C, 4, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[5] = pull_f_per<C, 5, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[6] = pull_f_per<C, 6, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[7] = pull_f_per<C, 7, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      d[8] = pull_f_per<C, 8, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[0] = pull_g_per<C, 0, 0, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[1] = pull_g_per<C, 0, 1, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[2] = pull_g_per<C, 1, 0, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[3] = pull_g_per<C, 1, 1, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[4] = pull_g_per<C, 2, 0, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[5] = pull_g_per<C, 2, 1, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[6] = pull_g_per<C, 3, 0, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[7] = pull_g_per<C, 3, 1, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[8] = pull_g_per<C, 4, 0, NTL>(D, src, bm, b0, bp, xm, x0, xp);
-      g[9] = pull_g_per<C, 4, 1, NTL>(D, src, bm, b0, bp, xm, x0, xp);
+      const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+      update_periodic<C, FORCED, NT, NTL>(G, src, dst, x, y, P);
     }
-    collide<FORCED>(d, g, P);
-    const uint32_t o = y * pitch + x0;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i)
-      st_at<T, NT>(dst + (int64_t)i * D.plane, o, C::enc(d[i], D.s));
-#pragma unroll
-    for (int k = 0; k < 2 * kQm; ++k)
-      st_at<T, NT>(dst + (int64_t)(kQ + k) * D.plane, o, C::enc(g[k], D.s));
   }
 }
 

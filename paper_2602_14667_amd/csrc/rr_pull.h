@@ -1,0 +1,111 @@
+// rr_pull.h -- the periodic node update shared by the single-domain and the
+// batched kernels: pull the 19 populations of node (x, y) from their
+// upstream neighbours (streaming, algorithm task 6), collide (tasks 1-5) and
+// store the post-collision values at (x, y).  Every plane base is
+// wave-uniform (scalar registers) and the in-plane position is a 32-bit byte
+// offset, so each access is one global load/store with a scalar base.
+#pragma once
+#include "rr_node.h"
+
+namespace rr {
+
+struct PlaneGeom {
+  int64_t plane;  // elements between plane starts
+  int nx, ny;
+  float s, inv_s;  // storage scale
+};
+
+template <class T>
+__device__ __forceinline__ const T *plane_ptr(const T *__restrict__ s, int p,
+                                              int64_t plane) {
+  return s + (int64_t)p * plane;
+}
+
+template <class T, bool NT = false>
+__device__ __forceinline__ T ld_at(const T *__restrict__ base, uint32_t byte_off) {
+  const T *p = (const T *)((const char *)base + byte_off);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <class T, bool NT>
+__device__ __forceinline__ void st_at(T *__restrict__ base, uint32_t byte_off, T v) {
+  T *p = (T *)((char *)base + byte_off);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Population I of node (x, y) comes from (x - c_Ix, y - c_Iy).
+template <class C, int I, bool NTL>
+__device__ __forceinline__ float pull_f_per(const PlaneGeom &G,
+                                            const typename C::T *__restrict__ s,
+                                            uint32_t bm, uint32_t b0, uint32_t bp,
+                                            uint32_t xm, uint32_t x0, uint32_t xp) {
+  constexpr int CX = cx(I), CY = cy(I);
+  const uint32_t row = CY == 0 ? b0 : (CY > 0 ? bm : bp);
+  const uint32_t col = CX == 0 ? x0 : (CX > 0 ? xm : xp);
+  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(s, I, G.plane), row + col), G.inv_s);
+}
+
+template <class C, int J, int COMP, bool NTL>
+__device__ __forceinline__ float pull_g_per(const PlaneGeom &G,
+                                            const typename C::T *__restrict__ s,
+                                            uint32_t bm, uint32_t b0, uint32_t bp,
+                                            uint32_t xm, uint32_t x0, uint32_t xp) {
+  constexpr int EX = ex(J), EY = ey(J);
+  const uint32_t row = EY == 0 ? b0 : (EY > 0 ? bm : bp);
+  const uint32_t col = EX == 0 ? x0 : (EX > 0 ? xm : xp);
+  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(s, gplane(J, COMP), G.plane), row + col),
+                G.inv_s);
+}
+
+// Pull, collide and store one node of a doubly periodic domain.  src/dst
+// point at plane 0 of the domain's two buffers.
+template <class C, bool FORCED, bool NT, bool NTL>
+__device__ __forceinline__ void update_periodic(const PlaneGeom &G,
+                                                const typename C::T *__restrict__ src,
+                                                typename C::T *__restrict__ dst, int x,
+                                                int y, const CollideParams &P) {
+  using T = typename C::T;
+  constexpr uint32_t E = sizeof(T);
+  const uint32_t pitch = G.nx * E;
+  const uint32_t x0 = x * E;
+  const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
+  const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
+  const uint32_t b0 = y * pitch;
+  const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
+  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
+  float d[kQ], g[2 * kQm];
+  d[0] = pull_f_per<C, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[1] = pull_f_per<C, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[2] = pull_f_per<C, 2, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[3] = pull_f_per<C, 3, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[4] = pull_f_per<C, 4, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[5] = pull_f_per<C, 5, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[6] = pull_f_per<C, 6, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[7] = pull_f_per<C, 7, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  d[8] = pull_f_per<C, 8, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[0] = pull_g_per<C, 0, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[1] = pull_g_per<C, 0, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[2] = pull_g_per<C, 1, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[3] = pull_g_per<C, 1, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[4] = pull_g_per<C, 2, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[5] = pull_g_per<C, 2, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[6] = pull_g_per<C, 3, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[7] = pull_g_per<C, 3, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[8] = pull_g_per<C, 4, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  g[9] = pull_g_per<C, 4, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  collide<FORCED>(d, g, P);
+  const uint32_t o = b0 + x0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) st_at<T, NT>(dst + (int64_t)i * G.plane, o, C::enc(d[i], G.s));
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k)
+    st_at<T, NT>(dst + (int64_t)(kQ + k) * G.plane, o, C::enc(g[k], G.s));
+}
+
+}  // namespace rr

