@@ -13,7 +13,6 @@ object prices the step kernel's algorithmic traffic (19 reads + 19 writes
 per node: 152 B in FP32 storage, 76 B in FP16) per launch against 8 TB/s.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -24,16 +23,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_NODE = {"f32": 152, "f16": 76}
-KERNEL_SOURCES = ["paper_2602_14667_amd/csrc/rr_node.h",
-                  "paper_2602_14667_amd/csrc/rr_kernels.hip"]
-
-
 def kernel_hash():
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2602_14667_amd import kernel_hash as kh
+    return kh()
 
 
 def measured_traffic(storage, n):

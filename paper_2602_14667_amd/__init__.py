@@ -5,3 +5,18 @@ The compute path is the HIP library ``librrmhd.so`` (built from ``csrc/``);
 binding loads the library on first use and raises if it is missing.
 """
 __all__ = ["rrmhd", "inputs"]
+
+# Sources of the step kernel; their hash tags measured traffic figures so a
+# figure taken on another kernel version is not reported.
+KERNEL_SOURCES = ("csrc/rr_node.h", "csrc/rr_pull.h", "csrc/rr_kernels.hip")
+
+
+def kernel_hash() -> str:
+    import hashlib
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(here, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]

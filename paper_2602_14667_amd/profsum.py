@@ -1,0 +1,100 @@
+"""Summarise rocprofv3 CSV output of the step kernel into profiles/.
+
+Usage: python -m paper_2602_14667_amd.profsum PROF_DIR OUT_DIR N
+
+PROF_DIR holds the rocprofv3 output directories written by
+  rocprofv3 --kernel-trace --stats --output-format csv -d PROF_DIR/stats_{f32,f16,copy} -o run -- python3 bench.py ...
+  rocprofv3 --pmc {FETCH_SIZE,WRITE_SIZE} --output-format csv -d PROF_DIR/pmc_<ctr>_{f32,f16,copy} -o run -- python3 bench.py ...
+Counter values (KiB per dispatch) are calibrated against the plain copy
+kernel of known size: factor = true bytes / counted bytes for that kernel.
+"""
+import csv
+import json
+import os
+import sys
+
+from . import kernel_hash
+
+COPY_BYTES = 4 << 30  # bench.py --mode copy default
+
+
+def _rows(path):
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def kernel_stats(d):
+    out = {}
+    for r in _rows(os.path.join(d, "run_kernel_stats.csv")):
+        out[r["Name"]] = dict(calls=int(r["Calls"]), avg_ns=float(r["AverageNs"]),
+                              min_ns=float(r["MinNs"]), max_ns=float(r["MaxNs"]))
+    return out
+
+
+def counter_mean(d, match):
+    vals = [float(r["Counter_Value"]) for r in _rows(os.path.join(d, "run_counter_collection.csv"))
+            if match in r["Kernel_Name"]]
+    return sum(vals) / len(vals) if vals else None
+
+
+def main(prof, out, n):
+    n = int(n)
+    nodes = n * n
+    fac = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        kib = counter_mean(os.path.join(prof, f"pmc_{ctr}_copy"), "k_copy16")
+        fac[ctr] = COPY_BYTES / (kib * 1024.0)
+    copy = kernel_stats(os.path.join(prof, "stats_copy"))
+    copy_ns = [v for k, v in copy.items() if "k_copy16" in k][0]["avg_ns"]
+    for st, bpn in (("f32", 152), ("f16", 76)):
+        stats = kernel_stats(os.path.join(prof, f"stats_{st}"))
+        name = [k for k in stats if "k_step" in k][0]
+        avg = stats[name]["avg_ns"]
+        rd = counter_mean(os.path.join(prof, f"pmc_FETCH_SIZE_{st}"), "k_step") * 1024 * fac["FETCH_SIZE"]
+        wr = counter_mean(os.path.join(prof, f"pmc_WRITE_SIZE_{st}"), "k_step") * 1024 * fac["WRITE_SIZE"]
+        alg = bpn * nodes
+        traffic = {"kernel": name, "kernel_hash": kernel_hash(), "n": n, "storage": st,
+                   "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+                   "algorithmic_bytes": alg, "fetch_factor": fac["FETCH_SIZE"],
+                   "write_factor": fac["WRITE_SIZE"]}
+        with open(os.path.join(out, f"traffic_step_{st}_{n}.json"), "w") as fh:
+            json.dump(traffic, fh, indent=1)
+        lines = [
+            f"# step kernel, {st.upper()} storage, turbulence {n}x{n}",
+            "",
+            f"Kernel: `{name}`  (source hash {kernel_hash()})",
+            "",
+            "Commands (from the repository root, on the GPU box):",
+            "```",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
+            "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/stats_copy -o run -- python3 bench.py --mode copy --steps 20",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/pmc_FETCH_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/pmc_WRITE_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
+            f"python -m paper_2602_14667_amd.profsum gpurun_out/prof profiles {n}",
+            "```",
+            "",
+            "| kernel | calls | avg ns | min ns | max ns |",
+            "|---|---|---|---|---|",
+        ]
+        for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+            lines.append(f"| `{k[:90]}` | {v['calls']} | {v['avg_ns']:.0f} | {v['min_ns']:.0f} | {v['max_ns']:.0f} |")
+        lines += [
+            "",
+            f"* nodes per launch: {nodes}; algorithmic bytes per launch: {alg / 1e9:.3f} GB ({bpn} B/node)",
+            f"* average launch: {avg / 1e3:.1f} us -> {nodes / avg * 1e3:.0f} MLUPS, "
+            f"{alg / avg:.1f} GB/s algorithmic = {alg / avg / 8000 * 100:.1f} % of 8 TB/s",
+            f"* HBM traffic per launch (PMC, calibrated): read {rd / 1e9:.3f} GB "
+            f"({rd / (alg / 2):.3f}x algorithmic), write {wr / 1e9:.3f} GB ({wr / (alg / 2):.3f}x); "
+            f"{(rd + wr) / avg:.1f} GB/s actual",
+            f"* calibration: plain copy of {COPY_BYTES} B reads as FETCH_SIZE x {fac['FETCH_SIZE']:.4f}, "
+            f"WRITE_SIZE x {fac['WRITE_SIZE']:.4f}; copy kernel {2 * COPY_BYTES / copy_ns:.1f} GB/s",
+        ]
+        with open(os.path.join(out, f"step_{st}_{n}.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    print("ok")
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:4])
