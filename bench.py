@@ -81,6 +81,42 @@ def copy_reference(torch, rrmhd, args):
                       "ms_per_copy": ms, "GBs": 2 * nb / ms / 1e6}), flush=True)
 
 
+def launch_sweep(torch, rrmhd, inputs, args):
+    """One JSON line per (plane gap, launch shape, XCD order) of the step
+    kernel on the benchmark workload (both storages)."""
+    import itertools
+    n = args.n
+    u, b = inputs.turbulence(n, 0.04)
+    ud, bd = torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda()
+    del u, b
+    st = torch.cuda.current_stream()
+    shapes = [(256, 1), (128, 2), (64, 4), (128, 1), (64, 1)]
+    for storage in ("f32", "f16"):
+        for gap in (0, 256, 4352, 65792):
+            os.environ["RRMHD_PLANE_PAD_BYTES"] = str(gap)
+            s = rrmhd.Solver(n, n, args.tau, args.tau, storage=storage)
+            s.init(ud, bd)
+            s.step(4)
+            for (bx, by), xcd, nt in itertools.product(shapes, (0, 1, 2), (0, 1)):
+                s.set_launch(bx, by, 1, xcd, nt)
+                s.step(2)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                s.step(args.steps)
+                e1.record(st)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                print(json.dumps({"storage": storage, "plane_gap_bytes": gap,
+                                  "bx": bx, "by": by, "xcd": xcd, "nt": nt,
+                                  "ms": round(ms, 4),
+                                  "GBs": round(BYTES_PER_NODE[storage] * n * n
+                                               / ms / 1e6, 1)}), flush=True)
+            s.close()
+            torch.cuda.empty_cache()
+    os.environ.pop("RRMHD_PLANE_PAD_BYTES", None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,8 +126,9 @@ def main():
     ap.add_argument("--tau", type=float, default=0.51)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["step", "copy"], default="step",
-                    help="copy: time the plain device-copy reference instead")
+    ap.add_argument("--mode", choices=["step", "copy", "sweep"], default="step",
+                    help="copy: time the plain device-copy reference; sweep: "
+                         "time launch shapes, XCD block orders and plane gaps")
     ap.add_argument("--copy-bytes", type=int, default=4 << 30)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -106,6 +143,9 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "copy":
         copy_reference(torch, rrmhd, args)
+        return
+    if args.mode == "sweep":
+        launch_sweep(torch, rrmhd, inputs, args)
         return
     n = args.n
     u, b = inputs.turbulence(n, 0.04)

@@ -74,6 +74,16 @@ def lib():
                                        ctypes.c_double, _dp, ctypes.c_int,
                                        _dp, _dp, _dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_closure_nparams.restype = ctypes.c_int
+        L.orc_set_closure.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_set_closure.restype = ctypes.c_int
+        L.orc_mlp_forward.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_mlp_loss_grad.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_mlp_loss_grad.restype = ctypes.c_double
+        L.orc_adam_step.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int]
         _lib = L
     return _lib
 
@@ -136,6 +146,44 @@ def node_collide(f, g, omega, omega_m, G=(0.0, 0.0), option=FEQ_ALGORITHM):
     d["a3"] = d["a3"].reshape(2, 2, 2)
     d["a4"] = d["a4"].reshape(2, 2, 2, 2)
     return fs, gs, d
+
+
+# ---- learned closure (project addition) -----------------------------------
+NPARAM = 4931   # W1[64][8], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]
+NNORM = 19      # mu[8], sigma[8], sigma_out[3]
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mlp_forward(params, norm, x):
+    """Network output y[n][3] (normalised units) for features x[n][8]."""
+    params, norm, x = _f64(params), _f64(norm), _f64(x)
+    assert params.size == NPARAM and norm.size == NNORM and x.shape[-1] == 8
+    n = x.shape[0]
+    y = np.zeros((n, 3))
+    lib().orc_mlp_forward(_ptr(params), _ptr(norm), _ptr(x), n, _ptr(y))
+    return y
+
+
+def mlp_loss_grad(params, norm, x, t):
+    """(MSE loss, gradient[4931]) for features x[n][8], targets t[n][3]."""
+    params, norm, x, t = _f64(params), _f64(norm), _f64(x), _f64(t)
+    g = np.zeros(NPARAM)
+    loss = lib().orc_mlp_loss_grad(_ptr(params), _ptr(norm), _ptr(x), _ptr(t),
+                                   x.shape[0], _ptr(g))
+    return float(loss), g
+
+
+def adam_step(params, m, v, grad, lr=1e-3, beta1=0.9, beta2=0.999,
+              eps=1e-8, t=1):
+    """In-place Adam update of params, m, v (float64 arrays)."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    grad = _f64(grad)
+    lib().orc_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                        params.size, lr, beta1, beta2, eps, int(t))
 
 
 class Oracle:
@@ -209,6 +257,16 @@ class Oracle:
         g = np.zeros((5, 2, self.ny, self.nx))
         lib().orc_get_state(self._h, _ptr(f), _ptr(g))
         return f, g
+
+    def set_closure(self, params, norm):
+        """Install the learned closure (None removes it)."""
+        if params is None:
+            lib().orc_set_closure(self._h, None, None)
+            return
+        params, norm = _f64(params), _f64(norm)
+        assert params.size == NPARAM and norm.size == NNORM
+        if lib().orc_set_closure(self._h, _ptr(params), _ptr(norm)) != 0:
+            raise MemoryError("oracle closure")
 
     def set_state(self, f, g):
         f = np.ascontiguousarray(f, dtype=np.float64)

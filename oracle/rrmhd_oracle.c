@@ -246,9 +246,28 @@ typedef struct {
 /* One collision at one node: algorithm tasks 1-5.  f[9], g[10] (g[2j+c]) are
  * the pre-collision populations; G is the body force per unit mass (zero in
  * the paper).  Outputs the post-collision populations fs, gs. */
+/* Learned closure (a project addition; the paper has none): an MLP maps the
+ * node's pre-collision (rho, u, b, a_1^(2)) to a correction of a_1^(2) that
+ * is added before the recursion of task 3.  Defined further below. */
+typedef struct closure closure;
+static void closure_apply(const closure *c, double rho, const double u[2],
+                          const double b[2], double a2[2][2]);
+
+static void collide_node_c(const double *f, const double *g, double omega,
+                           double omega_m, const double G[2], int feq_option,
+                           const closure *cl, double *fs, double *gs,
+                           node_aux *ax);
+
 static void collide_node(const double *f, const double *g, double omega,
                          double omega_m, const double G[2], int feq_option,
                          double *fs, double *gs, node_aux *ax) {
+  collide_node_c(f, g, omega, omega_m, G, feq_option, NULL, fs, gs, ax);
+}
+
+static void collide_node_c(const double *f, const double *g, double omega,
+                           double omega_m, const double G[2], int feq_option,
+                           const closure *cl, double *fs, double *gs,
+                           node_aux *ax) {
   node_aux local;
   node_aux *A = ax ? ax : &local;
   /* task 1: macroscopic variables */
@@ -282,6 +301,7 @@ static void collide_node(const double *f, const double *g, double omega,
       for (int c = 0; c < 2; ++c) a2[a][c] += H2T[i][a][c] * fn;
     }
   }
+  if (cl) closure_apply(cl, rho, u, b, a2);
   double a3[2][2][2], a4[2][2][2][2];
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 2; ++c)
@@ -363,6 +383,7 @@ typedef struct orc {
   double G[2];     /* body force per unit mass */
   double bwall[2]; /* wall magnetic field for the anti-bounce-back */
   int feq_option;
+  closure *cl;    /* NULL: plain method */
   long step;
   double *f, *g;       /* f[i][y][x], g[j][c][y][x]: pre-collision state */
   double *fn, *gn;     /* scratch for the next state */
@@ -407,6 +428,7 @@ orc *orc_create(int nx, int ny, double tau_f, double tau_m, int walls,
 
 void orc_destroy(orc *h) {
   if (!h) return;
+  free(h->cl);
   free(h->f);
   free(h->fn);
   free(h->g);
@@ -449,7 +471,8 @@ static void one_step(orc *h) {
       for (int i = 0; i < 9; ++i) f[i] = h->f[FIDX(h, i, y, x)];
       for (int j = 0; j < 5; ++j)
         for (int c = 0; c < 2; ++c) g[2 * j + c] = h->g[GIDX(h, j, c, y, x)];
-      collide_node(f, g, omega, omega_m, h->G, h->feq_option, fs, gs, NULL);
+      collide_node_c(f, g, omega, omega_m, h->G, h->feq_option, h->cl, fs, gs,
+                     NULL);
       for (int i = 0; i < 9; ++i) {
         int ty = y + CI[i][1];
         int tx = wrap(x + CI[i][0], nx);
@@ -681,4 +704,159 @@ int orc_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* ======================================================================== */
+/* Learned closure (project addition): MLP 8 -> 64 -> 64 -> 3 with GELU      */
+/* ======================================================================== */
+/* Parameter vector (4931 values): W1[64][8], b1[64], W2[64][64], b2[64],
+ * W3[3][64], b3[3].  Normalisation (19 values): mu[8], sigma[8],
+ * sigma_out[3].  Features x = (rho, u_x, u_y, b_x, b_y, a_xx, a_xy, a_yy);
+ * x_hat = (x - mu) / sigma; h1 = GELU(W1 x_hat + b1); h2 = GELU(W2 h1 + b2);
+ * y = W3 h2 + b3; correction = sigma_out * y added to (a_xx, a_xy, a_yy). */
+enum { NH = 64, NIN = 8, NOUT = 3 };
+enum {
+  OFF_W1 = 0,
+  OFF_B1 = OFF_W1 + NH * NIN,
+  OFF_W2 = OFF_B1 + NH,
+  OFF_B2 = OFF_W2 + NH * NH,
+  OFF_W3 = OFF_B2 + NH,
+  OFF_B3 = OFF_W3 + NOUT * NH,
+  NPARAM = OFF_B3 + NOUT
+};
+
+struct closure {
+  double p[NPARAM];
+  double norm[2 * NIN + NOUT];
+};
+
+/* GELU in the tanh form of Hendrycks & Gimpel (2016). */
+static double gelu(double z) {
+  const double k = 0.7978845608028654; /* sqrt(2/pi) */
+  return 0.5 * z * (1.0 + tanh(k * (z + 0.044715 * z * z * z)));
+}
+
+static double gelu_grad(double z) {
+  const double k = 0.7978845608028654;
+  const double t = tanh(k * (z + 0.044715 * z * z * z));
+  return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * k * (1.0 + 3.0 * 0.044715 * z * z);
+}
+
+typedef struct {
+  double xh[NIN], z1[NH], h1[NH], z2[NH], h2[NH], y[NOUT];
+} mlp_cache;
+
+static void mlp_forward(const double *p, const double *norm, const double *x,
+                        mlp_cache *c) {
+  for (int k = 0; k < NIN; ++k) c->xh[k] = (x[k] - norm[k]) / norm[NIN + k];
+  for (int i = 0; i < NH; ++i) {
+    double s = p[OFF_B1 + i];
+    for (int k = 0; k < NIN; ++k) s += p[OFF_W1 + i * NIN + k] * c->xh[k];
+    c->z1[i] = s;
+    c->h1[i] = gelu(s);
+  }
+  for (int i = 0; i < NH; ++i) {
+    double s = p[OFF_B2 + i];
+    for (int k = 0; k < NH; ++k) s += p[OFF_W2 + i * NH + k] * c->h1[k];
+    c->z2[i] = s;
+    c->h2[i] = gelu(s);
+  }
+  for (int o = 0; o < NOUT; ++o) {
+    double s = p[OFF_B3 + o];
+    for (int k = 0; k < NH; ++k) s += p[OFF_W3 + o * NH + k] * c->h2[k];
+    c->y[o] = s;
+  }
+}
+
+static void closure_apply(const closure *c, double rho, const double u[2],
+                          const double b[2], double a2[2][2]) {
+  const double x[NIN] = {rho, u[0], u[1], b[0], b[1], a2[0][0], a2[0][1], a2[1][1]};
+  mlp_cache m;
+  mlp_forward(c->p, c->norm, x, &m);
+  const double *so = c->norm + 2 * NIN;
+  a2[0][0] += so[0] * m.y[0];
+  a2[0][1] += so[1] * m.y[1];
+  a2[1][0] += so[1] * m.y[1];
+  a2[1][1] += so[2] * m.y[2];
+}
+
+int orc_closure_nparams(void) { return NPARAM; }
+
+/* Install (params, norm) on a grid solver; params == NULL removes it. */
+int orc_set_closure(orc *h, const double *params, const double *norm) {
+  free(h->cl);
+  h->cl = NULL;
+  if (!params) return 0;
+  h->cl = (closure *)malloc(sizeof(closure));
+  if (!h->cl) return -1;
+  memcpy(h->cl->p, params, sizeof h->cl->p);
+  memcpy(h->cl->norm, norm, sizeof h->cl->norm);
+  return 0;
+}
+
+/* Network output y[n][3] (normalised units) for inputs x[n][8]. */
+void orc_mlp_forward(const double *params, const double *norm, const double *x,
+                     int n, double *y) {
+  for (int s = 0; s < n; ++s) {
+    mlp_cache m;
+    mlp_forward(params, norm, x + (size_t)s * NIN, &m);
+    for (int o = 0; o < NOUT; ++o) y[(size_t)s * NOUT + o] = m.y[o];
+  }
+}
+
+/* Mean squared error L = (1/n) sum_s sum_o (y_o(x_s) - t_so)^2 and its
+ * gradient with respect to every parameter, by reverse-mode
+ * differentiation of the forward pass. */
+double orc_mlp_loss_grad(const double *params, const double *norm,
+                         const double *x, const double *t, int n,
+                         double *grad) {
+  const double *p = params;
+  memset(grad, 0, sizeof(double) * NPARAM);
+  double loss = 0.0;
+  for (int s = 0; s < n; ++s) {
+    mlp_cache m;
+    mlp_forward(p, norm, x + (size_t)s * NIN, &m);
+    double dy[NOUT], dh2[NH], dz2[NH], dh1[NH], dz1[NH];
+    for (int o = 0; o < NOUT; ++o) {
+      const double r = m.y[o] - t[(size_t)s * NOUT + o];
+      loss += r * r;
+      dy[o] = 2.0 * r / n;
+      grad[OFF_B3 + o] += dy[o];
+      for (int k = 0; k < NH; ++k) grad[OFF_W3 + o * NH + k] += dy[o] * m.h2[k];
+    }
+    for (int k = 0; k < NH; ++k) {
+      double sacc = 0.0;
+      for (int o = 0; o < NOUT; ++o) sacc += p[OFF_W3 + o * NH + k] * dy[o];
+      dh2[k] = sacc;
+      dz2[k] = sacc * gelu_grad(m.z2[k]);
+      grad[OFF_B2 + k] += dz2[k];
+    }
+    for (int i = 0; i < NH; ++i)
+      for (int k = 0; k < NH; ++k) grad[OFF_W2 + i * NH + k] += dz2[i] * m.h1[k];
+    for (int k = 0; k < NH; ++k) {
+      double sacc = 0.0;
+      for (int i = 0; i < NH; ++i) sacc += p[OFF_W2 + i * NH + k] * dz2[i];
+      dh1[k] = sacc;
+      dz1[k] = sacc * gelu_grad(m.z1[k]);
+      grad[OFF_B1 + k] += dz1[k];
+    }
+    for (int i = 0; i < NH; ++i)
+      for (int k = 0; k < NIN; ++k) grad[OFF_W1 + i * NIN + k] += dz1[i] * m.xh[k];
+    (void)dh2;
+    (void)dh1;
+  }
+  return loss / n;
+}
+
+/* One Adam step (Kingma & Ba 2015) at step number t >= 1. */
+void orc_adam_step(double *params, double *m, double *v, const double *grad,
+                   int n, double lr, double beta1, double beta2, double eps,
+                   int t) {
+  const double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+  for (int k = 0; k < n; ++k) {
+    m[k] = beta1 * m[k] + (1.0 - beta1) * grad[k];
+    v[k] = beta2 * v[k] + (1.0 - beta2) * grad[k] * grad[k];
+    const double mh = m[k] / c1, vh = v[k] / c2;
+    params[k] -= lr * mh / (sqrt(vh) + eps);
+  }
 }

@@ -1,0 +1,150 @@
+// rr_mlp.h -- the per-node closure network on matrix cores.
+//
+// Network (a project addition; the paper has no closure): features
+// x = (rho, u_x, u_y, b_x, b_y, a_xx, a_xy, a_yy) of a node, x_hat =
+// (x - mu) / sigma, h1 = GELU(W1 x_hat + b1) (64), h2 = GELU(W2 h1 + b2) (64),
+// y = W3 h2 + b3 (3); the correction sigma_out * y is added to the second-order
+// non-equilibrium coefficients before the recursion of algorithm task 3.
+// GELU is the tanh form (Hendrycks & Gimpel 2016).
+//
+// One wavefront evaluates 64 nodes (one per lane).  Layers 1 and 2 run as
+// BF16 MFMA 32x32x8 with FP32 accumulation, written transposed
+// (Z^T = W X^T): the accumulator layout of layer 1 (lane = node column,
+// registers = hidden rows) is exactly the B-operand layout layer 2 needs, so
+// activations never leave registers.  Layer 3 (3 outputs) is 32 FMAs per
+// lane plus one cross-half exchange.  x_hat, weights and h1/h2 are BF16
+// (round to nearest even); biases, GELU and accumulation are FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rr {
+
+constexpr int kNH = 64, kNIN = 8, kNOUT = 3;
+// Flat FP32 parameter vector: W1[64][8], b1[64], W2[64][64], b2[64],
+// W3[3][64], b3[3]; normalisation vector: mu[8], sigma[8], sigma_out[3].
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kNH * kNIN, kOffW2 = kOffB1 + kNH,
+              kOffB2 = kOffW2 + kNH * kNH, kOffW3 = kOffB2 + kNH,
+              kOffB3 = kOffW3 + kNOUT * kNH, kNParam = kOffB3 + kNOUT;
+constexpr int kNNorm = 2 * kNIN + kNOUT;
+
+// Prepared parameters (global memory and the LDS copy share this layout).
+struct MlpDev {
+  uint16_t w1[kNH * kNIN];  // BF16 bits
+  uint16_t w2[kNH * kNH];   // BF16 bits
+  float b1[kNH], b2[kNH];
+  float w3[kNOUT * kNH];  // BF16-rounded values
+  float b3[kNOUT];
+  float mu[kNIN], inv_sigma[kNIN], sigma_out[kNOUT];
+  int zero;  // 1: all weights and biases zero (correction is exactly 0)
+};
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__host__ __device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ __forceinline__ float bf2f(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+__device__ __forceinline__ float gelu_f(float z) {
+  const float k = 0.7978845608028654f;  // sqrt(2/pi)
+  const float z3 = z * z * z;
+  return 0.5f * z * (1.0f + tanhf(k * fmaf(0.044715f, z3, z)));
+}
+
+__device__ __forceinline__ shortx4 ld4(const uint16_t *p) {
+  shortx4 v;
+  __builtin_memcpy(&v, p, 8);
+  return v;
+}
+
+// Evaluate the network for the 64 nodes of the calling wavefront.  All 64
+// lanes must call it together.  xh: this lane's normalised features;
+// W: parameters (LDS); xs: 64 x 8 BF16 scratch of this wave (LDS).
+// Returns y[3] (normalised output) of this lane's node.
+__device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
+                                         uint16_t *__restrict__ xs,
+                                         const float (&xh)[kNIN], float (&y)[kNOUT]) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5, col = lane & 31;
+  // stage this node's features as row `lane` of X (64 x 8)
+#pragma unroll
+  for (int k = 0; k < kNIN; ++k) xs[lane * kNIN + k] = f2bf(xh[k]);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  float part[2][kNOUT];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    // layer 1, transposed: Z1^T (64 hidden x 32 nodes) = W1 (64 x 8) X^T
+    const shortx4 bx = ld4(xs + (32 * nb + col) * kNIN + 4 * half);
+    shortx4 b2op[8];  // layer-2 B operands: h1 rows 8 kk + 4 half + q
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const shortx4 aw = ld4(W->w1 + (32 * mb + col) * kNIN + 4 * half);
+      floatx16 acc = {0};
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, bx, acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        shortx4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int h = 32 * mb + 8 * r + 4 * half + q;
+          v[q] = (short)f2bf(gelu_f(acc[4 * r + q] + W->b1[h]));
+        }
+        b2op[4 * mb + r] = v;
+      }
+    }
+    // layer 2, transposed: Z2^T (64 x 32 nodes) = W2 (64 x 64) H1^T
+    float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f;
+#pragma unroll
+    for (int mb2 = 0; mb2 < 2; ++mb2) {
+      floatx16 acc = {0};
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const shortx4 aw = ld4(W->w2 + (32 * mb2 + col) * kNH + 8 * kk + 4 * half);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, b2op[kk], acc, 0, 0, 0);
+      }
+      // layer 3 partial sums over this lane's 16 rows of h2
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int h = 32 * mb2 + 8 * (i >> 2) + 4 * half + (i & 3);
+        const float h2 = bf2f(f2bf(gelu_f(acc[i] + W->b2[h])));
+        p0 = fmaf(W->w3[0 * kNH + h], h2, p0);
+        p1 = fmaf(W->w3[1 * kNH + h], h2, p1);
+        p2 = fmaf(W->w3[2 * kNH + h], h2, p2);
+      }
+    }
+    // the other half of the wave holds the other 32 rows of the same nodes
+    part[nb][0] = p0 + __shfl_xor(p0, 32, 64);
+    part[nb][1] = p1 + __shfl_xor(p1, 32, 64);
+    part[nb][2] = p2 + __shfl_xor(p2, 32, 64);
+  }
+  // lane l's node is node 32 * (l / 32) + l % 32 = l
+#pragma unroll
+  for (int o = 0; o < kNOUT; ++o) y[o] = (half ? part[1][o] : part[0][o]) + W->b3[o];
+}
+
+// Copy the prepared parameters into LDS (all threads of the block).
+__device__ __forceinline__ void mlp_to_lds(const MlpDev *__restrict__ g, MlpDev *s) {
+  const uint32_t *src = (const uint32_t *)g;
+  uint32_t *dst = (uint32_t *)s;
+  constexpr int n = sizeof(MlpDev) / 4;
+  for (int k = threadIdx.x + threadIdx.y * blockDim.x; k < n; k += blockDim.x * blockDim.y)
+    dst[k] = src[k];
+  __syncthreads();
+}
+
+}  // namespace rr

@@ -1,0 +1,147 @@
+"""Pins of the oracle's learned-closure pieces (CPU): GELU in its tanh form,
+reverse-mode gradients against central finite differences, the first Adam
+step's closed form, and that a zero network leaves the method unchanged."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_14667_amd import inputs
+
+RNG = np.random.default_rng(7)
+
+
+def random_params(scale=0.3):
+    return scale * RNG.standard_normal(oracle.NPARAM)
+
+
+def random_norm():
+    mu = 0.01 * RNG.standard_normal(8)
+    sig = 0.5 + RNG.random(8)
+    so = 0.1 + RNG.random(3)
+    return np.concatenate([mu, sig, so])
+
+
+def gelu_erf(z):
+    return 0.5 * z * (1 + math.erf(z / math.sqrt(2)))
+
+
+def one_unit_net(w, b):
+    """A network whose output is y0 = GELU(w * xhat_0 + b) exactly."""
+    p = np.zeros(oracle.NPARAM)
+    p[0] = w            # W1[0][0]
+    p[512] = b          # b1[0]
+    p[512 + 64 + 0] = 1.0   # W2[0][0]: z2_0 = h1_0
+    # y0 = W3[0][0] * GELU(z2_0)
+    p[512 + 64 + 4096 + 64 + 0] = 1.0
+    return p
+
+
+def test_gelu_tanh_form_values():
+    """GELU(z) = z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))): compare a
+    one-unit network with the formula evaluated here, and with the erf form
+    within the known approximation error (< 1e-3)."""
+    norm = np.concatenate([np.zeros(8), np.ones(8), np.ones(3)])
+    for z in (-3.0, -1.0, -0.2, 0.0, 0.5, 1.0, 2.5):
+        # feed z through the first layer (w = 1, b = 0) and a second GELU:
+        p = one_unit_net(1.0, 0.0)
+        x = np.zeros((1, 8)); x[0, 0] = z
+        y = oracle.mlp_forward(p, norm, x)[0, 0]
+        g1 = 0.5 * z * (1 + math.tanh(math.sqrt(2 / math.pi) * (z + 0.044715 * z ** 3)))
+        g2 = 0.5 * g1 * (1 + math.tanh(math.sqrt(2 / math.pi) * (g1 + 0.044715 * g1 ** 3)))
+        assert abs(y - g2) < 1e-15
+        assert abs(g1 - gelu_erf(z)) < 1e-3
+
+
+def test_gradient_against_central_differences():
+    p = random_params()
+    norm = random_norm()
+    x = 0.05 * RNG.standard_normal((6, 8)); x[:, 0] += 1.0
+    t = RNG.standard_normal((6, 3))
+    loss, g = oracle.mlp_loss_grad(p, norm, x, t)
+    idx = np.concatenate([np.arange(0, 8), [512, 513], 576 + np.arange(5),
+                          4672 + np.arange(3), 4736 + np.arange(3),
+                          RNG.integers(0, oracle.NPARAM, 30)])
+    h = 1e-6
+    for k in idx:
+        pp = p.copy(); pp[k] += h
+        pm = p.copy(); pm[k] -= h
+        fd = (oracle.mlp_loss_grad(pp, norm, x, t)[0]
+              - oracle.mlp_loss_grad(pm, norm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
+def test_loss_is_mean_squared_error():
+    p = random_params()
+    norm = random_norm()
+    x = RNG.standard_normal((5, 8))
+    t = RNG.standard_normal((5, 3))
+    y = oracle.mlp_forward(p, norm, x)
+    loss, _ = oracle.mlp_loss_grad(p, norm, x, t)
+    assert abs(loss - np.sum((y - t) ** 2) / 5) < 1e-12
+
+
+def test_adam_first_step_closed_form():
+    """At t = 1, m_hat = g and v_hat = g^2, so the step is -lr g/(|g| + eps)."""
+    n = 50
+    p0 = RNG.standard_normal(n)
+    g = RNG.standard_normal(n)
+    p = p0.copy(); m = np.zeros(n); v = np.zeros(n)
+    oracle.adam_step(p, m, v, g, lr=1e-3, t=1)
+    assert np.allclose(p, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_bias_correction():
+    """With a constant gradient the bias-corrected moments stay g and g^2:
+    every step moves by lr g / (|g| + eps)."""
+    n = 4
+    g = np.array([0.5, -2.0, 1e-3, 3.0])
+    p = np.zeros(n); m = np.zeros(n); v = np.zeros(n)
+    for t in range(1, 6):
+        oracle.adam_step(p, m, v, g, lr=0.01, t=t)
+    assert np.allclose(p, -5 * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_zero_network_is_the_plain_method():
+    n = 12
+    u, b = inputs.turbulence(n, 0.05)
+    a = oracle.Oracle(n, n, 0.52, 0.57); a.init(u, b); a.step(8)
+    c = oracle.Oracle(n, n, 0.52, 0.57); c.init(u, b)
+    c.set_closure(np.zeros(oracle.NPARAM), random_norm())
+    c.step(8)
+    fa, ga = a.get_state(); fc, gc = c.get_state()
+    assert np.array_equal(fa, fc) and np.array_equal(ga, gc)
+
+
+def test_closure_shifts_a2_by_the_network_output():
+    """A network with only output biases adds sigma_out * b3 to a_1^(2):
+    post-collision second moments move by (1 - omega) sigma_out b3."""
+    p = np.zeros(oracle.NPARAM)
+    b3 = np.array([0.3, -0.2, 0.5])
+    p[-3:] = b3
+    norm = np.concatenate([np.zeros(8), np.ones(8), [1e-4, 2e-4, 3e-4]])
+    delta = norm[-3:] * b3
+    n = 4
+    u, b = inputs.random_modes(n, n, 0.05, seed=3)
+    a = oracle.Oracle(n, n, 0.55, 0.6); a.init(u, b)
+    c = oracle.Oracle(n, n, 0.55, 0.6); c.init(u, b); c.set_closure(p, norm)
+    fa, _ = a.get_state()
+    om = 1 / 0.55
+    CX = np.array([0, -1, -1, -1, 0, 1, 1, 1, 0])
+    CY = np.array([0, 1, 0, -1, -1, -1, 0, 1, 1])
+    for y in range(n):
+        for x in range(n):
+            f = fa[:, y, x]
+            g = np.zeros(10)
+            fs0, _, _ = oracle.node_collide(f, g, om, 1 / 0.6)
+            # closure via a 1x1 grid with the same node
+            o = oracle.Oracle(1, 1, 0.55, 0.6); o.set_closure(p, norm)
+            o.set_state(f.reshape(9, 1, 1), g.reshape(5, 2, 1, 1)); o.step(1)
+            fs1 = o.get_state()[0][:, 0, 0]
+            d = fs1 - fs0
+            assert abs(d.sum()) < 1e-15
+            assert abs((d * CX * CX).sum() - (1 - om) * delta[0]) < 1e-15
+            assert abs((d * CX * CY).sum() - (1 - om) * delta[1]) < 1e-15
+            assert abs((d * CY * CY).sum() - (1 - om) * delta[2]) < 1e-15
