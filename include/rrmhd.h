@@ -171,6 +171,31 @@ int rrmhd_batch_info(const rrmhd_batch *b, int64_t *nodes, int64_t *steps,
 int rrmhd_batch_destroy(rrmhd_batch *b);
 const char *rrmhd_batch_last_error_detail(void);
 
+/* ---- Learned closure (a project addition; the paper has none) -------------
+ * A per-node MLP maps the node's pre-collision features x = (rho, u_x, u_y,
+ * b_x, b_y, a_xx, a_xy, a_yy) -- a_1^(2) from the projection of algorithm
+ * task 3 -- to a correction of a_1^(2) applied before the recursion:
+ *   x_hat = (x - mu) / sigma,  h1 = GELU(W1 x_hat + b1)  (64 units),
+ *   h2 = GELU(W2 h1 + b2)  (64),  y = W3 h2 + b3  (3),
+ *   (a_xx, a_xy, a_yy) += sigma_out * y,
+ * GELU(z) = z/2 (1 + tanh(sqrt(2/pi)(z + 0.044715 z^3))).  On the GPU the
+ * layers run as BF16 MFMA (x_hat, weights, h1, h2 rounded to BF16, FP32
+ * accumulation, FP32 biases and GELU) fused into the step kernel.
+ * params: 4931 FP32 = W1[64][8], b1[64], W2[64][64], b2[64], W3[3][64],
+ * b3[3]; norm: 19 FP32 = mu[8], sigma[8], sigma_out[3]; both DEVICE
+ * pointers, read at the call (stream-ordered).  Zero weights and biases give
+ * a correction of exactly zero. */
+/* Install parameters on a handle (params == NULL disables the closure). */
+int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm);
+/* Turn the installed closure on or off for subsequent rrmhd_step calls
+ * (periodic, unforced grids only; EINVAL otherwise or if none is set). */
+int rrmhd_closure_enable(rrmhd *h, int on);
+/* Network outputs y[n][3] (before the sigma_out scaling) for raw features
+ * x[n][8], all device FP32, with the same BF16 MFMA arithmetic as the fused
+ * step.  Synchronises hip_stream. */
+int rrmhd_closure_eval(const float *params, const float *norm, const float *x,
+                       int64_t n, float *y, void *hip_stream);
+
 /* ---- Autotuner -----------------------------------------------------------
  * Times candidate launch shapes of the step kernel on the handle's own grid
  * (trials steps each, best of three repetitions, HIP events) and installs

@@ -9,6 +9,7 @@
 #include <new>
 
 #include "../../include/rrmhd.h"
+#include "rr_closure.h"
 #include "rr_internal.h"
 #include "rr_kernels.h"
 
@@ -46,6 +47,9 @@ struct rrmhd {
   void *diag_work = nullptr;
   double *diag_out = nullptr;   // device, 8 doubles
   double *diag_host = nullptr;  // pinned, 8 doubles
+  void *mlp = nullptr;          // prepared closure parameters (device)
+  bool closure_on = false;
+  int closure_grid = 0;         // persistent blocks of the closure kernel
 };
 
 extern "C" {
@@ -76,6 +80,7 @@ int rrmhd_destroy(rrmhd *h) {
   if (h->diag_work) (void)hipFree(h->diag_work);
   if (h->diag_out) (void)hipFree(h->diag_out);
   if (h->diag_host) (void)hipHostFree(h->diag_host);
+  if (h->mlp) (void)hipFree(h->mlp);
   delete h;
   return rc;
 }
@@ -191,8 +196,14 @@ int rrmhd_step(rrmhd *h, int64_t n) {
   if (!h || n < 0) return RRMHD_EINVAL;
   if (!h->ready) return RRMHD_ESTATE;
   for (int64_t k = 0; k < n; ++k) {
-    HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur],
-                                  h->buf[h->cur ^ 1], h->shape, h->stream));
+    if (h->closure_on) {
+      HIP_OR_RETURN(rr::launch_step_closure(h->storage, h->D, (const rr::MlpDev *)h->mlp,
+                                            h->buf[h->cur], h->buf[h->cur ^ 1],
+                                            h->closure_grid, h->stream));
+    } else {
+      HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur], h->buf[h->cur ^ 1],
+                                    h->shape, h->stream));
+    }
     h->cur ^= 1;
     h->steps++;
   }
@@ -289,6 +300,46 @@ int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage, hipStream_t *
 
 void rr_handle_set_ready(rrmhd *h, int ready) {
   if (h) h->ready = ready != 0;
+}
+
+int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm) {
+  if (!h) return RRMHD_EINVAL;
+  if (!params) {
+    h->closure_on = false;
+    return RRMHD_OK;
+  }
+  if (!norm) return RRMHD_EINVAL;
+  if (!h->mlp) HIP_OR_RETURN(hipMalloc(&h->mlp, rr::mlp_dev_bytes()));
+  HIP_OR_RETURN(rr::launch_mlp_prepare(params, norm, (rr::MlpDev *)h->mlp, h->stream));
+  if (!h->closure_grid) {
+    int dev = 0, cus = 256;
+    HIP_OR_RETURN(hipGetDevice(&dev));
+    HIP_OR_RETURN(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    h->closure_grid = cus * 4;
+  }
+  return RRMHD_OK;
+}
+
+int rrmhd_closure_enable(rrmhd *h, int on) {
+  if (!h) return RRMHD_EINVAL;
+  if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f)) return RRMHD_EINVAL;
+  h->closure_on = on != 0;
+  return RRMHD_OK;
+}
+
+int rrmhd_closure_eval(const float *params, const float *norm, const float *x, int64_t n,
+                       float *y, void *hip_stream) {
+  if (!params || !norm || n < 0 || (n > 0 && (!x || !y))) return RRMHD_EINVAL;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  void *mlp = nullptr;
+  HIP_OR_RETURN(hipMalloc(&mlp, rr::mlp_dev_bytes()));
+  hipError_t e = rr::launch_mlp_prepare(params, norm, (rr::MlpDev *)mlp, st);
+  if (e == hipSuccess) e = rr::launch_mlp_eval((const rr::MlpDev *)mlp, x, y, n, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFree(mlp);
+  if (e != hipSuccess) return dev_err(e, "closure eval");
+  if (e2 != hipSuccess) return dev_err(e2, "hipStreamSynchronize");
+  return RRMHD_OK;
 }
 
 }  // extern "C"

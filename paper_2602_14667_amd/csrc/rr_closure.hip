@@ -1,0 +1,178 @@
+// rr_closure.hip -- the learned closure on the GPU: parameter preparation,
+// standalone BF16-MFMA inference, and the fused step with the network
+// correcting a_1^(2) inside the collision (periodic domains).
+#include <hip/hip_runtime.h>
+
+#include "rr_closure.h"
+#include "rr_mlp.h"
+#include "rr_node.h"
+#include "rr_pull.h"
+
+namespace rr {
+
+// Convert the FP32 parameter and normalisation vectors into the kernel
+// layout (BF16 weights, FP32 biases, reciprocal sigmas).
+__global__ void k_mlp_prepare(const float *__restrict__ p, const float *__restrict__ norm,
+                              MlpDev *__restrict__ out) {
+  const int t = threadIdx.x;
+  for (int k = t; k < kNH * kNIN; k += blockDim.x) out->w1[k] = f2bf(p[kOffW1 + k]);
+  for (int k = t; k < kNH * kNH; k += blockDim.x) out->w2[k] = f2bf(p[kOffW2 + k]);
+  for (int k = t; k < kNH; k += blockDim.x) {
+    out->b1[k] = p[kOffB1 + k];
+    out->b2[k] = p[kOffB2 + k];
+  }
+  for (int k = t; k < kNOUT * kNH; k += blockDim.x) out->w3[k] = bf2f(f2bf(p[kOffW3 + k]));
+  if (t < kNOUT) {
+    out->b3[t] = p[kOffB3 + t];
+    out->sigma_out[t] = norm[2 * kNIN + t];
+  }
+  if (t < kNIN) {
+    out->mu[t] = norm[t];
+    out->inv_sigma[t] = 1.0f / norm[kNIN + t];
+  }
+  if (t == 0) out->zero = 0;
+}
+
+struct ClosureHook {
+  const MlpDev *W;
+  uint16_t *xs;
+  __device__ __forceinline__ void operator()(float rho, float ux, float uy, float bx, float by,
+                                             float &axx, float &axy, float &ayy) const {
+    const float x[kNIN] = {rho, ux, uy, bx, by, axx, axy, ayy};
+    float xh[kNIN], y[kNOUT];
+#pragma unroll
+    for (int k = 0; k < kNIN; ++k) xh[k] = (x[k] - W->mu[k]) * W->inv_sigma[k];
+    mlp_wave(W, xs, xh, y);
+    axx = fmaf(W->sigma_out[0], y[0], axx);
+    axy = fmaf(W->sigma_out[1], y[1], axy);
+    ayy = fmaf(W->sigma_out[2], y[2], ayy);
+  }
+};
+
+// Standalone inference: y[n][3] (normalised outputs) for raw features
+// x[n][8].  One wave per 64 samples; lanes past n evaluate a copy of
+// sample 0 and discard it.
+__global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev *__restrict__ g,
+                                                  const float *__restrict__ x,
+                                                  float *__restrict__ y, int64_t n) {
+  __shared__ MlpDev W;
+  __shared__ uint16_t xs[4][64 * kNIN];
+  mlp_to_lds(g, &W);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nw = (n + 63) / 64;
+  for (int64_t w = (int64_t)blockIdx.x * 4 + wave; w < nw; w += (int64_t)gridDim.x * 4) {
+    const int64_t s = w * 64 + lane;
+    const int64_t sc = s < n ? s : 0;
+    float xh[kNIN], out[kNOUT];
+#pragma unroll
+    for (int k = 0; k < kNIN; ++k) xh[k] = (x[sc * kNIN + k] - W.mu[k]) * W.inv_sigma[k];
+    mlp_wave(&W, xs[wave], xh, out);
+    if (s < n) {
+#pragma unroll
+      for (int o = 0; o < kNOUT; ++o) y[s * kNOUT + o] = out[o];
+    }
+  }
+}
+
+// Fused step with the closure, periodic domain.  A tile is 64 x 4 nodes:
+// wave w of the block takes row 4 ty + w, lanes take 64 consecutive x.  The
+// grid is persistent so the parameters are staged into LDS once per block.
+template <class C, bool NT>
+__global__ __launch_bounds__(256) void k_step_closure(PlaneGeom G, CollideParams P,
+                                                      const MlpDev *__restrict__ g,
+                                                      int tiles_x, int ntiles,
+                                                      const typename C::T *__restrict__ src,
+                                                      typename C::T *__restrict__ dst) {
+  using T = typename C::T;
+  __shared__ MlpDev W;
+  __shared__ uint16_t xs[4][64 * kNIN];
+  mlp_to_lds(g, &W);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const ClosureHook hook{&W, xs[wave]};
+  constexpr uint32_t E = sizeof(T);
+  const uint32_t pitch = G.nx * E;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int y = ty * 4 + wave;
+    if (y >= G.ny) continue;  // whole wave idle (wave-uniform)
+    const int xr = tx * 64 + lane;
+    const bool active = xr < G.nx;
+    const int x = active ? xr : G.nx - 1;  // idle lanes still join the MLP
+    const uint32_t x0 = x * E;
+    const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
+    const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
+    const uint32_t b0 = y * pitch;
+    const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
+    const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
+    float d[kQ], gg[2 * kQm];
+    d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    gg[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    collide<false>(d, gg, P, hook);
+    if (active) {
+      const uint32_t o = b0 + x0;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) st_at<T, NT>(dst + (int64_t)i * G.plane, o, C::enc(d[i], G.s));
+#pragma unroll
+      for (int k = 0; k < 2 * kQm; ++k)
+        st_at<T, NT>(dst + (int64_t)(kQ + k) * G.plane, o, C::enc(gg[k], G.s));
+    }
+  }
+}
+
+size_t mlp_dev_bytes() { return sizeof(MlpDev); }
+
+hipError_t launch_mlp_prepare(const float *params, const float *norm, MlpDev *out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_prepare, dim3(1), dim3(256), 0, st, params, norm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_eval(const MlpDev *mlp, const float *x, float *y, int64_t n,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t waves = (n + 63) / 64, blocks = (waves + 3) / 4;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_mlp_eval, dim3((unsigned)blocks), dim3(256), 0, st, mlp, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_closure(int storage, const Domain &D, const MlpDev *mlp,
+                               const void *src, void *dst, int grid_blocks, hipStream_t st) {
+  const int tiles_x = (D.nx + 63) / 64, tiles_y = (D.ny + 3) / 4;
+  const int ntiles = tiles_x * tiles_y;
+  int grid = grid_blocks < ntiles ? grid_blocks : ntiles;
+  if (grid < 1) grid = 1;
+  CollideParams P;
+  P.om_c = D.om_c;
+  P.omm_c = D.omm_c;
+  P.Gx = 0.0f;
+  P.Gy = 0.0f;
+  P.src_c = 0.0f;
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+  if (storage == kF16)
+    hipLaunchKernelGGL((k_step_closure<CodecF16, true>), dim3(grid), dim3(256), 0, st, G, P, mlp,
+                       tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
+  else
+    hipLaunchKernelGGL((k_step_closure<CodecF32, true>), dim3(grid), dim3(256), 0, st, G, P, mlp,
+                       tiles_x, ntiles, (const float *)src, (float *)dst);
+  return hipGetLastError();
+}
+
+}  // namespace rr

@@ -85,8 +85,8 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  float part[2][kNOUT];
-#pragma unroll
+  float own[kNOUT] = {0.0f, 0.0f, 0.0f};
+#pragma unroll 1
   for (int nb = 0; nb < 2; ++nb) {
     // layer 1, transposed: Z1^T (64 hidden x 32 nodes) = W1 (64 x 8) X^T
     const shortx4 bx = ld4(xs + (32 * nb + col) * kNIN + 4 * half);
@@ -128,13 +128,18 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
       }
     }
     // the other half of the wave holds the other 32 rows of the same nodes
-    part[nb][0] = p0 + __shfl_xor(p0, 32, 64);
-    part[nb][1] = p1 + __shfl_xor(p1, 32, 64);
-    part[nb][2] = p2 + __shfl_xor(p2, 32, 64);
+    const float s0 = p0 + __shfl_xor(p0, 32, 64);
+    const float s1 = p1 + __shfl_xor(p1, 32, 64);
+    const float s2 = p2 + __shfl_xor(p2, 32, 64);
+    // lane l's node is node 32 * (l / 32) + l % 32 = l: keep block nb = l / 32
+    if (nb == half) {
+      own[0] = s0;
+      own[1] = s1;
+      own[2] = s2;
+    }
   }
-  // lane l's node is node 32 * (l / 32) + l % 32 = l
 #pragma unroll
-  for (int o = 0; o < kNOUT; ++o) y[o] = (half ? part[1][o] : part[0][o]) + W->b3[o];
+  for (int o = 0; o < kNOUT; ++o) y[o] = own[o] + W->b3[o];
 }
 
 // Copy the prepared parameters into LDS (all threads of the block).

@@ -172,11 +172,20 @@ __device__ __forceinline__ float post_f(const EqTerms &E, const Acoef &A,
   return qdiv(v, wdiv(I), 1.0f / wdiv(I));
 }
 
+// Hook applied to the second-order non-equilibrium coefficients between
+// their projection and the recursion (task 3).  The plain method uses none.
+struct NoCorrection {
+  __device__ __forceinline__ void operator()(float, float, float, float, float, float &,
+                                             float &, float &) const {}
+};
+
 // One collision (algorithm tasks 1-5) in place.  d[i] = f_i - w_i on entry,
-// f*_i - w_i on exit; g[2j + c] = g_j,c before and after.
-template <bool FORCED>
+// f*_i - w_i on exit; g[2j + c] = g_j,c before and after.  corr(rho, u_x,
+// u_y, b_x, b_y, a_xx, a_xy, a_yy) may adjust the three a_1^(2) components.
+template <bool FORCED, class Corr = NoCorrection>
 __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
-                                        const CollideParams &P) {
+                                        const CollideParams &P,
+                                        const Corr &corr = Corr()) {
   // task 1: macroscopic variables
   const float dr = ((d[0] + d[2]) + (d[4] + d[6])) +
                    (((d[1] + d[3]) + (d[5] + d[7])) + d[8]);
@@ -207,6 +216,7 @@ __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
   float axx = fmaf(-rux, ux, pxx - dr3) - mxx;
   float ayy = fmaf(-ruy, uy, pyy - dr3) + mxx;
   float axy = fmaf(-rux, uy, pxy) + bxy;
+  corr(rho, ux, uy, bx, by, axx, axy, ayy);
   // recursion for the third and fourth orders (D2Q9-supported components)
   const float axxy = fmaf(2.0f * ux, axy, uy * axx);
   const float axyy = fmaf(2.0f * uy, axy, ux * ayy);

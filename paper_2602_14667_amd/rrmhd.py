@@ -28,6 +28,7 @@ EXPORTED = [
     "rrmhd_batch_moments", "rrmhd_batch_diagnostics", "rrmhd_batch_info",
     "rrmhd_batch_destroy", "rrmhd_batch_last_error_detail",
     "rrmhd_autotune", "rrmhd_batch_autotune",
+    "rrmhd_closure_set", "rrmhd_closure_enable", "rrmhd_closure_eval",
 ]
 
 
@@ -102,6 +103,9 @@ def lib():
         ip = ctypes.POINTER(ci)
         L.rrmhd_autotune.argtypes = [vp, ctypes.c_char_p, ci, ip, ip, ip, dbl]
         L.rrmhd_batch_autotune.argtypes = [vp, ctypes.c_char_p, ci]
+        L.rrmhd_closure_set.argtypes = [vp, vp, vp]
+        L.rrmhd_closure_enable.argtypes = [vp, ci]
+        L.rrmhd_closure_eval.argtypes = [vp, vp, vp, i64, vp, vp]
         L.rrmhd_strerror.argtypes = [ctypes.c_int]
         L.rrmhd_strerror.restype = ctypes.c_char_p
         L.rrmhd_last_error_detail.argtypes = []
@@ -136,6 +140,29 @@ def _dev_f64(t, shape, name):
         raise ValueError(f"{name} must be a contiguous float64 device tensor "
                          f"of shape {shape}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, shape, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor "
+                         f"of shape {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def closure_eval(params, norm, x, stream=None):
+    """Network outputs y[n][3] for features x[n][8] (FP32 device tensors),
+    BF16 MFMA arithmetic as in the fused step."""
+    import torch
+    n = x.shape[0]
+    y = torch.empty((n, 3), dtype=torch.float32, device=x.device)
+    _check(lib().rrmhd_closure_eval(_dev_f32(params, (4931,), "params"),
+                                    _dev_f32(norm, (19,), "norm"),
+                                    _dev_f32(x, (n, 8), "x"), int(n),
+                                    _dev_f32(y, (n, 3), "y"),
+                                    _stream_handle(stream)), "rrmhd_closure_eval")
+    return y
 
 
 class Solver:
@@ -258,6 +285,20 @@ class Solver:
             ctypes.byref(bx), ctypes.byref(by), ctypes.byref(xcd),
             ctypes.byref(ms)), "rrmhd_autotune")
         return dict(bx=bx.value, by=by.value, xcd=xcd.value, ms=ms.value)
+
+    def closure_set(self, params, norm):
+        """Install closure parameters (FP32 device tensors of 4931 and 19
+        values); params=None disables the closure."""
+        if params is None:
+            _check(lib().rrmhd_closure_set(self._h, None, None), "rrmhd_closure_set")
+            return
+        _check(lib().rrmhd_closure_set(self._h, _dev_f32(params, (4931,), "params"),
+                                       _dev_f32(norm, (19,), "norm")),
+               "rrmhd_closure_set")
+
+    def closure_enable(self, on=True):
+        _check(lib().rrmhd_closure_enable(self._h, int(bool(on))),
+               "rrmhd_closure_enable")
 
     def set_stream(self, stream):
         self._stream = stream

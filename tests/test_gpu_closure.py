@@ -1,0 +1,121 @@
+"""GPU tests of the learned closure's inference: BF16-MFMA network against
+the FP64 oracle network, zero network = plain step (bitwise), and the fused
+step with a non-trivial network against the oracle with the same network."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_14667_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def R():
+    from paper_2602_14667_amd import rrmhd
+    rrmhd.lib()
+    return rrmhd
+
+
+def init_params(rng, gain=1.0):
+    """He-style random parameters (fan-in scaled), float64."""
+    p = np.zeros(oracle.NPARAM)
+    p[0:512] = rng.standard_normal(512) * gain / np.sqrt(8)
+    p[512:576] = 0.1 * rng.standard_normal(64)
+    p[576:4672] = rng.standard_normal(4096) * gain / np.sqrt(64)
+    p[4672:4736] = 0.1 * rng.standard_normal(64)
+    p[4736:4928] = rng.standard_normal(192) / np.sqrt(64)
+    p[4928:4931] = 0.1 * rng.standard_normal(3)
+    return p
+
+
+def features(rng, n):
+    x = np.empty((n, 8))
+    x[:, 0] = 1 + 0.01 * rng.standard_normal(n)
+    x[:, 1:5] = 0.04 * rng.standard_normal((n, 4))
+    x[:, 5:8] = 1e-4 * rng.standard_normal((n, 3))
+    return x
+
+
+def norm_of(x, so=(1e-4, 1e-4, 1e-4)):
+    return np.concatenate([x.mean(0), x.std(0), np.asarray(so)])
+
+
+def dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 70000])
+def test_network_inference_vs_fp64(n):
+    note(f"closure eval n={n}")
+    rr = R()
+    rng = np.random.default_rng(n)
+    p = init_params(rng)
+    x = features(rng, n)
+    nm = norm_of(features(rng, 4096))
+    # the oracle sees exactly the FP32 values the GPU reads
+    p32, nm32, x32 = (a.astype(np.float32).astype(np.float64) for a in (p, nm, x))
+    ref = oracle.mlp_forward(p32, nm32, x32)
+    got = rr.closure_eval(dev32(p), dev32(nm), dev32(x)).cpu().numpy()
+    e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    note(f"  BF16 MFMA vs FP64: rel L2 {e:.3e}")
+    assert e < 2e-2
+
+
+def test_zero_network_is_bitwise_plain():
+    note("zero closure = plain")
+    rr = R()
+    n = 96
+    u, b = inputs.turbulence(n, 0.04)
+    a = rr.Solver(n, n, 0.51, 0.52)
+    a.init(torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda())
+    a.step(20)
+    c = rr.Solver(n, n, 0.51, 0.52)
+    c.init(torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda())
+    c.closure_set(dev32(np.zeros(4931)), dev32(norm_of(features(np.random.default_rng(1), 100))))
+    c.closure_enable(True)
+    c.step(20)
+    for x, y in zip(a.moments(), c.moments()):
+        assert torch.equal(x, y)
+    a.close(); c.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (100, 37)])
+def test_fused_closure_step_vs_oracle(shape):
+    """A network whose correction is of the order of a_1^(2) itself; after 10
+    steps the GPU fields match the oracle-with-closure fields, and the
+    closure's effect (closure minus plain) agrees to BF16 accuracy."""
+    nx, ny = shape
+    note(f"fused closure step {nx}x{ny}")
+    rr = R()
+    rng = np.random.default_rng(3)
+    u, b = inputs.random_modes(nx, ny, 0.05, seed=11)
+    p = init_params(rng)
+    nm = norm_of(features(rng, 4096), so=(2e-4, 1e-4, 2e-4))
+    p32, nm32 = (a.astype(np.float32).astype(np.float64) for a in (p, nm))
+    tf, tm, steps = 0.52, 0.55, 10
+    o_plain = oracle.Oracle(nx, ny, tf, tm); o_plain.init(u, b); o_plain.step(steps)
+    o_cl = oracle.Oracle(nx, ny, tf, tm); o_cl.set_closure(p32, nm32); o_cl.init(u, b)
+    o_cl.step(steps)
+    s = rr.Solver(nx, ny, tf, tm)
+    s.init(torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda())
+    s.closure_set(dev32(p), dev32(nm))
+    s.closure_enable(True)
+    s.step(steps)
+    got = [t.cpu().numpy() for t in s.moments()]
+    s.close()
+    ref = o_cl.moments()
+    pl = o_plain.moments()
+    for k, (g, r, q) in enumerate(zip(got, ref, pl)):
+        e = np.linalg.norm(g - r) / np.linalg.norm(r)
+        eff = np.linalg.norm(r - q)
+        de = np.linalg.norm((g - q) - (r - q)) / max(eff, 1e-300)
+        note(f"  field {k}: rel L2 {e:.3e}, closure effect {eff:.3e}, "
+             f"effect error {de:.3e}")
+        assert e < 1e-4
+        if k > 0:
+            assert de < 5e-2
