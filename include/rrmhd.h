@@ -196,6 +196,38 @@ int rrmhd_closure_enable(rrmhd *h, int on);
 int rrmhd_closure_eval(const float *params, const float *norm, const float *x,
                        int64_t n, float *y, void *hip_stream);
 
+/* Training of the closure (FP32 kernels).  Data (a-priori regression): fine
+ * moments rho[nf][nf], u, b [2][nf][nf] (device FP64, e.g. from
+ * rrmhd_moments) are box-filtered over factor x factor blocks; each coarse
+ * node gives features x = (rho_bar, u_bar, b_bar, a_CE) with u_bar =
+ * (rho u)_bar / rho_bar and a_CE = -rho_bar c_s^2 tau_c (grad u_bar +
+ * grad u_bar^T) (isotropic gradient on the coarse grid), and a target
+ * tau_sgs / (tau_c - 1) with tau_sgs = (rho u u)_bar - rho_bar u_bar u_bar
+ * + M(b)_bar - M(b_bar).  work: 10 (nf/factor)^2 doubles; x [Nc][8] and
+ * target [Nc][3] FP32, Nc = (nf/factor)^2.  Asynchronous. */
+int rrmhd_train_samples(const double *rho, const double *u, const double *b,
+                        int nf, int factor, double tau_c, double *work,
+                        float *x, float *target, void *hip_stream);
+typedef struct rrmhd_trainer rrmhd_trainer;
+/* Workspace for minibatches of up to max_batch samples. */
+int rrmhd_train_create(int64_t max_batch, void *hip_stream,
+                       rrmhd_trainer **out);
+/* grad[4931] and *loss (device FP32; loss may be NULL) of the mean squared
+ * error (1/n) sum_s sum_o (y_o(x_s) - target_so / sigma_out_o)^2 of the
+ * FP32 network over samples x[n][8], target[n][3] (device).  Reductions run
+ * in a fixed order (deterministic).  Asynchronous. */
+int rrmhd_train_loss_grad(rrmhd_trainer *t, const float *params,
+                          const float *norm, const float *x,
+                          const float *target, int64_t n, float *grad,
+                          float *loss);
+/* One Adam step (Kingma & Ba 2015) on params[4931] with moments m, v
+ * (device FP32) at step number step >= 1.  Asynchronous. */
+int rrmhd_train_adam(rrmhd_trainer *t, float *params, float *m, float *v,
+                     const float *grad, float lr, float beta1, float beta2,
+                     float eps, int step);
+int rrmhd_train_destroy(rrmhd_trainer *t);
+const char *rrmhd_train_last_error_detail(void);
+
 /* ---- Autotuner -----------------------------------------------------------
  * Times candidate launch shapes of the step kernel on the handle's own grid
  * (trials steps each, best of three repetitions, HIP events) and installs

@@ -84,6 +84,8 @@ def lib():
                                     ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int]
+        L.orc_train_samples.argtypes = [_dp, _dp, _dp, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -184,6 +186,18 @@ def adam_step(params, m, v, grad, lr=1e-3, beta1=0.9, beta2=0.999,
     grad = _f64(grad)
     lib().orc_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad),
                         params.size, lr, beta1, beta2, eps, int(t))
+
+
+def train_samples(rho, u, b, factor, tau_c):
+    """Closure training samples (x[Nc][8], t[Nc][3]) from fine moments."""
+    rho, u, b = _f64(rho), _f64(u), _f64(b)
+    nf = rho.shape[0]
+    nc = nf // factor
+    x = np.zeros((nc * nc, 8))
+    t = np.zeros((nc * nc, 3))
+    lib().orc_train_samples(_ptr(rho), _ptr(u), _ptr(b), nf, int(factor),
+                            float(tau_c), _ptr(x), _ptr(t))
+    return x, t
 
 
 class Oracle:

@@ -860,3 +860,85 @@ void orc_adam_step(double *params, double *m, double *v, const double *grad,
     params[k] -= lr * mh / (sqrt(vh) + eps);
   }
 }
+
+/* Training samples of the closure (project addition) from fine moments
+ * rho[nf][nf], u[2][nf][nf], b[2][nf][nf]: box filter over fac x fac blocks;
+ * features (rho_bar, u_bar = (rho u)_bar / rho_bar, b_bar, a_CE) with
+ * a_CE = -rho_bar c_s^2 tau_c (grad u_bar + grad u_bar^T), the gradient being
+ * the isotropic lattice gradient of Sec. III on the coarse grid; target
+ * tau_sgs / (tau_c - 1), tau_sgs = (rho u u)_bar - rho_bar u_bar u_bar
+ * + M(b)_bar - M(b_bar).  x[nc*nc][8], t[nc*nc][3]. */
+void orc_train_samples(const double *rho, const double *u, const double *b,
+                       int nf, int fac, double tau_c, double *x, double *t) {
+  const int nc = nf / fac;
+  const size_t Nf = (size_t)nf * nf, Nc = (size_t)nc * nc;
+  double *R = calloc(Nc, sizeof(double)), *JX = calloc(Nc, sizeof(double)),
+         *JY = calloc(Nc, sizeof(double)), *BX = calloc(Nc, sizeof(double)),
+         *BY = calloc(Nc, sizeof(double)), *PXX = calloc(Nc, sizeof(double)),
+         *PXY = calloc(Nc, sizeof(double)), *PYY = calloc(Nc, sizeof(double)),
+         *MXX = calloc(Nc, sizeof(double)), *MXY = calloc(Nc, sizeof(double)),
+         *MYY = calloc(Nc, sizeof(double));
+  for (int y = 0; y < nf; ++y)
+    for (int xx = 0; xx < nf; ++xx) {
+      const size_t f = (size_t)y * nf + xx, c = (size_t)(y / fac) * nc + xx / fac;
+      const double r = rho[f], ux = u[f], uy = u[Nf + f], bx = b[f], by = b[Nf + f];
+      double bb[2] = {bx, by}, M[2][2];
+      maxwell(bb, M);
+      R[c] += r;
+      JX[c] += r * ux;
+      JY[c] += r * uy;
+      BX[c] += bx;
+      BY[c] += by;
+      PXX[c] += r * ux * ux;
+      PXY[c] += r * ux * uy;
+      PYY[c] += r * uy * uy;
+      MXX[c] += M[0][0];
+      MXY[c] += M[0][1];
+      MYY[c] += M[1][1];
+    }
+  const double a = 1.0 / ((double)fac * fac);
+  double *arrs[11] = {R, JX, JY, BX, BY, PXX, PXY, PYY, MXX, MXY, MYY};
+  for (int k = 0; k < 11; ++k)
+    for (size_t c = 0; c < Nc; ++c) arrs[k][c] *= a;
+  double *UX = malloc(Nc * sizeof(double)), *UY = malloc(Nc * sizeof(double));
+  for (size_t c = 0; c < Nc; ++c) {
+    UX[c] = JX[c] / R[c];
+    UY[c] = JY[c] / R[c];
+  }
+  for (int cy = 0; cy < nc; ++cy)
+    for (int cx = 0; cx < nc; ++cx) {
+      const size_t c = (size_t)cy * nc + cx;
+      double g[2][2]; /* g[a][b] = d_a u_b */
+      for (int aa = 0; aa < 2; ++aa) {
+        double sx = 0.0, sy = 0.0;
+        for (int i = 0; i < 9; ++i) {
+          const size_t q = (size_t)wrap(cy + CI[i][1], nc) * nc + wrap(cx + CI[i][0], nc);
+          sx += WI[i] * UX[q] * CI[i][aa];
+          sy += WI[i] * UY[q] * CI[i][aa];
+        }
+        g[aa][0] = sx / CS2;
+        g[aa][1] = sy / CS2;
+      }
+      const double r = R[c], ux = UX[c], uy = UY[c];
+      double bb[2] = {BX[c], BY[c]}, Mb[2][2];
+      maxwell(bb, Mb);
+      const double k = -r * CS2 * tau_c;
+      x[c * 8 + 0] = r;
+      x[c * 8 + 1] = ux;
+      x[c * 8 + 2] = uy;
+      x[c * 8 + 3] = BX[c];
+      x[c * 8 + 4] = BY[c];
+      x[c * 8 + 5] = k * (g[0][0] + g[0][0]);
+      x[c * 8 + 6] = k * (g[0][1] + g[1][0]);
+      x[c * 8 + 7] = k * (g[1][1] + g[1][1]);
+      const double sxx = PXX[c] - r * ux * ux + MXX[c] - Mb[0][0];
+      const double sxy = PXY[c] - r * ux * uy + MXY[c] - Mb[0][1];
+      const double syy = PYY[c] - r * uy * uy + MYY[c] - Mb[1][1];
+      t[c * 3 + 0] = sxx / (tau_c - 1.0);
+      t[c * 3 + 1] = sxy / (tau_c - 1.0);
+      t[c * 3 + 2] = syy / (tau_c - 1.0);
+    }
+  for (int k = 0; k < 11; ++k) free(arrs[k]);
+  free(UX);
+  free(UY);
+}

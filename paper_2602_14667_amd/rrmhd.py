@@ -29,6 +29,8 @@ EXPORTED = [
     "rrmhd_batch_destroy", "rrmhd_batch_last_error_detail",
     "rrmhd_autotune", "rrmhd_batch_autotune",
     "rrmhd_closure_set", "rrmhd_closure_enable", "rrmhd_closure_eval",
+    "rrmhd_train_samples", "rrmhd_train_create", "rrmhd_train_loss_grad",
+    "rrmhd_train_adam", "rrmhd_train_destroy", "rrmhd_train_last_error_detail",
 ]
 
 
@@ -106,6 +108,15 @@ def lib():
         L.rrmhd_closure_set.argtypes = [vp, vp, vp]
         L.rrmhd_closure_enable.argtypes = [vp, ci]
         L.rrmhd_closure_eval.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.rrmhd_train_samples.argtypes = [vp, vp, vp, ci, ci, ctypes.c_double,
+                                          vp, vp, vp, vp]
+        L.rrmhd_train_create.argtypes = [i64, vp, ctypes.POINTER(vp)]
+        L.rrmhd_train_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        fl = ctypes.c_float
+        L.rrmhd_train_adam.argtypes = [vp, vp, vp, vp, vp, fl, fl, fl, fl, ci]
+        L.rrmhd_train_destroy.argtypes = [vp]
+        L.rrmhd_train_last_error_detail.argtypes = []
+        L.rrmhd_train_last_error_detail.restype = ctypes.c_char_p
         L.rrmhd_strerror.argtypes = [ctypes.c_int]
         L.rrmhd_strerror.restype = ctypes.c_char_p
         L.rrmhd_last_error_detail.argtypes = []
@@ -113,7 +124,8 @@ def lib():
         for name in EXPORTED:
             if name not in ("rrmhd_strerror", "rrmhd_last_error_detail",
                             "rrmhd_state_bytes",
-                            "rrmhd_batch_last_error_detail"):
+                            "rrmhd_batch_last_error_detail",
+                            "rrmhd_train_last_error_detail"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -407,3 +419,60 @@ class Batch:
                                          ctypes.byref(grid)), "rrmhd_batch_info")
         return dict(nodes=nodes.value, steps=steps.value, tiles=nt.value,
                     grid=grid.value)
+
+
+def _ptr_t(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def train_samples(rho, u, b, factor, tau_c, stream=None):
+    """Coarse training samples (x[Nc][8], target[Nc][3], FP32 device) from
+    fine FP64 device moments rho[nf][nf], u, b [2][nf][nf]."""
+    import torch
+    nf = rho.shape[0]
+    nc = nf // factor
+    dev = rho.device
+    work = torch.empty(10 * nc * nc, dtype=torch.float64, device=dev)
+    x = torch.empty((nc * nc, 8), dtype=torch.float32, device=dev)
+    t = torch.empty((nc * nc, 3), dtype=torch.float32, device=dev)
+    _check(lib().rrmhd_train_samples(_ptr_t(rho), _ptr_t(u), _ptr_t(b), nf,
+                                     int(factor), float(tau_c), _ptr_t(work),
+                                     _ptr_t(x), _ptr_t(t),
+                                     _stream_handle(stream)),
+           "rrmhd_train_samples")
+    return x, t
+
+
+class Trainer:
+    """FP32 training kernels of the closure network."""
+
+    def __init__(self, max_batch, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().rrmhd_train_create(int(max_batch), _stream_handle(stream),
+                                        ctypes.byref(h)), "rrmhd_train_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rrmhd_train_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def loss_grad(self, params, norm, x, target, grad, loss=None):
+        _check(lib().rrmhd_train_loss_grad(self._h, _ptr_t(params), _ptr_t(norm),
+                                           _ptr_t(x), _ptr_t(target),
+                                           int(x.shape[0]), _ptr_t(grad),
+                                           _ptr_t(loss)),
+               "rrmhd_train_loss_grad")
+
+    def adam(self, params, m, v, grad, lr, step, beta1=0.9, beta2=0.999,
+             eps=1e-8):
+        _check(lib().rrmhd_train_adam(self._h, _ptr_t(params), _ptr_t(m),
+                                      _ptr_t(v), _ptr_t(grad), float(lr),
+                                      float(beta1), float(beta2), float(eps),
+                                      int(step)), "rrmhd_train_adam")

@@ -145,3 +145,41 @@ def test_closure_shifts_a2_by_the_network_output():
             assert abs((d * CX * CX).sum() - (1 - om) * delta[0]) < 1e-15
             assert abs((d * CX * CY).sum() - (1 - om) * delta[1]) < 1e-15
             assert abs((d * CY * CY).sum() - (1 - om) * delta[2]) < 1e-15
+
+
+def test_train_samples_closed_forms():
+    """Uniform fine fields: no subgrid stress, zero gradient features.
+    A fine field that is constant on each 2x2 block: filtering loses
+    nothing, so tau_sgs = 0 as well; a linear shear u_x = s y gives
+    a_CE_xy = -rho c_s^2 tau_c s exactly (isotropic gradient of a linear
+    field is exact), up to the periodic seam rows."""
+    nf, fac, tau_c = 16, 2, 0.52
+    rho = np.ones((nf, nf)) * 1.01
+    u = np.zeros((2, nf, nf)); u[0] = 0.03; u[1] = -0.01
+    b = np.zeros((2, nf, nf)); b[0] = 0.02; b[1] = 0.04
+    x, t = oracle.train_samples(rho, u, b, fac, tau_c)
+    assert np.allclose(x[:, 0], 1.01) and np.allclose(x[:, 1], 0.03)
+    assert np.allclose(x[:, 5:], 0, atol=1e-17) and np.allclose(t, 0, atol=1e-17)
+    blk = np.kron(np.random.default_rng(1).standard_normal((nf // 2, nf // 2)),
+                  np.ones((2, 2)))
+    u2 = np.stack([0.01 * blk, 0.02 * blk]); b2 = np.stack([0.01 * blk, -blk * 0.01])
+    _, t2 = oracle.train_samples(np.ones((nf, nf)), u2, b2, fac, tau_c)
+    assert np.allclose(t2, 0, atol=1e-17)
+    s = 1e-3
+    yy = np.arange(nf)[:, None] * np.ones((1, nf))
+    u3 = np.zeros((2, nf, nf)); u3[0] = s * yy
+    x3, _ = oracle.train_samples(np.ones((nf, nf)), u3, np.zeros((2, nf, nf)), 1, tau_c)
+    inner = x3.reshape(nf, nf, 8)[1:-1, :, 6]
+    assert np.allclose(inner, -tau_c / 3 * s, rtol=1e-12)
+
+
+def test_train_samples_subgrid_stress_of_unresolved_shear():
+    """A fine field alternating +-v within each block has a zero filtered
+    velocity, so tau_sgs_xx = <rho u_x^2> = v^2 and the target is
+    v^2 / (tau_c - 1)."""
+    nf, fac, tau_c, v = 8, 2, 0.51, 0.02
+    u = np.zeros((2, nf, nf))
+    u[0] = v * np.where((np.arange(nf)[None, :] % 2) == 0, 1.0, -1.0)
+    x, t = oracle.train_samples(np.ones((nf, nf)), u, np.zeros((2, nf, nf)), fac, tau_c)
+    assert np.allclose(x[:, 1], 0, atol=1e-18)
+    assert np.allclose(t[:, 0], v * v / (tau_c - 1)) and np.allclose(t[:, 1:], 0)
