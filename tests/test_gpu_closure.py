@@ -116,6 +116,8 @@ def test_fused_closure_step_vs_oracle(shape):
         de = np.linalg.norm((g - q) - (r - q)) / max(eff, 1e-300)
         note(f"  field {k}: rel L2 {e:.3e}, closure effect {eff:.3e}, "
              f"effect error {de:.3e}")
-        assert e < 1e-4
-        if k > 0:
-            assert de < 5e-2
+        # BF16 network: the closure's effect carries a few 1e-3 relative
+        # error per step (inference test above); the fields inherit it in
+        # proportion to the effect's size
+        assert de < 5e-2
+        assert e < 5e-2 * eff / np.linalg.norm(r) + 1e-6
