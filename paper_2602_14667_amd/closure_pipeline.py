@@ -1,0 +1,239 @@
+"""Learned-closure pipeline (a project addition; the paper has no closure).
+
+1. Fine runs: plain recursive-regularised solver on an n_f^2 grid from the
+   seeded turbulence field (tau_f), snapshots every `snap` steps.
+2. Training samples: each snapshot's moments are box-filtered by `factor`
+   into coarse features and a-priori targets (`rrmhd_train_samples`).
+3. Training: FP32 forward/backward and Adam kernels on random minibatches.
+4. Coarse runs (n_f / factor)^2 at the acoustically scaled relaxation time
+   tau_c = 1/2 + (tau_f - 1/2) / factor (dx and dt both scale by factor, so
+   coarse step n matches fine step factor * n), plain and with the closure.
+5. Judge: shell spectra of the coarse runs against the box-filtered fine run
+   at the same physical times (`spectral`).
+
+Runtime fallback: the closure run checkpoints its state; if a diagnostic
+turns non-finite it restarts from the last checkpoint with the closure off
+(the plain coarse solver) and reports it.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import inputs, rrmhd, spectral
+
+
+def tau_coarse(tau_f: float, factor: int) -> float:
+    return 0.5 + (tau_f - 0.5) / factor
+
+
+def fine_fields(n_f: int, seed: int):
+    return inputs.turbulence(n_f, 0.04, seed_psi=2 * seed + 1, seed_a=2 * seed + 2)
+
+
+def coarse_fields(n_f: int, factor: int, seed: int):
+    u, b = fine_fields(n_f, seed)
+    return (np.ascontiguousarray(spectral.box_filter(u, factor)),
+            np.ascontiguousarray(spectral.box_filter(b, factor)))
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def generate_samples(seed, n_f, tau_f, factor, snap_steps):
+    """Training samples (x, t) device tensors from one fine run."""
+    import torch
+    u, b = fine_fields(n_f, seed)
+    s = rrmhd.Solver(n_f, n_f, tau_f, tau_f)
+    s.init(_dev(u), _dev(b))
+    xs, ts = [], []
+    tc = tau_coarse(tau_f, factor)
+    for step in snap_steps:
+        s.step(step - s.step_count)
+        rho, uu, bb = s.moments()
+        x, t = rrmhd.train_samples(rho, uu, bb, factor, tc)
+        xs.append(x)
+        ts.append(t)
+    torch.cuda.synchronize()
+    s.close()
+    return xs, ts
+
+
+def normalization(x, t):
+    """mu, sigma of the features and sigma_out of the targets (FP32)."""
+    import torch
+    mu = x.double().mean(0)
+    sd = x.double().std(0)
+    sd = torch.where(sd > 0, sd, torch.ones_like(sd))
+    so = t.double().std(0)
+    so = torch.where(so > 0, so, torch.ones_like(so))
+    return torch.cat([mu, sd, so]).float().contiguous()
+
+
+def init_params(seed: int):
+    """Fan-in scaled random weights, zero biases, zero output layer (so the
+    untrained network adds nothing)."""
+    import torch
+    g = np.random.default_rng(seed)
+    p = np.zeros(4931, dtype=np.float32)
+    p[0:512] = g.standard_normal(512) / np.sqrt(8)
+    p[576:4672] = g.standard_normal(4096) / np.sqrt(64)
+    return torch.from_numpy(p).cuda()
+
+
+def train(x, t, norm, steps=2000, batch=65536, lr=1e-3, seed=0, log_every=0):
+    """Adam on random minibatches; returns (params, loss history)."""
+    import torch
+    n = x.shape[0]
+    batch = min(batch, n)
+    p = init_params(seed)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    grad = torch.empty_like(p)
+    loss = torch.empty(1, dtype=torch.float32, device=p.device)
+    tr = rrmhd.Trainer(batch)
+    gen = torch.Generator(device=p.device)
+    gen.manual_seed(seed)
+    hist = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (batch,), generator=gen, device=p.device)
+        xb = x[idx].contiguous()
+        tb = t[idx].contiguous()
+        tr.loss_grad(p, norm, xb, tb, grad, loss)
+        tr.adam(p, m, v, grad, lr, step)
+        if log_every and (step % log_every == 0 or step == 1):
+            hist.append((step, float(loss.item())))
+    tr.close()
+    return p, hist
+
+
+def spectra_run(n, tau, u, b, checkpoints, params=None, norm=None,
+                fallback_every=1000):
+    """Run a periodic grid, returning {step: (E(k), E_kin, E_mag)} and the
+    GPU wall time of the stepping (HIP events)."""
+    import torch
+    s = rrmhd.Solver(n, n, tau, tau)
+    s.init(_dev(u), _dev(b))
+    if params is not None:
+        s.closure_set(params, norm)
+        s.closure_enable(True)
+    st = torch.cuda.current_stream()
+    out, fell_back, gpu_ms = {}, None, 0.0
+    ck = torch.empty(s.state_bytes(), dtype=torch.uint8, device="cuda")
+    s.save_state(ck)
+    ck_step = 0
+    for c in checkpoints:
+        while s.step_count < c:
+            k = min(fallback_every, c - s.step_count)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            s.step(k)
+            e1.record(st)
+            torch.cuda.synchronize()
+            gpu_ms += e0.elapsed_time(e1)
+            if params is not None and fell_back is None:
+                rc, _ = s.diagnostics_rc()
+                if rc != rrmhd.OK:
+                    fell_back = s.step_count
+                    s.load_state(ck, ck_step)
+                    s.closure_enable(False)
+                    continue
+                s.save_state(ck)
+                ck_step = s.step_count
+        _, uu, bb = s.moments()
+        uh, bh = uu.cpu().numpy(), bb.cpu().numpy()
+        out[c] = (spectral.shell_spectrum(uh, bh), *spectral.energies(uh, bh))
+    s.close()
+    return out, gpu_ms, fell_back
+
+
+def fine_reference(n_f, tau_f, factor, seed, coarse_checkpoints):
+    """Box-filtered fine spectra at the physical times of the coarse
+    checkpoints (fine step = factor x coarse step)."""
+    import torch
+    u, b = fine_fields(n_f, seed)
+    s = rrmhd.Solver(n_f, n_f, tau_f, tau_f)
+    s.init(_dev(u), _dev(b))
+    st = torch.cuda.current_stream()
+    out, gpu_ms = {}, 0.0
+    for c in coarse_checkpoints:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.step(factor * c - s.step_count)
+        e1.record(st)
+        torch.cuda.synchronize()
+        gpu_ms += e0.elapsed_time(e1)
+        _, uu, bb = s.moments()
+        uf = spectral.box_filter(uu.cpu().numpy(), factor)
+        bf = spectral.box_filter(bb.cpu().numpy(), factor)
+        out[c] = (spectral.shell_spectrum(uf, bf), *spectral.energies(uf, bf))
+    s.close()
+    return out, gpu_ms
+
+
+def judge(run, ref, kmax):
+    rows = []
+    for c in sorted(ref):
+        e, ek, em = run[c]
+        er, ekr, emr = ref[c]
+        rows.append(dict(step=c, eps_spec=spectral.eps_spec(e, er, kmax),
+                         ekin_err=ek / ekr - 1.0, emag_err=em / emr - 1.0))
+    worst = dict(eps_spec=max(r["eps_spec"] for r in rows),
+                 ekin_err=max(abs(r["ekin_err"]) for r in rows),
+                 emag_err=max(abs(r["emag_err"]) for r in rows))
+    worst["within_5pct"] = bool(worst["eps_spec"] <= 0.05 and worst["ekin_err"] <= 0.05
+                                and worst["emag_err"] <= 0.05)
+    return rows, worst
+
+
+def pipeline(n_f=2048, factor=4, tau_f=0.51, fine_steps=64000, snaps=8,
+             train_seeds=range(16), test_seeds=range(20, 24), train_steps=3000,
+             batch=65536, lr=1e-3, n_times=5, log=print):
+    """Full protocol; returns a dict of results."""
+    import torch
+    t0 = time.time()
+    snap_steps = [fine_steps * (k + 1) // snaps for k in range(snaps)]
+    xs, ts = [], []
+    for sd in train_seeds:
+        x, t = generate_samples(sd, n_f, tau_f, factor, snap_steps)
+        xs += x
+        ts += t
+        log(f"fine run seed {sd}: {len(x)} snapshots")
+    X = torch.cat(xs)
+    T = torch.cat(ts)
+    del xs, ts
+    norm = normalization(X, T)
+    t_data = time.time() - t0
+    t1 = time.time()
+    params, hist = train(X, T, norm, steps=train_steps, batch=batch, lr=lr,
+                         log_every=max(train_steps // 10, 1))
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    log(f"training: {hist}")
+    del X, T
+    n_c = n_f // factor
+    tc = tau_coarse(tau_f, factor)
+    checkpoints = [fine_steps // factor * (k + 1) // n_times for k in range(n_times)]
+    kmax = n_c // 4
+    res = dict(train_loss=hist, data_s=t_data, train_s=t_train, tests=[])
+    for sd in test_seeds:
+        ref, ms_fine = fine_reference(n_f, tau_f, factor, sd, checkpoints)
+        uc, bc = coarse_fields(n_f, factor, sd)
+        plain, ms_plain, _ = spectra_run(n_c, tc, uc, bc, checkpoints)
+        clos, ms_clos, fb = spectra_run(n_c, tc, uc, bc, checkpoints, params, norm)
+        rp, wp = judge(plain, ref, kmax)
+        rc, wc = judge(clos, ref, kmax)
+        res["tests"].append(dict(seed=sd, plain=wp, closure=wc, plain_rows=rp,
+                                 closure_rows=rc, fine_gpu_ms=ms_fine,
+                                 plain_gpu_ms=ms_plain, closure_gpu_ms=ms_clos,
+                                 fallback_at=fb))
+        log(f"seed {sd}: plain {wp} closure {wc} fine {ms_fine:.0f} ms, "
+            f"coarse {ms_plain:.0f} / {ms_clos:.0f} ms")
+    res["params"] = params.cpu().numpy().tolist()
+    res["norm"] = norm.cpu().numpy().tolist()
+    return res
