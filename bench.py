@@ -117,6 +117,104 @@ def launch_sweep(torch, rrmhd, inputs, args):
     os.environ.pop("RRMHD_PLANE_PAD_BYTES", None)
 
 
+def batch_bench(torch, rrmhd, inputs, args):
+    """The 256-domain ensemble (sides 64..1024, tau uniform in [0.501, 0.6]),
+    FP32, autotuned tiles, graph-captured persistent launches."""
+    doms = inputs.batch_domains(256, seed=0)
+    shapes = [(d["side"], d["side"]) for d in doms]
+    b = rrmhd.Batch(shapes, [d["tau_f"] for d in doms], [d["tau_m"] for d in doms])
+    for k, d in enumerate(doms):
+        u, bf = inputs.batch_fields(d)
+        b.init(k, torch.from_numpy(u).cuda(), torch.from_numpy(bf).cuda())
+    t0 = time.perf_counter()
+    b.autotune(None, trials=5)
+    tune_s = time.perf_counter() - t0
+    chunk = 100
+    b.set_graph_chunk(chunk)
+    b.step(args.warmup if args.warmup >= chunk else chunk)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps = max(chunk, (args.steps // chunk) * chunk)
+    e0.record(st)
+    b.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = b.info()
+    nodes = info["nodes"]
+    # sequential standalone launches of the same domains, for comparison
+    seq_ms = 0.0
+    for k, d in enumerate(doms):
+        s = rrmhd.Solver(d["side"], d["side"], d["tau_f"], d["tau_m"])
+        u, bf = inputs.batch_fields(d)
+        s.init(torch.from_numpy(u).cuda(), torch.from_numpy(bf).cuda())
+        s.step(2)
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(st)
+        s.step(20)
+        f1.record(st)
+        torch.cuda.synchronize()
+        seq_ms += f0.elapsed_time(f1) / 20
+        s.close()
+    b.close()
+    gbs = 152 * nodes / ms / 1e6
+    print(json.dumps({
+        "metric": "MLUPS & % HBM roofline (batched ensemble step)",
+        "value": round(nodes / ms / 1e3, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": steps, "warmup": chunk, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256 periodic domains, sides 64..1024, "
+                               "OT or turbulence, tau in [0.501, 0.6]",
+                   "nodes": nodes, "tiles": info["tiles"],
+                   "persistent_workgroups": info["grid"],
+                   "graph_chunk": chunk, "autotune_s": round(tune_s, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+        "sequential_standalone_ms_per_step": round(seq_ms, 4),
+        "speedup_vs_sequential": round(seq_ms / ms, 3)}), flush=True)
+
+
+def closure_bench(args):
+    """Learned-closure protocol: coarse 512^2 (plain and with the trained
+    network) against the 4x4-filtered 2048^2 run."""
+    from paper_2602_14667_amd import closure_pipeline as cp
+    if args.closure_scale == "full":
+        kw = dict(n_f=2048, factor=4, tau_f=0.51, fine_steps=64000, snaps=8,
+                  train_seeds=range(16), test_seeds=range(20, 24),
+                  train_steps=3000, batch=65536)
+    else:
+        kw = dict(n_f=1024, factor=4, tau_f=0.51, fine_steps=16000, snaps=4,
+                  train_seeds=range(4), test_seeds=[20], train_steps=1000,
+                  batch=65536)
+    res = cp.pipeline(log=lambda m: print(m, file=sys.stderr, flush=True), **kw)
+    tests = res["tests"]
+    worst = {side: max(t[side]["eps_spec"] for t in tests) for side in ("plain", "closure")}
+    e_err = {side: max(max(t[side]["ekin_err"], t[side]["emag_err"]) for t in tests)
+             for side in ("plain", "closure")}
+    ms = {k: sum(t[k] for t in tests) / len(tests)
+          for k in ("fine_gpu_ms", "plain_gpu_ms", "closure_gpu_ms")}
+    print(json.dumps({
+        "metric": "closure-vs-fine wall time at 5% spectral error",
+        "value": round(ms["closure_gpu_ms"] / 1e3, 3), "unit": "s (GPU, coarse+closure run)",
+        "higher_is_better": False, "n_gpus": 1, "vs_baseline": None,
+        "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": "decaying 2D MHD turbulence, coarse "
+                               f"{kw['n_f'] // kw['factor']}^2 vs fine {kw['n_f']}^2",
+                   **{k: (list(v) if isinstance(v, range) else v) for k, v in kw.items()}},
+        "eps_spec_worst": worst, "energy_err_worst": e_err,
+        "within_5pct": {side: all(t[side]["within_5pct"] for t in tests)
+                        for side in ("plain", "closure")},
+        "gpu_s": {k: round(v / 1e3, 3) for k, v in ms.items()},
+        "train_s": round(res["train_s"], 2), "data_s": round(res["data_s"], 2),
+        "train_loss_first_last": [res["train_loss"][0], res["train_loss"][-1]],
+        "fallbacks": [t["fallback_at"] for t in tests]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +228,11 @@ def main():
                     help="copy: time the plain device-copy reference; sweep: "
                          "time launch shapes, XCD block orders and plane gaps")
     ap.add_argument("--copy-bytes", type=int, default=4 << 30)
+    ap.add_argument("--workload", choices=["turbulence", "batch", "closure"],
+                    default="turbulence",
+                    help="batch: the 256-domain ensemble; closure: the "
+                         "learned-closure protocol (coarse vs fine spectra)")
+    ap.add_argument("--closure-scale", choices=["full", "reduced"], default="full")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for "
@@ -146,6 +249,12 @@ def main():
         return
     if args.mode == "sweep":
         launch_sweep(torch, rrmhd, inputs, args)
+        return
+    if args.workload == "batch":
+        batch_bench(torch, rrmhd, inputs, args)
+        return
+    if args.workload == "closure":
+        closure_bench(args)
         return
     n = args.n
     u, b = inputs.turbulence(n, 0.04)
