@@ -99,6 +99,13 @@ int rrmhd_moments(rrmhd *h, double *rho, double *u, double *b);
 int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag,
                       double *max_div_b);
 
+/* Derived fields of a periodic grid, FP64 device arrays [ny][nx] (either
+ * may be NULL): the local current density j_z of Eq. current, computed from
+ * the magnetic populations' departure from equilibrium (no finite
+ * differences), and the vorticity w_z = d_x u_y - d_y u_x with the isotropic
+ * lattice gradient of Sec. III.  EINVAL with walls.  Asynchronous. */
+int rrmhd_current_vorticity(rrmhd *h, double *jz, double *wz);
+
 /* Host out[5] = mass sum rho, momentum sum_i c_i f_i (x, y), total field
  * sum b (x, y), FP64, over the current state.  Synchronises the stream. */
 int rrmhd_invariants(rrmhd *h, double out[5]);

@@ -342,4 +342,17 @@ int rrmhd_closure_eval(const float *params, const float *norm, const float *x, i
   return RRMHD_OK;
 }
 
+int rrmhd_current_vorticity(rrmhd *h, double *jz, double *wz) {
+  if (!h) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  if (h->D.walls) return RRMHD_EINVAL;
+  if (!jz && !wz) return RRMHD_OK;
+  if (!h->diag_work) HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
+  // the diagnostics workspace starts with 2 nx ny doubles: the velocity planes
+  int rc = rr_launch_current_vorticity(h->storage, &h->D, h->buf[h->cur], 1.0 / h->tau_m, jz, wz,
+                                       (double *)h->diag_work, h->stream);
+  if (rc != RRMHD_OK) return dev_err(hipGetLastError(), "current/vorticity kernels");
+  return RRMHD_OK;
+}
+
 }  // extern "C"

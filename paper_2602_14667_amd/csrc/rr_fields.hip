@@ -1,0 +1,115 @@
+// rr_fields.hip -- derived diagnostic fields of a periodic grid (FP64):
+// the local current density j_z of Eq. current, evaluated from g - g_eq
+// (no finite differences), and the vorticity w_z = d_x u_y - d_y u_x with
+// the isotropic lattice gradient of Sec. III.  Used to compare with the
+// peak current and vorticity the paper tabulates.
+#include <hip/hip_runtime.h>
+
+#include "rr_internal.h"
+#include "rr_kernels.h"
+#include "rr_node.h"
+#include "rr_pull.h"
+
+namespace rr {
+
+template <class C>
+__global__ void k_current(PlaneGeom G, const typename C::T *__restrict__ src, double omega_m,
+                          double Gx, double Gy, double *__restrict__ jz,
+                          double *__restrict__ upl) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= G.nx) return;
+  using T = typename C::T;
+  constexpr uint32_t E = sizeof(T);
+  const uint32_t pitch = G.nx * E, x0 = x * E;
+  const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E, xp = (x == G.nx - 1 ? 0 : x + 1) * E;
+  const uint32_t b0 = y * pitch, bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
+  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
+  float d[kQ], g[2 * kQm];
+  d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  double dr = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    dr += (double)d[i];
+    jx += (double)cx(i) * d[i];
+    jy += (double)cy(i) * d[i];
+  }
+#pragma unroll
+  for (int j = 0; j < kQm; ++j) {
+    bx += (double)g[2 * j];
+    by += (double)g[2 * j + 1];
+  }
+  const double rho = 1.0 + dr;
+  const double ux = (jx + 0.5 * rho * Gx) / rho, uy = (jy + 0.5 * rho * Gy) / rho;
+  // eps_ab sum_j e_ja (g_jb - g_eq,jb) = sum_j [e_jx (g_jy - geq_jy) - e_jy (g_jx - geq_jx)]
+  const double Ez = ux * by - uy * bx;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 1; j < kQm; ++j) {
+    const double psi = 1.0 / 6.0;
+    const double gxe = psi * (bx - 3.0 * ey(j) * Ez), gye = psi * (by + 3.0 * ex(j) * Ez);
+    s += ex(j) * ((double)g[2 * j + 1] - gye) - ey(j) * ((double)g[2 * j] - gxe);
+  }
+  const int64_t N = (int64_t)G.nx * G.ny, o = (int64_t)y * G.nx + x;
+  if (jz) jz[o] = -omega_m * 3.0 * s;
+  upl[o] = ux;
+  upl[N + o] = uy;
+}
+
+__global__ void k_vorticity(int nx, int ny, const double *__restrict__ upl,
+                            double *__restrict__ wz) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= nx) return;
+  const int64_t N = (int64_t)nx * ny;
+  double dxuy = 0.0, dyux = 0.0;
+#pragma unroll
+  for (int i = 1; i < kQ; ++i) {
+    int xx = x + cx(i), yy = y + cy(i);
+    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    const int64_t o = (int64_t)yy * nx + xx;
+    const double w = (i & 1) ? 1.0 / 36.0 : 1.0 / 9.0;
+    dxuy += w * upl[N + o] * cx(i);
+    dyux += w * upl[o] * cy(i);
+  }
+  wz[(int64_t)y * nx + x] = 3.0 * (dxuy - dyux);
+}
+
+}  // namespace rr
+
+// Launcher used by rrmhd_current_vorticity (rr_api.hip).
+extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Domain *D, const void *src,
+                                           double omega_m, double *jz, double *wz,
+                                           double *upl, hipStream_t st) {
+  const dim3 block(64), grid((D->nx + 63) / 64, D->ny);
+  const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s};
+  if (storage == rr::kF16)
+    hipLaunchKernelGGL(rr::k_current<rr::CodecF16>, grid, block, 0, st, G,
+                       (const uint16_t *)src, omega_m, (double)D->Gx, (double)D->Gy, jz, upl);
+  else
+    hipLaunchKernelGGL(rr::k_current<rr::CodecF32>, grid, block, 0, st, G, (const float *)src,
+                       omega_m, (double)D->Gx, (double)D->Gy, jz, upl);
+  if (hipGetLastError() != hipSuccess) return RRMHD_EDEVICE;
+  if (wz) {
+    hipLaunchKernelGGL(rr::k_vorticity, grid, block, 0, st, D->nx, D->ny, upl, wz);
+    if (hipGetLastError() != hipSuccess) return RRMHD_EDEVICE;
+  }
+  return RRMHD_OK;
+}

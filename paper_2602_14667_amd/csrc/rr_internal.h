@@ -21,3 +21,11 @@ RR_HIDDEN int rr_batch_save(rrmhd_batch *b, void **copy);
 RR_HIDDEN int rr_batch_restore(rrmhd_batch *b, void *copy, int64_t steps);
 RR_HIDDEN hipStream_t rr_batch_stream(const rrmhd_batch *b);
 }
+
+namespace rr {
+struct Domain;
+}
+extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Domain *D,
+                                                     const void *src, double omega_m,
+                                                     double *jz, double *wz, double *upl,
+                                                     hipStream_t st);

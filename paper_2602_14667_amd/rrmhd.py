@@ -31,6 +31,7 @@ EXPORTED = [
     "rrmhd_closure_set", "rrmhd_closure_enable", "rrmhd_closure_eval",
     "rrmhd_train_samples", "rrmhd_train_create", "rrmhd_train_loss_grad",
     "rrmhd_train_adam", "rrmhd_train_destroy", "rrmhd_train_last_error_detail",
+    "rrmhd_current_vorticity",
 ]
 
 
@@ -115,6 +116,7 @@ def lib():
         fl = ctypes.c_float
         L.rrmhd_train_adam.argtypes = [vp, vp, vp, vp, vp, fl, fl, fl, fl, ci]
         L.rrmhd_train_destroy.argtypes = [vp]
+        L.rrmhd_current_vorticity.argtypes = [vp, dp, dp]
         L.rrmhd_train_last_error_detail.argtypes = []
         L.rrmhd_train_last_error_detail.restype = ctypes.c_char_p
         L.rrmhd_strerror.argtypes = [ctypes.c_int]
@@ -244,6 +246,17 @@ class Solver:
             _dev_f64(u, (2, self.ny, self.nx), "u"),
             _dev_f64(b, (2, self.ny, self.nx), "b")), "rrmhd_moments")
         return rho, u, b
+
+    def current_vorticity(self):
+        """(j_z, w_z) FP64 device tensors [ny][nx]."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        jz = torch.empty((self.ny, self.nx), dtype=torch.float64, device=dev)
+        wz = torch.empty((self.ny, self.nx), dtype=torch.float64, device=dev)
+        _check(lib().rrmhd_current_vorticity(self._h, ctypes.c_void_p(jz.data_ptr()),
+                                             ctypes.c_void_p(wz.data_ptr())),
+               "rrmhd_current_vorticity")
+        return jz, wz
 
     def diagnostics(self, allow_nonfinite=False):
         ek, em, dv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
