@@ -16,7 +16,7 @@ def test_closure_pipeline_small():
     from paper_2602_14667_amd import closure_pipeline as cp, rrmhd
     rrmhd.lib()
     print("[gpu] closure pipeline 256 -> 64", flush=True)
-    res = cp.pipeline(n_f=256, factor=4, tau_f=0.51, fine_steps=4000, snaps=4,
+    res = cp.pipeline(n_f=256, factor=4, tau_f=0.54, fine_steps=4000, snaps=4,
                       train_seeds=range(3), test_seeds=[20], train_steps=300,
                       batch=16384, lr=1e-3, n_times=4,
                       log=lambda m: print("[gpu]  ", m, flush=True))
