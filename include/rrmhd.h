@@ -163,16 +163,22 @@ int rrmhd_batch_step(rrmhd_batch *b, int64_t n);
 /* Steps per captured hipGraph (0: plain launches, the default). */
 int rrmhd_batch_set_graph_chunk(rrmhd_batch *b, int chunk);
 /* Tile width bx (a divisor of 256, tile = bx x 256/bx) for domain d, or for
- * all domains when d = -1 (0 keeps it); persistent workgroup count grid (0
- * keeps it); nt = 1/0 non-temporal stores (-1 keeps it).  Results do not
- * depend on these (bitwise). */
+ * all domains when d = -1 (0 keeps it); workgroups per launch grid (0 keeps
+ * it, -1 = one workgroup per tile); nt = 1/0 non-temporal stores (-1 keeps
+ * it).  Results do not depend on these (bitwise). */
 int rrmhd_batch_set_shape(rrmhd_batch *b, int d, int bx, int grid, int nt);
+/* Work distribution inside a launch: 0 (default) = static, workgroup w
+ * takes tiles w, w + grid, ...; k in 1..64 = dynamic, each workgroup takes
+ * its next k consecutive tiles from a device counter (persistent workgroups
+ * that keep the tiles in flight contiguous).  Results do not depend on it
+ * (bitwise).  EINVAL outside 0..64. */
+int rrmhd_batch_set_fetch(rrmhd_batch *b, int tiles_per_fetch);
 int rrmhd_batch_moments(rrmhd_batch *b, int d, double *rho, double *u,
                         double *bf);
 /* As rrmhd_diagnostics for domain d (synchronises). */
 int rrmhd_batch_diagnostics(rrmhd_batch *b, int d, double *E_kin,
                             double *E_mag, double *max_div_b);
-/* Total nodes, steps taken, tiles in the work list, persistent grid size. */
+/* Total nodes, steps taken, tiles in the work list, workgroups per launch. */
 int rrmhd_batch_info(const rrmhd_batch *b, int64_t *nodes, int64_t *steps,
                      int *ntiles, int *grid);
 int rrmhd_batch_destroy(rrmhd_batch *b);
@@ -247,8 +253,9 @@ const char *rrmhd_train_last_error_detail(void);
 int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
                    int *out_by, int *out_xcd, double *out_ms);
 /* Ensemble version: a tile width for every distinct domain size (timed on a
- * standalone grid of that size) and then the persistent workgroup count
- * (timed on the ensemble, state preserved); same cache file. */
+ * standalone grid of that size) and then the work distribution (workgroup
+ * count and static or dynamic schedule, timed on the ensemble, state
+ * preserved); same cache file. */
 int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials);
 
 /* Measurement helper, not part of the method: copies `bytes` (a multiple of

@@ -4,8 +4,10 @@
 // All domains live in one pair of buffers; domain d's 19 planes start at
 // element offset base[d].  The work list is flat: domain d owns tiles
 // [tile_first[d], tile_first[d] + ntiles[d]) of 256 threads (bx x by, its own
-// tile shape), and a fixed grid of workgroups strides over the whole list, so
-// the load is balanced tile by tile whatever the mix of sizes.  The node
+// tile shape), and the workgroups of one launch share out the whole list
+// (statically by stride, one tile per workgroup, or by dynamic fetches from a
+// device counter), so the load is balanced tile by tile whatever the mix of
+// sizes.  The node
 // update is the same device function as the single-domain kernel, so each
 // domain evolves bitwise as a standalone run would.  n steps are captured
 // into one hipGraph and launched at once.
@@ -35,28 +37,68 @@ struct BatchDom {
   int tile_first;
 };
 
+// One step of the whole ensemble.  Static schedule (per_fetch = 0): workgroup
+// w takes tiles w, w + G, w + 2G, ... (G = grid size; G = ntiles is one tile
+// per workgroup).  Dynamic schedule (per_fetch = k > 0): workgroup w starts
+// with chunk w of k consecutive tiles and then takes the next chunk number
+// from a device counter, so the chunks in flight stay a contiguous window of
+// the list.  ctr[0] counts fetched chunks, ctr[1] finished workgroups; the
+// last workgroup to finish sets both back to zero, so every launch starts
+// from zero without a memset node.  Each workgroup leaves its loop once a
+// fetched chunk lies past the end of the list, so no workgroup waits on
+// another.
 template <class C, bool NT>
+__device__ __forceinline__ void batch_tile(const BatchDom *__restrict__ doms,
+                                           const int *__restrict__ tile_dom, int t, float s,
+                                           float inv_s, const typename C::T *__restrict__ src,
+                                           typename C::T *__restrict__ dst) {
+  const int d = __builtin_amdgcn_readfirstlane(tile_dom[t]);
+  const BatchDom D = doms[d];
+  const int lt = t - D.tile_first;
+  const int ty = lt / D.tiles_x, tx = lt - ty * D.tiles_x;
+  const int ly = threadIdx.x / D.bx, lx = threadIdx.x - ly * D.bx;
+  const int x = tx * D.bx + lx, y = ty * D.by + ly;
+  if (x < D.nx && y < D.ny) {
+    CollideParams P;
+    P.om_c = D.om_c;
+    P.omm_c = D.omm_c;
+    P.Gx = 0.0f;
+    P.Gy = 0.0f;
+    P.src_c = 0.0f;
+    const PlaneGeom G{D.plane, D.nx, D.ny, s, inv_s};
+    update_periodic<C, false, NT, false>(G, src + D.base, dst + D.base, x, y, P);
+  }
+}
+
+template <class C, bool NT, bool DYN>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchDom *__restrict__ doms,
                                                     const int *__restrict__ tile_dom,
-                                                    int ntiles, float s, float inv_s,
+                                                    int ntiles, int per_fetch, float s,
+                                                    float inv_s,
                                                     const typename C::T *__restrict__ src,
-                                                    typename C::T *__restrict__ dst) {
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int d = __builtin_amdgcn_readfirstlane(tile_dom[t]);
-    const BatchDom D = doms[d];
-    const int lt = t - D.tile_first;
-    const int ty = lt / D.tiles_x, tx = lt - ty * D.tiles_x;
-    const int ly = threadIdx.x / D.bx, lx = threadIdx.x - ly * D.bx;
-    const int x = tx * D.bx + lx, y = ty * D.by + ly;
-    if (x < D.nx && y < D.ny) {
-      CollideParams P;
-      P.om_c = D.om_c;
-      P.omm_c = D.omm_c;
-      P.Gx = 0.0f;
-      P.Gy = 0.0f;
-      P.src_c = 0.0f;
-      const PlaneGeom G{D.plane, D.nx, D.ny, s, inv_s};
-      update_periodic<C, false, NT, false>(G, src + D.base, dst + D.base, x, y, P);
+                                                    typename C::T *__restrict__ dst,
+                                                    int *__restrict__ ctr) {
+  if (!DYN) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+      batch_tile<C, NT>(doms, tile_dom, t, s, inv_s, src, dst);
+    return;
+  }
+  __shared__ int next[2];
+  int k = 0;
+  for (int t0 = blockIdx.x * per_fetch; t0 < ntiles;) {
+    const int t1 = min(t0 + per_fetch, ntiles);
+    for (int t = t0; t < t1; ++t) batch_tile<C, NT>(doms, tile_dom, t, s, inv_s, src, dst);
+    if (threadIdx.x == 0) next[k] = (atomicAdd(&ctr[0], 1) + (int)gridDim.x) * per_fetch;
+    __syncthreads();
+    t0 = next[k];
+    k ^= 1;  // the other slot: thread 0 may write it before slower waves read this one
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+      __threadfence();
+      atomicExch(&ctr[0], 0);
+      atomicExch(&ctr[1], 0);
     }
   }
 }
@@ -90,8 +132,10 @@ struct rrmhd_batch {
   std::vector<double> tau_f, tau_m;
   std::vector<int64_t> init_step;  // batch step at which domain d was initialised
   int ntiles = 0;
-  int grid = 0;  // persistent workgroups
+  int grid = 0;      // workgroups per launch (-1: one per tile)
+  int per_fetch = 0;  // tiles per dynamic fetch (0: static stride)
   int nt = 1;
+  int *d_ctr = nullptr;  // dynamic-schedule counters (zero between launches)
   rr::BatchDom *d_doms = nullptr;
   int *d_tile_dom = nullptr;
   void *buf[2] = {nullptr, nullptr};
@@ -135,28 +179,44 @@ static int upload_tiles(rrmhd_batch *b) {
   return RRMHD_OK;
 }
 
+template <class C, bool NT>
+static void launch_sched(const rrmhd_batch *b, dim3 grid, hipStream_t st, const void *src,
+                         void *dst) {
+  using T = typename C::T;
+  const dim3 block(256);
+  if (b->per_fetch > 0)
+    hipLaunchKernelGGL((rr::k_batch_step<C, NT, true>), grid, block, 0, st, b->d_doms,
+                       b->d_tile_dom, b->ntiles, b->per_fetch, b->s, b->inv_s,
+                       (const T *)src, (T *)dst, b->d_ctr);
+  else
+    hipLaunchKernelGGL((rr::k_batch_step<C, NT, false>), grid, block, 0, st, b->d_doms,
+                       b->d_tile_dom, b->ntiles, 0, b->s, b->inv_s, (const T *)src, (T *)dst,
+                       b->d_ctr);
+}
+
+static int launch_grid(const rrmhd_batch *b) {
+  if (b->per_fetch > 0) {
+    // never more workgroups than chunks
+    const int chunks = (b->ntiles + b->per_fetch - 1) / b->per_fetch;
+    return (b->grid < 0 || b->grid > chunks) ? chunks : b->grid;
+  }
+  return b->grid < 0 ? b->ntiles : b->grid;
+}
+
 static hipError_t launch_one(rrmhd_batch *b, hipStream_t st) {
   const void *src = b->buf[b->cur];
   void *dst = b->buf[b->cur ^ 1];
-  const dim3 grid(b->grid), block(256);
+  const dim3 grid(launch_grid(b));
   if (b->storage == RRMHD_STORE_F16) {
     if (b->nt)
-      hipLaunchKernelGGL((rr::k_batch_step<rr::CodecF16, true>), grid, block, 0, st, b->d_doms,
-                         b->d_tile_dom, b->ntiles, b->s, b->inv_s, (const uint16_t *)src,
-                         (uint16_t *)dst);
+      launch_sched<rr::CodecF16, true>(b, grid, st, src, dst);
     else
-      hipLaunchKernelGGL((rr::k_batch_step<rr::CodecF16, false>), grid, block, 0, st, b->d_doms,
-                         b->d_tile_dom, b->ntiles, b->s, b->inv_s, (const uint16_t *)src,
-                         (uint16_t *)dst);
+      launch_sched<rr::CodecF16, false>(b, grid, st, src, dst);
   } else {
     if (b->nt)
-      hipLaunchKernelGGL((rr::k_batch_step<rr::CodecF32, true>), grid, block, 0, st, b->d_doms,
-                         b->d_tile_dom, b->ntiles, b->s, b->inv_s, (const float *)src,
-                         (float *)dst);
+      launch_sched<rr::CodecF32, true>(b, grid, st, src, dst);
     else
-      hipLaunchKernelGGL((rr::k_batch_step<rr::CodecF32, false>), grid, block, 0, st, b->d_doms,
-                         b->d_tile_dom, b->ntiles, b->s, b->inv_s, (const float *)src,
-                         (float *)dst);
+      launch_sched<rr::CodecF32, false>(b, grid, st, src, dst);
   }
   return hipGetLastError();
 }
@@ -187,6 +247,7 @@ int rrmhd_batch_destroy(rrmhd_batch *b) {
     if (p) (void)hipFree(p), p = nullptr;
   if (b->d_doms) (void)hipFree(b->d_doms);
   if (b->d_tile_dom) (void)hipFree(b->d_tile_dom);
+  if (b->d_ctr) (void)hipFree(b->d_ctr);
   if (b->diag_work) (void)hipFree(b->diag_work);
   if (b->diag_out) (void)hipFree(b->diag_out);
   if (b->diag_host) (void)hipHostFree(b->diag_host);
@@ -249,6 +310,8 @@ int rrmhd_batch_create(int n, const rrmhd_grid *grids, const double *tau_f,
   chk(hipMalloc((void **)&b->diag_out, 8 * sizeof(double)), "hipMalloc(diag)");
   chk(hipHostMalloc((void **)&b->diag_host, 8 * sizeof(double), hipHostMallocDefault),
       "hipHostMalloc(diag)");
+  chk(hipMalloc((void **)&b->d_ctr, 2 * sizeof(int)), "hipMalloc(counters)");
+  if (rc == RRMHD_OK) chk(hipMemset(b->d_ctr, 0, 2 * sizeof(int)), "hipMemset(counters)");
   chk(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking), "hipStreamCreate");
   chk(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "hipEventCreate");
   chk(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "hipEventCreate");
@@ -280,7 +343,7 @@ int rrmhd_batch_init(rrmhd_batch *b, int d, const double *u, const double *bf) {
 int rrmhd_batch_set_shape(rrmhd_batch *b, int d, int bx, int grid, int nt) {
   if (!b || d < -1 || d >= b->n) return RRMHD_EINVAL;
   if (bx != 0 && (bx < 1 || bx > 256 || 256 % bx != 0)) return RRMHD_EINVAL;
-  if (grid < 0) return RRMHD_EINVAL;
+  if (grid < -1) return RRMHD_EINVAL;
   if (bx) {
     for (int k = (d < 0 ? 0 : d); k < (d < 0 ? b->n : d + 1); ++k) {
       b->doms[k].bx = bx;
@@ -290,6 +353,13 @@ int rrmhd_batch_set_shape(rrmhd_batch *b, int d, int bx, int grid, int nt) {
   if (grid) b->grid = grid;
   if (nt >= 0) b->nt = nt ? 1 : 0;
   return upload_tiles(b);
+}
+
+int rrmhd_batch_set_fetch(rrmhd_batch *b, int tiles_per_fetch) {
+  if (!b || tiles_per_fetch < 0 || tiles_per_fetch > 64) return RRMHD_EINVAL;
+  b->per_fetch = tiles_per_fetch;
+  free_graphs(b);
+  return RRMHD_OK;
 }
 
 static int plain_steps(rrmhd_batch *b, int64_t n, hipStream_t st) {
@@ -384,7 +454,7 @@ int rrmhd_batch_info(const rrmhd_batch *b, int64_t *nodes, int64_t *steps, int *
   if (nodes) *nodes = s;
   if (steps) *steps = b->steps;
   if (ntiles) *ntiles = b->ntiles;
-  if (grid) *grid = b->grid;
+  if (grid) *grid = launch_grid(b);
   return RRMHD_OK;
 }
 

@@ -20,11 +20,11 @@ struct Shape {
 };
 
 struct Entry {
-  int bx = 0, by = 0, xcd = 0, grid = 0;
+  int bx = 0, by = 0, xcd = 0, grid = 0, fetch = 0;
   double ms = 0.0;
 };
 
-// ---- cache file: {"key": {"bx": 128, "by": 2, "xcd": 2, "grid": 0, "ms": 1.7}, ...}
+// ---- cache file: {"key": {"bx": 128, "by": 2, "xcd": 2, "grid": 0, "fetch": 0, "ms": 1.7}, ...}
 std::map<std::string, Entry> read_cache(const char *path) {
   std::map<std::string, Entry> m;
   if (!path) return m;
@@ -54,17 +54,19 @@ std::map<std::string, Entry> read_cache(const char *path) {
       if (t == std::string::npos) return;
       *out = std::strtod(body.c_str() + t + 1, nullptr);
     };
-    double v[5] = {0, 0, 0, 0, 0};
+    double v[6] = {0, 0, 0, 0, 0, 0};
     num("bx", &v[0]);
     num("by", &v[1]);
     num("xcd", &v[2]);
     num("grid", &v[3]);
     num("ms", &v[4]);
+    num("fetch", &v[5]);
     e.bx = (int)v[0];
     e.by = (int)v[1];
     e.xcd = (int)v[2];
     e.grid = (int)v[3];
     e.ms = v[4];
+    e.fetch = (int)v[5];
     if (e.bx > 0 && e.by > 0) m[key] = e;
     p = cb + 1;
   }
@@ -79,9 +81,11 @@ void write_cache(const char *path, const std::map<std::string, Entry> &m) {
   std::fprintf(f, "{\n");
   size_t i = 0;
   for (const auto &kv : m) {
-    std::fprintf(f, "  \"%s\": {\"bx\": %d, \"by\": %d, \"xcd\": %d, \"grid\": %d, \"ms\": %.6f}%s\n",
+    std::fprintf(f,
+                 "  \"%s\": {\"bx\": %d, \"by\": %d, \"xcd\": %d, \"grid\": %d, \"fetch\": %d, "
+                 "\"ms\": %.6f}%s\n",
                  kv.first.c_str(), kv.second.bx, kv.second.by, kv.second.xcd, kv.second.grid,
-                 kv.second.ms, (++i < m.size()) ? "," : "");
+                 kv.second.fetch, kv.second.ms, (++i < m.size()) ? "," : "");
   }
   std::fprintf(f, "}\n");
   std::fclose(f);
@@ -264,25 +268,30 @@ int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials) {
     rc = rrmhd_batch_set_shape(b, d, width[std::make_pair(nxs[d], nys[d])], 0, -1);
     if (rc != RRMHD_OK) return rc;
   }
-  // 2) persistent grid size, timed on the ensemble itself (state preserved)
+  // 2) work distribution, timed on the ensemble itself (state preserved):
+  // static stride over 2..16 workgroups per CU, one workgroup per tile, and
+  // dynamic fetches of 1 or 4 tiles by 4 or 8 persistent workgroups per CU
   char kb[64];
   std::snprintf(kb, sizeof kb, "batch%d_%lld", n, (long long)nodes);
   const std::string gkey = key_of(kb, 0, 0, storage);
   auto git = cache.find(gkey);
-  int best_grid = grid0;
-  if (git != cache.end() && git->second.grid > 0) {
+  int best_grid = grid0, best_fetch = 0;
+  if (git != cache.end() && git->second.grid != 0) {
     best_grid = git->second.grid;
+    best_fetch = git->second.fetch;
   } else {
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const std::pair<int, int> cand[] = {{2 * cus, 0}, {4 * cus, 0}, {8 * cus, 0}, {16 * cus, 0},
+                                        {-1, 0},      {4 * cus, 1}, {8 * cus, 1}, {8 * cus, 4}};
     void *save = nullptr;
     rc = rr_batch_save(b, &save);
     if (rc != RRMHD_OK) return rc;
     double best_ms = 1e30;
-    const int mult[] = {2, 4, 8, 16};
-    for (int m : mult) {
-      rc = rrmhd_batch_set_shape(b, -1, 0, cus * m, -1);
+    for (const auto &c : cand) {
+      rc = rrmhd_batch_set_shape(b, -1, 0, c.first, -1);
+      if (rc == RRMHD_OK) rc = rrmhd_batch_set_fetch(b, c.second);
       if (rc != RRMHD_OK) break;
       double ms = 0.0;
       rc = time_steps([&](int k) { return rrmhd_batch_step(b, k); },
@@ -290,7 +299,8 @@ int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials) {
       if (rc != RRMHD_OK) break;
       if (ms < best_ms) {
         best_ms = ms;
-        best_grid = cus * m;
+        best_grid = c.first;
+        best_fetch = c.second;
       }
     }
     int rc2 = rr_batch_restore(b, save, steps0);
@@ -300,11 +310,14 @@ int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials) {
     e.bx = 1;
     e.by = 1;
     e.grid = best_grid;
+    e.fetch = best_fetch;
     e.ms = best_ms;
     cache[gkey] = e;
   }
   write_cache(cache_path, cache);
-  return rrmhd_batch_set_shape(b, -1, 0, best_grid, -1);
+  rc = rrmhd_batch_set_shape(b, -1, 0, best_grid, -1);
+  if (rc != RRMHD_OK) return rc;
+  return rrmhd_batch_set_fetch(b, best_fetch);
 }
 
 }  // extern "C"

@@ -24,7 +24,7 @@ EXPORTED = [
     "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
     "rrmhd_batch_create", "rrmhd_batch_init", "rrmhd_batch_step",
-    "rrmhd_batch_set_graph_chunk", "rrmhd_batch_set_shape",
+    "rrmhd_batch_set_graph_chunk", "rrmhd_batch_set_shape", "rrmhd_batch_set_fetch",
     "rrmhd_batch_moments", "rrmhd_batch_diagnostics", "rrmhd_batch_info",
     "rrmhd_batch_destroy", "rrmhd_batch_last_error_detail",
     "rrmhd_autotune", "rrmhd_batch_autotune",
@@ -95,6 +95,7 @@ def lib():
         L.rrmhd_batch_step.argtypes = [vp, i64]
         L.rrmhd_batch_set_graph_chunk.argtypes = [vp, ci]
         L.rrmhd_batch_set_shape.argtypes = [vp, ci, ci, ci, ci]
+        L.rrmhd_batch_set_fetch.argtypes = [vp, ci]
         L.rrmhd_batch_moments.argtypes = [vp, ci, dp, dp, dp]
         L.rrmhd_batch_diagnostics.argtypes = [vp, ci, dbl, dbl, dbl]
         L.rrmhd_batch_info.argtypes = [vp, ctypes.POINTER(i64),
@@ -397,6 +398,10 @@ class Batch:
         self._chk(lib().rrmhd_batch_set_shape(self._h, int(d), int(bx),
                                               int(grid), int(nt)),
                   "rrmhd_batch_set_shape")
+
+    def set_fetch(self, tiles_per_fetch):
+        self._chk(lib().rrmhd_batch_set_fetch(self._h, int(tiles_per_fetch)),
+                  "rrmhd_batch_set_fetch")
 
     def moments(self, d):
         import torch

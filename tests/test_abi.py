@@ -79,3 +79,6 @@ def test_null_handle_calls_are_rejected():
     assert L.rrmhd_step(None, 1) == rrmhd.EINVAL
     assert L.rrmhd_init(None, None, None) == rrmhd.EINVAL
     assert L.rrmhd_destroy(None) == rrmhd.OK
+    assert L.rrmhd_batch_set_fetch(None, 1) == rrmhd.EINVAL
+    assert L.rrmhd_batch_set_shape(None, -1, 0, 0, -1) == rrmhd.EINVAL
+    assert L.rrmhd_batch_step(None, 1) == rrmhd.EINVAL

@@ -73,16 +73,22 @@ def test_batch_graph_and_tile_shape_bitwise():
     a.step(30)
     ref = [moments_np(a.moments(d)) for d in range(len(SHAPES))]
     a.close()
-    for chunk, bx, grid in ((10, 0, 0), (4, 32, 0), (7, 256, 300), (0, 64, 17)):
+    # (graph chunk, tile width, workgroups, tiles per dynamic fetch); the
+    # dynamic cases run many launches in a row (the counters must return to
+    # zero after each) inside and outside captured graphs
+    for chunk, bx, grid, fetch in ((10, 0, 0, 0), (4, 32, 0, 0), (7, 256, 300, 0),
+                                   (0, 64, 17, 0), (0, 0, -1, 0), (10, 0, 64, 1),
+                                   (7, 32, 5, 4), (0, 128, -1, 3), (4, 64, 2048, 1)):
         b = make_batch()
         b.set_shape(-1, bx=bx, grid=grid)
+        b.set_fetch(fetch)
         b.set_graph_chunk(chunk)
         b.step(13)
         b.step(17)
         for d in range(len(SHAPES)):
             got = moments_np(b.moments(d))
             for g, r in zip(got, ref[d]):
-                assert np.array_equal(g, r), (chunk, bx, grid, d)
+                assert np.array_equal(g, r), (chunk, bx, grid, fetch, d)
         assert b.info()["steps"] == 30
         b.close()
 
