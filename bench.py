@@ -170,7 +170,7 @@ def batch_bench(torch, rrmhd, inputs, args):
         "config": {"workload": "256 periodic domains, sides 64..1024, "
                                "OT or turbulence, tau in [0.501, 0.6]",
                    "nodes": nodes, "tiles": info["tiles"],
-                   "persistent_workgroups": info["grid"],
+                   "workgroups_per_launch": info["grid"],
                    "graph_chunk": chunk, "autotune_s": round(tune_s, 2)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -184,11 +184,11 @@ def closure_bench(args):
     network) against the 4x4-filtered 2048^2 run."""
     from paper_2602_14667_amd import closure_pipeline as cp
     if args.closure_scale == "full":
-        kw = dict(n_f=2048, factor=4, tau_f=0.54, fine_steps=64000, snaps=8,
+        kw = dict(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
                   train_seeds=range(16), test_seeds=range(20, 24),
                   train_steps=3000, batch=65536)
     else:
-        kw = dict(n_f=1024, factor=4, tau_f=0.54, fine_steps=16000, snaps=4,
+        kw = dict(n_f=1024, factor=4, tau_f=0.56, fine_steps=16000, snaps=4,
                   train_seeds=range(4), test_seeds=[20], train_steps=1000,
                   batch=65536)
     res = cp.pipeline(log=lambda m: print(m, file=sys.stderr, flush=True), **kw)

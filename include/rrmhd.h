@@ -168,10 +168,11 @@ int rrmhd_batch_set_graph_chunk(rrmhd_batch *b, int chunk);
  * it).  Results do not depend on these (bitwise). */
 int rrmhd_batch_set_shape(rrmhd_batch *b, int d, int bx, int grid, int nt);
 /* Work distribution inside a launch: 0 (default) = static, workgroup w
- * takes tiles w, w + grid, ...; k in 1..64 = dynamic, each workgroup takes
- * its next k consecutive tiles from a device counter (persistent workgroups
- * that keep the tiles in flight contiguous).  Results do not depend on it
- * (bitwise).  EINVAL outside 0..64. */
+ * takes tiles w, w + grid, ...; k in 1..64 = dynamic: the tile list is cut
+ * into 8 contiguous segments, one per XCD, and each workgroup takes its next
+ * k consecutive tiles of its segment from that segment's device counter
+ * (persistent workgroups; the counters return to zero at the end of every
+ * launch).  Results do not depend on it (bitwise).  EINVAL outside 0..64. */
 int rrmhd_batch_set_fetch(rrmhd_batch *b, int tiles_per_fetch);
 int rrmhd_batch_moments(rrmhd_batch *b, int d, double *rho, double *u,
                         double *bf);

@@ -39,14 +39,19 @@ struct BatchDom {
 
 // One step of the whole ensemble.  Static schedule (per_fetch = 0): workgroup
 // w takes tiles w, w + G, w + 2G, ... (G = grid size; G = ntiles is one tile
-// per workgroup).  Dynamic schedule (per_fetch = k > 0): workgroup w starts
-// with chunk w of k consecutive tiles and then takes the next chunk number
-// from a device counter, so the chunks in flight stay a contiguous window of
-// the list.  ctr[0] counts fetched chunks, ctr[1] finished workgroups; the
-// last workgroup to finish sets both back to zero, so every launch starts
-// from zero without a memset node.  Each workgroup leaves its loop once a
-// fetched chunk lies past the end of the list, so no workgroup waits on
-// another.
+// per workgroup).  Dynamic schedule (per_fetch = k > 0): the list is cut into
+// kSeg contiguous segments, one per XCD (workgroups are dispatched to the
+// XCDs round-robin, so workgroup w runs on XCD w % kSeg); a workgroup starts
+// with its own first chunk of k tiles of its segment and then takes chunk
+// numbers from the segment's device counter, so each XCD works through a
+// contiguous window of its segment and the counters are not shared across
+// XCDs.  Per segment, ctr[kCtrStride s] counts fetched chunks and
+// ctr[kCtrStride s + 1] finished workgroups; the segment's last workgroup to
+// finish sets both back to zero, so every launch starts from zero without a
+// memset node.  A workgroup leaves its loop once a fetched chunk lies past
+// its segment, so no workgroup waits on another.
+constexpr int kSeg = 8, kCtrStride = 64;  // counters 256 B apart
+
 template <class C, bool NT>
 __device__ __forceinline__ void batch_tile(const BatchDom *__restrict__ doms,
                                            const int *__restrict__ tile_dom, int t, float s,
@@ -84,21 +89,27 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchDom *__restrict__
     return;
   }
   __shared__ int next[2];
+  const int seg = blockIdx.x % kSeg;
+  const int wl = blockIdx.x / kSeg;
+  const int nwg = ((int)gridDim.x - seg + kSeg - 1) / kSeg;  // workgroups of this segment
+  const int lo = (int)((int64_t)ntiles * seg / kSeg);
+  const int hi = (int)((int64_t)ntiles * (seg + 1) / kSeg);
+  int *c = ctr + kCtrStride * seg;
   int k = 0;
-  for (int t0 = blockIdx.x * per_fetch; t0 < ntiles;) {
-    const int t1 = min(t0 + per_fetch, ntiles);
+  for (int t0 = lo + wl * per_fetch; t0 < hi;) {
+    const int t1 = min(t0 + per_fetch, hi);
     for (int t = t0; t < t1; ++t) batch_tile<C, NT>(doms, tile_dom, t, s, inv_s, src, dst);
-    if (threadIdx.x == 0) next[k] = (atomicAdd(&ctr[0], 1) + (int)gridDim.x) * per_fetch;
+    if (threadIdx.x == 0) next[k] = lo + (atomicAdd(&c[0], 1) + nwg) * per_fetch;
     __syncthreads();
     t0 = next[k];
     k ^= 1;  // the other slot: thread 0 may write it before slower waves read this one
   }
   if (threadIdx.x == 0) {
     __threadfence();
-    if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+    if (atomicAdd(&c[1], 1) == nwg - 1) {
       __threadfence();
-      atomicExch(&ctr[0], 0);
-      atomicExch(&ctr[1], 0);
+      atomicExch(&c[0], 0);
+      atomicExch(&c[1], 0);
     }
   }
 }
@@ -196,9 +207,10 @@ static void launch_sched(const rrmhd_batch *b, dim3 grid, hipStream_t st, const 
 
 static int launch_grid(const rrmhd_batch *b) {
   if (b->per_fetch > 0) {
-    // never more workgroups than chunks
-    const int chunks = (b->ntiles + b->per_fetch - 1) / b->per_fetch;
-    return (b->grid < 0 || b->grid > chunks) ? chunks : b->grid;
+    // at least one workgroup per segment; never more than the chunks need
+    const int chunks = (b->ntiles + b->per_fetch - 1) / b->per_fetch + rr::kSeg;
+    int g = (b->grid < 0 || b->grid > chunks) ? chunks : b->grid;
+    return g < rr::kSeg ? rr::kSeg : g;
   }
   return b->grid < 0 ? b->ntiles : b->grid;
 }
@@ -295,7 +307,10 @@ int rrmhd_batch_create(int n, const rrmhd_grid *grids, const double *tau_f,
     off += D.plane * rr::kStatePlanes;
     D.om_c = (float)(1.0 - 1.0 / tau_f[d]);
     D.omm_c = (float)(1.0 - 1.0 / tau_m[d]);
-    D.bx = D.nx >= 256 ? (b->elem == 2 ? 256 : 128) : (D.nx >= 128 ? 128 : 64);
+    // 32 x 8 tiles, one workgroup per tile: the fastest measured default on
+    // the uneven 64..1024 mix (hardware dispatch keeps the tiles in flight a
+    // contiguous window of the list)
+    D.bx = 32;
     D.by = 256 / D.bx;
     rr::Domain dd = domain_of(b, d);
     diag = std::max(diag, rr::diag_work_bytes(dd));
@@ -310,18 +325,13 @@ int rrmhd_batch_create(int n, const rrmhd_grid *grids, const double *tau_f,
   chk(hipMalloc((void **)&b->diag_out, 8 * sizeof(double)), "hipMalloc(diag)");
   chk(hipHostMalloc((void **)&b->diag_host, 8 * sizeof(double), hipHostMallocDefault),
       "hipHostMalloc(diag)");
-  chk(hipMalloc((void **)&b->d_ctr, 2 * sizeof(int)), "hipMalloc(counters)");
-  if (rc == RRMHD_OK) chk(hipMemset(b->d_ctr, 0, 2 * sizeof(int)), "hipMemset(counters)");
+  const size_t ctr_bytes = sizeof(int) * rr::kSeg * rr::kCtrStride;
+  chk(hipMalloc((void **)&b->d_ctr, ctr_bytes), "hipMalloc(counters)");
+  if (rc == RRMHD_OK) chk(hipMemset(b->d_ctr, 0, ctr_bytes), "hipMemset(counters)");
   chk(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking), "hipStreamCreate");
   chk(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "hipEventCreate");
   chk(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "hipEventCreate");
-  if (rc == RRMHD_OK) {
-    int dev = 0, cus = 0;
-    chk(hipGetDevice(&dev), "hipGetDevice");
-    chk(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
-        "hipDeviceGetAttribute");
-    b->grid = (cus > 0 ? cus : 256) * 8;
-  }
+  b->grid = -1;  // one workgroup per tile
   if (rc == RRMHD_OK) rc = upload_tiles(b);
   if (rc != RRMHD_OK) {
     rrmhd_batch_destroy(b);

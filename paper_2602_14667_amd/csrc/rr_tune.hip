@@ -314,10 +314,53 @@ int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials) {
     e.ms = best_ms;
     cache[gkey] = e;
   }
-  write_cache(cache_path, cache);
   rc = rrmhd_batch_set_shape(b, -1, 0, best_grid, -1);
+  if (rc == RRMHD_OK) rc = rrmhd_batch_set_fetch(b, best_fetch);
   if (rc != RRMHD_OK) return rc;
-  return rrmhd_batch_set_fetch(b, best_fetch);
+  // 3) the per-size widths of step 1 were timed on standalone grids; compare
+  // them, on the ensemble with the chosen distribution, against one width for
+  // every domain (state preserved)
+  const std::string ukey = key_of(kb, 1, 0, storage);
+  auto uit = cache.find(ukey);
+  int uniform = 0;
+  if (uit != cache.end()) {
+    uniform = uit->second.bx > 1 ? uit->second.bx : 0;
+  } else {
+    void *save = nullptr;
+    rc = rr_batch_save(b, &save);
+    if (rc != RRMHD_OK) return rc;
+    double best_ms = 0.0;
+    rc = time_steps([&](int k) { return rrmhd_batch_step(b, k); }, rr_batch_stream(b), trials,
+                    &best_ms);
+    const int widths[] = {32, 64};
+    for (int w : widths) {
+      if (rc != RRMHD_OK) break;
+      rc = rrmhd_batch_set_shape(b, -1, w, 0, -1);
+      double ms = 0.0;
+      if (rc == RRMHD_OK)
+        rc = time_steps([&](int k) { return rrmhd_batch_step(b, k); }, rr_batch_stream(b),
+                        trials, &ms);
+      if (rc == RRMHD_OK && ms < best_ms) {
+        best_ms = ms;
+        uniform = w;
+      }
+    }
+    int rc2 = rr_batch_restore(b, save, steps0);
+    if (rc == RRMHD_OK) rc = rc2;
+    if (rc != RRMHD_OK) return rc;
+    Entry e;
+    e.bx = uniform > 0 ? uniform : 1;  // 1: keep the per-size widths
+    e.by = 1;
+    e.ms = best_ms;
+    cache[ukey] = e;
+  }
+  write_cache(cache_path, cache);
+  for (int d = 0; d < n; ++d) {
+    rc = rrmhd_batch_set_shape(b, d, uniform > 0 ? uniform : width[std::make_pair(nxs[d], nys[d])],
+                               0, -1);
+    if (rc != RRMHD_OK) return rc;
+  }
+  return RRMHD_OK;
 }
 
 }  // extern "C"
