@@ -86,6 +86,13 @@ def lib():
                                     ctypes.c_int]
         L.orc_train_samples.argtypes = [_dp, _dp, _dp, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.orc_mlp_vjp.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_onestep_objective.restype = ctypes.c_double
+        L.orc_onestep_objective.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp,
+                                            ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.orc_onestep_adjoint.argtypes = [_dp, ctypes.c_int, ctypes.c_double,
+                                          _dp, _dp]
         _lib = L
     return _lib
 
@@ -198,6 +205,60 @@ def train_samples(rho, u, b, factor, tau_c):
     lib().orc_train_samples(_ptr(rho), _ptr(u), _ptr(b), nf, int(factor),
                             float(tau_c), _ptr(x), _ptr(t))
     return x, t
+
+
+def mlp_vjp(params, norm, x, dy):
+    """Gradient of sum_s dy[s] . y(x_s) with respect to the parameters."""
+    params, norm, x, dy = _f64(params), _f64(norm), _f64(x), _f64(dy)
+    g = np.zeros(NPARAM)
+    lib().orc_mlp_vjp(_ptr(params), _ptr(norm), _ptr(x), _ptr(dy), x.shape[0],
+                      _ptr(g))
+    return g
+
+
+def onestep_objective(m0, m1, factor, tau_c, delta=None):
+    """One-step solver-in-the-loop objective of the closure.
+
+    m0, m1: fine moments (rho, u, b) at t and t + factor.  delta: [Nc][3]
+    correction of a_1^(2) per coarse node (None: zero).  Returns (L, resid
+    [Nc][2], x [Nc][8] restart features, den)."""
+    rho0, u0, b0 = map(_f64, m0)
+    rho1, u1, b1 = map(_f64, m1)
+    nf = rho0.shape[0]
+    nc = nf // factor
+    resid = np.zeros((nc * nc, 2))
+    x = np.zeros((nc * nc, 8))
+    den = np.zeros(1)
+    d = None if delta is None else _f64(delta)
+    if d is not None:
+        assert d.shape == (nc * nc, 3)
+    L = lib().orc_onestep_objective(_ptr(rho0), _ptr(u0), _ptr(b0), _ptr(rho1),
+                                    _ptr(u1), _ptr(b1), nf, int(factor),
+                                    float(tau_c), _ptr(d), _ptr(resid), _ptr(x),
+                                    _ptr(den))
+    return float(L), resid, x, float(den[0])
+
+
+def onestep_adjoint(x, nc, tau_c, w):
+    """Transpose of the linear map delta -> coarse momentum, applied to w[Nc][2]."""
+    x, w = _f64(x), _f64(w)
+    out = np.zeros((nc * nc, 3))
+    lib().orc_onestep_adjoint(_ptr(x), int(nc), float(tau_c), _ptr(w), _ptr(out))
+    return out
+
+
+def onestep_loss_grad(params, norm, m0, m1, factor, tau_c):
+    """(L, dL/dparams) of the one-step objective with delta = sigma_out * y(x),
+    x the restart features: MLP forward, the objective, its adjoint, MLP
+    reverse mode."""
+    params, norm = _f64(params), _f64(norm)
+    nc = np.asarray(m0[0]).shape[0] // factor
+    _, _, x, _ = onestep_objective(m0, m1, factor, tau_c)
+    so = norm[16:19]
+    delta = mlp_forward(params, norm, x) * so
+    L, resid, _, den = onestep_objective(m0, m1, factor, tau_c, delta)
+    g_delta = onestep_adjoint(x, nc, tau_c, resid) * (2.0 / den)
+    return L, mlp_vjp(params, norm, x, g_delta * so)
 
 
 class Oracle:

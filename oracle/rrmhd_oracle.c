@@ -255,19 +255,58 @@ static void closure_apply(const closure *c, double rho, const double u[2],
 
 static void collide_node_c(const double *f, const double *g, double omega,
                            double omega_m, const double G[2], int feq_option,
-                           const closure *cl, double *fs, double *gs,
-                           node_aux *ax);
+                           const closure *cl, const double *dnode, double *fs,
+                           double *gs, node_aux *ax);
 
 static void collide_node(const double *f, const double *g, double omega,
                          double omega_m, const double G[2], int feq_option,
                          double *fs, double *gs, node_aux *ax) {
-  collide_node_c(f, g, omega, omega_m, G, feq_option, NULL, fs, gs, ax);
+  collide_node_c(f, g, omega, omega_m, G, feq_option, NULL, NULL, fs, gs, ax);
+}
+
+/* Tasks 3 (recursion) and 4 without the weight: r[i] such that the
+ * regularised non-equilibrium population is w_i r[i], from the velocity and
+ * a_1^(2); a3, a4 receive the recursive coefficients.  Only the
+ * D2Q9-supported index sets enter the sums. */
+static void reg_expand(const double u[2], const double a2[2][2],
+                       double a3[2][2][2], double a4[2][2][2][2], double r[9]) {
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c)
+      for (int g3 = 0; g3 < 2; ++g3)
+        a3[a][c][g3] = u[a] * a2[c][g3] + u[c] * a2[a][g3] + u[g3] * a2[a][c];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c)
+      for (int g3 = 0; g3 < 2; ++g3)
+        for (int d = 0; d < 2; ++d)
+          a4[a][c][g3][d] =
+              u[a] * a3[c][g3][d] + u[c] * a3[a][g3][d] + u[g3] * a3[a][c][d] +
+              u[d] * a3[a][c][g3] -
+              (u[a] * u[c] * a2[g3][d] + u[a] * u[g3] * a2[c][d] +
+               u[a] * u[d] * a2[c][g3] + u[c] * u[g3] * a2[a][d] +
+               u[c] * u[d] * a2[a][g3] + u[g3] * u[d] * a2[a][c]);
+  for (int i = 0; i < 9; ++i) {
+    double s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 2; ++c) {
+        s2 += a2[a][c] * H2T[i][a][c];
+        for (int g3 = 0; g3 < 2; ++g3) {
+          int i3[3] = {a, c, g3};
+          if (supported(3, i3)) s3 += a3[a][c][g3] * H3T[i][a][c][g3];
+          for (int d = 0; d < 2; ++d) {
+            int i4[4] = {a, c, g3, d};
+            if (supported(4, i4)) s4 += a4[a][c][g3][d] * H4T[i][a][c][g3][d];
+          }
+        }
+      }
+    r[i] = s2 / (2.0 * CS2 * CS2) + s3 / (6.0 * CS2 * CS2 * CS2) +
+           s4 / (24.0 * CS2 * CS2 * CS2 * CS2);
+  }
 }
 
 static void collide_node_c(const double *f, const double *g, double omega,
                            double omega_m, const double G[2], int feq_option,
-                           const closure *cl, double *fs, double *gs,
-                           node_aux *ax) {
+                           const closure *cl, const double *dnode, double *fs,
+                           double *gs, node_aux *ax) {
   node_aux local;
   node_aux *A = ax ? ax : &local;
   /* task 1: macroscopic variables */
@@ -302,40 +341,20 @@ static void collide_node_c(const double *f, const double *g, double omega,
     }
   }
   if (cl) closure_apply(cl, rho, u, b, a2);
-  double a3[2][2][2], a4[2][2][2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c)
-      for (int g3 = 0; g3 < 2; ++g3)
-        a3[a][c][g3] = u[a] * a2[c][g3] + u[c] * a2[a][g3] + u[g3] * a2[a][c];
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c)
-      for (int g3 = 0; g3 < 2; ++g3)
-        for (int d = 0; d < 2; ++d)
-          a4[a][c][g3][d] =
-              u[a] * a3[c][g3][d] + u[c] * a3[a][g3][d] + u[g3] * a3[a][c][d] +
-              u[d] * a3[a][c][g3] -
-              (u[a] * u[c] * a2[g3][d] + u[a] * u[g3] * a2[c][d] +
-               u[a] * u[d] * a2[c][g3] + u[c] * u[g3] * a2[a][d] +
-               u[c] * u[d] * a2[a][g3] + u[g3] * u[d] * a2[a][c]);
+  if (dnode) {
+    /* a prescribed correction (dxx, dxy, dyy) of this node */
+    a2[0][0] += dnode[0];
+    a2[0][1] += dnode[1];
+    a2[1][0] += dnode[1];
+    a2[1][1] += dnode[2];
+  }
+  double a3[2][2][2], a4[2][2][2][2], rr[9];
+  reg_expand(u, (const double(*)[2])a2, a3, a4, rr);
 
   /* task 4: regularised non-equilibrium populations (Eq. fineq_reg) */
   double fneq[9];
   for (int i = 0; i < 9; ++i) {
-    double s2 = 0.0, s3 = 0.0, s4 = 0.0;
-    for (int a = 0; a < 2; ++a)
-      for (int c = 0; c < 2; ++c) {
-        s2 += a2[a][c] * H2T[i][a][c];
-        for (int g3 = 0; g3 < 2; ++g3) {
-          int i3[3] = {a, c, g3};
-          if (supported(3, i3)) s3 += a3[a][c][g3] * H3T[i][a][c][g3];
-          for (int d = 0; d < 2; ++d) {
-            int i4[4] = {a, c, g3, d};
-            if (supported(4, i4)) s4 += a4[a][c][g3][d] * H4T[i][a][c][g3][d];
-          }
-        }
-      }
-    double r = s2 / (2.0 * CS2 * CS2) + s3 / (6.0 * CS2 * CS2 * CS2) +
-               s4 / (24.0 * CS2 * CS2 * CS2 * CS2);
+    double r = rr[i];
     /* forcing reading: the first-order term of the series, which vanishes
      * without a force, is kept when a force acts */
     if (forced) r += (CI[i][0] * a1[0] + CI[i][1] * a1[1]) / CS2;
@@ -384,6 +403,7 @@ typedef struct orc {
   double bwall[2]; /* wall magnetic field for the anti-bounce-back */
   int feq_option;
   closure *cl;    /* NULL: plain method */
+  const double *delta; /* NULL, or a prescribed a_1^(2) correction [ny][nx][3] */
   long step;
   double *f, *g;       /* f[i][y][x], g[j][c][y][x]: pre-collision state */
   double *fn, *gn;     /* scratch for the next state */
@@ -471,8 +491,9 @@ static void one_step(orc *h) {
       for (int i = 0; i < 9; ++i) f[i] = h->f[FIDX(h, i, y, x)];
       for (int j = 0; j < 5; ++j)
         for (int c = 0; c < 2; ++c) g[2 * j + c] = h->g[GIDX(h, j, c, y, x)];
-      collide_node_c(f, g, omega, omega_m, h->G, h->feq_option, h->cl, fs, gs,
-                     NULL);
+      const double *dn = h->delta ? h->delta + 3 * ((size_t)y * nx + x) : NULL;
+      collide_node_c(f, g, omega, omega_m, h->G, h->feq_option, h->cl, dn, fs,
+                     gs, NULL);
       for (int i = 0; i < 9; ++i) {
         int ty = y + CI[i][1];
         int tx = wrap(x + CI[i][0], nx);
@@ -804,48 +825,64 @@ void orc_mlp_forward(const double *params, const double *norm, const double *x,
   }
 }
 
+/* Reverse mode through one forward pass: adds d(dy . y)/d(params) to grad. */
+static void mlp_backprop(const double *p, const mlp_cache *m, const double dy[NOUT],
+                         double *grad) {
+  double dz2[NH], dz1[NH];
+  for (int o = 0; o < NOUT; ++o) {
+    grad[OFF_B3 + o] += dy[o];
+    for (int k = 0; k < NH; ++k) grad[OFF_W3 + o * NH + k] += dy[o] * m->h2[k];
+  }
+  for (int k = 0; k < NH; ++k) {
+    double sacc = 0.0;
+    for (int o = 0; o < NOUT; ++o) sacc += p[OFF_W3 + o * NH + k] * dy[o];
+    dz2[k] = sacc * gelu_grad(m->z2[k]);
+    grad[OFF_B2 + k] += dz2[k];
+  }
+  for (int i = 0; i < NH; ++i)
+    for (int k = 0; k < NH; ++k) grad[OFF_W2 + i * NH + k] += dz2[i] * m->h1[k];
+  for (int k = 0; k < NH; ++k) {
+    double sacc = 0.0;
+    for (int i = 0; i < NH; ++i) sacc += p[OFF_W2 + i * NH + k] * dz2[i];
+    dz1[k] = sacc * gelu_grad(m->z1[k]);
+    grad[OFF_B1 + k] += dz1[k];
+  }
+  for (int i = 0; i < NH; ++i)
+    for (int k = 0; k < NIN; ++k) grad[OFF_W1 + i * NIN + k] += dz1[i] * m->xh[k];
+}
+
 /* Mean squared error L = (1/n) sum_s sum_o (y_o(x_s) - t_so)^2 and its
  * gradient with respect to every parameter, by reverse-mode
  * differentiation of the forward pass. */
 double orc_mlp_loss_grad(const double *params, const double *norm,
                          const double *x, const double *t, int n,
                          double *grad) {
-  const double *p = params;
   memset(grad, 0, sizeof(double) * NPARAM);
   double loss = 0.0;
   for (int s = 0; s < n; ++s) {
     mlp_cache m;
-    mlp_forward(p, norm, x + (size_t)s * NIN, &m);
-    double dy[NOUT], dh2[NH], dz2[NH], dh1[NH], dz1[NH];
+    mlp_forward(params, norm, x + (size_t)s * NIN, &m);
+    double dy[NOUT];
     for (int o = 0; o < NOUT; ++o) {
       const double r = m.y[o] - t[(size_t)s * NOUT + o];
       loss += r * r;
       dy[o] = 2.0 * r / n;
-      grad[OFF_B3 + o] += dy[o];
-      for (int k = 0; k < NH; ++k) grad[OFF_W3 + o * NH + k] += dy[o] * m.h2[k];
     }
-    for (int k = 0; k < NH; ++k) {
-      double sacc = 0.0;
-      for (int o = 0; o < NOUT; ++o) sacc += p[OFF_W3 + o * NH + k] * dy[o];
-      dh2[k] = sacc;
-      dz2[k] = sacc * gelu_grad(m.z2[k]);
-      grad[OFF_B2 + k] += dz2[k];
-    }
-    for (int i = 0; i < NH; ++i)
-      for (int k = 0; k < NH; ++k) grad[OFF_W2 + i * NH + k] += dz2[i] * m.h1[k];
-    for (int k = 0; k < NH; ++k) {
-      double sacc = 0.0;
-      for (int i = 0; i < NH; ++i) sacc += p[OFF_W2 + i * NH + k] * dz2[i];
-      dh1[k] = sacc;
-      dz1[k] = sacc * gelu_grad(m.z1[k]);
-      grad[OFF_B1 + k] += dz1[k];
-    }
-    for (int i = 0; i < NH; ++i)
-      for (int k = 0; k < NIN; ++k) grad[OFF_W1 + i * NIN + k] += dz1[i] * m.xh[k];
-    (void)dh2;
-    (void)dh1;
+    mlp_backprop(params, &m, dy, grad);
   }
   return loss / n;
+}
+
+/* Vector-Jacobian product: grad = d/d(params) sum_s dy[s] . y(x_s), for
+ * dy[n][3] (normalised output units). */
+void orc_mlp_vjp(const double *params, const double *norm, const double *x,
+                 const double *dy, int n, double *grad) {
+  memset(grad, 0, sizeof(double) * NPARAM);
+  for (int s = 0; s < n; ++s) {
+    mlp_cache m;
+    mlp_forward(params, norm, x + (size_t)s * NIN, &m);
+    mlp_backprop(params, &m, dy + (size_t)s * NOUT, grad);
+  }
 }
 
 /* One Adam step (Kingma & Ba 2015) at step number t >= 1. */
@@ -941,4 +978,158 @@ void orc_train_samples(const double *rho, const double *u, const double *b,
   for (int k = 0; k < 11; ++k) free(arrs[k]);
   free(UX);
   free(UY);
+}
+
+/* ======================================================================== */
+/* One-step solver-in-the-loop objective of the closure (project addition) */
+/* ======================================================================== */
+/* Coarse node X of an nc x nc grid covers the fine block fac X .. fac X +
+ * fac - 1 (both axes); coarse step n corresponds to fine step fac n
+ * (acoustic scaling, tau_c = 1/2 + (tau_f - 1/2) / fac).
+ *
+ * Restart at fine time t: box-filter rho, rho u and b; u_bar = (rho u)_bar /
+ * rho_bar; a_CE = -rho_bar c_s^2 tau_c (grad u_bar + grad u_bar^T) with the
+ * isotropic gradient of Sec. III on the coarse grid; f = f_eq(rho_bar, u_bar,
+ * b_bar) + f_neq,reg(u_bar, a_CE) (tasks 2-4); g = g_eq(u_bar, b_bar).
+ * One coarse step of this state with delta(X) added to a_1^(2) at every node
+ * before the recursion gives the momentum j_c(X) = sum_i c_i f_i(X) at coarse
+ * time 1.  Objective
+ *   L = sum_X |j_c(X) - j_bar(X, t + fac)|^2 / sum_X |j_bar(t + fac) - j_bar(t)|^2. */
+
+/* Box filter of rho, rho u_x, rho u_y, b_x, b_y: out[5][nc][nc]. */
+static void filter_rjb(const double *rho, const double *u, const double *b,
+                       int nf, int fac, double *out) {
+  const int nc = nf / fac;
+  const size_t Nf = (size_t)nf * nf, Nc = (size_t)nc * nc;
+  memset(out, 0, 5 * Nc * sizeof(double));
+  for (int y = 0; y < nf; ++y)
+    for (int x = 0; x < nf; ++x) {
+      const size_t f = (size_t)y * nf + x, c = (size_t)(y / fac) * nc + x / fac;
+      out[c] += rho[f];
+      out[Nc + c] += rho[f] * u[f];
+      out[2 * Nc + c] += rho[f] * u[Nf + f];
+      out[3 * Nc + c] += b[f];
+      out[4 * Nc + c] += b[Nf + f];
+    }
+  const double a = 1.0 / ((double)fac * fac);
+  for (size_t k = 0; k < 5 * Nc; ++k) out[k] *= a;
+}
+
+/* Restart populations (solver layout f[9][nc][nc], g[5][2][nc][nc]) from
+ * filtered fields F[5][nc][nc]. */
+static void restart_state(const double *F, int nc, double tau_c, double *f,
+                          double *g) {
+  const size_t Nc = (size_t)nc * nc;
+  double *U = malloc(2 * Nc * sizeof(double));
+  for (size_t c = 0; c < Nc; ++c) {
+    U[c] = F[Nc + c] / F[c];
+    U[Nc + c] = F[2 * Nc + c] / F[c];
+  }
+  for (int cy = 0; cy < nc; ++cy)
+    for (int cx = 0; cx < nc; ++cx) {
+      const size_t c = (size_t)cy * nc + cx;
+      double gr[2][2] = {{0.0, 0.0}, {0.0, 0.0}}; /* gr[a][b] = d_a u_b */
+      for (int i = 0; i < 9; ++i) {
+        const size_t q = (size_t)wrap(cy + CI[i][1], nc) * nc + wrap(cx + CI[i][0], nc);
+        for (int a = 0; a < 2; ++a)
+          for (int bb = 0; bb < 2; ++bb) gr[a][bb] += WI[i] * CI[i][a] * U[bb * Nc + q] / CS2;
+      }
+      const double rho = F[c], u[2] = {U[c], U[Nc + c]}, b[2] = {F[3 * Nc + c], F[4 * Nc + c]};
+      double a2[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb) a2[a][bb] = -rho * CS2 * tau_c * (gr[a][bb] + gr[bb][a]);
+      double feq[9], geq[10], a3[2][2][2], a4[2][2][2][2], r[9];
+      feq_algorithm(rho, u, b, feq);
+      geq_vector(u, b, geq);
+      reg_expand(u, (const double(*)[2])a2, a3, a4, r);
+      for (int i = 0; i < 9; ++i) f[(size_t)i * Nc + c] = feq[i] + WI[i] * r[i];
+      for (int j = 0; j < 5; ++j)
+        for (int k = 0; k < 2; ++k) g[((size_t)j * 2 + k) * Nc + c] = geq[2 * j + k];
+    }
+  free(U);
+}
+
+/* The objective for fine moments (rho0, u0, b0) at t and (rho1, u1, b1) at
+ * t + fac (rho [nf][nf], u and b [2][nf][nf]) and a correction delta[Nc][3]
+ * (NULL: none).  Returns L; optional outputs: resid[Nc][2] = j_c - j_bar(t +
+ * fac), x[Nc][8] = the restart state's features (rho, u, b, a_1^(2)) computed
+ * from its populations as the collision computes them, *den. */
+double orc_onestep_objective(const double *rho0, const double *u0, const double *b0,
+                             const double *rho1, const double *u1, const double *b1,
+                             int nf, int fac, double tau_c, const double *delta,
+                             double *resid, double *x, double *den_out) {
+  build_tables();
+  const int nc = nf / fac;
+  const size_t Nc = (size_t)nc * nc;
+  double *F0 = malloc(5 * Nc * sizeof(double)), *F1 = malloc(5 * Nc * sizeof(double));
+  double *f = malloc(9 * Nc * sizeof(double)), *g = malloc(10 * Nc * sizeof(double));
+  filter_rjb(rho0, u0, b0, nf, fac, F0);
+  filter_rjb(rho1, u1, b1, nf, fac, F1);
+  restart_state(F0, nc, tau_c, f, g);
+  orc *h = orc_create(nc, nc, tau_c, tau_c, 0, 0.0, 0.0, 0.0, 0.0, FEQ_ALGORITHM);
+  orc_set_state(h, f, g);
+  if (x) {
+    const double G0[2] = {0.0, 0.0};
+    for (size_t c = 0; c < Nc; ++c) {
+      double fl[9], gl[10], fs[9], gs[10];
+      node_aux ax;
+      for (int i = 0; i < 9; ++i) fl[i] = f[(size_t)i * Nc + c];
+      for (int k = 0; k < 10; ++k) gl[k] = g[(size_t)k * Nc + c];
+      collide_node(fl, gl, 1.0 / tau_c, 1.0 / tau_c, G0, FEQ_ALGORITHM, fs, gs, &ax);
+      const double v[8] = {ax.rho, ax.u[0], ax.u[1], ax.b[0], ax.b[1],
+                           ax.a2[0][0], ax.a2[0][1], ax.a2[1][1]};
+      memcpy(x + 8 * c, v, sizeof v);
+    }
+  }
+  h->delta = delta;
+  one_step(h);
+  h->delta = NULL;
+  double num = 0.0, den = 0.0;
+  for (size_t c = 0; c < Nc; ++c) {
+    double j[2] = {0.0, 0.0};
+    for (int i = 0; i < 9; ++i)
+      for (int a = 0; a < 2; ++a) j[a] += CI[i][a] * h->f[(size_t)i * Nc + c];
+    for (int a = 0; a < 2; ++a) {
+      const double r = j[a] - F1[(1 + a) * Nc + c];
+      const double d = F1[(1 + a) * Nc + c] - F0[(1 + a) * Nc + c];
+      if (resid) resid[2 * c + a] = r;
+      num += r * r;
+      den += d * d;
+    }
+  }
+  if (den_out) *den_out = den;
+  orc_destroy(h);
+  free(F0);
+  free(F1);
+  free(f);
+  free(g);
+  return num / den;
+}
+
+/* Transpose of the linear part of delta -> j_c of the objective, applied to
+ * w[Nc][2]: out[Y][k] = sum_i (c_i . w(Y + c_i)) d fs_i(Y) / d delta_k(Y).
+ * At the restart velocity u(Y) (x[Y][1..2]) the post-collision populations
+ * depend on delta only through (1 - 1/tau_c) f_neq,reg(u, a_1^(2) + delta),
+ * which is linear in a_1^(2); its columns are the regularised populations of
+ * the unit corrections (the xy unit sets both off-diagonal entries). */
+void orc_onestep_adjoint(const double *x, int nc, double tau_c, const double *w,
+                         double *out) {
+  build_tables();
+  const double E[3][2][2] = {{{1, 0}, {0, 0}}, {{0, 1}, {1, 0}}, {{0, 0}, {0, 1}}};
+  for (int cy = 0; cy < nc; ++cy)
+    for (int cx = 0; cx < nc; ++cx) {
+      const size_t c = (size_t)cy * nc + cx;
+      const double u[2] = {x[8 * c + 1], x[8 * c + 2]};
+      double m[9];
+      for (int i = 0; i < 9; ++i) {
+        const size_t q = (size_t)wrap(cy + CI[i][1], nc) * nc + wrap(cx + CI[i][0], nc);
+        m[i] = CI[i][0] * w[2 * q] + CI[i][1] * w[2 * q + 1];
+      }
+      for (int k = 0; k < 3; ++k) {
+        double a3[2][2][2], a4[2][2][2][2], r[9], s = 0.0;
+        reg_expand(u, E[k], a3, a4, r);
+        for (int i = 0; i < 9; ++i) s += m[i] * (1.0 - 1.0 / tau_c) * WI[i] * r[i];
+        out[3 * c + k] = s;
+      }
+    }
 }

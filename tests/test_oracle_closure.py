@@ -183,3 +183,156 @@ def test_train_samples_subgrid_stress_of_unresolved_shear():
     x, t = oracle.train_samples(np.ones((nf, nf)), u, np.zeros((2, nf, nf)), fac, tau_c)
     assert np.allclose(x[:, 1], 0, atol=1e-18)
     assert np.allclose(t[:, 0], v * v / (tau_c - 1)) and np.allclose(t[:, 1:], 0)
+
+
+# ---- one-step solver-in-the-loop objective ---------------------------------
+
+def _fine_pair(nf, tau_f, fac, steps, seed=1):
+    """Fine moments at t = steps and t + fac from the oracle's own run of a
+    random-phase turbulence field."""
+    u, b = inputs.turbulence(nf, 0.04, seed_psi=2 * seed + 1, seed_a=2 * seed + 2)
+    o = oracle.Oracle(nf, nf, tau_f, tau_f)
+    o.init(u, b)
+    o.step(steps)
+    m0 = o.moments()
+    o.step(fac)
+    m1 = o.moments()
+    o.close()
+    return m0, m1
+
+
+@pytest.fixture(scope="module")
+def fine_pair():
+    fac, tf = 4, 0.8
+    m0, m1 = _fine_pair(32, tf, fac, 40)
+    return m0, m1, fac, 0.5 + (tf - 0.5) / fac
+
+
+def test_onestep_restart_reproduces_the_filtered_fields(fine_pair):
+    """The restart state's moments and a_1^(2) (computed from its
+    populations) equal the filtered fields and the Chapman-Enskog estimate of
+    the a-priori sample builder: f_neq,reg carries no mass or momentum and
+    returns its a_1^(2) exactly (reconstruction invariants)."""
+    m0, m1, fac, tc = fine_pair
+    _, _, x, _ = oracle.onestep_objective(m0, m1, fac, tc)
+    xs, _ = oracle.train_samples(m0[0], m0[1], m0[2], fac, tc)
+    scale = np.abs(xs).max(axis=0)
+    assert np.all(np.abs(x - xs).max(axis=0) <= 1e-13 * scale + 1e-300)
+
+
+def test_onestep_adjoint_dot_product(fine_pair):
+    """<J v, w> = <v, J^T w> for the linear part J of delta -> momentum,
+    J v taken as resid(v) - resid(0) (the map is affine)."""
+    m0, m1, fac, tc = fine_pair
+    nc = m0[0].shape[0] // fac
+    rng = np.random.default_rng(3)
+    _, r0, x, _ = oracle.onestep_objective(m0, m1, fac, tc)
+    for _ in range(3):
+        v = 1e-4 * rng.standard_normal((nc * nc, 3))
+        w = rng.standard_normal((nc * nc, 2))
+        _, rv, _, _ = oracle.onestep_objective(m0, m1, fac, tc, v)
+        lhs = np.sum((rv - r0) * w)
+        rhs = np.sum(v * oracle.onestep_adjoint(x, nc, tc, w))
+        assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_onestep_adjoint_is_a_local_push(fine_pair):
+    """A unit momentum residual at one node X reaches only delta at X - c_i
+    (the pull of one step), i.e. J^T is the transpose stencil."""
+    m0, m1, fac, tc = fine_pair
+    nc = m0[0].shape[0] // fac
+    _, _, x, _ = oracle.onestep_objective(m0, m1, fac, tc)
+    w = np.zeros((nc * nc, 2))
+    X = (3, 5)
+    w[X[1] * nc + X[0], 0] = 1.0
+    g = oracle.onestep_adjoint(x, nc, tc, w).reshape(nc, nc, 3)
+    nz = {(int(cx), int(cy)) for cy, cx in zip(*np.nonzero(np.abs(g).sum(axis=2)))}
+    allowed = {((X[0] - dx) % nc, (X[1] - dy) % nc) for dx in (-1, 0, 1) for dy in (-1, 0, 1)
+               if dx != 0}  # c_x = 0 carries no x momentum
+    assert nz and nz <= allowed
+
+
+def test_onestep_gradient_against_central_differences(fine_pair):
+    """dL/d delta = (2 / den) J^T resid against central differences of L
+    (quadratic in delta, so central differences are exact up to rounding)."""
+    m0, m1, fac, tc = fine_pair
+    nc = m0[0].shape[0] // fac
+    rng = np.random.default_rng(4)
+    v = 1e-4 * rng.standard_normal((nc * nc, 3))
+    _, rv, x, den = oracle.onestep_objective(m0, m1, fac, tc, v)
+    g = oracle.onestep_adjoint(x, nc, tc, rv) * (2.0 / den)
+    for k, c in ((5, 0), (17, 1), (40, 2), (63, 1)):
+        h = 1e-6
+        vp, vm = v.copy(), v.copy()
+        vp[k, c] += h
+        vm[k, c] -= h
+        fd = (oracle.onestep_objective(m0, m1, fac, tc, vp)[0]
+              - oracle.onestep_objective(m0, m1, fac, tc, vm)[0]) / (2 * h)
+        assert abs(fd - g[k, c]) <= 1e-6 * abs(g[k, c])
+
+
+def test_mlp_vjp_against_central_differences():
+    p = random_params()
+    norm = random_norm()
+    x = 0.05 * RNG.standard_normal((5, 8)); x[:, 0] += 1.0
+    dy = RNG.standard_normal((5, 3))
+    g = oracle.mlp_vjp(p, norm, x, dy)
+    for k in (3, 600, 2000, 4700, 4930):
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (np.sum(dy * oracle.mlp_forward(pp, norm, x))
+              - np.sum(dy * oracle.mlp_forward(pm, norm, x))) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-7 * max(1.0, abs(g[k]))
+
+
+def test_onestep_parameter_gradient_against_central_differences(fine_pair):
+    """The composed chain (network, objective, adjoint, reverse mode) against
+    central differences of L(params) evaluated through the solver step."""
+    m0, m1, fac, tc = fine_pair
+    p = 0.3 * np.random.default_rng(5).standard_normal(oracle.NPARAM)
+    norm = np.concatenate([[1.0, 0, 0, 0, 0, 0, 0, 0], [0.01, 0.02, 0.02, 0.02, 0.02,
+                                                        2e-3, 2e-3, 2e-3], [1e-4] * 3])
+    L, g = oracle.onestep_loss_grad(p, norm, m0, m1, fac, tc)
+    _, _, x, _ = oracle.onestep_objective(m0, m1, fac, tc)
+
+    def L_of(q):
+        d = oracle.mlp_forward(q, norm, x) * norm[16:19]
+        return oracle.onestep_objective(m0, m1, fac, tc, d)[0]
+
+    assert abs(L_of(p) - L) <= 1e-14 * L
+    for k in (7, 530, 1500, 4680, 4929):
+        h = 1e-5
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (L_of(pp) - L_of(pm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-5 * max(abs(g[k]), 1e-3 * np.abs(g).max())
+
+
+def test_onestep_restart_of_a_resolved_shear_wave_converges():
+    """Physical pin of the restart: for a viscous shear wave the one coarse
+    step from the Chapman-Enskog restart reproduces the filtered fine
+    momentum change over fac fine steps up to the discretisation error, which
+    falls at second order in the coarse spacing (L is its square: about 16x
+    per halving).  A restart without the non-equilibrium part, or with its
+    sign flipped, leaves an O(1) error that does not converge."""
+    fac, tf = 4, 0.8
+    tc = 0.5 + (tf - 0.5) / fac
+    Ls = []
+    for nf in (64, 128):
+        yy = np.arange(nf)
+        u = np.zeros((2, nf, nf))
+        u[0] = 0.01 * np.sin(2 * np.pi * yy / nf)[:, None]
+        b = np.zeros((2, nf, nf))
+        o = oracle.Oracle(nf, nf, tf, tf)
+        o.init(u, b)
+        o.step(300 * (nf // 64) ** 2)
+        m0 = o.moments()
+        o.step(fac)
+        m1 = o.moments()
+        o.close()
+        Ls.append(oracle.onestep_objective(m0, m1, fac, tc)[0])
+    assert Ls[1] < 5e-3
+    assert Ls[0] / Ls[1] > 10.0
