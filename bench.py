@@ -185,12 +185,13 @@ def closure_bench(args):
     from paper_2602_14667_amd import closure_pipeline as cp
     if args.closure_scale == "full":
         kw = dict(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
-                  train_seeds=range(16), test_seeds=range(20, 24),
-                  train_steps=3000, batch=65536)
+                  train_seeds=range(16), val_seeds=range(16, 20),
+                  test_seeds=range(20, 24), train_steps=3000, onestep_steps=2000,
+                  batch=65536)
     else:
         kw = dict(n_f=1024, factor=4, tau_f=0.56, fine_steps=16000, snaps=4,
-                  train_seeds=range(4), test_seeds=[20], train_steps=1000,
-                  batch=65536)
+                  train_seeds=range(4), val_seeds=[5], test_seeds=[20],
+                  train_steps=1000, onestep_steps=600, batch=65536)
     res = cp.pipeline(log=lambda m: print(m, file=sys.stderr, flush=True), **kw)
     tests = res["tests"]
     worst = {side: max(t[side]["eps_spec"] for t in tests) for side in ("plain", "closure")}
@@ -212,6 +213,8 @@ def closure_bench(args):
         "gpu_s": {k: round(v / 1e3, 3) for k, v in ms.items()},
         "train_s": round(res["train_s"], 2), "data_s": round(res["data_s"], 2),
         "train_loss_first_last": [res["train_loss"][0], res["train_loss"][-1]],
+        "onestep_objective": {"train": res["onestep_objective"],
+                              "validation": res["onestep_objective_val"]},
         "fallbacks": [t["fallback_at"] for t in tests]}), flush=True)
 
 

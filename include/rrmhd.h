@@ -234,6 +234,38 @@ int rrmhd_train_loss_grad(rrmhd_trainer *t, const float *params,
                           const float *norm, const float *x,
                           const float *target, int64_t n, float *grad,
                           float *loss);
+/* One-step solver-in-the-loop data (training objective of the closure).
+ * Fine moments at t (rho0, u0, b0) and at t + factor (rho1, u1, b1), device
+ * FP64 in the layout of rrmhd_moments, nf x nf periodic; the coarse grid has
+ * nc = nf/factor nodes per side and relaxation time tau_c (coarse step =
+ * factor fine steps).  The coarse grid is restarted from the filtered fields
+ * at t with f = f_eq(rho_bar, u_bar, b_bar) + f_neq,reg(u_bar, a_CE) and g =
+ * g_eq(u_bar, b_bar) (features x as in rrmhd_train_samples).  Outputs
+ * (device): x[Nc][8] FP32; r0[Nc][2] FP32 = momentum j_c(X) after one coarse
+ * step without correction minus j_bar(X, t + factor) (computed in FP64);
+ * *den FP64 = sum_X |j_bar(t + factor) - j_bar(t)|^2.  work: 29 Nc doubles.
+ * Asynchronous; EINVAL for null pointers, nf not a multiple of factor or
+ * tau_c <= 1/2. */
+int rrmhd_train_onestep_samples(const double *rho0, const double *u0,
+                                const double *b0, const double *rho1,
+                                const double *u1, const double *b1, int nf,
+                                int factor, double tau_c, double *work,
+                                float *x, float *r0, double *den,
+                                void *hip_stream);
+/* grad[4931] and *loss (device FP32; loss may be NULL) of the one-step
+ * objective L = sum_X |r(X)|^2 / den over nsnap snapshots stored back to back
+ * (x [nsnap][Nc][8], r0 [nsnap][Nc][2] from rrmhd_train_onestep_samples, den
+ * their summed denominators, host value > 0), where r = r0 plus the effect of
+ * the correction D = sigma_out * y(x) added to a_1^(2) at every coarse node
+ * before the recursion: one collision of the restart state and the pull of
+ * one step.  The gradient is exact: the transpose of that stencil, then
+ * reverse mode through the FP32 network.  nsnap nc^2 <= max_batch.
+ * Asynchronous. */
+int rrmhd_train_onestep_loss_grad(rrmhd_trainer *t, const float *params,
+                                  const float *norm, const float *x,
+                                  const float *r0, int nsnap, int nc,
+                                  double tau_c, double den, float *grad,
+                                  float *loss);
 /* One Adam step (Kingma & Ba 2015) on params[4931] with moments m, v
  * (device FP32) at step number step >= 1.  Asynchronous. */
 int rrmhd_train_adam(rrmhd_trainer *t, float *params, float *m, float *v,

@@ -4,7 +4,11 @@
    seeded turbulence field (tau_f), snapshots every `snap` steps.
 2. Training samples: each snapshot's moments are box-filtered by `factor`
    into coarse features and a-priori targets (`rrmhd_train_samples`).
-3. Training: FP32 forward/backward and Adam kernels on random minibatches.
+3. Training: FP32 forward/backward and Adam kernels, first on the a-priori
+   regression (warm start), then on the one-step solver-in-the-loop
+   objective (`rrmhd_train_onestep_*`): the coarse grid restarted from the
+   filtered fine state at t and advanced one coarse step with the network's
+   correction must reproduce the filtered fine momentum at t + factor.
 4. Coarse runs (n_f / factor)^2 at the acoustically scaled relaxation time
    tau_c = 1/2 + (tau_f - 1/2) / factor (dx and dt both scale by factor, so
    coarse step n matches fine step factor * n), plain and with the closure.
@@ -51,22 +55,30 @@ def _dev(a):
 
 
 def generate_samples(seed, n_f, tau_f, factor, snap_steps):
-    """Training samples (x, t) device tensors from one fine run."""
+    """Training data from one fine run, per snapshot: features x[Nc][8],
+    a-priori targets t[Nc][3], one-step residuals r0[Nc][2] and the one-step
+    denominator (host float).  The run is stepped `factor` steps past each
+    snapshot for the one-step target."""
     import torch
     u, b = fine_fields(n_f, seed)
     s = rrmhd.Solver(n_f, n_f, tau_f, tau_f)
     s.init(_dev(u), _dev(b))
-    xs, ts = [], []
+    xs, ts, rs, dens = [], [], [], []
     tc = tau_coarse(tau_f, factor)
     for step in snap_steps:
         s.step(step - s.step_count)
-        rho, uu, bb = s.moments()
-        x, t = rrmhd.train_samples(rho, uu, bb, factor, tc)
+        m0 = s.moments()
+        _, t = rrmhd.train_samples(*m0, factor, tc)
+        s.step(factor)
+        m1 = s.moments()
+        x, r0, den = rrmhd.train_onestep_samples(m0, m1, factor, tc)
         xs.append(x)
         ts.append(t)
+        rs.append(r0)
+        dens.append(den)
     torch.cuda.synchronize()
     s.close()
-    return xs, ts
+    return xs, ts, rs, [float(d.item()) for d in dens]
 
 
 def normalization(x, t):
@@ -91,12 +103,14 @@ def init_params(seed: int):
     return torch.from_numpy(p).cuda()
 
 
-def train(x, t, norm, steps=2000, batch=65536, lr=1e-3, seed=0, log_every=0):
-    """Adam on random minibatches; returns (params, loss history)."""
+def train(x, t, norm, steps=2000, batch=65536, lr=1e-3, seed=0, log_every=0,
+          params=None):
+    """A-priori regression: Adam on random minibatches; returns (params,
+    loss history)."""
     import torch
     n = x.shape[0]
     batch = min(batch, n)
-    p = init_params(seed)
+    p = init_params(seed) if params is None else params
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
     grad = torch.empty_like(p)
@@ -115,6 +129,51 @@ def train(x, t, norm, steps=2000, batch=65536, lr=1e-3, seed=0, log_every=0):
             hist.append((step, float(loss.item())))
     tr.close()
     return p, hist
+
+
+def train_onestep(p, xs, rs, dens, norm, nc, tau_c, steps=1000, nodes=65536,
+                  lr=1e-3, seed=0, log_every=0):
+    """One-step solver-in-the-loop objective: Adam where each step uses
+    ceil(nodes / nc^2) random whole snapshots (the correction stencil needs
+    the neighbours of every node).  Returns (params, loss history)."""
+    import torch
+    per = max(1, -(-nodes // (nc * nc)))
+    per = min(per, len(xs))
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    grad = torch.empty_like(p)
+    loss = torch.empty(1, dtype=torch.float32, device=p.device)
+    tr = rrmhd.Trainer(per * nc * nc)
+    g = np.random.default_rng(seed)
+    hist = []
+    for step in range(1, steps + 1):
+        pick = g.choice(len(xs), size=per, replace=False)
+        if per == 1:
+            xb, rb = xs[pick[0]], rs[pick[0]]
+        else:
+            xb = torch.cat([xs[k] for k in pick])
+            rb = torch.cat([rs[k] for k in pick])
+        den = float(sum(dens[k] for k in pick))
+        tr.onestep_loss_grad(p, norm, xb, rb, per, nc, tau_c, den, grad, loss)
+        tr.adam(p, m, v, grad, lr, step)
+        if log_every and (step % log_every == 0 or step == 1):
+            hist.append((step, float(loss.item())))
+    tr.close()
+    return p, hist
+
+
+def onestep_loss(p, xs, rs, dens, norm, nc, tau_c):
+    """The one-step objective over all snapshots (device network)."""
+    import torch
+    tr = rrmhd.Trainer(nc * nc)
+    grad = torch.empty_like(p)
+    loss = torch.empty(1, dtype=torch.float32, device=p.device)
+    num = 0.0
+    for x, r, d in zip(xs, rs, dens):
+        tr.onestep_loss_grad(p, norm, x, r, 1, nc, tau_c, d, grad, loss)
+        num += float(loss.item()) * d
+    tr.close()
+    return num / sum(dens)
 
 
 def spectra_run(n, tau, u, b, checkpoints, params=None, norm=None,
@@ -199,35 +258,70 @@ def judge(run, ref, kmax):
 
 
 def pipeline(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
-             train_seeds=range(16), test_seeds=range(20, 24), train_steps=3000,
-             batch=65536, lr=1e-3, n_times=5, log=print):
-    """Full protocol; returns a dict of results."""
+             train_seeds=range(16), val_seeds=range(16, 20), test_seeds=range(20, 24),
+             train_steps=3000, onestep_steps=2000, batch=65536, lr=1e-3, n_times=5,
+             log=print):
+    """Full protocol; returns a dict of results.  Training: train_steps of
+    a-priori regression (warm start), then onestep_steps of the one-step
+    solver-in-the-loop objective (0: a-priori only).  The one-step objective
+    is reported on the training snapshots and on held-out validation seeds;
+    the spectral judge runs on the test seeds."""
     import torch
     t0 = time.time()
     snap_steps = [fine_steps * (k + 1) // snaps for k in range(snaps)]
-    xs, ts = [], []
+    xs, ts, rs, dens = [], [], [], []
     for sd in train_seeds:
-        x, t = generate_samples(sd, n_f, tau_f, factor, snap_steps)
+        x, t, r, d = generate_samples(sd, n_f, tau_f, factor, snap_steps)
         xs += x
         ts += t
+        rs += r
+        dens += d
         log(f"fine run seed {sd}: {len(x)} snapshots")
     X = torch.cat(xs)
     T = torch.cat(ts)
-    del xs, ts
+    del ts
     norm = normalization(X, T)
     t_data = time.time() - t0
+    n_c = n_f // factor
+    tc = tau_coarse(tau_f, factor)
     t1 = time.time()
     params, hist = train(X, T, norm, steps=train_steps, batch=batch, lr=lr,
                          log_every=max(train_steps // 10, 1))
+    del X, T
+    L_zero = onestep_loss(init_params(0), xs, rs, dens, norm, n_c, tc)
+    L_apriori = onestep_loss(params, xs, rs, dens, norm, n_c, tc)
+    hist1 = []
+    if onestep_steps:
+        params, hist1 = train_onestep(params, xs, rs, dens, norm, n_c, tc,
+                                      steps=onestep_steps, nodes=batch, lr=lr,
+                                      log_every=max(onestep_steps // 10, 1))
+    L_final = onestep_loss(params, xs, rs, dens, norm, n_c, tc)
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    log(f"training: {hist}")
-    del X, T
-    n_c = n_f // factor
-    tc = tau_coarse(tau_f, factor)
+    log(f"training (a-priori): {hist}")
+    log(f"training (one-step): {hist1}")
+    log(f"one-step objective over the training snapshots: no closure {L_zero:.4f}, "
+        f"a-priori {L_apriori:.4f}, final {L_final:.4f}")
+    del xs, rs
+    val = None
+    if val_seeds:
+        vx, vr, vd = [], [], []
+        for sd in val_seeds:
+            x, _, r, d = generate_samples(sd, n_f, tau_f, factor, snap_steps)
+            vx += x
+            vr += r
+            vd += d
+        val = dict(no_closure=onestep_loss(init_params(0), vx, vr, vd, norm, n_c, tc),
+                   final=onestep_loss(params, vx, vr, vd, norm, n_c, tc))
+        log(f"one-step objective over the validation seeds: no closure "
+            f"{val['no_closure']:.4f}, final {val['final']:.4f}")
+        del vx, vr
     checkpoints = [fine_steps // factor * (k + 1) // n_times for k in range(n_times)]
     kmax = n_c // 4
-    res = dict(train_loss=hist, data_s=t_data, train_s=t_train, tests=[])
+    res = dict(train_loss=hist, train_loss_onestep=hist1, data_s=t_data,
+               train_s=t_train, onestep_objective=dict(
+                   no_closure=L_zero, apriori=L_apriori, final=L_final),
+               onestep_objective_val=val, tests=[])
     for sd in test_seeds:
         ref, ms_fine = fine_reference(n_f, tau_f, factor, sd, checkpoints)
         uc, bc = coarse_fields(n_f, factor, sd)

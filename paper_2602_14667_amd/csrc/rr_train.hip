@@ -11,14 +11,30 @@
 // u_bar + M(b)_bar - M(b_bar), M = |b|^2 I / 2 - b b.  A constant correction
 // D added to a_1^(2) every step settles at a = (tau - 1) D, so this target
 // makes the added momentum flux equal the subgrid stress.
+//
+// One-step solver-in-the-loop objective: the coarse grid is restarted from
+// the filtered fine fields at t (f = f_eq(rho_bar, u_bar, b_bar) +
+// f_neq,reg(u_bar, a_CE), g = g_eq) and advanced one coarse step with the
+// network's correction D(Y) added to a_1^(2) at every node Y; the loss is
+// L = sum_X |j_c(X) - j_bar(X, t + fac)|^2 / sum_X |j_bar(t + fac) - j_bar(t)|^2.
+// The post-collision populations of a node are affine in its own D:
+// f*_i(Y) = f*_i(Y)|_{D=0} + (1 - 1/tau_c) w_i R_i(u(Y)) . D(Y), with
+// R_i . D the regularised expansion (second order 9/2, recursive third order
+// 27/2, fourth order 81/4) of the coefficient D, so after the pull
+// j_c(X) = j_c(X)|_{D=0} + sum_i c_i (1 - 1/tau_c) w_i R_i(u(X - c_i)) . D(X - c_i),
+// and dL/dD(Y) is the transpose stencil: (2/den) (1 - 1/tau_c) sum_i
+// (c_i . r(Y + c_i)) w_i R_i(u(Y)).  The D = 0 part is prepared once per
+// snapshot in FP64; the network-dependent part runs in FP32.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <new>
 
 #include "../../include/rrmhd.h"
 #include "rr_mlp.h"
+#include "rr_node.h"
 
 namespace rr {
 
@@ -68,13 +84,11 @@ __global__ void k_box_filter(const double *__restrict__ rho, const double *__res
   for (int k = 0; k < kFilt; ++k) out[(int64_t)k * Nc + c] = acc[k] * inv;
 }
 
-// Features x[Nc][8] and raw targets t[Nc][3] (FP32) from the filtered fields.
-__global__ void k_samples(const double *__restrict__ flt, int nc, double tau_c,
-                          float *__restrict__ x, float *__restrict__ t) {
+// Coarse features (rho_bar, u_bar, b_bar, a_CE) of node (cx, cy), FP64, from
+// the filtered fields.
+__device__ void features_at(const double *__restrict__ flt, int nc, double tau_c, int cx,
+                            int cy, double out[8]) {
   const int64_t Nc = (int64_t)nc * nc;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= Nc) return;
-  const int cy = (int)(c / nc), cx = (int)(c - (int64_t)cy * nc);
   auto F = [&](int k, int xx, int yy) {
     xx = (xx + nc) % nc;
     yy = (yy + nc) % nc;
@@ -82,36 +96,136 @@ __global__ void k_samples(const double *__restrict__ flt, int nc, double tau_c,
   };
   auto ubar = [&](int comp, int xx, int yy) { return F(1 + comp, xx, yy) / F(0, xx, yy); };
   // isotropic gradient d_a phi = 3 sum_i w_i phi(x + c_i) c_ia on D2Q9
-  const int CXs[9] = {0, -1, -1, -1, 0, 1, 1, 1, 0};
-  const int CYs[9] = {0, 1, 0, -1, -1, -1, 0, 1, 1};
   double g[2][2] = {{0, 0}, {0, 0}};  // g[a][b] = d_a u_b
   for (int i = 1; i < 9; ++i) {
-    const double w = (i & 1) ? 1.0 / 36.0 : 1.0 / 9.0;
+    const double w = 1.0 / (double)wdiv(i);
     for (int comp = 0; comp < 2; ++comp) {
-      const double v = ubar(comp, cx + CXs[i], cy + CYs[i]);
-      g[0][comp] += 3.0 * w * v * CXs[i];
-      g[1][comp] += 3.0 * w * v * CYs[i];
+      const double v = ubar(comp, cx + rr::cx(i), cy + rr::cy(i));
+      g[0][comp] += 3.0 * w * v * rr::cx(i);
+      g[1][comp] += 3.0 * w * v * rr::cy(i);
     }
   }
-  const double r = F(0, cx, cy), ux = ubar(0, cx, cy), uy = ubar(1, cx, cy);
-  const double bx = F(3, cx, cy), by = F(4, cx, cy);
+  const double r = F(0, cx, cy);
   const double k = -r * tau_c / 3.0;
-  x[c * 8 + 0] = (float)r;
-  x[c * 8 + 1] = (float)ux;
-  x[c * 8 + 2] = (float)uy;
-  x[c * 8 + 3] = (float)bx;
-  x[c * 8 + 4] = (float)by;
-  x[c * 8 + 5] = (float)(k * 2.0 * g[0][0]);
-  x[c * 8 + 6] = (float)(k * (g[0][1] + g[1][0]));
-  x[c * 8 + 7] = (float)(k * 2.0 * g[1][1]);
+  out[0] = r;
+  out[1] = ubar(0, cx, cy);
+  out[2] = ubar(1, cx, cy);
+  out[3] = F(3, cx, cy);
+  out[4] = F(4, cx, cy);
+  out[5] = k * 2.0 * g[0][0];
+  out[6] = k * (g[0][1] + g[1][0]);
+  out[7] = k * 2.0 * g[1][1];
+}
+
+// Features x[Nc][8] and raw targets t[Nc][3] (FP32) from the filtered fields.
+__global__ void k_samples(const double *__restrict__ flt, int nc, double tau_c,
+                          float *__restrict__ x, float *__restrict__ t) {
+  const int64_t Nc = (int64_t)nc * nc;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int cy = (int)(c / nc), cx = (int)(c - (int64_t)cy * nc);
+  double ft[8];
+  features_at(flt, nc, tau_c, cx, cy, ft);
+  for (int k = 0; k < 8; ++k) x[c * 8 + k] = (float)ft[k];
+  const double r = ft[0], ux = ft[1], uy = ft[2], bx = ft[3], by = ft[4];
+  auto F = [&](int k) { return flt[(int64_t)k * Nc + c]; };
   const double mbxx = 0.5 * (by * by - bx * bx), mbxy = -bx * by;
-  const double sxx = F(5, cx, cy) - r * ux * ux + F(8, cx, cy) - mbxx;
-  const double sxy = F(6, cx, cy) - r * ux * uy + F(9, cx, cy) - mbxy;
-  const double syy = F(7, cx, cy) - r * uy * uy - F(8, cx, cy) + mbxx;
+  const double sxx = F(5) - r * ux * ux + F(8) - mbxx;
+  const double sxy = F(6) - r * ux * uy + F(9) - mbxy;
+  const double syy = F(7) - r * uy * uy - F(8) + mbxx;
   const double inv = 1.0 / (tau_c - 1.0);
   t[c * 3 + 0] = (float)(sxx * inv);
   t[c * 3 + 1] = (float)(sxy * inv);
   t[c * 3 + 2] = (float)(syy * inv);
+}
+
+// ---- one-step objective: data preparation (FP64) ----------------------------
+// Regularised expansion R_i . a of a second-order coefficient (axx, axy,
+// ayy) at velocity u, without the weight: 9/2 H2:a + 27/2 (H_xxy a_xxy +
+// H_xyy a_xyy) + 81/4 H_xxyy a_xxyy with the recursive a_xxy = 2 u_x a_xy +
+// u_y a_xx, a_xyy = 2 u_y a_xy + u_x a_yy, a_xxyy = u_x^2 a_yy + u_y^2 a_xx +
+// 4 u_x u_y a_xy; written with X2 = 3 c_x^2 - 1 = 3 H_xx, Y2 = 3 c_y^2 - 1.
+template <typename R>
+__device__ __forceinline__ R reg_expand(int i, R ux, R uy, R axx, R axy, R ayy) {
+  const R X2 = (R)(3 * rr::cx(i) * rr::cx(i) - 1), Y2 = (R)(3 * rr::cy(i) * rr::cy(i) - 1);
+  const R CX = (R)rr::cx(i), CY = (R)rr::cy(i);
+  const R a3x = 2 * ux * axy + uy * axx, a3y = 2 * uy * axy + ux * ayy;
+  const R a4 = ux * ux * ayy + uy * uy * axx + 4 * ux * uy * axy;
+  return (R)1.5 * (X2 * axx + Y2 * ayy) + (R)9 * CX * CY * axy +
+         (R)4.5 * (CY * X2 * a3x + CX * Y2 * a3y) + (R)2.25 * X2 * Y2 * a4;
+}
+
+// Equilibrium population i (fourth-order Hermite with the Maxwell stress at
+// second order), FP64.
+__device__ __forceinline__ double feq64(int i, double rho, double ux, double uy, double bx,
+                                        double by) {
+  const double X2 = 3 * rr::cx(i) * rr::cx(i) - 1, Y2 = 3 * rr::cy(i) * rr::cy(i) - 1;
+  const double CX = rr::cx(i), CY = rr::cy(i);
+  const double Axx = rho * ux * ux + 0.5 * (by * by - bx * bx);
+  const double Axy = rho * ux * uy - bx * by;
+  const double Ayy = rho * uy * uy + 0.5 * (bx * bx - by * by);
+  const double t2 = 1.5 * (X2 * Axx + Y2 * Ayy) + 9.0 * CX * CY * Axy;
+  const double t3 = 4.5 * rho * (CY * X2 * ux * ux * uy + CX * Y2 * ux * uy * uy);
+  const double t4 = 2.25 * rho * X2 * Y2 * ux * ux * uy * uy;
+  return (rho + 3.0 * rho * (CX * ux + CY * uy) + t2 + t3 + t4) / (double)wdiv(i);
+}
+
+// FP64 features of every coarse node: feat[8][Nc].
+__global__ void k_features64(const double *__restrict__ flt, int nc, double tau_c,
+                             double *__restrict__ feat) {
+  const int64_t Nc = (int64_t)nc * nc;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int cy = (int)(c / nc), cx = (int)(c - (int64_t)cy * nc);
+  double ft[8];
+  features_at(flt, nc, tau_c, cx, cy, ft);
+  for (int k = 0; k < 8; ++k) feat[(int64_t)k * Nc + c] = ft[k];
+}
+
+// x[Nc][8] (FP32 features), r0[Nc][2] = j_c(X)|_{D=0} - j_bar(X, t + fac)
+// (FP32 of FP64) and dm[Nc] = |j_bar(t + fac) - j_bar(t)|^2 (FP64).
+__global__ void k_onestep_prep(const double *__restrict__ flt0, const double *__restrict__ flt1,
+                               const double *__restrict__ feat, int nc, double omega,
+                               float *__restrict__ x, float *__restrict__ r0,
+                               double *__restrict__ dm) {
+  const int64_t Nc = (int64_t)nc * nc;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int cy = (int)(c / nc), cx = (int)(c - (int64_t)cy * nc);
+  for (int k = 0; k < 8; ++k) x[c * 8 + k] = (float)feat[(int64_t)k * Nc + c];
+  double jx = 0.0, jy = 0.0;
+  for (int i = 1; i < 9; ++i) {
+    // f*_i of the upstream node Y = X - c_i arrives at X
+    const int yx = (cx - rr::cx(i) + nc) % nc, yy = (cy - rr::cy(i) + nc) % nc;
+    const int64_t q = (int64_t)yy * nc + yx;
+    double v[8];
+    for (int k = 0; k < 8; ++k) v[k] = feat[(int64_t)k * Nc + q];
+    const double fs = feq64(i, v[0], v[1], v[2], v[3], v[4]) +
+                      (1.0 - omega) * reg_expand<double>(i, v[1], v[2], v[5], v[6], v[7]) /
+                          (double)wdiv(i);
+    jx += rr::cx(i) * fs;
+    jy += rr::cy(i) * fs;
+  }
+  const double j1x = flt1[1 * Nc + c], j1y = flt1[2 * Nc + c];
+  const double dx = j1x - flt0[1 * Nc + c], dy = j1y - flt0[2 * Nc + c];
+  r0[2 * c + 0] = (float)(jx - j1x);
+  r0[2 * c + 1] = (float)(jy - j1y);
+  dm[c] = dx * dx + dy * dy;
+}
+
+// out[0] = sum of v[0..n) in a fixed order (one workgroup of 256).
+__global__ __launch_bounds__(256) void k_sum64(const double *__restrict__ v, int64_t n,
+                                               double *__restrict__ out) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) a += v[k];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // ---- forward / backward -----------------------------------------------------
@@ -121,6 +235,7 @@ struct Acts {
   float *xh, *h1, *g1, *h2, *g2, *dy, *dz1, *dz2;  // [8|64|3][n]
 };
 
+// tg = nullptr: no a-priori loss; A.dy receives the outputs y instead.
 __global__ __launch_bounds__(kTB) void k_forward(const float *__restrict__ p,
                                                  const float *__restrict__ norm,
                                                  const float *__restrict__ x,
@@ -159,11 +274,17 @@ __global__ __launch_bounds__(kTB) void k_forward(const float *__restrict__ p,
 #pragma unroll
       for (int o = 0; o < kNOUT; ++o) y[o] = fmaf(P[kOffW3 + o * kNH + i], h2, y[o]);
     }
+    if (tg) {
 #pragma unroll
-    for (int o = 0; o < kNOUT; ++o) {
-      const float r = y[o] - tg[(int64_t)s * kNOUT + o] / norm[2 * kNIN + o];
-      l = fmaf(r, r, l);
-      A.dy[(int64_t)o * n + s] = 2.0f * r / (float)n;
+      for (int o = 0; o < kNOUT; ++o) {
+        const float r = y[o] - tg[(int64_t)s * kNOUT + o] / norm[2 * kNIN + o];
+        l = fmaf(r, r, l);
+        A.dy[(int64_t)o * n + s] = 2.0f * r / (float)n;
+      }
+    } else {
+      // no target: keep the output for the one-step objective
+#pragma unroll
+      for (int o = 0; o < kNOUT; ++o) A.dy[(int64_t)o * n + s] = y[o];
     }
   }
   // block sum of the squared residuals (fixed order)
@@ -197,6 +318,77 @@ __global__ __launch_bounds__(kTB) void k_backward(const float *__restrict__ p, i
     for (int i = 0; i < kNH; ++i) d = fmaf(P[kOffW2 + i * kNH + k], dz2[i], d);
     A.dz1[(int64_t)k * n + s] = d * A.g1[(int64_t)k * n + s];
   }
+}
+
+// One-step objective, network-dependent part (FP32).  Node s of the batch is
+// node s % Nc of snapshot s / Nc (periodic nc x nc).  D = sigma_out * y with
+// y = A.dy from k_forward.  res[2][n] = r0 + sum_i c_i (1 - omega) w_i
+// R_i(u(X - c_i)) . D(X - c_i); loss_part = per-workgroup sums of |res|^2.
+__global__ __launch_bounds__(kTB) void k_onestep_fwd(const float *__restrict__ x,
+                                                     const float *__restrict__ r0,
+                                                     const float *__restrict__ norm, int nsnap,
+                                                     int nc, float om1, Acts A,
+                                                     float *__restrict__ res,
+                                                     float *__restrict__ loss_part) {
+  __shared__ float red[kTB / 64];
+  const int Nc = nc * nc, n = nsnap * Nc;
+  const int s = blockIdx.x * kTB + threadIdx.x;
+  float l = 0.0f;
+  if (s < n) {
+    const int sn = s / Nc, c = s - sn * Nc;
+    const int cy = c / nc, cx = c - cy * nc;
+    const float so0 = norm[2 * kNIN + 0], so1 = norm[2 * kNIN + 1], so2 = norm[2 * kNIN + 2];
+    float jx = r0[2 * (int64_t)s], jy = r0[2 * (int64_t)s + 1];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int yx = (cx - rr::cx(i) + nc) % nc, yy = (cy - rr::cy(i) + nc) % nc;
+      const int q = sn * Nc + yy * nc + yx;
+      const float ux = x[(int64_t)q * kNIN + 1], uy = x[(int64_t)q * kNIN + 2];
+      const float dxx = so0 * A.dy[q], dxy = so1 * A.dy[(int64_t)n + q],
+                  dyy = so2 * A.dy[2 * (int64_t)n + q];
+      const float d = om1 * reg_expand<float>(i, ux, uy, dxx, dxy, dyy) / wdiv(i);
+      if (rr::cx(i)) jx = fmaf((float)rr::cx(i), d, jx);
+      if (rr::cy(i)) jy = fmaf((float)rr::cy(i), d, jy);
+    }
+    res[s] = jx;
+    res[(int64_t)n + s] = jy;
+    l = fmaf(jx, jx, jy * jy);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) l += __shfl_xor(l, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Transpose stencil: dL/dy_k(Y) = sigma_out_k scale om1 sum_i (c_i . res(Y +
+// c_i)) w_i dR_i/dD_k(u(Y)), scale = 2 / den; written to A.dy (the outputs
+// it overwrites are no longer needed).
+__global__ __launch_bounds__(kTB) void k_onestep_adj(const float *__restrict__ x,
+                                                     const float *__restrict__ norm, int nsnap,
+                                                     int nc, float om1, float scale, Acts A,
+                                                     const float *__restrict__ res) {
+  const int Nc = nc * nc, n = nsnap * Nc;
+  const int s = blockIdx.x * kTB + threadIdx.x;
+  if (s >= n) return;
+  const int sn = s / Nc, c = s - sn * Nc;
+  const int cy = c / nc, cx = c - cy * nc;
+  const float ux = x[(int64_t)s * kNIN + 1], uy = x[(int64_t)s * kNIN + 2];
+  float gxx = 0.0f, gxy = 0.0f, gyy = 0.0f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int xx = (cx + rr::cx(i) + nc) % nc, xy = (cy + rr::cy(i) + nc) % nc;
+    const int q = sn * Nc + xy * nc + xx;
+    const float m = ((float)rr::cx(i) * res[q] + (float)rr::cy(i) * res[(int64_t)n + q]) / wdiv(i);
+    // columns of the linear map D -> R_i . D
+    gxx = fmaf(m, reg_expand<float>(i, ux, uy, 1.0f, 0.0f, 0.0f), gxx);
+    gxy = fmaf(m, reg_expand<float>(i, ux, uy, 0.0f, 1.0f, 0.0f), gxy);
+    gyy = fmaf(m, reg_expand<float>(i, ux, uy, 0.0f, 0.0f, 1.0f), gyy);
+  }
+  const float k = scale * om1;
+  A.dy[s] = norm[2 * kNIN + 0] * k * gxx;
+  A.dy[(int64_t)n + s] = norm[2 * kNIN + 1] * k * gxy;
+  A.dy[2 * (int64_t)n + s] = norm[2 * kNIN + 2] * k * gyy;
 }
 
 // Gradient reduction: out[chunk][param] = sum over the chunk's samples of
@@ -276,7 +468,7 @@ __global__ __launch_bounds__(kTB) void k_grad_chunks(int n, Acts A, float *__res
 }
 
 __global__ void k_grad_final(const float *__restrict__ part, int nchunks,
-                             const float *__restrict__ loss_part, int nlb, int n,
+                             const float *__restrict__ loss_part, int nlb, double loss_scale,
                              float *__restrict__ grad, float *__restrict__ loss) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < kNParam) {
@@ -287,7 +479,7 @@ __global__ void k_grad_final(const float *__restrict__ part, int nchunks,
   if (q == 0 && loss) {
     double l = 0.0;
     for (int b = 0; b < nlb; ++b) l += loss_part[b];
-    *loss = (float)(l / n);
+    *loss = (float)(l * loss_scale);
   }
 }
 
@@ -315,6 +507,7 @@ struct rrmhd_trainer {
   float *acts = nullptr;  // SoA activations
   float *part = nullptr;  // [chunks][4931]
   float *loss_part = nullptr;
+  float *res = nullptr;  // one-step residuals [2][cap]
   rr::Acts A{};
 };
 
@@ -339,6 +532,7 @@ int rrmhd_train_destroy(rrmhd_trainer *t) {
   if (t->acts) (void)hipFree(t->acts);
   if (t->part) (void)hipFree(t->part);
   if (t->loss_part) (void)hipFree(t->loss_part);
+  if (t->res) (void)hipFree(t->res);
   delete t;
   return RRMHD_OK;
 }
@@ -357,6 +551,7 @@ int rrmhd_train_create(int64_t max_batch, void *hip_stream, rrmhd_trainer **out)
   hipError_t e = hipMalloc((void **)&t->acts, sizeof(float) * per * max_batch);
   if (e == hipSuccess) e = hipMalloc((void **)&t->part, sizeof(float) * chunks * rr::kNParam);
   if (e == hipSuccess) e = hipMalloc((void **)&t->loss_part, sizeof(float) * lblocks);
+  if (e == hipSuccess) e = hipMalloc((void **)&t->res, sizeof(float) * 2 * max_batch);
   if (e != hipSuccess) {
     int rc = terr(e, "hipMalloc(trainer)");
     rrmhd_train_destroy(t);
@@ -366,13 +561,11 @@ int rrmhd_train_create(int64_t max_batch, void *hip_stream, rrmhd_trainer **out)
   return RRMHD_OK;
 }
 
-int rrmhd_train_loss_grad(rrmhd_trainer *t, const float *params, const float *norm,
-                          const float *x, const float *target, int64_t n, float *grad,
-                          float *loss) {
-  if (!t || !params || !norm || !x || !target || !grad || n < 1 || n > t->cap)
-    return RRMHD_EINVAL;
+}  // extern "C"
+
+// SoA activation arrays of a batch of n samples inside the trainer's buffer.
+static rr::Acts acts_of(const rrmhd_trainer *t, int64_t N) {
   float *a = t->acts;
-  const int64_t N = n;
   rr::Acts A;
   A.xh = a;
   a += rr::kNIN * N;
@@ -389,20 +582,63 @@ int rrmhd_train_loss_grad(rrmhd_trainer *t, const float *params, const float *no
   A.dz1 = a;
   a += rr::kNH * N;
   A.dz2 = a;
+  return A;
+}
+
+// Reverse mode from dL/dy in A.dy to the parameter gradient, and the loss
+// from the per-workgroup partial sums.
+static int backward_and_reduce(rrmhd_trainer *t, const float *params, const rr::Acts &A,
+                               int64_t n, int nlb, double loss_scale, float *grad,
+                               float *loss) {
   const int nb = (int)((n + rr::kTB - 1) / rr::kTB);
   const int nch = (int)((n + rr::kChunk - 1) / rr::kChunk);
-  hipLaunchKernelGGL(rr::k_forward, dim3(nb), dim3(rr::kTB), 0, t->st, params, norm, x, target,
-                     (int)n, A, t->loss_part);
-  THIP(hipGetLastError());
   hipLaunchKernelGGL(rr::k_backward, dim3(nb), dim3(rr::kTB), 0, t->st, params, (int)n, A);
   THIP(hipGetLastError());
   hipLaunchKernelGGL(rr::k_grad_chunks, dim3(nch, (rr::kNParam + rr::kTB - 1) / rr::kTB),
                      dim3(rr::kTB), 0, t->st, (int)n, A, t->part);
   THIP(hipGetLastError());
   hipLaunchKernelGGL(rr::k_grad_final, dim3((rr::kNParam + 255) / 256), dim3(256), 0, t->st,
-                     t->part, nch, t->loss_part, nb, (int)n, grad, loss);
+                     t->part, nch, t->loss_part, nlb, loss_scale, grad, loss);
   THIP(hipGetLastError());
   return RRMHD_OK;
+}
+
+extern "C" {
+
+int rrmhd_train_loss_grad(rrmhd_trainer *t, const float *params, const float *norm,
+                          const float *x, const float *target, int64_t n, float *grad,
+                          float *loss) {
+  if (!t || !params || !norm || !x || !target || !grad || n < 1 || n > t->cap)
+    return RRMHD_EINVAL;
+  const rr::Acts A = acts_of(t, n);
+  const int nb = (int)((n + rr::kTB - 1) / rr::kTB);
+  hipLaunchKernelGGL(rr::k_forward, dim3(nb), dim3(rr::kTB), 0, t->st, params, norm, x, target,
+                     (int)n, A, t->loss_part);
+  THIP(hipGetLastError());
+  return backward_and_reduce(t, params, A, n, nb, 1.0 / (double)n, grad, loss);
+}
+
+int rrmhd_train_onestep_loss_grad(rrmhd_trainer *t, const float *params, const float *norm,
+                                  const float *x, const float *r0, int nsnap, int nc,
+                                  double tau_c, double den, float *grad, float *loss) {
+  if (!t || !params || !norm || !x || !r0 || !grad || nsnap < 1 || nc < 1 ||
+      !(tau_c > 0.5) || !(den > 0.0) || !std::isfinite(den))
+    return RRMHD_EINVAL;
+  const int64_t n = (int64_t)nsnap * nc * nc;
+  if (n > t->cap || n > INT32_MAX) return RRMHD_EINVAL;
+  const rr::Acts A = acts_of(t, n);
+  const int nb = (int)((n + rr::kTB - 1) / rr::kTB);
+  const float om1 = (float)(1.0 - 1.0 / tau_c);
+  hipLaunchKernelGGL(rr::k_forward, dim3(nb), dim3(rr::kTB), 0, t->st, params, norm, x,
+                     (const float *)nullptr, (int)n, A, t->loss_part);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_onestep_fwd, dim3(nb), dim3(rr::kTB), 0, t->st, x, r0, norm, nsnap,
+                     nc, om1, A, t->res, t->loss_part);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_onestep_adj, dim3(nb), dim3(rr::kTB), 0, t->st, x, norm, nsnap, nc,
+                     om1, (float)(2.0 / den), A, (const float *)t->res);
+  THIP(hipGetLastError());
+  return backward_and_reduce(t, params, A, n, nb, 1.0 / den, grad, loss);
 }
 
 int rrmhd_train_adam(rrmhd_trainer *t, float *params, float *m, float *v, const float *grad,
@@ -430,6 +666,38 @@ int rrmhd_train_samples(const double *rho, const double *u, const double *b, int
                      work);
   THIP(hipGetLastError());
   hipLaunchKernelGGL(rr::k_samples, dim3(blocks), dim3(256), 0, st, work, nc, tau_c, x, target);
+  THIP(hipGetLastError());
+  return RRMHD_OK;
+}
+
+int rrmhd_train_onestep_samples(const double *rho0, const double *u0, const double *b0,
+                                const double *rho1, const double *u1, const double *b1,
+                                int nf, int factor, double tau_c, double *work, float *x,
+                                float *r0, double *den, void *hip_stream) {
+  if (!rho0 || !u0 || !b0 || !rho1 || !u1 || !b1 || !work || !x || !r0 || !den ||
+      factor < 1 || nf < factor || nf % factor != 0 || !(tau_c > 0.5))
+    return RRMHD_EINVAL;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const int nc = nf / factor;
+  const int64_t Nc = (int64_t)nc * nc;
+  const int blocks = (int)((Nc + 255) / 256);
+  // work: filtered fields at t [10][Nc] and t + factor [10][Nc], FP64
+  // features [8][Nc], per-node |j_bar(t + factor) - j_bar(t)|^2 [Nc]: 29 Nc
+  double *flt0 = work, *flt1 = work + rr::kFilt * Nc, *feat = work + 2 * rr::kFilt * Nc;
+  double *dm = feat + 8 * Nc;
+  hipLaunchKernelGGL(rr::k_box_filter, dim3(blocks), dim3(256), 0, st, rho0, u0, b0, nf, factor,
+                     flt0);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_box_filter, dim3(blocks), dim3(256), 0, st, rho1, u1, b1, nf, factor,
+                     flt1);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_features64, dim3(blocks), dim3(256), 0, st, (const double *)flt0, nc,
+                     tau_c, feat);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_onestep_prep, dim3(blocks), dim3(256), 0, st, (const double *)flt0,
+                     (const double *)flt1, (const double *)feat, nc, 1.0 / tau_c, x, r0, dm);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_sum64, dim3(1), dim3(256), 0, st, (const double *)dm, Nc, den);
   THIP(hipGetLastError());
   return RRMHD_OK;
 }

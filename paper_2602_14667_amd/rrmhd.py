@@ -30,6 +30,7 @@ EXPORTED = [
     "rrmhd_autotune", "rrmhd_batch_autotune",
     "rrmhd_closure_set", "rrmhd_closure_enable", "rrmhd_closure_eval",
     "rrmhd_train_samples", "rrmhd_train_create", "rrmhd_train_loss_grad",
+    "rrmhd_train_onestep_samples", "rrmhd_train_onestep_loss_grad",
     "rrmhd_train_adam", "rrmhd_train_destroy", "rrmhd_train_last_error_detail",
     "rrmhd_current_vorticity",
 ]
@@ -114,6 +115,12 @@ def lib():
                                           vp, vp, vp, vp]
         L.rrmhd_train_create.argtypes = [i64, vp, ctypes.POINTER(vp)]
         L.rrmhd_train_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.rrmhd_train_onestep_samples.argtypes = [vp, vp, vp, vp, vp, vp, ci, ci,
+                                                  ctypes.c_double, vp, vp, vp, vp,
+                                                  vp]
+        L.rrmhd_train_onestep_loss_grad.argtypes = [vp, vp, vp, vp, vp, ci, ci,
+                                                    ctypes.c_double,
+                                                    ctypes.c_double, vp, vp]
         fl = ctypes.c_float
         L.rrmhd_train_adam.argtypes = [vp, vp, vp, vp, vp, fl, fl, fl, fl, ci]
         L.rrmhd_train_destroy.argtypes = [vp]
@@ -461,6 +468,28 @@ def train_samples(rho, u, b, factor, tau_c, stream=None):
     return x, t
 
 
+def train_onestep_samples(m0, m1, factor, tau_c, stream=None):
+    """One-step objective data from fine FP64 device moments m0 = (rho, u, b)
+    at t and m1 at t + factor: (x[Nc][8] FP32, r0[Nc][2] FP32, den[1] FP64),
+    all on the device."""
+    import torch
+    rho0, u0, b0 = m0
+    rho1, u1, b1 = m1
+    nf = rho0.shape[0]
+    nc = nf // factor
+    dev = rho0.device
+    work = torch.empty(29 * nc * nc, dtype=torch.float64, device=dev)
+    x = torch.empty((nc * nc, 8), dtype=torch.float32, device=dev)
+    r0 = torch.empty((nc * nc, 2), dtype=torch.float32, device=dev)
+    den = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(lib().rrmhd_train_onestep_samples(
+        _ptr_t(rho0), _ptr_t(u0), _ptr_t(b0), _ptr_t(rho1), _ptr_t(u1),
+        _ptr_t(b1), nf, int(factor), float(tau_c), _ptr_t(work), _ptr_t(x),
+        _ptr_t(r0), _ptr_t(den), _stream_handle(stream)),
+        "rrmhd_train_onestep_samples")
+    return x, r0, den
+
+
 class Trainer:
     """FP32 training kernels of the closure network."""
 
@@ -487,6 +516,13 @@ class Trainer:
                                            int(x.shape[0]), _ptr_t(grad),
                                            _ptr_t(loss)),
                "rrmhd_train_loss_grad")
+
+    def onestep_loss_grad(self, params, norm, x, r0, nsnap, nc, tau_c, den,
+                          grad, loss=None):
+        _check(lib().rrmhd_train_onestep_loss_grad(
+            self._h, _ptr_t(params), _ptr_t(norm), _ptr_t(x), _ptr_t(r0),
+            int(nsnap), int(nc), float(tau_c), float(den), _ptr_t(grad),
+            _ptr_t(loss)), "rrmhd_train_onestep_loss_grad")
 
     def adam(self, params, m, v, grad, lr, step, beta1=0.9, beta2=0.999,
              eps=1e-8):

@@ -133,3 +133,142 @@ def test_short_fit_reduces_loss():
     note(f"  loss {l0:.4f} -> {loss.item():.4f}")
     assert loss.item() < 0.2 * l0
     tr.close()
+
+
+# ---- one-step solver-in-the-loop objective ---------------------------------
+
+def fine_pair(nf, tau_f, fac, steps, seed):
+    """Fine moments at t and t + fac from the oracle's run (FP64, CPU)."""
+    u, b = inputs.turbulence(nf, 0.04, seed_psi=2 * seed + 1, seed_a=2 * seed + 2)
+    o = oracle.Oracle(nf, nf, tau_f, tau_f)
+    o.init(u, b)
+    o.step(steps)
+    m0 = o.moments()
+    o.step(fac)
+    m1 = o.moments()
+    o.close()
+    return m0, m1
+
+
+def onestep_norm(x):
+    """Feature statistics and an output scale of the order of a_CE."""
+    nm = np.concatenate([x.mean(0), x.std(0) + 1e-12, x[:, 5:8].std(0)])
+    return nm.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("nf", [64, 96])
+def test_onestep_samples_vs_oracle(nf):
+    """Restart features, the uncorrected one-step residual and the
+    denominator against the oracle, which builds the restart populations,
+    runs one solver step and takes the momentum of the result."""
+    note(f"one-step samples {nf} -> {nf // 4}")
+    rr = R()
+    fac, tf = 4, 0.8
+    tc = 0.5 + (tf - 0.5) / fac
+    m0, m1 = fine_pair(nf, tf, fac, 40, seed=1)
+    _, r_ref, x_ref, den_ref = oracle.onestep_objective(m0, m1, fac, tc)
+    x, r0, den = rr.train_onestep_samples(tuple(f64(a) for a in m0),
+                                          tuple(f64(a) for a in m1), fac, tc)
+    x, r0, den = x.cpu().numpy(), r0.cpu().numpy(), float(den.item())
+    for k in range(8):
+        e = np.linalg.norm(x[:, k] - x_ref[:, k]) / np.linalg.norm(x_ref[:, k])
+        assert e < 1e-6, (k, e)
+    e = np.linalg.norm(r0 - r_ref) / np.linalg.norm(r_ref)
+    note(f"  r0 rel L2 {e:.3e}, den {den:.6e} vs {den_ref:.6e}")
+    assert e < 1e-6
+    assert abs(den / den_ref - 1) < 1e-12
+
+
+def test_onestep_loss_and_gradient_vs_fp64():
+    """Two snapshots in one call: loss and gradient of the FP32 kernels
+    (network, correction stencil, its transpose, reverse mode) against the
+    oracle's FP64 chain, fed the oracle's own restart data."""
+    note("one-step loss/grad, 2 snapshots 64 -> 16")
+    rr = R()
+    fac, tf = 4, 0.8
+    tc = 0.5 + (tf - 0.5) / fac
+    pairs = [fine_pair(64, tf, fac, 40, seed=s) for s in (1, 2)]
+    data = [oracle.onestep_objective(m0, m1, fac, tc) for m0, m1 in pairs]
+    X = np.concatenate([d[2] for d in data]).astype(np.float32).astype(np.float64)
+    R0 = np.concatenate([d[1] for d in data])
+    dens = [d[3] for d in data]
+    nm = onestep_norm(X)
+    p = params(np.random.default_rng(11))
+    # oracle: L = sum num / sum den, gradient weighted by each den
+    Ls, gs = zip(*[oracle.onestep_loss_grad(p, nm, m0, m1, fac, tc) for m0, m1 in pairs])
+    D = sum(dens)
+    L_ref = sum(l * d for l, d in zip(Ls, dens)) / D
+    g_ref = sum(g * d for g, d in zip(gs, dens)) / D
+    tr = rr.Trainer(2 * 16 * 16)
+    grad = torch.empty(4931, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    tr.onestep_loss_grad(f32(p), f32(nm), f32(X), f32(R0), 2, 16, tc, D, grad, loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    e = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    note(f"  grad rel L2 {e:.3e}, loss {loss.item():.6e} vs {L_ref:.6e} (L0 "
+         f"{sum(d[0] * d[3] for d in data) / D:.6e})")
+    assert e < 1e-4
+    assert abs(loss.item() / L_ref - 1) < 1e-5
+    grad2 = torch.empty_like(grad)
+    tr.onestep_loss_grad(f32(p), f32(nm), f32(X), f32(R0), 2, 16, tc, D, grad2, None)
+    assert torch.equal(grad, grad2)
+    tr.close()
+
+
+def test_onestep_zero_output_layer_gives_the_uncorrected_loss():
+    """A network with a zero output layer corrects nothing: the loss is the
+    uncorrected sum |r0|^2 / den, and only the output layer gets a gradient."""
+    note("one-step zero output layer")
+    rr = R()
+    fac, tf = 4, 0.8
+    tc = 0.5 + (tf - 0.5) / fac
+    m0, m1 = fine_pair(64, tf, fac, 40, seed=3)
+    L0, r_ref, x_ref, den = oracle.onestep_objective(m0, m1, fac, tc)
+    p = params(np.random.default_rng(12))
+    p[4736:] = 0.0
+    nm = onestep_norm(x_ref)
+    tr = rr.Trainer(256)
+    grad = torch.empty(4931, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    tr.onestep_loss_grad(f32(p), f32(nm), f32(x_ref), f32(r_ref), 1, 16, tc, den, grad, loss)
+    g = grad.cpu().numpy()
+    assert abs(loss.item() / L0 - 1) < 1e-6
+    assert np.all(g[:4736] == 0.0) and np.any(g[4736:] != 0.0)
+    tr.close()
+
+
+def test_onestep_short_fit_reduces_loss():
+    """Adam on the one-step objective over under-resolved snapshots (16^2
+    coarse from 64^2): the corrected coarse step must track the filtered fine
+    momentum better than the uncorrected one."""
+    note("one-step short fit")
+    rr = R()
+    fac, tf = 4, 0.8
+    tc = 0.5 + (tf - 0.5) / fac
+    pairs = [fine_pair(64, tf, fac, 40 + 20 * k, seed=4) for k in range(4)]
+    data = [oracle.onestep_objective(m0, m1, fac, tc) for m0, m1 in pairs]
+    X = np.concatenate([d[2] for d in data])
+    R0 = np.concatenate([d[1] for d in data])
+    D = sum(d[3] for d in data)
+    L0 = sum(d[0] * d[3] for d in data) / D
+    nm = onestep_norm(X)
+    p = params(np.random.default_rng(13))
+    p[4736:] = 0.0
+    tr = rr.Trainer(4 * 256)
+    pd, md, vd = f32(p), f32(np.zeros(4931)), f32(np.zeros(4931))
+    xd, rd, nd = f32(X), f32(R0), f32(nm)
+    grad = torch.empty(4931, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    for step in range(1, 301):
+        tr.onestep_loss_grad(pd, nd, xd, rd, 4, 16, tc, D, grad, loss)
+        tr.adam(pd, md, vd, grad, 3e-3, step)
+    tr.onestep_loss_grad(pd, nd, xd, rd, 4, 16, tc, D, grad, loss)
+    note(f"  loss {L0:.4f} -> {loss.item():.4f}")
+    assert loss.item() < 0.8 * L0
+    # the trained network's objective, evaluated by the oracle's solver step
+    pt = pd.cpu().numpy().astype(np.float64)
+    L_or = [oracle.onestep_objective(
+        m0, m1, fac, tc, oracle.mlp_forward(pt, nm, d[2]) * nm[16:19])[0] * d[3]
+        for (m0, m1), d in zip(pairs, data)]
+    assert abs(sum(L_or) / D / loss.item() - 1) < 1e-3
+    tr.close()
