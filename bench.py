@@ -215,6 +215,7 @@ def closure_bench(args):
         "train_loss_first_last": [res["train_loss"][0], res["train_loss"][-1]],
         "onestep_objective": {"train": res["onestep_objective"],
                               "validation": res["onestep_objective_val"]},
+        "alpha": res["alpha"], "calibration": res["calibration"],
         "fallbacks": [t["fallback_at"] for t in tests]}), flush=True)
 
 

@@ -70,13 +70,14 @@ def orszag_tang(n: int, u0: float, b0: float, perturb: float = 0.0,
     return np.ascontiguousarray(u), np.ascontiguousarray(b)
 
 
-def orszag_tang_paper(n: int):
-    """Orszag-Tang in the paper's low-Re unit mapping (Sec. III): lattice
-    amplitude 0.2/pi at n = 128 with diffusive scaling 128/n, tau for
-    Re = 200 pi and Pr_m = 1, and the step count of one physical time unit.
+def orszag_tang_paper(n: int, re: float = 200.0 * np.pi):
+    """Orszag-Tang in the paper's unit mapping (Sec. III): lattice amplitude
+    0.2/pi at n = 128 with diffusive scaling 128/n, tau for Reynolds number
+    re (Re = 200 pi in the low-Re case, 2500 and 5000 in the turbulent
+    cases) and Pr_m = 1, and the step count of one physical time unit.
     """
     ut = 0.2 / np.pi * 128.0 / n
-    nu_phys = 2.0 * 2.0 * np.pi / (200.0 * np.pi)  # Re = u0 L / nu, u0 = 2
+    nu_phys = 2.0 * 2.0 * np.pi / re  # Re = u0 L / nu, u0 = 2, L = 2 pi
     dx = 2.0 * np.pi / n
     dt = dx * ut / 2.0  # lattice speed ut <-> physical speed 2
     nu_lat = nu_phys * dt / dx ** 2
