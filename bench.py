@@ -179,6 +179,61 @@ def batch_bench(torch, rrmhd, inputs, args):
         "speedup_vs_sequential": round(seq_ms / ms, 3)}), flush=True)
 
 
+def closure_step_bench(torch, rrmhd, inputs, args):
+    """The fused step with the closure network (BF16 MFMA inside the
+    collision) against the plain step on the same grid, FP32 storage, a
+    random network with a nonzero output layer."""
+    import numpy as np
+    n = args.n
+    u, b = inputs.turbulence(n, 0.04)
+    ud, bd = torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda()
+    del u, b
+    g = np.random.default_rng(0)
+    p = np.zeros(4931, dtype=np.float32)
+    p[0:512] = g.standard_normal(512) / np.sqrt(8)
+    p[576:4672] = g.standard_normal(4096) / np.sqrt(64)
+    p[4736:4928] = g.standard_normal(192) / np.sqrt(64)
+    norm = np.concatenate([[1.0, 0, 0, 0, 0, 0, 0, 0], [0.01, 0.04, 0.04, 0.04, 0.04,
+                                                        1e-3, 1e-3, 1e-3], [1e-5] * 3])
+    pd = torch.from_numpy(p).cuda()
+    nd = torch.from_numpy(norm.astype(np.float32)).cuda()
+    st = torch.cuda.current_stream()
+    res = {}
+    for mode in ("plain", "closure"):
+        s = rrmhd.Solver(n, n, args.tau, args.tau)
+        s.init(ud, bd)
+        if mode == "closure":
+            s.closure_set(pd, nd)
+            s.closure_enable(True)
+        s.step(args.warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.step(args.steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        res[mode] = e0.elapsed_time(e1) / args.steps
+        s.close()
+    ms = res["closure"]
+    nodes = n * n
+    gbs = 152 * nodes / ms / 1e6
+    mfma_tf = 9216 * nodes / ms / 1e9
+    print(json.dumps({
+        "metric": "MLUPS (fused RR-MHD step with the closure network)",
+        "value": round(nodes / ms / 1e3, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": f"decaying 2D MHD turbulence {n}x{n} periodic, "
+                               "random closure network (8-64-64-3 GELU)",
+                   "nodes": nodes, "tau": args.tau},
+        "plain_ms_per_step": round(res["plain"], 4),
+        "closure_over_plain": round(ms / res["plain"], 3),
+        "hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+        "mfma_bf16_TFLOPs": round(mfma_tf, 2),
+        "mfma_frac": round(mfma_tf / 2500.0, 5)}), flush=True)
+
+
 def closure_bench(args):
     """Learned-closure protocol: coarse 512^2 (plain and with the trained
     network) against the 4x4-filtered 2048^2 run."""
@@ -232,10 +287,13 @@ def main():
                     help="copy: time the plain device-copy reference; sweep: "
                          "time launch shapes, XCD block orders and plane gaps")
     ap.add_argument("--copy-bytes", type=int, default=4 << 30)
-    ap.add_argument("--workload", choices=["turbulence", "batch", "closure"],
+    ap.add_argument("--workload", choices=["turbulence", "batch", "closure",
+                                           "closure-step"],
                     default="turbulence",
                     help="batch: the 256-domain ensemble; closure: the "
-                         "learned-closure protocol (coarse vs fine spectra)")
+                         "learned-closure protocol (coarse vs fine spectra); "
+                         "closure-step: the fused step with the closure "
+                         "network against the plain step (--n grid)")
     ap.add_argument("--closure-scale", choices=["full", "reduced"], default="full")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -260,6 +318,9 @@ def main():
     if args.workload == "closure":
         closure_bench(args)
         return
+    if args.workload == "closure-step":
+        closure_step_bench(torch, rrmhd, inputs, args)
+        return
     n = args.n
     u, b = inputs.turbulence(n, 0.04)
     ud = torch.from_numpy(u).cuda()
@@ -282,6 +343,15 @@ def main():
     wall = time.perf_counter() - t0
     ms_launches = e0.elapsed_time(e1)
     ek, em, dv = s.diagnostics()
+    # diagnostics (every K steps in a run, not per step): timed separately
+    d0 = torch.cuda.Event(enable_timing=True)
+    d1 = torch.cuda.Event(enable_timing=True)
+    d0.record(st)
+    for _ in range(5):
+        s.diagnostics()
+    d1.record(st)
+    torch.cuda.synchronize()
+    diag_ms = d0.elapsed_time(d1) / 5
     s.close()
 
     nodes = n * n
@@ -316,6 +386,7 @@ def main():
                      "traffic": traffic},
         "wall_s_timed": round(wall, 4),
         "diagnostics_after": {"E_kin": ek, "E_mag": em, "max_div_b": dv},
+        "diagnostics_ms_per_call": round(diag_ms, 4),
         "kernel_hash": kernel_hash(),
     }
     if not args.no_cpu_baseline:

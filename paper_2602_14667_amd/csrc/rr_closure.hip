@@ -52,7 +52,7 @@ struct ClosureHook {
 // Standalone inference: y[n][3] (normalised outputs) for raw features
 // x[n][8].  One wave per 64 samples; lanes past n evaluate a copy of
 // sample 0 and discard it.
-__global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev *__restrict__ g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_eval(const MlpDev *__restrict__ g,
                                                   const float *__restrict__ x,
                                                   float *__restrict__ y, int64_t n) {
   __shared__ MlpDev W;
@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev *__restrict__ g,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nw = (n + 63) / 64;
   for (int64_t w = (int64_t)blockIdx.x * 4 + wave; w < nw; w += (int64_t)gridDim.x * 4) {
+    asm volatile("" ::: "memory");  // weights stay in LDS (see k_step_closure)
     const int64_t s = w * 64 + lane;
     const int64_t sc = s < n ? s : 0;
     float xh[kNIN], out[kNOUT];
@@ -77,8 +78,10 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const MlpDev *__restrict__ g,
 // Fused step with the closure, periodic domain.  A tile is 64 x 4 nodes:
 // wave w of the block takes row 4 ty + w, lanes take 64 consecutive x.  The
 // grid is persistent so the parameters are staged into LDS once per block.
+// Register budget: 3 waves per SIMD (167 VGPRs, no AGPR or scratch use); a
+// budget of 4 spills the MLP's operands to scratch.
 template <class C, bool NT>
-__global__ __launch_bounds__(256) void k_step_closure(PlaneGeom G, CollideParams P,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_closure(PlaneGeom G, CollideParams P,
                                                       const MlpDev *__restrict__ g,
                                                       int tiles_x, int ntiles,
                                                       const typename C::T *__restrict__ src,
@@ -92,6 +95,9 @@ __global__ __launch_bounds__(256) void k_step_closure(PlaneGeom G, CollideParams
   constexpr uint32_t E = sizeof(T);
   const uint32_t pitch = G.nx * E;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // keep the weights in LDS: without this the compiler hoists their loads
+    // out of the tile loop and the register file overflows into AGPRs
+    asm volatile("" ::: "memory");
     const int ty = t / tiles_x, tx = t - ty * tiles_x;
     const int y = ty * 4 + wave;
     if (y >= G.ny) continue;  // whole wave idle (wave-uniform)

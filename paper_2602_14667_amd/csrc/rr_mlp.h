@@ -58,10 +58,15 @@ __host__ __device__ __forceinline__ float bf2f(uint16_t h) {
   return f;
 }
 
+// GELU in its tanh form, evaluated through the identity
+// z/2 (1 + tanh(v)) = z / (1 + exp(-2 v)), v = sqrt(2/pi) (z + 0.044715 z^3):
+// one hardware exp2 and one reciprocal instead of a tanh.  Large |v| give
+// exp2 -> inf (result -0 or 0) or -> 0 (result z), as the tanh form does.
 __device__ __forceinline__ float gelu_f(float z) {
-  const float k = 0.7978845608028654f;  // sqrt(2/pi)
-  const float z3 = z * z * z;
-  return 0.5f * z * (1.0f + tanhf(k * fmaf(0.044715f, z3, z)));
+  const float k2 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) / ln 2
+  const float v = fmaf(0.044715f * z, z * z, z);
+  const float e = __builtin_amdgcn_exp2f(k2 * v);
+  return z * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
 __device__ __forceinline__ shortx4 ld4(const uint16_t *p) {
@@ -88,6 +93,9 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
   float own[kNOUT] = {0.0f, 0.0f, 0.0f};
 #pragma unroll 1
   for (int nb = 0; nb < 2; ++nb) {
+    // weights are re-read from LDS in each pass: hoisting them out of this
+    // loop would hold ~200 loop-invariant values in registers
+    asm volatile("" ::: "memory");
     // layer 1, transposed: Z1^T (64 hidden x 32 nodes) = W1 (64 x 8) X^T
     const shortx4 bx = ld4(xs + (32 * nb + col) * kNIN + 4 * half);
     shortx4 b2op[8];  // layer-2 B operands: h1 rows 8 kk + 4 half + q

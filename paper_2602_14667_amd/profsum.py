@@ -7,6 +7,11 @@ PROF_DIR holds the rocprofv3 output directories written by
   rocprofv3 --pmc {FETCH_SIZE,WRITE_SIZE} --output-format csv -d PROF_DIR/pmc_<ctr>_{f32,f16,copy} -o run -- python3 bench.py ...
 Counter values (KiB per dispatch) are calibrated against the plain copy
 kernel of known size: factor = true bytes / counted bytes for that kernel.
+
+Second form, kernel-trace statistics of any workload:
+  python -m paper_2602_14667_amd.profsum stats STATS_DIR OUT.md KERNEL BYTES TITLE COMMAND
+writes the per-kernel table and, for the kernel whose name contains KERNEL,
+the average launch time and its algorithmic rate (BYTES per launch).
 """
 import csv
 import json
@@ -96,5 +101,30 @@ def main(prof, out, n):
     print("ok")
 
 
+def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command):
+    stats = kernel_stats(stats_dir)
+    bpl = float(bytes_per_launch)
+    names = [k for k in stats if kernel in k]
+    lines = [f"# {title}", "", "Command (from the repository root, on the GPU box):", "```",
+             command, f"python -m paper_2602_14667_amd.profsum stats {stats_dir} {out_md} "
+             f"{kernel} {bytes_per_launch} ...", "```", "",
+             "| kernel | calls | avg ns | min ns | max ns |", "|---|---|---|---|---|"]
+    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+        lines.append(f"| `{k[:90]}` | {v['calls']} | {v['avg_ns']:.0f} | {v['min_ns']:.0f} "
+                     f"| {v['max_ns']:.0f} |")
+    lines.append("")
+    for k in names:
+        avg = stats[k]["avg_ns"]
+        lines.append(f"* `{k[:90]}`: average launch {avg / 1e3:.1f} us; {bpl / 1e9:.4f} GB "
+                     f"algorithmic per launch -> {bpl / avg:.1f} GB/s = "
+                     f"{bpl / avg / 8000 * 100:.1f} % of 8 TB/s")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("ok")
+
+
 if __name__ == "__main__":
-    main(*sys.argv[1:4])
+    if sys.argv[1] == "stats":
+        stats_summary(*sys.argv[2:8])
+    else:
+        main(*sys.argv[1:4])
