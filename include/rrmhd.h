@@ -258,14 +258,20 @@ int rrmhd_train_onestep_samples(const double *rho0, const double *u0,
  * their summed denominators, host value > 0), where r = r0 plus the effect of
  * the correction D = sigma_out * y(x) added to a_1^(2) at every coarse node
  * before the recursion: one collision of the restart state and the pull of
- * one step.  The gradient is exact: the transpose of that stencil, then
- * reverse mode through the FP32 network.  nsnap nc^2 <= max_batch.
- * Asynchronous. */
+ * one step.  feedback = 1: the restart also carries the closure's own steady
+ * response q = (tau_c - 1) D0, D0 = sigma_out * y(x) (a correction added every
+ * step settles at a non-equilibrium (tau - 1) D), and the step's correction
+ * is D = sigma_out * y(x1) on the features x1 of that restart (a_1^(2)
+ * entries shifted by q), so the collision relaxes q + D; feedback = 0: the
+ * plain form.  The gradient is exact: the transpose of the stencil, then
+ * reverse mode through the FP32 network (through both evaluations in the
+ * feedback form).  nsnap nc^2 <= max_batch.  Asynchronous; EINVAL for
+ * feedback outside {0, 1}. */
 int rrmhd_train_onestep_loss_grad(rrmhd_trainer *t, const float *params,
                                   const float *norm, const float *x,
                                   const float *r0, int nsnap, int nc,
-                                  double tau_c, double den, float *grad,
-                                  float *loss);
+                                  double tau_c, double den, int feedback,
+                                  float *grad, float *loss);
 /* One Adam step (Kingma & Ba 2015) on params[4931] with moments m, v
  * (device FP32) at step number step >= 1.  Asynchronous. */
 int rrmhd_train_adam(rrmhd_trainer *t, float *params, float *m, float *v,

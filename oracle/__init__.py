@@ -90,7 +90,9 @@ def lib():
         L.orc_onestep_objective.restype = ctypes.c_double
         L.orc_onestep_objective.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp,
                                             ctypes.c_int, ctypes.c_int,
-                                            ctypes.c_double, _dp, _dp, _dp, _dp]
+                                            ctypes.c_double, _dp, _dp, _dp, _dp,
+                                            _dp]
+        L.orc_mlp_vjp_input.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int, _dp]
         L.orc_onestep_adjoint.argtypes = [_dp, ctypes.c_int, ctypes.c_double,
                                           _dp, _dp]
         _lib = L
@@ -216,12 +218,13 @@ def mlp_vjp(params, norm, x, dy):
     return g
 
 
-def onestep_objective(m0, m1, factor, tau_c, delta=None):
+def onestep_objective(m0, m1, factor, tau_c, delta=None, q=None):
     """One-step solver-in-the-loop objective of the closure.
 
     m0, m1: fine moments (rho, u, b) at t and t + factor.  delta: [Nc][3]
-    correction of a_1^(2) per coarse node (None: zero).  Returns (L, resid
-    [Nc][2], x [Nc][8] restart features, den)."""
+    correction of a_1^(2) per coarse node (None: zero).  q: [Nc][3] extra
+    non-equilibrium of the restart (None: zero).  Returns (L, resid [Nc][2],
+    x [Nc][8] restart features, den)."""
     rho0, u0, b0 = map(_f64, m0)
     rho1, u1, b1 = map(_f64, m1)
     nf = rho0.shape[0]
@@ -230,12 +233,14 @@ def onestep_objective(m0, m1, factor, tau_c, delta=None):
     x = np.zeros((nc * nc, 8))
     den = np.zeros(1)
     d = None if delta is None else _f64(delta)
-    if d is not None:
-        assert d.shape == (nc * nc, 3)
+    qq = None if q is None else _f64(q)
+    for a in (d, qq):
+        if a is not None:
+            assert a.shape == (nc * nc, 3)
     L = lib().orc_onestep_objective(_ptr(rho0), _ptr(u0), _ptr(b0), _ptr(rho1),
                                     _ptr(u1), _ptr(b1), nf, int(factor),
-                                    float(tau_c), _ptr(d), _ptr(resid), _ptr(x),
-                                    _ptr(den))
+                                    float(tau_c), _ptr(qq), _ptr(d), _ptr(resid),
+                                    _ptr(x), _ptr(den))
     return float(L), resid, x, float(den[0])
 
 
@@ -247,18 +252,44 @@ def onestep_adjoint(x, nc, tau_c, w):
     return out
 
 
-def onestep_loss_grad(params, norm, m0, m1, factor, tau_c):
+def mlp_vjp_input(params, norm, x, dy):
+    """Gradient of sum_s dy[s] . y(x_s) with respect to the raw inputs x."""
+    params, norm, x, dy = _f64(params), _f64(norm), _f64(x), _f64(dy)
+    gx = np.zeros_like(x)
+    lib().orc_mlp_vjp_input(_ptr(params), _ptr(norm), _ptr(x), _ptr(dy),
+                            x.shape[0], _ptr(gx))
+    return gx
+
+
+def onestep_loss_grad(params, norm, m0, m1, factor, tau_c, feedback=False):
     """(L, dL/dparams) of the one-step objective with delta = sigma_out * y(x),
     x the restart features: MLP forward, the objective, its adjoint, MLP
-    reverse mode."""
+    reverse mode.
+
+    feedback=True: the restart also carries the closure's own steady
+    response q = (tau_c - 1) D0, D0 = sigma_out * y(x_CE) (a correction D
+    added every step settles at a non-equilibrium (tau - 1) D), and the
+    step's correction is evaluated on the features of that restart, as a
+    closure run sees them; the gradient runs through both evaluations."""
     params, norm = _f64(params), _f64(norm)
     nc = np.asarray(m0[0]).shape[0] // factor
-    _, _, x, _ = onestep_objective(m0, m1, factor, tau_c)
     so = norm[16:19]
-    delta = mlp_forward(params, norm, x) * so
-    L, resid, _, den = onestep_objective(m0, m1, factor, tau_c, delta)
-    g_delta = onestep_adjoint(x, nc, tau_c, resid) * (2.0 / den)
-    return L, mlp_vjp(params, norm, x, g_delta * so)
+    _, _, x0, _ = onestep_objective(m0, m1, factor, tau_c)
+    if not feedback:
+        delta = mlp_forward(params, norm, x0) * so
+        L, resid, _, den = onestep_objective(m0, m1, factor, tau_c, delta)
+        g_delta = onestep_adjoint(x0, nc, tau_c, resid) * (2.0 / den)
+        return L, mlp_vjp(params, norm, x0, g_delta * so)
+    q = (tau_c - 1.0) * mlp_forward(params, norm, x0) * so
+    _, _, x1, _ = onestep_objective(m0, m1, factor, tau_c, q=q)
+    d1 = mlp_forward(params, norm, x1) * so
+    L, resid, _, den = onestep_objective(m0, m1, factor, tau_c, d1, q=q)
+    # the post-collision populations see E = q + d1
+    gE = onestep_adjoint(x1, nc, tau_c, resid) * (2.0 / den)
+    g1 = mlp_vjp(params, norm, x1, gE * so)
+    gq = gE + mlp_vjp_input(params, norm, x1, gE * so)[:, 5:8]
+    g0 = mlp_vjp(params, norm, x0, (tau_c - 1.0) * gq * so)
+    return L, g1 + g0
 
 
 class Oracle:

@@ -873,6 +873,32 @@ double orc_mlp_loss_grad(const double *params, const double *norm,
   return loss / n;
 }
 
+/* Input gradient: gx[s] = d/dx_s (dy[s] . y(x_s)) for raw features x[n][8]. */
+void orc_mlp_vjp_input(const double *params, const double *norm, const double *x,
+                       const double *dy, int n, double *gx) {
+  const double *p = params;
+  for (int s = 0; s < n; ++s) {
+    mlp_cache m;
+    mlp_forward(p, norm, x + (size_t)s * NIN, &m);
+    double dz2[NH], dz1[NH];
+    for (int k = 0; k < NH; ++k) {
+      double a = 0.0;
+      for (int o = 0; o < NOUT; ++o) a += p[OFF_W3 + o * NH + k] * dy[(size_t)s * NOUT + o];
+      dz2[k] = a * gelu_grad(m.z2[k]);
+    }
+    for (int k = 0; k < NH; ++k) {
+      double a = 0.0;
+      for (int i = 0; i < NH; ++i) a += p[OFF_W2 + i * NH + k] * dz2[i];
+      dz1[k] = a * gelu_grad(m.z1[k]);
+    }
+    for (int k = 0; k < NIN; ++k) {
+      double a = 0.0;
+      for (int i = 0; i < NH; ++i) a += p[OFF_W1 + i * NIN + k] * dz1[i];
+      gx[(size_t)s * NIN + k] = a / norm[NIN + k];
+    }
+  }
+}
+
 /* Vector-Jacobian product: grad = d/d(params) sum_s dy[s] . y(x_s), for
  * dy[n][3] (normalised output units). */
 void orc_mlp_vjp(const double *params, const double *norm, const double *x,
@@ -1016,9 +1042,10 @@ static void filter_rjb(const double *rho, const double *u, const double *b,
 }
 
 /* Restart populations (solver layout f[9][nc][nc], g[5][2][nc][nc]) from
- * filtered fields F[5][nc][nc]. */
-static void restart_state(const double *F, int nc, double tau_c, double *f,
-                          double *g) {
+ * filtered fields F[5][nc][nc]; q[Nc][3] (may be NULL) is an extra
+ * non-equilibrium (xx, xy, yy) added to a_CE. */
+static void restart_state(const double *F, int nc, double tau_c, const double *q,
+                          double *f, double *g) {
   const size_t Nc = (size_t)nc * nc;
   double *U = malloc(2 * Nc * sizeof(double));
   for (size_t c = 0; c < Nc; ++c) {
@@ -1038,6 +1065,12 @@ static void restart_state(const double *F, int nc, double tau_c, double *f,
       double a2[2][2];
       for (int a = 0; a < 2; ++a)
         for (int bb = 0; bb < 2; ++bb) a2[a][bb] = -rho * CS2 * tau_c * (gr[a][bb] + gr[bb][a]);
+      if (q) {
+        a2[0][0] += q[3 * c];
+        a2[0][1] += q[3 * c + 1];
+        a2[1][0] += q[3 * c + 1];
+        a2[1][1] += q[3 * c + 2];
+      }
       double feq[9], geq[10], a3[2][2][2], a4[2][2][2][2], r[9];
       feq_algorithm(rho, u, b, feq);
       geq_vector(u, b, geq);
@@ -1050,14 +1083,17 @@ static void restart_state(const double *F, int nc, double tau_c, double *f,
 }
 
 /* The objective for fine moments (rho0, u0, b0) at t and (rho1, u1, b1) at
- * t + fac (rho [nf][nf], u and b [2][nf][nf]) and a correction delta[Nc][3]
- * (NULL: none).  Returns L; optional outputs: resid[Nc][2] = j_c - j_bar(t +
+ * t + fac (rho [nf][nf], u and b [2][nf][nf]), an extra restart
+ * non-equilibrium q[Nc][3] (NULL: none; the closure's own steady response
+ * (tau_c - 1) D in the feedback form of the objective) and a correction
+ * delta[Nc][3] (NULL: none).  Returns L; optional outputs: resid[Nc][2] = j_c - j_bar(t +
  * fac), x[Nc][8] = the restart state's features (rho, u, b, a_1^(2)) computed
  * from its populations as the collision computes them, *den. */
 double orc_onestep_objective(const double *rho0, const double *u0, const double *b0,
                              const double *rho1, const double *u1, const double *b1,
-                             int nf, int fac, double tau_c, const double *delta,
-                             double *resid, double *x, double *den_out) {
+                             int nf, int fac, double tau_c, const double *q,
+                             const double *delta, double *resid, double *x,
+                             double *den_out) {
   build_tables();
   const int nc = nf / fac;
   const size_t Nc = (size_t)nc * nc;
@@ -1065,7 +1101,7 @@ double orc_onestep_objective(const double *rho0, const double *u0, const double 
   double *f = malloc(9 * Nc * sizeof(double)), *g = malloc(10 * Nc * sizeof(double));
   filter_rjb(rho0, u0, b0, nf, fac, F0);
   filter_rjb(rho1, u1, b1, nf, fac, F1);
-  restart_state(F0, nc, tau_c, f, g);
+  restart_state(F0, nc, tau_c, q, f, g);
   orc *h = orc_create(nc, nc, tau_c, tau_c, 0, 0.0, 0.0, 0.0, 0.0, FEQ_ALGORITHM);
   orc_set_state(h, f, g);
   if (x) {

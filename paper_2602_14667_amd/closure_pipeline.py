@@ -132,10 +132,12 @@ def train(x, t, norm, steps=2000, batch=65536, lr=1e-3, seed=0, log_every=0,
 
 
 def train_onestep(p, xs, rs, dens, norm, nc, tau_c, steps=1000, nodes=65536,
-                  lr=1e-3, seed=0, log_every=0):
+                  lr=1e-3, seed=0, log_every=0, feedback=True):
     """One-step solver-in-the-loop objective: Adam where each step uses
     ceil(nodes / nc^2) random whole snapshots (the correction stencil needs
-    the neighbours of every node).  Returns (params, loss history)."""
+    the neighbours of every node); feedback selects the form in which the
+    restart carries the closure's own steady response.  Returns (params,
+    loss history)."""
     import torch
     per = max(1, -(-nodes // (nc * nc)))
     per = min(per, len(xs))
@@ -154,7 +156,8 @@ def train_onestep(p, xs, rs, dens, norm, nc, tau_c, steps=1000, nodes=65536,
             xb = torch.cat([xs[k] for k in pick])
             rb = torch.cat([rs[k] for k in pick])
         den = float(sum(dens[k] for k in pick))
-        tr.onestep_loss_grad(p, norm, xb, rb, per, nc, tau_c, den, grad, loss)
+        tr.onestep_loss_grad(p, norm, xb, rb, per, nc, tau_c, den, grad, loss,
+                             feedback=feedback)
         tr.adam(p, m, v, grad, lr, step)
         if log_every and (step % log_every == 0 or step == 1):
             hist.append((step, float(loss.item())))
@@ -162,7 +165,7 @@ def train_onestep(p, xs, rs, dens, norm, nc, tau_c, steps=1000, nodes=65536,
     return p, hist
 
 
-def onestep_loss(p, xs, rs, dens, norm, nc, tau_c):
+def onestep_loss(p, xs, rs, dens, norm, nc, tau_c, feedback=True):
     """The one-step objective over all snapshots (device network)."""
     import torch
     tr = rrmhd.Trainer(nc * nc)
@@ -170,7 +173,8 @@ def onestep_loss(p, xs, rs, dens, norm, nc, tau_c):
     loss = torch.empty(1, dtype=torch.float32, device=p.device)
     num = 0.0
     for x, r, d in zip(xs, rs, dens):
-        tr.onestep_loss_grad(p, norm, x, r, 1, nc, tau_c, d, grad, loss)
+        tr.onestep_loss_grad(p, norm, x, r, 1, nc, tau_c, d, grad, loss,
+                             feedback=feedback)
         num += float(loss.item()) * d
     tr.close()
     return num / sum(dens)
@@ -260,7 +264,7 @@ def judge(run, ref, kmax):
 def pipeline(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
              train_seeds=range(16), val_seeds=range(16, 20), test_seeds=range(20, 24),
              train_steps=3000, onestep_steps=2000, batch=65536, lr=1e-3, n_times=5,
-             alphas=(1.0, 0.3, 0.1, 0.05, 0.03, 0.02, 0.01), log=print):
+             alphas=(1.0, 0.3, 0.1, 0.05, 0.03, 0.02, 0.01), feedback=True, log=print):
     """Full protocol; returns a dict of results.  Training: train_steps of
     a-priori regression (warm start), then onestep_steps of the one-step
     solver-in-the-loop objective (0: a-priori only).  The one-step objective
@@ -290,14 +294,16 @@ def pipeline(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
     params, hist = train(X, T, norm, steps=train_steps, batch=batch, lr=lr,
                          log_every=max(train_steps // 10, 1))
     del X, T
-    L_zero = onestep_loss(init_params(0), xs, rs, dens, norm, n_c, tc)
-    L_apriori = onestep_loss(params, xs, rs, dens, norm, n_c, tc)
+    fb = feedback
+    L_zero = onestep_loss(init_params(0), xs, rs, dens, norm, n_c, tc, fb)
+    L_apriori = onestep_loss(params, xs, rs, dens, norm, n_c, tc, fb)
     hist1 = []
     if onestep_steps:
         params, hist1 = train_onestep(params, xs, rs, dens, norm, n_c, tc,
                                       steps=onestep_steps, nodes=batch, lr=lr,
-                                      log_every=max(onestep_steps // 10, 1))
-    L_final = onestep_loss(params, xs, rs, dens, norm, n_c, tc)
+                                      log_every=max(onestep_steps // 10, 1),
+                                      feedback=fb)
+    L_final = onestep_loss(params, xs, rs, dens, norm, n_c, tc, fb)
     torch.cuda.synchronize()
     t_train = time.time() - t1
     log(f"training (a-priori): {hist}")
@@ -313,8 +319,8 @@ def pipeline(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
             vx += x
             vr += r
             vd += d
-        val = dict(no_closure=onestep_loss(init_params(0), vx, vr, vd, norm, n_c, tc),
-                   final=onestep_loss(params, vx, vr, vd, norm, n_c, tc))
+        val = dict(no_closure=onestep_loss(init_params(0), vx, vr, vd, norm, n_c, tc, fb),
+                   final=onestep_loss(params, vx, vr, vd, norm, n_c, tc, fb))
         log(f"one-step objective over the validation seeds: no closure "
             f"{val['no_closure']:.4f}, final {val['final']:.4f}")
         del vx, vr

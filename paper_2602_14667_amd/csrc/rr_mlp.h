@@ -51,7 +51,22 @@ __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__host__ __device__ __forceinline__ float bf2f(uint16_t h) {
+__host__ // Two FP32 values -> two BF16 (round to nearest even) packed low/high, one
+// v_cvt_pk_bf16_f32 on gfx950; same results as f2bf for finite values.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const floatx2 f = {lo, hi};
+  const bf16x2_t v = __builtin_convertvector(f, bf16x2_t);
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  return u;
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+
+__device__ __forceinline__ float bf2f(uint16_t h) {
   const uint32_t u = (uint32_t)h << 16;
   float f;
   __builtin_memcpy(&f, &u, 4);
@@ -85,8 +100,9 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5, col = lane & 31;
   // stage this node's features as row `lane` of X (64 x 8)
+  uint32_t *xrow = reinterpret_cast<uint32_t *>(xs + lane * kNIN);
 #pragma unroll
-  for (int k = 0; k < kNIN; ++k) xs[lane * kNIN + k] = f2bf(xh[k]);
+  for (int k = 0; k < kNIN / 2; ++k) xrow[k] = pack_bf16x2(xh[2 * k], xh[2 * k + 1]);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -106,13 +122,13 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
       acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, bx, acc, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        shortx4 v;
+        const int h = 32 * mb + 8 * r + 4 * half;
+        uint32_t w[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int h = 32 * mb + 8 * r + 4 * half + q;
-          v[q] = (short)f2bf(gelu_f(acc[4 * r + q] + W->b1[h]));
-        }
-        b2op[4 * mb + r] = v;
+        for (int q = 0; q < 4; q += 2)
+          w[q / 2] = pack_bf16x2(gelu_f(acc[4 * r + q] + W->b1[h + q]),
+                                 gelu_f(acc[4 * r + q + 1] + W->b1[h + q + 1]));
+        __builtin_memcpy(&b2op[4 * mb + r], w, 8);
       }
     }
     // layer 2, transposed: Z2^T (64 x 32 nodes) = W2 (64 x 64) H1^T
@@ -125,14 +141,19 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
         const shortx4 aw = ld4(W->w2 + (32 * mb2 + col) * kNH + 8 * kk + 4 * half);
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, b2op[kk], acc, 0, 0, 0);
       }
-      // layer 3 partial sums over this lane's 16 rows of h2
+      // layer 3 partial sums over this lane's 16 rows of h2 (h2 rounded to
+      // BF16 like the layer inputs)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < 16; i += 2) {
         const int h = 32 * mb2 + 8 * (i >> 2) + 4 * half + (i & 3);
-        const float h2 = bf2f(f2bf(gelu_f(acc[i] + W->b2[h])));
-        p0 = fmaf(W->w3[0 * kNH + h], h2, p0);
-        p1 = fmaf(W->w3[1 * kNH + h], h2, p1);
-        p2 = fmaf(W->w3[2 * kNH + h], h2, p2);
+        const uint32_t u = pack_bf16x2(gelu_f(acc[i] + W->b2[h]), gelu_f(acc[i + 1] + W->b2[h + 1]));
+        const float ha = bf16_lo(u), hb = bf16_hi(u);
+        p0 = fmaf(W->w3[0 * kNH + h], ha, p0);
+        p1 = fmaf(W->w3[1 * kNH + h], ha, p1);
+        p2 = fmaf(W->w3[2 * kNH + h], ha, p2);
+        p0 = fmaf(W->w3[0 * kNH + h + 1], hb, p0);
+        p1 = fmaf(W->w3[1 * kNH + h + 1], hb, p1);
+        p2 = fmaf(W->w3[2 * kNH + h + 1], hb, p2);
       }
     }
     // the other half of the wave holds the other 32 rows of the same nodes

@@ -324,10 +324,13 @@ __global__ __launch_bounds__(kTB) void k_backward(const float *__restrict__ p, i
 // node s % Nc of snapshot s / Nc (periodic nc x nc).  D = sigma_out * y with
 // y = A.dy from k_forward.  res[2][n] = r0 + sum_i c_i (1 - omega) w_i
 // R_i(u(X - c_i)) . D(X - c_i); loss_part = per-workgroup sums of |res|^2.
+// q (SoA [3][n], may be null) is added to D (feedback form: the restart's
+// extra non-equilibrium relaxes with the correction).
 __global__ __launch_bounds__(kTB) void k_onestep_fwd(const float *__restrict__ x,
                                                      const float *__restrict__ r0,
                                                      const float *__restrict__ norm, int nsnap,
                                                      int nc, float om1, Acts A,
+                                                     const float *__restrict__ q,
                                                      float *__restrict__ res,
                                                      float *__restrict__ loss_part) {
   __shared__ float red[kTB / 64];
@@ -342,10 +345,15 @@ __global__ __launch_bounds__(kTB) void k_onestep_fwd(const float *__restrict__ x
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const int yx = (cx - rr::cx(i) + nc) % nc, yy = (cy - rr::cy(i) + nc) % nc;
-      const int q = sn * Nc + yy * nc + yx;
-      const float ux = x[(int64_t)q * kNIN + 1], uy = x[(int64_t)q * kNIN + 2];
-      const float dxx = so0 * A.dy[q], dxy = so1 * A.dy[(int64_t)n + q],
-                  dyy = so2 * A.dy[2 * (int64_t)n + q];
+      const int qn = sn * Nc + yy * nc + yx;
+      const float ux = x[(int64_t)qn * kNIN + 1], uy = x[(int64_t)qn * kNIN + 2];
+      float dxx = so0 * A.dy[qn], dxy = so1 * A.dy[(int64_t)n + qn],
+            dyy = so2 * A.dy[2 * (int64_t)n + qn];
+      if (q) {
+        dxx += q[qn];
+        dxy += q[(int64_t)n + qn];
+        dyy += q[2 * (int64_t)n + qn];
+      }
       const float d = om1 * reg_expand<float>(i, ux, uy, dxx, dxy, dyy) / wdiv(i);
       if (rr::cx(i)) jx = fmaf((float)rr::cx(i), d, jx);
       if (rr::cy(i)) jy = fmaf((float)rr::cy(i), d, jy);
@@ -364,10 +372,12 @@ __global__ __launch_bounds__(kTB) void k_onestep_fwd(const float *__restrict__ x
 // Transpose stencil: dL/dy_k(Y) = sigma_out_k scale om1 sum_i (c_i . res(Y +
 // c_i)) w_i dR_i/dD_k(u(Y)), scale = 2 / den; written to A.dy (the outputs
 // it overwrites are no longer needed).
+// gE (SoA [3][n], may be null) receives dL/dD itself (before sigma_out).
 __global__ __launch_bounds__(kTB) void k_onestep_adj(const float *__restrict__ x,
                                                      const float *__restrict__ norm, int nsnap,
                                                      int nc, float om1, float scale, Acts A,
-                                                     const float *__restrict__ res) {
+                                                     const float *__restrict__ res,
+                                                     float *__restrict__ gE) {
   const int Nc = nc * nc, n = nsnap * Nc;
   const int s = blockIdx.x * kTB + threadIdx.x;
   if (s >= n) return;
@@ -389,6 +399,55 @@ __global__ __launch_bounds__(kTB) void k_onestep_adj(const float *__restrict__ x
   A.dy[s] = norm[2 * kNIN + 0] * k * gxx;
   A.dy[(int64_t)n + s] = norm[2 * kNIN + 1] * k * gxy;
   A.dy[2 * (int64_t)n + s] = norm[2 * kNIN + 2] * k * gyy;
+  if (gE) {
+    gE[s] = k * gxx;
+    gE[(int64_t)n + s] = k * gxy;
+    gE[2 * (int64_t)n + s] = k * gyy;
+  }
+}
+
+// Feedback form, first network pass done (outputs y0 in A0.dy): the
+// restart's extra non-equilibrium q = (tau_c - 1) sigma_out y0 (SoA), and
+// the features x1 of that restart (a_1^(2) entries shifted by q).
+__global__ __launch_bounds__(kTB) void k_feedback_x1(const float *__restrict__ x,
+                                                     const float *__restrict__ norm, int n,
+                                                     float tm1, Acts A0, float *__restrict__ q,
+                                                     float *__restrict__ x1) {
+  const int s = blockIdx.x * kTB + threadIdx.x;
+  if (s >= n) return;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) x1[(int64_t)s * kNIN + k] = x[(int64_t)s * kNIN + k];
+#pragma unroll
+  for (int o = 0; o < kNOUT; ++o) {
+    const float v = tm1 * (norm[2 * kNIN + o] * A0.dy[(int64_t)o * n + s]);
+    q[(int64_t)o * n + s] = v;
+    x1[(int64_t)s * kNIN + 5 + o] = x[(int64_t)s * kNIN + 5 + o] + v;
+  }
+}
+
+// Feedback form, after reverse mode through the second pass (dz1 in A1):
+// dL/dq = gE + dL/dx1 (a_1^(2) entries, through the second pass's input),
+// and the first pass's output gradient dL/dy0 = sigma_out (tau_c - 1) dL/dq.
+__global__ __launch_bounds__(kTB) void k_feedback_back(const float *__restrict__ p,
+                                                       const float *__restrict__ norm, int n,
+                                                       float tm1, Acts A1,
+                                                       const float *__restrict__ gE, Acts A0) {
+  __shared__ float W1[kNH * kNIN];
+  for (int k = threadIdx.x; k < kNH * kNIN; k += kTB) W1[k] = p[kOffW1 + k];
+  __syncthreads();
+  const int s = blockIdx.x * kTB + threadIdx.x;
+  if (s >= n) return;
+  float g[kNOUT] = {0.0f, 0.0f, 0.0f};
+  for (int i = 0; i < kNH; ++i) {
+    const float d = A1.dz1[(int64_t)i * n + s];
+#pragma unroll
+    for (int o = 0; o < kNOUT; ++o) g[o] = fmaf(W1[i * kNIN + 5 + o], d, g[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < kNOUT; ++o) {
+    const float gq = gE[(int64_t)o * n + s] + g[o] / norm[kNIN + 5 + o];
+    A0.dy[(int64_t)o * n + s] = norm[2 * kNIN + o] * (tm1 * gq);
+  }
 }
 
 // Gradient reduction: out[chunk][param] = sum over the chunk's samples of
@@ -508,6 +567,8 @@ struct rrmhd_trainer {
   float *part = nullptr;  // [chunks][4931]
   float *loss_part = nullptr;
   float *res = nullptr;  // one-step residuals [2][cap]
+  float *acts2 = nullptr;  // second activation set (feedback form)
+  float *fb = nullptr;     // feedback form: x1 [cap][8], q [3][cap], gE [3][cap]
   rr::Acts A{};
 };
 
@@ -533,6 +594,8 @@ int rrmhd_train_destroy(rrmhd_trainer *t) {
   if (t->part) (void)hipFree(t->part);
   if (t->loss_part) (void)hipFree(t->loss_part);
   if (t->res) (void)hipFree(t->res);
+  if (t->acts2) (void)hipFree(t->acts2);
+  if (t->fb) (void)hipFree(t->fb);
   delete t;
   return RRMHD_OK;
 }
@@ -549,9 +612,12 @@ int rrmhd_train_create(int64_t max_batch, void *hip_stream, rrmhd_trainer **out)
   const int64_t chunks = (max_batch + rr::kChunk - 1) / rr::kChunk;
   const int64_t lblocks = (max_batch + rr::kTB - 1) / rr::kTB;
   hipError_t e = hipMalloc((void **)&t->acts, sizeof(float) * per * max_batch);
-  if (e == hipSuccess) e = hipMalloc((void **)&t->part, sizeof(float) * chunks * rr::kNParam);
+  // two chunk sets: the feedback form reduces two activation sets
+  if (e == hipSuccess) e = hipMalloc((void **)&t->part, sizeof(float) * 2 * chunks * rr::kNParam);
   if (e == hipSuccess) e = hipMalloc((void **)&t->loss_part, sizeof(float) * lblocks);
   if (e == hipSuccess) e = hipMalloc((void **)&t->res, sizeof(float) * 2 * max_batch);
+  if (e == hipSuccess) e = hipMalloc((void **)&t->acts2, sizeof(float) * per * max_batch);
+  if (e == hipSuccess) e = hipMalloc((void **)&t->fb, sizeof(float) * 14 * max_batch);
   if (e != hipSuccess) {
     int rc = terr(e, "hipMalloc(trainer)");
     rrmhd_train_destroy(t);
@@ -564,8 +630,8 @@ int rrmhd_train_create(int64_t max_batch, void *hip_stream, rrmhd_trainer **out)
 }  // extern "C"
 
 // SoA activation arrays of a batch of n samples inside the trainer's buffer.
-static rr::Acts acts_of(const rrmhd_trainer *t, int64_t N) {
-  float *a = t->acts;
+static rr::Acts acts_of(const rrmhd_trainer *t, int64_t N, bool second = false) {
+  float *a = second ? t->acts2 : t->acts;
   rr::Acts A;
   A.xh = a;
   a += rr::kNIN * N;
@@ -620,25 +686,63 @@ int rrmhd_train_loss_grad(rrmhd_trainer *t, const float *params, const float *no
 
 int rrmhd_train_onestep_loss_grad(rrmhd_trainer *t, const float *params, const float *norm,
                                   const float *x, const float *r0, int nsnap, int nc,
-                                  double tau_c, double den, float *grad, float *loss) {
+                                  double tau_c, double den, int feedback, float *grad,
+                                  float *loss) {
   if (!t || !params || !norm || !x || !r0 || !grad || nsnap < 1 || nc < 1 ||
-      !(tau_c > 0.5) || !(den > 0.0) || !std::isfinite(den))
+      !(tau_c > 0.5) || !(den > 0.0) || !std::isfinite(den) || (feedback != 0 && feedback != 1))
     return RRMHD_EINVAL;
   const int64_t n = (int64_t)nsnap * nc * nc;
   if (n > t->cap || n > INT32_MAX) return RRMHD_EINVAL;
-  const rr::Acts A = acts_of(t, n);
   const int nb = (int)((n + rr::kTB - 1) / rr::kTB);
   const float om1 = (float)(1.0 - 1.0 / tau_c);
+  const rr::Acts A = acts_of(t, n);
   hipLaunchKernelGGL(rr::k_forward, dim3(nb), dim3(rr::kTB), 0, t->st, params, norm, x,
                      (const float *)nullptr, (int)n, A, t->loss_part);
   THIP(hipGetLastError());
-  hipLaunchKernelGGL(rr::k_onestep_fwd, dim3(nb), dim3(rr::kTB), 0, t->st, x, r0, norm, nsnap,
-                     nc, om1, A, t->res, t->loss_part);
+  if (!feedback) {
+    hipLaunchKernelGGL(rr::k_onestep_fwd, dim3(nb), dim3(rr::kTB), 0, t->st, x, r0, norm,
+                       nsnap, nc, om1, A, (const float *)nullptr, t->res, t->loss_part);
+    THIP(hipGetLastError());
+    hipLaunchKernelGGL(rr::k_onestep_adj, dim3(nb), dim3(rr::kTB), 0, t->st, x, norm, nsnap,
+                       nc, om1, (float)(2.0 / den), A, (const float *)t->res, (float *)nullptr);
+    THIP(hipGetLastError());
+    return backward_and_reduce(t, params, A, n, nb, 1.0 / den, grad, loss);
+  }
+  // feedback form: pass 0 on the Chapman-Enskog features (A), pass 1 on the
+  // features of the restart carrying q = (tau_c - 1) D0 (A1)
+  const float tm1 = (float)(tau_c - 1.0);
+  const rr::Acts A1 = acts_of(t, n, true);
+  float *x1 = t->fb, *q = t->fb + 8 * n, *gE = t->fb + 11 * n;
+  hipLaunchKernelGGL(rr::k_feedback_x1, dim3(nb), dim3(rr::kTB), 0, t->st, x, norm, (int)n, tm1,
+                     A, q, x1);
   THIP(hipGetLastError());
-  hipLaunchKernelGGL(rr::k_onestep_adj, dim3(nb), dim3(rr::kTB), 0, t->st, x, norm, nsnap, nc,
-                     om1, (float)(2.0 / den), A, (const float *)t->res);
+  hipLaunchKernelGGL(rr::k_forward, dim3(nb), dim3(rr::kTB), 0, t->st, params, norm,
+                     (const float *)x1, (const float *)nullptr, (int)n, A1, t->loss_part);
   THIP(hipGetLastError());
-  return backward_and_reduce(t, params, A, n, nb, 1.0 / den, grad, loss);
+  hipLaunchKernelGGL(rr::k_onestep_fwd, dim3(nb), dim3(rr::kTB), 0, t->st, (const float *)x1, r0,
+                     norm, nsnap, nc, om1, A1, (const float *)q, t->res, t->loss_part);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_onestep_adj, dim3(nb), dim3(rr::kTB), 0, t->st, (const float *)x1,
+                     norm, nsnap, nc, om1, (float)(2.0 / den), A1, (const float *)t->res, gE);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_backward, dim3(nb), dim3(rr::kTB), 0, t->st, params, (int)n, A1);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_feedback_back, dim3(nb), dim3(rr::kTB), 0, t->st, params, norm, (int)n,
+                     tm1, A1, (const float *)gE, A);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_backward, dim3(nb), dim3(rr::kTB), 0, t->st, params, (int)n, A);
+  THIP(hipGetLastError());
+  const int nch = (int)((n + rr::kChunk - 1) / rr::kChunk);
+  const dim3 gq(nch, (rr::kNParam + rr::kTB - 1) / rr::kTB);
+  hipLaunchKernelGGL(rr::k_grad_chunks, gq, dim3(rr::kTB), 0, t->st, (int)n, A, t->part);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_grad_chunks, gq, dim3(rr::kTB), 0, t->st, (int)n, A1,
+                     t->part + (int64_t)nch * rr::kNParam);
+  THIP(hipGetLastError());
+  hipLaunchKernelGGL(rr::k_grad_final, dim3((rr::kNParam + 255) / 256), dim3(256), 0, t->st,
+                     t->part, 2 * nch, t->loss_part, nb, 1.0 / den, grad, loss);
+  THIP(hipGetLastError());
+  return RRMHD_OK;
 }
 
 int rrmhd_train_adam(rrmhd_trainer *t, float *params, float *m, float *v, const float *grad,

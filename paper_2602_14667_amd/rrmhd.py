@@ -120,7 +120,7 @@ def lib():
                                                   vp]
         L.rrmhd_train_onestep_loss_grad.argtypes = [vp, vp, vp, vp, vp, ci, ci,
                                                     ctypes.c_double,
-                                                    ctypes.c_double, vp, vp]
+                                                    ctypes.c_double, ci, vp, vp]
         fl = ctypes.c_float
         L.rrmhd_train_adam.argtypes = [vp, vp, vp, vp, vp, fl, fl, fl, fl, ci]
         L.rrmhd_train_destroy.argtypes = [vp]
@@ -518,11 +518,11 @@ class Trainer:
                "rrmhd_train_loss_grad")
 
     def onestep_loss_grad(self, params, norm, x, r0, nsnap, nc, tau_c, den,
-                          grad, loss=None):
+                          grad, loss=None, feedback=False):
         _check(lib().rrmhd_train_onestep_loss_grad(
             self._h, _ptr_t(params), _ptr_t(norm), _ptr_t(x), _ptr_t(r0),
-            int(nsnap), int(nc), float(tau_c), float(den), _ptr_t(grad),
-            _ptr_t(loss)), "rrmhd_train_onestep_loss_grad")
+            int(nsnap), int(nc), float(tau_c), float(den), int(bool(feedback)),
+            _ptr_t(grad), _ptr_t(loss)), "rrmhd_train_onestep_loss_grad")
 
     def adam(self, params, m, v, grad, lr, step, beta1=0.9, beta2=0.999,
              eps=1e-8):

@@ -179,11 +179,14 @@ def test_onestep_samples_vs_oracle(nf):
     assert abs(den / den_ref - 1) < 1e-12
 
 
-def test_onestep_loss_and_gradient_vs_fp64():
+@pytest.mark.parametrize("feedback", [False, True])
+def test_onestep_loss_and_gradient_vs_fp64(feedback):
     """Two snapshots in one call: loss and gradient of the FP32 kernels
-    (network, correction stencil, its transpose, reverse mode) against the
-    oracle's FP64 chain, fed the oracle's own restart data."""
-    note("one-step loss/grad, 2 snapshots 64 -> 16")
+    (network, correction stencil, its transpose, reverse mode; in the
+    feedback form two network evaluations and the input gradient of the
+    second) against the oracle's FP64 chain, fed the oracle's own restart
+    data."""
+    note(f"one-step loss/grad, 2 snapshots 64 -> 16, feedback={feedback}")
     rr = R()
     fac, tf = 4, 0.8
     tc = 0.5 + (tf - 0.5) / fac
@@ -195,14 +198,18 @@ def test_onestep_loss_and_gradient_vs_fp64():
     nm = onestep_norm(X)
     p = params(np.random.default_rng(11))
     # oracle: L = sum num / sum den, gradient weighted by each den
-    Ls, gs = zip(*[oracle.onestep_loss_grad(p, nm, m0, m1, fac, tc) for m0, m1 in pairs])
+    if feedback:
+        nm[16:19] *= 10.0  # a correction large enough that its feedback matters
+    Ls, gs = zip(*[oracle.onestep_loss_grad(p, nm, m0, m1, fac, tc, feedback=feedback)
+                   for m0, m1 in pairs])
     D = sum(dens)
     L_ref = sum(l * d for l, d in zip(Ls, dens)) / D
     g_ref = sum(g * d for g, d in zip(gs, dens)) / D
     tr = rr.Trainer(2 * 16 * 16)
     grad = torch.empty(4931, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    tr.onestep_loss_grad(f32(p), f32(nm), f32(X), f32(R0), 2, 16, tc, D, grad, loss)
+    tr.onestep_loss_grad(f32(p), f32(nm), f32(X), f32(R0), 2, 16, tc, D, grad, loss,
+                         feedback=feedback)
     g = grad.cpu().numpy().astype(np.float64)
     e = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     note(f"  grad rel L2 {e:.3e}, loss {loss.item():.6e} vs {L_ref:.6e} (L0 "
@@ -210,7 +217,8 @@ def test_onestep_loss_and_gradient_vs_fp64():
     assert e < 1e-4
     assert abs(loss.item() / L_ref - 1) < 1e-5
     grad2 = torch.empty_like(grad)
-    tr.onestep_loss_grad(f32(p), f32(nm), f32(X), f32(R0), 2, 16, tc, D, grad2, None)
+    tr.onestep_loss_grad(f32(p), f32(nm), f32(X), f32(R0), 2, 16, tc, D, grad2, None,
+                         feedback=feedback)
     assert torch.equal(grad, grad2)
     tr.close()
 
@@ -230,7 +238,8 @@ def test_onestep_zero_output_layer_gives_the_uncorrected_loss():
     tr = rr.Trainer(256)
     grad = torch.empty(4931, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    tr.onestep_loss_grad(f32(p), f32(nm), f32(x_ref), f32(r_ref), 1, 16, tc, den, grad, loss)
+    tr.onestep_loss_grad(f32(p), f32(nm), f32(x_ref), f32(r_ref), 1, 16, tc, den, grad, loss,
+                         feedback=True)
     g = grad.cpu().numpy()
     assert abs(loss.item() / L0 - 1) < 1e-6
     assert np.all(g[:4736] == 0.0) and np.any(g[4736:] != 0.0)
@@ -238,9 +247,9 @@ def test_onestep_zero_output_layer_gives_the_uncorrected_loss():
 
 
 def test_onestep_short_fit_reduces_loss():
-    """Adam on the one-step objective over under-resolved snapshots (16^2
-    coarse from 64^2): the corrected coarse step must track the filtered fine
-    momentum better than the uncorrected one."""
+    """Adam on the one-step objective (feedback form) over under-resolved
+    snapshots (16^2 coarse from 64^2): the corrected coarse step must track
+    the filtered fine momentum better than the uncorrected one."""
     note("one-step short fit")
     rr = R()
     fac, tf = 4, 0.8
@@ -260,15 +269,20 @@ def test_onestep_short_fit_reduces_loss():
     grad = torch.empty(4931, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     for step in range(1, 301):
-        tr.onestep_loss_grad(pd, nd, xd, rd, 4, 16, tc, D, grad, loss)
+        tr.onestep_loss_grad(pd, nd, xd, rd, 4, 16, tc, D, grad, loss, feedback=True)
         tr.adam(pd, md, vd, grad, 3e-3, step)
-    tr.onestep_loss_grad(pd, nd, xd, rd, 4, 16, tc, D, grad, loss)
+    tr.onestep_loss_grad(pd, nd, xd, rd, 4, 16, tc, D, grad, loss, feedback=True)
     note(f"  loss {L0:.4f} -> {loss.item():.4f}")
     assert loss.item() < 0.8 * L0
-    # the trained network's objective, evaluated by the oracle's solver step
+    # the trained network's objective (feedback form), evaluated by the
+    # oracle's solver step
     pt = pd.cpu().numpy().astype(np.float64)
-    L_or = [oracle.onestep_objective(
-        m0, m1, fac, tc, oracle.mlp_forward(pt, nm, d[2]) * nm[16:19])[0] * d[3]
-        for (m0, m1), d in zip(pairs, data)]
+    so = nm[16:19]
+    L_or = []
+    for (m0, m1), d in zip(pairs, data):
+        q = (tc - 1.0) * oracle.mlp_forward(pt, nm, d[2]) * so
+        _, _, x1, _ = oracle.onestep_objective(m0, m1, fac, tc, q=q)
+        d1 = oracle.mlp_forward(pt, nm, x1) * so
+        L_or.append(oracle.onestep_objective(m0, m1, fac, tc, d1, q=q)[0] * d[3])
     assert abs(sum(L_or) / D / loss.item() - 1) < 1e-3
     tr.close()

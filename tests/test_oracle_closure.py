@@ -336,3 +336,72 @@ def test_onestep_restart_of_a_resolved_shear_wave_converges():
         Ls.append(oracle.onestep_objective(m0, m1, fac, tc)[0])
     assert Ls[1] < 5e-3
     assert Ls[0] / Ls[1] > 10.0
+
+
+def test_mlp_input_gradient_against_central_differences():
+    p = random_params()
+    norm = random_norm()
+    x = 0.05 * RNG.standard_normal((4, 8)); x[:, 0] += 1.0
+    dy = RNG.standard_normal((4, 3))
+    gx = oracle.mlp_vjp_input(p, norm, x, dy)
+    for s in range(4):
+        for k in range(8):
+            h = 1e-6
+            xp, xm = x.copy(), x.copy()
+            xp[s, k] += h
+            xm[s, k] -= h
+            fd = (np.sum(dy * oracle.mlp_forward(p, norm, xp))
+                  - np.sum(dy * oracle.mlp_forward(p, norm, xm))) / (2 * h)
+            assert abs(fd - gx[s, k]) <= 1e-6 * max(1.0, abs(gx[s, k]))
+
+
+def test_onestep_restart_carries_the_extra_non_equilibrium(fine_pair):
+    """With q added to the restart's a_CE, the restart's a_1^(2) (from its
+    populations) is a_CE + q, and its rho, u, b are unchanged."""
+    m0, m1, fac, tc = fine_pair
+    nc = m0[0].shape[0] // fac
+    q = 1e-4 * np.random.default_rng(8).standard_normal((nc * nc, 3))
+    _, _, x0, _ = oracle.onestep_objective(m0, m1, fac, tc)
+    _, _, x1, _ = oracle.onestep_objective(m0, m1, fac, tc, q=q)
+    assert np.max(np.abs(x1[:, :5] - x0[:, :5])) < 1e-15
+    assert np.max(np.abs(x1[:, 5:] - x0[:, 5:] - q)) < 1e-15
+
+
+def test_onestep_feedback_gradient_against_central_differences(fine_pair):
+    """Feedback form of the objective (restart with the closure's steady
+    response (tau_c - 1) D0, correction evaluated on that restart's
+    features): the composed gradient through both network evaluations
+    against central differences through the solver."""
+    m0, m1, fac, tc = fine_pair
+    p = 0.3 * np.random.default_rng(9).standard_normal(oracle.NPARAM)
+    norm = np.concatenate([[1.0, 0, 0, 0, 0, 0, 0, 0], [0.01, 0.02, 0.02, 0.02, 0.02,
+                                                        2e-3, 2e-3, 2e-3], [3e-4] * 3])
+    so = norm[16:19]
+    L, g = oracle.onestep_loss_grad(p, norm, m0, m1, fac, tc, feedback=True)
+    _, _, x0, _ = oracle.onestep_objective(m0, m1, fac, tc)
+
+    def L_of(w):
+        q = (tc - 1.0) * oracle.mlp_forward(w, norm, x0) * so
+        _, _, x1, _ = oracle.onestep_objective(m0, m1, fac, tc, q=q)
+        d1 = oracle.mlp_forward(w, norm, x1) * so
+        return oracle.onestep_objective(m0, m1, fac, tc, d1, q=q)[0]
+
+    assert abs(L_of(p) - L) <= 1e-14 * L
+    for k in (7, 300, 530, 1500, 4680, 4929):
+        h = 1e-5
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (L_of(pp) - L_of(pm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-5 * max(abs(g[k]), 1e-3 * np.abs(g).max())
+
+
+def test_onestep_feedback_with_a_silent_network_is_the_plain_objective(fine_pair):
+    m0, m1, fac, tc = fine_pair
+    p = 0.3 * np.random.default_rng(10).standard_normal(oracle.NPARAM)
+    p[4736:] = 0.0
+    norm = random_norm()
+    L0 = oracle.onestep_objective(m0, m1, fac, tc)[0]
+    L, g = oracle.onestep_loss_grad(p, norm, m0, m1, fac, tc, feedback=True)
+    assert abs(L - L0) <= 1e-15 * L0
+    assert np.all(g[:4736] == 0.0)
