@@ -327,7 +327,8 @@ def main():
     bd = torch.from_numpy(b).cuda()
     del u, b
     s = rrmhd.Solver(n, n, args.tau, args.tau, storage=args.storage)
-    launch = "library default (f32: 128x2, f16: 256x1 threads; NT stores)"
+    launch = ("library default (f32: 128x2 threads; f16: 128x1 threads, two nodes "
+              "per thread; NT stores)")
     s.init(ud, bd)
     del ud, bd
     s.step(args.warmup)

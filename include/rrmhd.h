@@ -130,8 +130,11 @@ int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes,
  * xcd = 1 renumbers workgroups so each XCD gets one contiguous run of tiles,
  * xcd = 2 so each XCD gets 8 neighbouring tiles out of every 64; nt bit 0
  * writes populations with non-temporal stores, bit 1 reads them with
- * non-temporal loads (periodic grids).  Results do not depend on
- * the shape (bitwise).  Host-side only. */
+ * non-temporal loads (periodic grids), bit 2 lets each thread update two
+ * neighbouring nodes with 32-bit plane accesses (FP16 storage, periodic
+ * grids with even nx; a workgroup then covers 2 bx nodes in x; ignored
+ * otherwise).  Results do not depend on the shape (bitwise).  Host-side
+ * only. */
 int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 
 /* Stream used by the handle; NULL is the null stream. */

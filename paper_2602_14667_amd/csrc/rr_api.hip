@@ -172,7 +172,7 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
   h->shape.by = by;
   h->shape.ry = ry;
   h->shape.xcd = (xcd >= 0 && xcd <= 2) ? xcd : 0;
-  h->shape.nt = nt & 3;
+  h->shape.nt = nt & 7;
   return RRMHD_OK;
 }
 
@@ -297,6 +297,8 @@ int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage, hipStream_t *
   if (ready) *ready = h->ready ? 1 : 0;
   return RRMHD_OK;
 }
+
+int rr_handle_walls(const rrmhd *h) { return h && h->D.walls ? 1 : 0; }
 
 void rr_handle_set_ready(rrmhd *h, int ready) {
   if (h) h->ready = ready != 0;

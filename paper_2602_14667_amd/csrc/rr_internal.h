@@ -13,6 +13,8 @@ extern "C" {
 RR_HIDDEN int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage,
                              hipStream_t *stream, int *ready);
 RR_HIDDEN void rr_handle_set_ready(rrmhd *h, int ready);
+// 1 when the handle has walls (the paired FP16 update is periodic only)
+RR_HIDDEN int rr_handle_walls(const rrmhd *h);
 // batch: domain sizes (arrays may be NULL to query n and storage)
 RR_HIDDEN int rr_batch_domains(const rrmhd_batch *b, int *n, int *storage, int *nx,
                                int *ny);

@@ -24,7 +24,8 @@ struct LaunchShape {
   int bx, by;  // threads per block in x and y
   int ry;      // rows per thread (block covers by * ry rows)
   int xcd;     // 1: XCD-aware block order
-  int nt;      // bit 0: non-temporal stores, bit 1: non-temporal loads
+  int nt;      // bit 0: non-temporal stores, bit 1: non-temporal loads,
+               // bit 2: FP16 storage, periodic, even nx: two nodes per thread
 };
 
 hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,

@@ -414,15 +414,51 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_final(
   if (threadIdx.x == 0) out[2] = r;
 }
 
+// FP16 storage, periodic grid with even nx: each thread updates the node pair
+// (x, x + 1) with 32-bit plane accesses (update_periodic_pair); a workgroup
+// of bx x by threads covers 2 bx x by ry nodes.
+template <bool FORCED, bool NT, bool NTL>
+__global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry, int xcd,
+                                                   const uint16_t *__restrict__ src,
+                                                   uint16_t *__restrict__ dst) {
+  const int ntiles = gridDim.x;
+  const int L = xcd == 1 ? xcd_remap(blockIdx.x, ntiles)
+                         : (xcd == 2 ? xcd_local(blockIdx.x, ntiles) : (int)blockIdx.x);
+  const int tx = L % tiles_x, ty = L / tiles_x;
+  const int x = 2 * (tx * blockDim.x + threadIdx.x);
+  const int y0 = (ty * blockDim.y + threadIdx.y) * ry;
+  if (x >= D.nx) return;
+  CollideParams P;
+  P.om_c = D.om_c;
+  P.omm_c = D.omm_c;
+  P.Gx = D.Gx;
+  P.Gy = D.Gy;
+  P.src_c = D.src_c;
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+  for (int r = 0; r < ry; ++r) {
+    const int y = y0 + r;
+    if (y >= D.ny) return;
+    update_periodic_pair<FORCED, NT, NTL>(G, src, dst, x, y, P);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 LaunchShape default_shape(const Domain &D) {
   // Measured on MI355X at 8192^2 (planes 256 B apart beyond alignment):
-  // 128 x 2 for FP32 storage and 256 x 1 for FP16 storage, plain block order,
-  // non-temporal stores.
+  // 128 x 2 for FP32 storage; for FP16 storage 128 x 1 threads with two nodes
+  // per thread on periodic grids of even width (4-6 % faster than one node
+  // per thread), else 256 x 1; plain block order, non-temporal stores.
   LaunchShape L;
-  if (D.nx >= 256) {
+  L.ry = 1;
+  L.xcd = 0;
+  L.nt = 1;
+  if (D.elem == 2 && !D.walls && D.nx % 2 == 0 && D.nx >= 512) {
+    L.bx = 128;
+    L.by = 1;
+    L.nt = 5;
+  } else if (D.nx >= 256) {
     L.bx = D.elem == 2 ? 256 : 128;
     L.by = 256 / L.bx;
   } else {
@@ -430,9 +466,6 @@ LaunchShape default_shape(const Domain &D) {
     if (L.bx > 256) L.bx = 256;
     L.by = 256 / L.bx;
   }
-  L.ry = 1;
-  L.xcd = 0;
-  L.nt = 1;
   return L;
 }
 
@@ -459,10 +492,36 @@ static void step_nt(const Domain &D, const void *src, void *dst, const LaunchSha
   }
 }
 
+template <bool NT, bool NTL>
+static void step_pair_nt(const Domain &D, const void *src, void *dst, const LaunchShape &L,
+                         hipStream_t st) {
+  const int tiles_x = (D.nx / 2 + L.bx - 1) / L.bx;
+  const int rows_per_tile = L.by * L.ry;
+  const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
+  const dim3 grid(tiles_x * tiles_y), block(L.bx, L.by);
+  auto s = (const uint16_t *)src;
+  auto d = (uint16_t *)dst;
+  if (D.Gx != 0.0f || D.Gy != 0.0f)
+    hipLaunchKernelGGL((k_step_pair<true, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  else
+    hipLaunchKernelGGL((k_step_pair<false, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+}
+
 template <class C>
 static hipError_t step_t(const Domain &D, const void *src, void *dst,
                          const LaunchShape &L, hipStream_t st) {
   const bool nts = L.nt & 1, ntl = (L.nt & 2) != 0;
+  if (sizeof(typename C::T) == 2 && (L.nt & 4) && !D.walls && D.nx % 2 == 0) {
+    if (nts && ntl)
+      step_pair_nt<true, true>(D, src, dst, L, st);
+    else if (nts)
+      step_pair_nt<true, false>(D, src, dst, L, st);
+    else if (ntl)
+      step_pair_nt<false, true>(D, src, dst, L, st);
+    else
+      step_pair_nt<false, false>(D, src, dst, L, st);
+    return hipGetLastError();
+  }
   if (nts && ntl)
     step_nt<C, true, true>(D, src, dst, L, st);
   else if (nts)

@@ -108,4 +108,78 @@ __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
     st_at<T, NT>(dst + (int64_t)(kQ + k) * G.plane, o, C::enc(g[k], G.s));
 }
 
+// ---- FP16 storage, two neighbouring nodes per thread ------------------------
+// Nodes (x, x + 1), x even, nx even: every plane moves as one 32-bit word per
+// thread (low half node x, high half node x + 1), which halves the memory
+// instructions per byte of the 2-byte codec.  The planes shifted by +-1 in x
+// read the word at an odd 16-bit position (gfx950 loads unaligned global
+// words natively); at the periodic seam (x = 0 for c_x = +1, x = nx - 2 for
+// c_x = -1) the two halves come from opposite ends of the row and are read
+// separately.
+template <int CX, bool NTL>
+__device__ __forceinline__ uint32_t ld_pair(const uint16_t *__restrict__ plane, uint32_t row,
+                                            int x, int nx) {
+  const char *b = (const char *)plane + row;
+  if (CX == 0) return ld_at<uint32_t, NTL>((const uint32_t *)b, 2u * x);
+  const bool seam = CX > 0 ? x == 0 : x == nx - 2;
+  if (!seam) return ld_at<uint32_t, NTL>((const uint32_t *)b, 2u * (x - CX));
+  // the pair straddles the seam: (nx - 1, 0) in both cases
+  const uint32_t lo = ld_at<uint16_t, NTL>((const uint16_t *)b, 2u * (nx - 1));
+  const uint32_t hi = ld_at<uint16_t, NTL>((const uint16_t *)b, 0u);
+  return lo | (hi << 16);
+}
+
+__device__ __forceinline__ float h16_lo(uint32_t w, float inv_s) {
+  return CodecF16::dec((uint16_t)(w & 0xffffu), inv_s);
+}
+__device__ __forceinline__ float h16_hi(uint32_t w, float inv_s) {
+  return CodecF16::dec((uint16_t)(w >> 16), inv_s);
+}
+
+template <bool FORCED, bool NT, bool NTL>
+__device__ __forceinline__ void update_periodic_pair(const PlaneGeom &G,
+                                                     const uint16_t *__restrict__ src,
+                                                     uint16_t *__restrict__ dst, int x, int y,
+                                                     const CollideParams &P) {
+  const uint32_t pitch = G.nx * 2u;
+  const uint32_t b0 = y * pitch;
+  const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
+  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
+  uint32_t w[kPlanes];
+  auto rowf = [&](int cyv) { return cyv == 0 ? b0 : (cyv > 0 ? bm : bp); };
+#define RR_LDF(I) w[I] = ld_pair<cx(I), NTL>(plane_ptr(src, I, G.plane), rowf(cy(I)), x, G.nx)
+#define RR_LDG(J, C) \
+  w[gplane(J, C)] = ld_pair<ex(J), NTL>(plane_ptr(src, gplane(J, C), G.plane), rowf(ey(J)), x, G.nx)
+  RR_LDF(0); RR_LDF(1); RR_LDF(2); RR_LDF(3); RR_LDF(4); RR_LDF(5); RR_LDF(6); RR_LDF(7); RR_LDF(8);
+  RR_LDG(0, 0); RR_LDG(0, 1); RR_LDG(1, 0); RR_LDG(1, 1); RR_LDG(2, 0); RR_LDG(2, 1);
+  RR_LDG(3, 0); RR_LDG(3, 1); RR_LDG(4, 0); RR_LDG(4, 1);
+#undef RR_LDF
+#undef RR_LDG
+  float d[kQ], g[2 * kQm];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) d[i] = h16_lo(w[i], G.inv_s);
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k) g[k] = h16_lo(w[kQ + k], G.inv_s);
+  collide<FORCED>(d, g, P);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) w[i] = (w[i] & 0xffff0000u) | CodecF16::enc(d[i], G.s);
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k)
+    w[kQ + k] = (w[kQ + k] & 0xffff0000u) | CodecF16::enc(g[k], G.s);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) d[i] = h16_hi(w[i], G.inv_s);
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k) g[k] = h16_hi(w[kQ + k], G.inv_s);
+  collide<FORCED>(d, g, P);
+  const uint32_t o = b0 + 2u * x;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i)
+    st_at<uint32_t, NT>((uint32_t *)(dst + (int64_t)i * G.plane), o,
+                        (w[i] & 0xffffu) | ((uint32_t)CodecF16::enc(d[i], G.s) << 16));
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k)
+    st_at<uint32_t, NT>((uint32_t *)(dst + (int64_t)(kQ + k) * G.plane), o,
+                        (w[kQ + k] & 0xffffu) | ((uint32_t)CodecF16::enc(g[k], G.s) << 16));
+}
+
 }  // namespace rr

@@ -16,15 +16,16 @@
 namespace {
 
 struct Shape {
-  int bx, by, xcd;
+  int bx, by, xcd, nt;  // nt: launch flags of rrmhd_set_launch
 };
 
 struct Entry {
-  int bx = 0, by = 0, xcd = 0, grid = 0, fetch = 0;
+  int bx = 0, by = 0, xcd = 0, grid = 0, fetch = 0, nt = 1;
   double ms = 0.0;
 };
 
-// ---- cache file: {"key": {"bx": 128, "by": 2, "xcd": 2, "grid": 0, "fetch": 0, "ms": 1.7}, ...}
+// ---- cache file: {"key": {"bx": 128, "by": 2, "xcd": 2, "grid": 0, "fetch": 0, "nt": 1,
+// "ms": 1.7}, ...}
 std::map<std::string, Entry> read_cache(const char *path) {
   std::map<std::string, Entry> m;
   if (!path) return m;
@@ -54,19 +55,21 @@ std::map<std::string, Entry> read_cache(const char *path) {
       if (t == std::string::npos) return;
       *out = std::strtod(body.c_str() + t + 1, nullptr);
     };
-    double v[6] = {0, 0, 0, 0, 0, 0};
+    double v[7] = {0, 0, 0, 0, 0, 0, 1};
     num("bx", &v[0]);
     num("by", &v[1]);
     num("xcd", &v[2]);
     num("grid", &v[3]);
     num("ms", &v[4]);
     num("fetch", &v[5]);
+    num("nt", &v[6]);
     e.bx = (int)v[0];
     e.by = (int)v[1];
     e.xcd = (int)v[2];
     e.grid = (int)v[3];
     e.ms = v[4];
     e.fetch = (int)v[5];
+    e.nt = (int)v[6];
     if (e.bx > 0 && e.by > 0) m[key] = e;
     p = cb + 1;
   }
@@ -83,9 +86,9 @@ void write_cache(const char *path, const std::map<std::string, Entry> &m) {
   for (const auto &kv : m) {
     std::fprintf(f,
                  "  \"%s\": {\"bx\": %d, \"by\": %d, \"xcd\": %d, \"grid\": %d, \"fetch\": %d, "
-                 "\"ms\": %.6f}%s\n",
+                 "\"nt\": %d, \"ms\": %.6f}%s\n",
                  kv.first.c_str(), kv.second.bx, kv.second.by, kv.second.xcd, kv.second.grid,
-                 kv.second.fetch, kv.second.ms, (++i < m.size()) ? "," : "");
+                 kv.second.fetch, kv.second.nt, kv.second.ms, (++i < m.size()) ? "," : "");
   }
   std::fprintf(f, "}\n");
   std::fclose(f);
@@ -169,13 +172,20 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
     } else {
       rc = rrmhd_load_state(h, save, nb, 0);
     }
-    const Shape cands[] = {{256, 1, 0}, {128, 2, 0}, {64, 4, 0}, {128, 1, 0}, {64, 1, 0},
-                           {32, 8, 0},  {256, 1, 2}, {128, 2, 2}, {64, 4, 2}};
+    // nt = 5: non-temporal stores and, for FP16 storage on periodic grids
+    // with even nx, two nodes per thread
+    const Shape cands[] = {{256, 1, 0, 1}, {128, 2, 0, 1}, {64, 4, 0, 1}, {128, 1, 0, 1},
+                           {64, 1, 0, 1},  {32, 8, 0, 1},  {256, 1, 2, 1}, {128, 2, 2, 1},
+                           {64, 4, 2, 1},  {128, 1, 0, 5}, {128, 2, 0, 5}, {64, 4, 0, 5},
+                           {256, 1, 0, 5}, {64, 2, 0, 5}};
+    const bool pair_ok = storage == RRMHD_STORE_F16 && nx % 2 == 0 && !rr_handle_walls(h);
     best.ms = 1e30;
     for (const Shape &c : cands) {
       if (rc != RRMHD_OK) break;
-      if (c.bx > 64 && c.bx / 2 >= nx) continue;  // mostly idle lanes
-      rc = rrmhd_set_launch(h, c.bx, c.by, 1, c.xcd, 1);
+      if ((c.nt & 4) && !pair_ok) continue;
+      const int span = (c.nt & 4) ? 2 * c.bx : c.bx;  // nodes per workgroup row
+      if (span > 64 && span / 2 >= nx) continue;      // mostly idle lanes
+      rc = rrmhd_set_launch(h, c.bx, c.by, 1, c.xcd, c.nt);
       if (rc != RRMHD_OK) break;
       double ms = 0.0;
       rc = time_steps([&](int n) { return rrmhd_step(h, n); }, st, trials, &ms);
@@ -183,6 +193,7 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
         best.bx = c.bx;
         best.by = c.by;
         best.xcd = c.xcd;
+        best.nt = c.nt;
         best.ms = ms;
       }
     }
@@ -195,7 +206,7 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
     cache[key] = best;
     write_cache(cache_path, cache);
   }
-  rc = rrmhd_set_launch(h, best.bx, best.by, 1, best.xcd, 1);
+  rc = rrmhd_set_launch(h, best.bx, best.by, 1, best.xcd, best.nt > 0 ? best.nt : 1);
   if (out_bx) *out_bx = best.bx;
   if (out_by) *out_by = best.by;
   if (out_xcd) *out_xcd = best.xcd;

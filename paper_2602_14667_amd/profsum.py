@@ -9,9 +9,11 @@ Counter values (KiB per dispatch) are calibrated against the plain copy
 kernel of known size: factor = true bytes / counted bytes for that kernel.
 
 Second form, kernel-trace statistics of any workload:
-  python -m paper_2602_14667_amd.profsum stats STATS_DIR OUT.md KERNEL BYTES TITLE COMMAND
+  python -m paper_2602_14667_amd.profsum stats STATS_DIR OUT.md KERNEL BYTES TITLE COMMAND [LAST]
 writes the per-kernel table and, for the kernel whose name contains KERNEL,
-the average launch time and its algorithmic rate (BYTES per launch).
+the average launch time and its algorithmic rate (BYTES per launch); with
+LAST, also the average over its last LAST dispatches (the timed region of a
+bench run, after any autotuning launches).
 """
 import csv
 import json
@@ -101,7 +103,18 @@ def main(prof, out, n):
     print("ok")
 
 
-def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command):
+def last_dispatches(stats_dir, kernel, count):
+    """Average duration (ns) of the last `count` dispatches of the kernel
+    whose name contains `kernel` (the timed region of a bench run)."""
+    rows = [r for r in _rows(os.path.join(stats_dir, "run_kernel_trace.csv"))
+            if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    rows = rows[-count:]
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+    return sum(durs) / len(durs), len(durs), rows[-1]["Kernel_Name"] if rows else ""
+
+
+def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command, last=0):
     stats = kernel_stats(stats_dir)
     bpl = float(bytes_per_launch)
     names = [k for k in stats if kernel in k]
@@ -118,6 +131,11 @@ def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command):
         lines.append(f"* `{k[:90]}`: average launch {avg / 1e3:.1f} us; {bpl / 1e9:.4f} GB "
                      f"algorithmic per launch -> {bpl / avg:.1f} GB/s = "
                      f"{bpl / avg / 8000 * 100:.1f} % of 8 TB/s")
+    if int(last) > 0:
+        avg, cnt, name = last_dispatches(stats_dir, kernel, int(last))
+        lines.append(f"* last {cnt} dispatches (the timed region) of `{name[:90]}`: average "
+                     f"{avg / 1e3:.1f} us -> {bpl / avg:.1f} GB/s = "
+                     f"{bpl / avg / 8000 * 100:.1f} % of 8 TB/s")
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("ok")
@@ -125,6 +143,6 @@ def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command):
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats_summary(*sys.argv[2:8])
+        stats_summary(*sys.argv[2:9])
     else:
         main(*sys.argv[1:4])
