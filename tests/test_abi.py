@@ -82,3 +82,12 @@ def test_null_handle_calls_are_rejected():
     assert L.rrmhd_batch_set_fetch(None, 1) == rrmhd.EINVAL
     assert L.rrmhd_batch_set_shape(None, -1, 0, 0, -1) == rrmhd.EINVAL
     assert L.rrmhd_batch_step(None, 1) == rrmhd.EINVAL
+    # training entry points: argument checks come before any device work
+    assert L.rrmhd_train_onestep_samples(None, None, None, None, None, None, 64, 4,
+                                         0.55, None, None, None, None, None) == rrmhd.EINVAL
+    assert L.rrmhd_train_onestep_loss_grad(None, None, None, None, None, 1, 16, 0.55,
+                                           1.0, 0, None, None) == rrmhd.EINVAL
+    assert L.rrmhd_train_samples(None, None, None, 64, 4, 0.55, None, None, None,
+                                 None) == rrmhd.EINVAL
+    assert L.rrmhd_closure_enable(None, 1) == rrmhd.EINVAL
+    assert L.rrmhd_autotune(None, None, 3, None, None, None, None) == rrmhd.EINVAL
