@@ -221,9 +221,9 @@ static hipError_t launch_one(rrmhd_batch *b, hipStream_t st) {
   const dim3 grid(launch_grid(b));
   if (b->storage == RRMHD_STORE_F16) {
     if (b->nt)
-      launch_sched<rr::CodecF16, true>(b, grid, st, src, dst);
+      launch_sched<rr::CodecF16U, true>(b, grid, st, src, dst);  // ensemble storage scale is 1
     else
-      launch_sched<rr::CodecF16, false>(b, grid, st, src, dst);
+      launch_sched<rr::CodecF16U, false>(b, grid, st, src, dst);
   } else {
     if (b->nt)
       launch_sched<rr::CodecF32, true>(b, grid, st, src, dst);

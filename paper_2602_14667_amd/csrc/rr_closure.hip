@@ -132,14 +132,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     gg[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
     gg[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
     collide<false>(d, gg, P, hook);
-    if (active) {
-      const uint32_t o = b0 + x0;
-#pragma unroll
-      for (int i = 0; i < kQ; ++i) st_at<T, NT>(dst + (int64_t)i * G.plane, o, C::enc(d[i], G.s));
-#pragma unroll
-      for (int k = 0; k < 2 * kQm; ++k)
-        st_at<T, NT>(dst + (int64_t)(kQ + k) * G.plane, o, C::enc(gg[k], G.s));
-    }
+    if (active) store_planes<C, NT>(G, dst, b0 + x0, d, gg);
   }
 }
 
@@ -173,7 +166,10 @@ hipError_t launch_step_closure(int storage, const Domain &D, const MlpDev *mlp,
   P.Gy = 0.0f;
   P.src_c = 0.0f;
   const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
-  if (storage == kF16)
+  if (storage == kF16 && D.s == 1.0f)
+    hipLaunchKernelGGL((k_step_closure<CodecF16U, true>), dim3(grid), dim3(256), 0, st, G, P, mlp,
+                       tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
+  else if (storage == kF16)
     hipLaunchKernelGGL((k_step_closure<CodecF16, true>), dim3(grid), dim3(256), 0, st, G, P, mlp,
                        tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
   else

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_final(
 // FP16 storage, periodic grid with even nx: each thread updates the node pair
 // (x, x + 1) with 32-bit plane accesses (update_periodic_pair); a workgroup
 // of bx x by threads covers 2 bx x by ry nodes.
-template <bool FORCED, bool NT, bool NTL>
+template <class C, bool FORCED, bool NT, bool NTL>
 __global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry, int xcd,
                                                    const uint16_t *__restrict__ src,
                                                    uint16_t *__restrict__ dst) {
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
-    update_periodic_pair<FORCED, NT, NTL>(G, src, dst, x, y, P);
+    update_periodic_pair<C, FORCED, NT, NTL>(G, src, dst, x, y, P);
   }
 }
 
@@ -448,8 +448,8 @@ __global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry
 LaunchShape default_shape(const Domain &D) {
   // Measured on MI355X at 8192^2 (planes 256 B apart beyond alignment):
   // 128 x 2 for FP32 storage; for FP16 storage 128 x 1 threads with two nodes
-  // per thread on periodic grids of even width (level with one node per
-  // thread to 4 % faster across repeats), else 256 x 1; plain block order,
+  // per thread on periodic grids of even width (2-4 % faster than one node
+  // per thread in the same run), else 256 x 1; plain block order,
   // non-temporal stores.
   LaunchShape L;
   L.ry = 1;
@@ -493,7 +493,7 @@ static void step_nt(const Domain &D, const void *src, void *dst, const LaunchSha
   }
 }
 
-template <bool NT, bool NTL>
+template <class C, bool NT, bool NTL>
 static void step_pair_nt(const Domain &D, const void *src, void *dst, const LaunchShape &L,
                          hipStream_t st) {
   const int tiles_x = (D.nx / 2 + L.bx - 1) / L.bx;
@@ -503,25 +503,27 @@ static void step_pair_nt(const Domain &D, const void *src, void *dst, const Laun
   auto s = (const uint16_t *)src;
   auto d = (uint16_t *)dst;
   if (D.Gx != 0.0f || D.Gy != 0.0f)
-    hipLaunchKernelGGL((k_step_pair<true, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    hipLaunchKernelGGL((k_step_pair<C, true, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
   else
-    hipLaunchKernelGGL((k_step_pair<false, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    hipLaunchKernelGGL((k_step_pair<C, false, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
 }
 
 template <class C>
 static hipError_t step_t(const Domain &D, const void *src, void *dst,
                          const LaunchShape &L, hipStream_t st) {
   const bool nts = L.nt & 1, ntl = (L.nt & 2) != 0;
-  if (sizeof(typename C::T) == 2 && (L.nt & 4) && !D.walls && D.nx % 2 == 0) {
-    if (nts && ntl)
-      step_pair_nt<true, true>(D, src, dst, L, st);
-    else if (nts)
-      step_pair_nt<true, false>(D, src, dst, L, st);
-    else if (ntl)
-      step_pair_nt<false, true>(D, src, dst, L, st);
-    else
-      step_pair_nt<false, false>(D, src, dst, L, st);
-    return hipGetLastError();
+  if constexpr (sizeof(typename C::T) == 2) {
+    if ((L.nt & 4) && !D.walls && D.nx % 2 == 0) {
+      if (nts && ntl)
+        step_pair_nt<C, true, true>(D, src, dst, L, st);
+      else if (nts)
+        step_pair_nt<C, true, false>(D, src, dst, L, st);
+      else if (ntl)
+        step_pair_nt<C, false, true>(D, src, dst, L, st);
+      else
+        step_pair_nt<C, false, false>(D, src, dst, L, st);
+      return hipGetLastError();
+    }
   }
   if (nts && ntl)
     step_nt<C, true, true>(D, src, dst, L, st);
@@ -540,15 +542,19 @@ hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
   // byte offsets inside one plane are 32-bit
   if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
     return hipErrorInvalidValue;
-  return storage == kF16 ? step_t<CodecF16>(D, src, dst, L, st)
-                         : step_t<CodecF32>(D, src, dst, L, st);
+  if (storage == kF16)  // S = 1 (the default) needs no scaling of the stored values
+    return D.s == 1.0f ? step_t<CodecF16U>(D, src, dst, L, st) : step_t<CodecF16>(D, src, dst, L, st);
+  return step_t<CodecF32>(D, src, dst, L, st);
 }
 
 hipError_t launch_init(int storage, const Domain &D, const double *u,
                        const double *b, double bwx, double bwy, void *dst,
                        hipStream_t st) {
   const dim3 block(64), grid((D.nx + 63) / 64, D.ny);
-  if (storage == kF16)
+  if (storage == kF16 && D.s == 1.0f)
+    hipLaunchKernelGGL(k_init<CodecF16U>, grid, block, 0, st, D, u, b, bwx, bwy,
+                       (uint16_t *)dst);
+  else if (storage == kF16)
     hipLaunchKernelGGL(k_init<CodecF16>, grid, block, 0, st, D, u, b, bwx, bwy,
                        (uint16_t *)dst);
   else

@@ -85,6 +85,20 @@ struct CodecF16 {
     return __half_as_ushort(__float2half_rn(v * s));
   }
 };
+// The F16 codec at S = 1 (the default), used by every kernel that writes
+// populations when S = 1: no multiply by 1 on decoded values, and a plain
+// round-to-nearest-even conversion on encode (CodecF16's scaled encode is
+// fused into one mixed-precision FMA, which returns +0 for -0 and so is not
+// bit-identical at S = 1).
+struct CodecF16U {
+  using T = uint16_t;
+  __device__ __forceinline__ static float dec(T v, float) {
+    return __half2float(__ushort_as_half(v));
+  }
+  __device__ __forceinline__ static T enc(float v, float) {
+    return __half_as_ushort(__float2half_rn(v));
+  }
+};
 
 // ---- parameters of the collision ------------------------------------------
 struct CollideParams {

@@ -5,6 +5,8 @@
 // wave-uniform (scalar registers) and the in-plane position is a 32-bit byte
 // offset, so each access is one global load/store with a scalar base.
 #pragma once
+#include <utility>
+
 #include "rr_node.h"
 
 namespace rr {
@@ -63,6 +65,28 @@ __device__ __forceinline__ float pull_g_per(const PlaneGeom &G,
                 G.inv_s);
 }
 
+// Store the post-collision populations of one node at byte offset o of
+// every plane.  Written plane by plane (not as a loop over a running
+// pointer) so each store keeps a scalar plane base and the 32-bit offset.
+template <class C, bool NT, int P>
+__device__ __forceinline__ void store_plane(const PlaneGeom &G, typename C::T *__restrict__ dst,
+                                            uint32_t o, const float *d, const float *g) {
+  const float v = P < kQ ? d[P] : g[P - kQ];
+  st_at<typename C::T, NT>(dst + (int64_t)P * G.plane, o, C::enc(v, G.s));
+}
+template <class C, bool NT, int... P>
+__device__ __forceinline__ void store_planes_seq(const PlaneGeom &G,
+                                                 typename C::T *__restrict__ dst, uint32_t o,
+                                                 const float *d, const float *g,
+                                                 std::integer_sequence<int, P...>) {
+  (store_plane<C, NT, P>(G, dst, o, d, g), ...);
+}
+template <class C, bool NT>
+__device__ __forceinline__ void store_planes(const PlaneGeom &G, typename C::T *__restrict__ dst,
+                                             uint32_t o, const float *d, const float *g) {
+  store_planes_seq<C, NT>(G, dst, o, d, g, std::make_integer_sequence<int, kPlanes>{});
+}
+
 // Pull, collide and store one node of a doubly periodic domain.  src/dst
 // point at plane 0 of the domain's two buffers.
 template <class C, bool FORCED, bool NT, bool NTL>
@@ -100,15 +124,10 @@ __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
   g[8] = pull_g_per<C, 4, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
   g[9] = pull_g_per<C, 4, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
   collide<FORCED>(d, g, P);
-  const uint32_t o = b0 + x0;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) st_at<T, NT>(dst + (int64_t)i * G.plane, o, C::enc(d[i], G.s));
-#pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k)
-    st_at<T, NT>(dst + (int64_t)(kQ + k) * G.plane, o, C::enc(g[k], G.s));
+  store_planes<C, NT>(G, dst, b0 + x0, d, g);
 }
 
-// ---- FP16 storage, two neighbouring nodes per thread ------------------------
+// ---- 16-bit storage, two neighbouring nodes per thread -----------------------
 // Nodes (x, x + 1), x even, nx even: every plane moves as one 32-bit word per
 // thread (low half node x, high half node x + 1), which halves the memory
 // instructions per byte of the 2-byte codec.  The planes shifted by +-1 in x
@@ -119,24 +138,39 @@ __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
 template <int CX, bool NTL>
 __device__ __forceinline__ uint32_t ld_pair(const uint16_t *__restrict__ plane, uint32_t row,
                                             int x, int nx) {
-  const char *b = (const char *)plane + row;
-  if (CX == 0) return ld_at<uint32_t, NTL>((const uint32_t *)b, 2u * x);
-  const bool seam = CX > 0 ? x == 0 : x == nx - 2;
-  if (!seam) return ld_at<uint32_t, NTL>((const uint32_t *)b, 2u * (x - CX));
-  // the pair straddles the seam: (nx - 1, 0) in both cases
-  const uint32_t lo = ld_at<uint16_t, NTL>((const uint16_t *)b, 2u * (nx - 1));
-  const uint32_t hi = ld_at<uint16_t, NTL>((const uint16_t *)b, 0u);
-  return lo | (hi << 16);
+  if (CX == 0) return ld_at<uint32_t, NTL>((const uint32_t *)plane, row + 2u * x);
+  // first source node, kept inside the row so the word is always in bounds
+  const int xs = CX > 0 ? (x > 0 ? x - 1 : 0) : (x + 1 < nx - 1 ? x + 1 : nx - 2);
+  uint32_t w = ld_at<uint32_t, NTL>((const uint32_t *)plane, row + 2u * xs);
+  if (CX > 0 ? x == 0 : x == nx - 2) {
+    // the pair straddles the seam: (nx - 1, 0) in both cases
+    const uint32_t lo = ld_at<uint16_t, NTL>(plane, row + 2u * (nx - 1));
+    const uint32_t hi = ld_at<uint16_t, NTL>(plane, row);
+    w = lo | (hi << 16);
+  }
+  return w;
 }
 
-__device__ __forceinline__ float h16_lo(uint32_t w, float inv_s) {
-  return CodecF16::dec((uint16_t)(w & 0xffffu), inv_s);
+// Store plane P's word: node x's value (the low half already encoded in
+// lo[P]) and node x + 1's from its post-collision arrays.
+template <class C, bool NT, int P>
+__device__ __forceinline__ void store_pair_plane(const PlaneGeom &G, uint16_t *__restrict__ dst,
+                                                 uint32_t o, const uint16_t *lo, const float *d,
+                                                 const float *g) {
+  const float v = P < kQ ? d[P] : g[P - kQ];
+  st_at<uint32_t, NT>((uint32_t *)(dst + (int64_t)P * G.plane), o,
+                      (uint32_t)lo[P] | ((uint32_t)C::enc(v, G.s) << 16));
 }
-__device__ __forceinline__ float h16_hi(uint32_t w, float inv_s) {
-  return CodecF16::dec((uint16_t)(w >> 16), inv_s);
+template <class C, bool NT, int... P>
+__device__ __forceinline__ void store_pair_planes(const PlaneGeom &G, uint16_t *__restrict__ dst,
+                                                  uint32_t o, const uint16_t *lo, const float *d,
+                                                  const float *g,
+                                                  std::integer_sequence<int, P...>) {
+  (store_pair_plane<C, NT, P>(G, dst, o, lo, d, g), ...);
 }
 
-template <bool FORCED, bool NT, bool NTL>
+// C: a 16-bit codec (CodecF16 or CodecF16U).
+template <class C, bool FORCED, bool NT, bool NTL>
 __device__ __forceinline__ void update_periodic_pair(const PlaneGeom &G,
                                                      const uint16_t *__restrict__ src,
                                                      uint16_t *__restrict__ dst, int x, int y,
@@ -148,38 +182,32 @@ __device__ __forceinline__ void update_periodic_pair(const PlaneGeom &G,
   uint32_t w[kPlanes];
   auto rowf = [&](int cyv) { return cyv == 0 ? b0 : (cyv > 0 ? bm : bp); };
 #define RR_LDF(I) w[I] = ld_pair<cx(I), NTL>(plane_ptr(src, I, G.plane), rowf(cy(I)), x, G.nx)
-#define RR_LDG(J, C) \
-  w[gplane(J, C)] = ld_pair<ex(J), NTL>(plane_ptr(src, gplane(J, C), G.plane), rowf(ey(J)), x, G.nx)
+#define RR_LDG(J, K) \
+  w[gplane(J, K)] = ld_pair<ex(J), NTL>(plane_ptr(src, gplane(J, K), G.plane), rowf(ey(J)), x, G.nx)
   RR_LDF(0); RR_LDF(1); RR_LDF(2); RR_LDF(3); RR_LDF(4); RR_LDF(5); RR_LDF(6); RR_LDF(7); RR_LDF(8);
   RR_LDG(0, 0); RR_LDG(0, 1); RR_LDG(1, 0); RR_LDG(1, 1); RR_LDG(2, 0); RR_LDG(2, 1);
   RR_LDG(3, 0); RR_LDG(3, 1); RR_LDG(4, 0); RR_LDG(4, 1);
 #undef RR_LDF
 #undef RR_LDG
+  // node x (low halves), then node x + 1 (high halves)
   float d[kQ], g[2 * kQm];
+  uint16_t lo[kPlanes];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) d[i] = h16_lo(w[i], G.inv_s);
+  for (int i = 0; i < kQ; ++i) d[i] = C::dec((uint16_t)(w[i] & 0xffffu), G.inv_s);
 #pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k) g[k] = h16_lo(w[kQ + k], G.inv_s);
+  for (int k = 0; k < 2 * kQm; ++k) g[k] = C::dec((uint16_t)(w[kQ + k] & 0xffffu), G.inv_s);
   collide<FORCED>(d, g, P);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) w[i] = (w[i] & 0xffff0000u) | CodecF16::enc(d[i], G.s);
+  for (int i = 0; i < kQ; ++i) lo[i] = C::enc(d[i], G.s);
 #pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k)
-    w[kQ + k] = (w[kQ + k] & 0xffff0000u) | CodecF16::enc(g[k], G.s);
+  for (int k = 0; k < 2 * kQm; ++k) lo[kQ + k] = C::enc(g[k], G.s);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) d[i] = h16_hi(w[i], G.inv_s);
+  for (int i = 0; i < kQ; ++i) d[i] = C::dec((uint16_t)(w[i] >> 16), G.inv_s);
 #pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k) g[k] = h16_hi(w[kQ + k], G.inv_s);
+  for (int k = 0; k < 2 * kQm; ++k) g[k] = C::dec((uint16_t)(w[kQ + k] >> 16), G.inv_s);
   collide<FORCED>(d, g, P);
-  const uint32_t o = b0 + 2u * x;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i)
-    st_at<uint32_t, NT>((uint32_t *)(dst + (int64_t)i * G.plane), o,
-                        (w[i] & 0xffffu) | ((uint32_t)CodecF16::enc(d[i], G.s) << 16));
-#pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k)
-    st_at<uint32_t, NT>((uint32_t *)(dst + (int64_t)(kQ + k) * G.plane), o,
-                        (w[kQ + k] & 0xffffu) | ((uint32_t)CodecF16::enc(g[k], G.s) << 16));
+  store_pair_planes<C, NT>(G, dst, b0 + 2u * x, lo, d, g,
+                           std::make_integer_sequence<int, kPlanes>{});
 }
 
 }  // namespace rr

@@ -207,6 +207,17 @@ class Hartmann:
         b[1] = self.B0
         return u, b
 
+    def profile(self, y):
+        """Steady analytic solution of the incompressible MHD system for this
+        channel (insulating walls at distance a from the centre): u_x(y) and
+        b_x(y) at node rows y, the reference of the convergence runs."""
+        a, Ha, B0 = self.a, self.Ha, self.B0
+        yp = np.asarray(y, dtype=np.float64) - (self.ny - 1) / 2.0
+        u = (self.G * a * a / (self.nu * Ha)) * (math.cosh(Ha) - np.cosh(Ha * yp / a)) \
+            / math.sinh(Ha)
+        bx = (self.G * a / B0) * (np.sinh(Ha * yp / a) / math.sinh(Ha) - yp / a)
+        return u, bx
+
 
 def hartmann_c2() -> Hartmann:
     """512 x 256 Hartmann channel: G = 1e-6, Ha = 10, tau_f 0.6, tau_m 0.55."""
