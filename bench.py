@@ -44,7 +44,8 @@ def measured_traffic(storage, n):
 
 
 def cpu_baseline(n_sample=2048, steps=60):
-    """The FP64 oracle on a bounded sample of the same workload."""
+    """The FP64 oracle on a bounded sample of the same workload: all host
+    threads on 2048^2 x 60 steps, and one thread on 512^2 x 20 steps."""
     import oracle
     from paper_2602_14667_amd import inputs
     u, b = inputs.turbulence(n_sample, 0.04)
@@ -54,11 +55,27 @@ def cpu_baseline(n_sample=2048, steps=60):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    cores = oracle.threads()
+    o.close()
+    # one thread, smaller sample of the same field
+    n1, s1 = 512, 20
+    u1, b1 = inputs.turbulence(n1, 0.04)
+    oracle.set_threads(1)
+    o1 = oracle.Oracle(n1, n1, 0.52, 0.52)
+    o1.init(u1, b1)
+    o1.step(1)
+    t1 = time.perf_counter()
+    o1.step(s1)
+    dt1 = time.perf_counter() - t1
+    o1.close()
+    oracle.set_threads(cores)
     return {"value": n_sample * n_sample * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{n_sample}^2 of the same turbulence field, {steps} "
                       f"steps after 1 warm-up step, FP64, OpenMP rows",
-            "seconds": dt}
+            "seconds": dt,
+            "single_thread": {"value": n1 * n1 * s1 / dt1 / 1e6, "unit": "MLUPS",
+                              "sample": f"{n1}^2, {s1} steps", "seconds": dt1}}
 
 
 def copy_reference(torch, rrmhd, args):
@@ -129,7 +146,8 @@ def batch_bench(torch, rrmhd, inputs, args):
         u, bf = inputs.batch_fields(d)
         b.init(k, torch.from_numpy(u).cuda(), torch.from_numpy(bf).cuda())
     t0 = time.perf_counter()
-    b.autotune(None, trials=5)
+    if not args.no_autotune:
+        b.autotune(None, trials=10)
     tune_s = time.perf_counter() - t0
     chunk = 100
     b.set_graph_chunk(chunk)
@@ -173,7 +191,8 @@ def batch_bench(torch, rrmhd, inputs, args):
                                "OT or turbulence, tau in [0.501, 0.6]",
                    "nodes": nodes, "tiles": info["tiles"],
                    "workgroups_per_launch": info["grid"],
-                   "graph_chunk": chunk, "autotune_s": round(tune_s, 2)},
+                   "graph_chunk": chunk, "autotuned": not args.no_autotune,
+                   "autotune_s": round(tune_s, 2)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
@@ -369,6 +388,9 @@ def main():
     ap.add_argument("--tau", type=float, default=0.52)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch workload: keep the library's default launch "
+                         "(one workgroup per 32x8 tile) instead of autotuning")
     ap.add_argument("--mode", choices=["step", "copy", "sweep"], default="step",
                     help="copy: time the plain device-copy reference; sweep: "
                          "time launch shapes, XCD block orders and plane gaps")

@@ -74,6 +74,7 @@ def lib():
                                        ctypes.c_double, _dp, ctypes.c_int,
                                        _dp, _dp, _dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_closure_nparams.restype = ctypes.c_int
         L.orc_set_closure.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_set_closure.restype = ctypes.c_int
@@ -109,6 +110,11 @@ def _ptr(a: np.ndarray | None):
 def threads() -> int:
     """OpenMP threads the oracle's grid loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of later grid loops (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def hermite(n: int, idx, i: int) -> float:

@@ -727,6 +727,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Thread count of later grid loops (timing only; n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ======================================================================== */
 /* Learned closure (project addition): MLP 8 -> 64 -> 64 -> 3 with GELU      */
 /* ======================================================================== */
