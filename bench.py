@@ -407,7 +407,7 @@ def main():
     ap.add_argument("--closure-scale", choices=["full", "reduced"], default="full")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for "
+        print(f"bench.py: this implementation runs on one GPU only (asked for "
               f"--gpus {args.gpus}); the domain-decomposed multi-GPU path is "
               "a design, not built", file=sys.stderr)
         sys.exit(2)

@@ -71,15 +71,15 @@ def main(prof, out, n):
             "",
             f"Kernel: `{name}`  (source hash {kernel_hash()})",
             "",
-            "Commands (from the repository root, on the GPU box):",
+            "Commands (from the repository root, on the MI355X host):",
             "```",
-            f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline",
-            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
-            "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/stats_copy -o run -- python3 bench.py --mode copy --steps 20",
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/pmc_FETCH_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/pmc_WRITE_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
-            f"python -m paper_2602_14667_amd.profsum gpurun_out/prof profiles {n}",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_copy -o run -- python3 bench.py --mode copy --steps 20",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
+            f"python -m paper_2602_14667_amd.profsum {prof} profiles {n}",
             "```",
             "",
             "| kernel | calls | avg ns | min ns | max ns |",
@@ -118,7 +118,7 @@ def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command, l
     stats = kernel_stats(stats_dir)
     bpl = float(bytes_per_launch)
     names = [k for k in stats if kernel in k]
-    lines = [f"# {title}", "", "Command (from the repository root, on the GPU box):", "```",
+    lines = [f"# {title}", "", "Command (from the repository root, on the MI355X host):", "```",
              command, f"python -m paper_2602_14667_amd.profsum stats {stats_dir} {out_md} "
              f"{kernel} {bytes_per_launch} ...", "```", "",
              "| kernel | calls | avg ns | min ns | max ns |", "|---|---|---|---|---|"]
