@@ -140,6 +140,21 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 /* Stream used by the handle; NULL is the null stream. */
 int rrmhd_set_stream(rrmhd *h, void *hip_stream);
 
+/* Equilibrium of the fluid populations.  RRMHD_FEQ_ALGORITHM (the default)
+ * is the fourth-order Hermite equilibrium the algorithm uses (Eq. feq_4th,
+ * task 2 of the algorithm in Sec. II.B), with the Maxwell stress in the
+ * second-order coefficient only.  RRMHD_FEQ_FULL_MAXWELL adds the u.M cross
+ * terms of the third- and fourth-order equilibrium coefficients (Eq.
+ * eq:a0_4) on the D2Q9-supported components xxy, xyy and xxyy: an ablation
+ * of the reading that the two equilibria differ, for comparing them on the
+ * same kernels.  It applies to every following rrmhd_init and rrmhd_step of
+ * the handle (single-node update with non-temporal stores; the launch
+ * shape's nt bits are ignored).  EINVAL for another kind, or for
+ * FULL_MAXWELL while the learned closure is enabled (the closure was
+ * trained on the algorithm's equilibrium).  Host-side only. */
+enum { RRMHD_FEQ_ALGORITHM = 0, RRMHD_FEQ_FULL_MAXWELL = 1 };
+int rrmhd_set_equilibrium(rrmhd *h, int kind);
+
 int rrmhd_destroy(rrmhd *h);
 
 /* ---- Batched ensemble --------------------------------------------------

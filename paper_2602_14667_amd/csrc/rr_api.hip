@@ -182,6 +182,13 @@ int rrmhd_set_stream(rrmhd *h, void *hip_stream) {
   return RRMHD_OK;
 }
 
+int rrmhd_set_equilibrium(rrmhd *h, int kind) {
+  if (!h || (kind != RRMHD_FEQ_ALGORITHM && kind != RRMHD_FEQ_FULL_MAXWELL)) return RRMHD_EINVAL;
+  if (kind == RRMHD_FEQ_FULL_MAXWELL && h->closure_on) return RRMHD_EINVAL;
+  h->D.feq = kind;
+  return RRMHD_OK;
+}
+
 int rrmhd_init(rrmhd *h, const double *u, const double *b) {
   if (!h || !u || !b) return RRMHD_EINVAL;
   HIP_OR_RETURN(rr::launch_init(h->storage, h->D, u, b, h->bc.b_wall[0],
@@ -324,7 +331,8 @@ int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm) {
 
 int rrmhd_closure_enable(rrmhd *h, int on) {
   if (!h) return RRMHD_EINVAL;
-  if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f)) return RRMHD_EINVAL;
+  if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f || h->D.feq))
+    return RRMHD_EINVAL;
   h->closure_on = on != 0;
   return RRMHD_OK;
 }

@@ -18,6 +18,8 @@ struct Domain {
   float bw2x, bw2y;  // 2 psi_j b_wall for j = 1..4 (psi = 1/6): b_wall / 3
   float s, inv_s;    // storage scale (F16)
   int elem;          // bytes per stored value (4 or 2)
+  int feq;           // 0: the algorithm's equilibrium; 1: with the u.M
+                     // cross terms of the third and fourth orders (ablation)
 };
 
 struct LaunchShape {

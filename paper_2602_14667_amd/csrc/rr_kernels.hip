@@ -135,7 +135,7 @@ __device__ __forceinline__ int xcd_local(int L, int n) {
 // 1-D grid of tiles; a tile is blockDim.x nodes of ry consecutive rows,
 // blockDim.y tiles high.
 // ---------------------------------------------------------------------------
-template <class C, bool WALLS, bool FORCED, bool NT, bool NTL>
+template <class C, bool WALLS, bool FORCED, bool NT, bool NTL, bool FULLM = false>
 __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
                                               int xcd,
                                               const typename C::T *__restrict__ src,
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
     if constexpr (WALLS) {
       float d[kQ], g[2 * kQm];
       pull_node<C, true>(D, src, x, y, d, g);
-      collide<FORCED>(d, g, P);
+      collide<FORCED, NoCorrection, FULLM>(d, g, P);
       const int o = y * D.nx + x;
 #pragma unroll
       for (int i = 0; i < kQ; ++i) dst[(int64_t)i * D.plane + o] = C::enc(d[i], D.s);
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
         dst[(int64_t)(kQ + k) * D.plane + o] = C::enc(g[k], D.s);
     } else {
       const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
-      update_periodic<C, FORCED, NT, NTL>(G, src, dst, x, y, P);
+      update_periodic<C, FORCED, NT, NTL, FULLM>(G, src, dst, x, y, P);
     }
   }
 }
@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
 // that the first pull yields exactly f_eq(1, u, b), g_eq(u, b) everywhere.
 // FP64 arithmetic, rounded once to the storage type.
 // ---------------------------------------------------------------------------
-__device__ double feq_dev_d(int i, double ux, double uy, double bx, double by) {
+__device__ double feq_dev_d(int i, double ux, double uy, double bx, double by,
+                           int full) {
   // D1Q3 factors minus one, times the weight split w_i = wx * wy
   const int cxi = cx(i), cyi = cy(i);
   const double ax = cxi == 0 ? -1.5 * ux * ux : 3.0 * cxi * ux + 3.0 * ux * ux;
@@ -189,7 +190,17 @@ __device__ double feq_dev_d(int i, double ux, double uy, double bx, double by) {
   const double cb = cxi * bx + cyi * by;
   const double q = 0.5 * (bx * bx + by * by) * c2 - cb * cb;
   const double w = (i == 0) ? 16.0 / 36.0 : ((i & 1) ? 1.0 / 36.0 : 4.0 / 36.0);
-  return w * (ax + ay + ax * ay + 4.5 * q);
+  double B = ax + ay + ax * ay + 4.5 * q;
+  if (full) {
+    // u.M cross terms of a0^(3), a0^(4) (Eq. eq:a0_4) with h = 3 c^2 - 1
+    const double mxx = 0.5 * (by * by - bx * bx), mxy = -bx * by;
+    const double hx = 3.0 * cxi * cxi - 1.0, hy = 3.0 * cyi * cyi - 1.0;
+    const double m3xxy = 2.0 * ux * mxy + uy * mxx;
+    const double m3xyy = -ux * mxx + 2.0 * uy * mxy;
+    const double m4 = -ux * ux * mxx + uy * uy * mxx + 4.0 * ux * uy * mxy;
+    B += 4.5 * (cyi * hx * m3xxy + cxi * hy * m3xyy) + 2.25 * hx * hy * m4;
+  }
+  return w * B;
 }
 
 __device__ void geq_d(int j, double ux, double uy, double bx, double by,
@@ -218,11 +229,11 @@ __global__ void k_init(Domain D, const double *__restrict__ u,
     double v;
     if (D.walls && (ty < 0 || ty >= D.ny)) {
       v = feq_dev_d(opp_f(i), fld(u, 0, x, y), fld(u, 1, x, y), fld(b, 0, x, y),
-                    fld(b, 1, x, y));
+                    fld(b, 1, x, y), D.feq);
     } else {
       ty = ty < 0 ? ty + D.ny : (ty >= D.ny ? ty - D.ny : ty);
       v = feq_dev_d(i, fld(u, 0, tx, ty), fld(u, 1, tx, ty), fld(b, 0, tx, ty),
-                    fld(b, 1, tx, ty));
+                    fld(b, 1, tx, ty), D.feq);
     }
     dst[(int64_t)i * D.plane + o] = C::enc((float)v, D.s);
   }
@@ -493,6 +504,31 @@ static void step_nt(const Domain &D, const void *src, void *dst, const LaunchSha
   }
 }
 
+// The equilibrium ablation (Domain::feq = 1): single-node update with
+// non-temporal stores whatever the launch shape's flags say.
+template <class C>
+static void step_fullm(const Domain &D, const void *src, void *dst, const LaunchShape &L,
+                       hipStream_t st) {
+  const int tiles_x = (D.nx + L.bx - 1) / L.bx;
+  const int rows_per_tile = L.by * L.ry;
+  const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
+  const dim3 grid(tiles_x * tiles_y), block(L.bx, L.by);
+  const bool forced = D.Gx != 0.0f || D.Gy != 0.0f;
+  auto s = (const typename C::T *)src;
+  auto d = (typename C::T *)dst;
+  if (D.walls) {
+    if (forced)
+      hipLaunchKernelGGL((k_step<C, true, true, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    else
+      hipLaunchKernelGGL((k_step<C, true, false, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  } else {
+    if (forced)
+      hipLaunchKernelGGL((k_step<C, false, true, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    else
+      hipLaunchKernelGGL((k_step<C, false, false, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  }
+}
+
 template <class C, bool NT, bool NTL>
 static void step_pair_nt(const Domain &D, const void *src, void *dst, const LaunchShape &L,
                          hipStream_t st) {
@@ -512,6 +548,10 @@ template <class C>
 static hipError_t step_t(const Domain &D, const void *src, void *dst,
                          const LaunchShape &L, hipStream_t st) {
   const bool nts = L.nt & 1, ntl = (L.nt & 2) != 0;
+  if (D.feq) {
+    step_fullm<C>(D, src, dst, L, st);
+    return hipGetLastError();
+  }
   if constexpr (sizeof(typename C::T) == 2) {
     if ((L.nt & 4) && !D.walls && D.nx % 2 == 0) {
       if (nts && ntl)

@@ -51,7 +51,7 @@ __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__host__ // Two FP32 values -> two BF16 (round to nearest even) packed low/high, one
+// Two FP32 values -> two BF16 (round to nearest even) packed low/high, one
 // v_cvt_pk_bf16_f32 on gfx950; same results as f2bf for finite values.
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));

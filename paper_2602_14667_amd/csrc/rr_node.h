@@ -196,7 +196,11 @@ struct NoCorrection {
 // One collision (algorithm tasks 1-5) in place.  d[i] = f_i - w_i on entry,
 // f*_i - w_i on exit; g[2j + c] = g_j,c before and after.  corr(rho, u_x,
 // u_y, b_x, b_y, a_xx, a_xy, a_yy) may adjust the three a_1^(2) components.
-template <bool FORCED, class Corr = NoCorrection>
+// FULLM selects the equilibrium variant that keeps the u.M cross terms of
+// the third- and fourth-order equilibrium coefficients (Eq. eq:a0_4), which
+// the algorithm's equilibrium (Eq. feq_4th, task 2) leaves out; it exists
+// for the ablation of that reading only.
+template <bool FORCED, class Corr = NoCorrection, bool FULLM = false>
 __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
                                         const CollideParams &P,
                                         const Corr &corr = Corr()) {
@@ -242,6 +246,21 @@ __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
   A.xxy = P.om_c * axxy;
   A.xyy = P.om_c * axyy;
   A.xxyy = P.om_c * axxyy;
+  if constexpr (FULLM) {
+    // The cross terms of a0^(3) and a0^(4) on the supported components,
+    // with M_yy = -M_xx and M_xy = -b_x b_y:
+    //   xxy: 2 u_x M_xy + u_y M_xx,  xyy: u_x M_yy + 2 u_y M_xy,
+    //   xxyy: u_x^2 M_yy + u_y^2 M_xx + 4 u_x u_y M_xy.
+    // Their Hermite weights in the equilibrium series equal those of the
+    // regularised bracket (4.5 c_y h_x, 4.5 c_x h_y, 2.25 h_x h_y), so they
+    // enter as additions to the third- and fourth-order coefficients.
+    const float m3xxy = fmaf(uy, mxx, -2.0f * (ux * bxy));
+    const float m3xyy = fmaf(-ux, mxx, -2.0f * (uy * bxy));
+    const float m4 = fmaf(fmaf(uy, uy, -ux * ux), mxx, -4.0f * (ux * (uy * bxy)));
+    A.xxy = A.xxy + m3xxy;
+    A.xyy = A.xyy + m3xyy;
+    A.xxyy = A.xxyy + m4;
+  }
 
   // task 2: equilibrium factors
   EqTerms E;

@@ -89,7 +89,7 @@ __device__ __forceinline__ void store_planes(const PlaneGeom &G, typename C::T *
 
 // Pull, collide and store one node of a doubly periodic domain.  src/dst
 // point at plane 0 of the domain's two buffers.
-template <class C, bool FORCED, bool NT, bool NTL>
+template <class C, bool FORCED, bool NT, bool NTL, bool FULLM = false>
 __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
                                                 const typename C::T *__restrict__ src,
                                                 typename C::T *__restrict__ dst, int x,
@@ -123,7 +123,7 @@ __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
   g[7] = pull_g_per<C, 3, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
   g[8] = pull_g_per<C, 4, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
   g[9] = pull_g_per<C, 4, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  collide<FORCED>(d, g, P);
+  collide<FORCED, NoCorrection, FULLM>(d, g, P);
   store_planes<C, NT>(G, dst, b0 + x0, d, g);
 }
 

@@ -16,12 +16,14 @@ LIB_PATH = os.path.join(HERE, "librrmhd.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
 STORE_F32, STORE_F16 = 0, 1
 BC_PERIODIC, BC_WALLS_Y = 0, 1
+FEQ_ALGORITHM, FEQ_FULL_MAXWELL = 0, 1
 
 EXPORTED = [
     "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
     "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
-    "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_destroy", "rrmhd_strerror",
+    "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium",
+    "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
     "rrmhd_batch_create", "rrmhd_batch_init", "rrmhd_batch_step",
     "rrmhd_batch_set_graph_chunk", "rrmhd_batch_set_shape", "rrmhd_batch_set_fetch",
@@ -87,6 +89,7 @@ def lib():
         L.rrmhd_set_stream.argtypes = [vp, vp]
         ci = ctypes.c_int
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
+        L.rrmhd_set_equilibrium.argtypes = [vp, ci]
         L.rrmhd_destroy.argtypes = [vp]
         L.rrmhd_bandwidth_probe.argtypes = [vp, vp, i64, vp]
         dbl = ctypes.POINTER(ctypes.c_double)
@@ -193,11 +196,13 @@ class Solver:
     storage: "f32" or "f16" (populations stored as offsets f - w).
     walls: half-way bounce-back walls in y (periodic x); force: body force
     per unit mass; b_wall: field imposed by the magnetic walls.
+    equilibrium: "algorithm" (the method's) or "full_maxwell" (ablation with
+    the u.M cross terms of the third and fourth orders).
     """
 
     def __init__(self, nx, ny, tau_f, tau_m, storage="f32", walls=False,
                  force=(0.0, 0.0), b_wall=(0.0, 0.0), codec_scale=0.0,
-                 stream=None):
+                 stream=None, equilibrium="algorithm"):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.storage = storage
@@ -211,6 +216,8 @@ class Solver:
                               ctypes.byref(bc), _stream_handle(stream),
                               ctypes.byref(h)), "rrmhd_create")
         self._h = h
+        if equilibrium != "algorithm":
+            self.set_equilibrium(equilibrium)
 
     # -- lifetime ----------------------------------------------------------
     def close(self):
@@ -332,6 +339,11 @@ class Solver:
     def closure_enable(self, on=True):
         _check(lib().rrmhd_closure_enable(self._h, int(bool(on))),
                "rrmhd_closure_enable")
+
+    def set_equilibrium(self, kind):
+        """"algorithm" or "full_maxwell"; applies to later init and steps."""
+        k = {"algorithm": FEQ_ALGORITHM, "full_maxwell": FEQ_FULL_MAXWELL}[kind]
+        _check(lib().rrmhd_set_equilibrium(self._h, k), "rrmhd_set_equilibrium")
 
     def set_stream(self, stream):
         self._stream = stream

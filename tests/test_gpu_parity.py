@@ -53,7 +53,7 @@ def gpu_moments(s):
 
 def run_pair(nx, ny, u, b, tau_f, tau_m, checkpoints, storage="f32",
              walls=False, force=(0.0, 0.0), b_wall=(0.0, 0.0),
-             initial_norm=False):
+             initial_norm=False, equilibrium="algorithm"):
     """Run GPU and oracle side by side; per-field rel L2 at each checkpoint.
 
     With initial_norm the error of a field is divided by the larger of its
@@ -62,10 +62,12 @@ def run_pair(nx, ny, u, b, tau_f, tau_m, checkpoints, storage="f32",
     the arithmetic."""
     R = rrmhd()
     s = R.Solver(nx, ny, tau_f, tau_m, storage=storage, walls=walls,
-                 force=force, b_wall=b_wall)
+                 force=force, b_wall=b_wall, equilibrium=equilibrium)
     s.init(dev(u), dev(b))
     o = oracle.Oracle(nx, ny, tau_f, tau_m, walls=walls, force=force,
-                      b_wall=b_wall)
+                      b_wall=b_wall,
+                      option=(oracle.FEQ_SERIES_FULL if equilibrium == "full_maxwell"
+                              else oracle.FEQ_ALGORITHM))
     o.init(u, b)
     ref0 = split(*o.moments())
     errs = []

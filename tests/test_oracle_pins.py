@@ -155,17 +155,73 @@ def test_feq_algorithm_equals_hermite_series():
         assert np.allclose(f1, f2, rtol=0, atol=1e-16)
 
 
-def test_full_series_adds_cross_terms_only():
-    """The u.M cross terms of the full series change only the third and
-    fourth moments: Sum H_xxy f = rho ux^2 uy + uy Mxx + 2 ux Mxy."""
-    rho, u, b = 1.02, np.array([0.05, -0.04]), np.array([0.03, 0.05])
-    fB = oracle.node_feq_series(rho, u, b, full=True)
+@pytest.mark.parametrize("trial", range(5))
+def test_full_series_adds_cross_terms_only(trial):
+    """The equilibrium with the u.M cross terms of Eq. eq:a0_4 (the ablation
+    of the reading that the algorithm keeps M at second order only) has the
+    same moments up to second order, and its third and fourth supported
+    Hermite moments are the hand-expanded components
+      xxy:  rho ux^2 uy + uy Mxx + 2 ux Mxy,
+      xyy:  rho ux uy^2 + ux Myy + 2 uy Mxy,
+      xxyy: rho ux^2 uy^2 + ux^2 Myy + uy^2 Mxx + 4 ux uy Mxy."""
+    rho = 1 + 0.1 * RNG.standard_normal()
+    u = 0.1 * RNG.standard_normal(2)
+    b = 0.1 * RNG.standard_normal(2)
     M = 0.5 * (b @ b) * np.eye(2) - np.outer(b, b)
-    assert abs(fB.sum() - rho) < 1e-15
-    assert abs((fB * CX).sum() - rho * u[0]) < 1e-15
-    m = (fB * Hvec((0, 0, 1))).sum()
-    assert abs(m - (rho * u[0] ** 2 * u[1] + u[1] * M[0, 0]
-                    + 2 * u[0] * M[0, 1])) < 1e-15
+    ux, uy = u
+    for fB in (oracle.node_feq_series(rho, u, b, full=True),
+               oracle.node_equilibrium(rho, u, b, option=oracle.FEQ_SERIES_FULL)[0]):
+        tol = 1e-15
+        assert abs(fB.sum() - rho) < tol
+        assert abs((fB * CX).sum() - rho * ux) < tol
+        assert abs((fB * CY).sum() - rho * uy) < tol
+        for a in range(2):
+            for c in range(2):
+                m = (fB * Hvec((a, c))).sum()
+                assert abs(m - (rho * u[a] * u[c] + M[a, c])) < tol
+        assert abs((fB * Hvec((0, 0, 1))).sum()
+                   - (rho * ux ** 2 * uy + uy * M[0, 0] + 2 * ux * M[0, 1])) < tol
+        assert abs((fB * Hvec((0, 1, 1))).sum()
+                   - (rho * ux * uy ** 2 + ux * M[1, 1] + 2 * uy * M[0, 1])) < tol
+        assert abs((fB * Hvec((0, 0, 1, 1))).sum()
+                   - (rho * ux ** 2 * uy ** 2 + ux ** 2 * M[1, 1]
+                      + uy ** 2 * M[0, 0] + 4 * ux * uy * M[0, 1])) < tol
+
+
+def test_full_series_difference_size():
+    """B - A at |u_a| = |b_a| = 0.05 per component is of order 1e-4 (the size
+    quoted for the difference of the two readings), and vanishes at b = 0:
+    without a field both equilibria are the hydrodynamic one (Sec. II)."""
+    u, b = np.array([0.05, 0.05]), np.array([0.05, -0.05])
+    fA, _ = oracle.node_equilibrium(1.0, u, b)
+    fB, _ = oracle.node_equilibrium(1.0, u, b, option=oracle.FEQ_SERIES_FULL)
+    d = np.abs(fB - fA).max()
+    assert 1e-5 < d < 3e-4
+    fA0, _ = oracle.node_equilibrium(1.0, u, [0.0, 0.0])
+    fB0, _ = oracle.node_equilibrium(1.0, u, [0.0, 0.0], option=oracle.FEQ_SERIES_FULL)
+    assert np.allclose(fA0, fB0, rtol=0, atol=1e-16)  # product vs series order
+
+
+def test_full_series_grid_conserves_and_reduces_without_field():
+    """The grid run with the full-series equilibrium conserves mass,
+    momentum and sum b on a periodic grid, and with b = 0 follows the
+    algorithm's run to round-off."""
+    n = 16
+    u, b = inputs.random_modes(n, n, 0.04, seed=5)
+    o = oracle.Oracle(n, n, 0.56, 0.58, option=oracle.FEQ_SERIES_FULL)
+    o.init(u, b)
+    inv0 = o.invariants()
+    o.step(50)
+    assert np.allclose(o.invariants(), inv0, rtol=0, atol=1e-12)
+    z = np.zeros_like(b)
+    oA = oracle.Oracle(n, n, 0.56, 0.58)
+    oB = oracle.Oracle(n, n, 0.56, 0.58, option=oracle.FEQ_SERIES_FULL)
+    oA.init(u, z)
+    oB.init(u, z)
+    oA.step(50)
+    oB.step(50)
+    for xa, xb in zip(oA.moments(), oB.moments()):
+        assert np.allclose(xa, xb, rtol=0, atol=1e-15)
 
 
 @pytest.mark.parametrize("trial", range(5))
