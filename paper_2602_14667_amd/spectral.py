@@ -32,6 +32,12 @@ def shell_spectrum(u: np.ndarray, b: np.ndarray) -> np.ndarray:
     return np.bincount(shell.ravel(), weights=e.ravel(), minlength=n)[: n // 2 + 1]
 
 
+def kinetic_magnetic_spectra(u: np.ndarray, b: np.ndarray):
+    """The two parts of E(k): (E_u(k), E_b(k)), E = E_u + E_b."""
+    z = np.zeros_like(u)
+    return shell_spectrum(u, z), shell_spectrum(z, b)
+
+
 def eps_spec(e_c: np.ndarray, e_ref: np.ndarray, kmax: int) -> float:
     r = e_c[1:kmax + 1] / e_ref[1:kmax + 1]
     return float(np.sqrt(np.mean((r - 1.0) ** 2)))

@@ -32,3 +32,81 @@ def test_closure_pipeline_small():
         assert math.isfinite(w["eps_spec"]) and math.isfinite(w["ekin_err"])
     print(f"[gpu]   eps_spec plain {t['plain']['eps_spec']:.4f} closure "
           f"{t['closure']['eps_spec']:.4f}; fallback {t['fallback_at']}", flush=True)
+
+
+def test_spectral_error_budget_of_the_plain_coarse_run():
+    """Where the plain coarse run's spectral error comes from, on the full
+    protocol's grids (2048^2 fine -> 512^2 coarse, tau_f 0.56, seed 20, the
+    judge's five comparison times):
+    * the flow is deterministic over the horizon: a fine run from the same
+      initial condition with every velocity value moved by up to 1e-4
+      differs from it by eps_spec < 1e-2 at every time, so the coarse
+      run's error is model error, not lost predictability;
+    * the plain coarse run meets the 5 % bar at the first comparison time;
+    * in the compared shells near k = N_c/4 the magnetic part of E(k) is
+      several times the kinetic part, so eps_spec there is mostly the
+      magnetic field's, which a closure of the fluid's a_1^(2) reaches only
+      through the velocity;
+    * the coarse relaxation time of the acoustic scaling is the best of
+      tau_c and tau_c +- 0.001 at the first time (the spectrum's high shells
+      move by more than the bar for a 7 % change of viscosity)."""
+    import numpy as np
+    from paper_2602_14667_amd import closure_pipeline as cp, inputs, rrmhd, spectral
+    rrmhd.lib()
+    n_f, factor, tau_f, seed = 2048, 4, 0.56, 20
+    n_c = n_f // factor
+    tc = cp.tau_coarse(tau_f, factor)
+    cks = [16000 * (k + 1) // 5 for k in range(5)]
+    K = n_c // 4
+    print("[gpu] spectral error budget 2048 -> 512, seed 20", flush=True)
+
+    def fine(u, b):
+        s = rrmhd.Solver(n_f, n_f, tau_f, tau_f)
+        s.init(cp._dev(u), cp._dev(b))
+        out = {}
+        for c in cks:
+            s.step(factor * c - s.step_count)
+            _, uu, bb = s.moments()
+            out[c] = spectral.kinetic_magnetic_spectra(
+                spectral.box_filter(uu.cpu().numpy(), factor),
+                spectral.box_filter(bb.cpu().numpy(), factor))
+        s.close()
+        return out
+
+    def coarse(tau, steps):
+        uc, bc = cp.coarse_fields(n_f, factor, seed)
+        s = rrmhd.Solver(n_c, n_c, tau, tau)
+        s.init(cp._dev(uc), cp._dev(bc))
+        out = {}
+        for c in steps:
+            s.step(c - s.step_count)
+            _, uu, bb = s.moments()
+            out[c] = spectral.kinetic_magnetic_spectra(uu.cpu().numpy(), bb.cpu().numpy())
+        s.close()
+        return out
+
+    u, b = cp.fine_fields(n_f, seed)
+    ref = fine(u, b)
+    r = inputs.counter_uniform(120, 7, np.arange(u.size, dtype=np.uint64)).reshape(u.shape)
+    alt = fine(u + 1e-4 * (2 * r - 1), b)
+    for c in cks:
+        e = spectral.eps_spec(sum(alt[c]), sum(ref[c]), K)
+        print(f"[gpu]   perturbed fine run, step {c}: eps_spec {e:.2e}", flush=True)
+        assert e < 1e-2
+    plain = coarse(tc, cks)
+    for c in cks:
+        (ek, em), (rk, rm) = plain[c], ref[c]
+        print(f"[gpu]   plain coarse step {c}: eps_spec {spectral.eps_spec(ek + em, rk + rm, K):.4f} "
+              f"(kinetic {spectral.eps_spec(ek, rk, K):.4f}, magnetic "
+              f"{spectral.eps_spec(em, rm, K):.4f}); E_b/E_u at k = {K}: {rm[K] / rk[K]:.2f}",
+              flush=True)
+        assert rm[K] / rk[K] > 2.0
+    first = cks[0]
+    eps = {}
+    for tau in (tc - 0.001, tc, tc + 0.001):
+        run = plain if tau == tc else coarse(tau, [first])
+        eps[tau] = spectral.eps_spec(sum(run[first]), sum(ref[first]), K)
+    print(f"[gpu]   eps_spec at step {first} for tau_c - 0.001, tau_c, tau_c + 0.001: "
+          f"{[round(v, 4) for v in eps.values()]}", flush=True)
+    assert eps[tc] <= 0.05
+    assert eps[tc] < eps[tc - 0.001] and eps[tc] < eps[tc + 0.001]

@@ -424,8 +424,11 @@ def patch_oracle(u, b, x, y, k, tau_f, tau_m):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_full_size_8192_sampled(storage):
-    n, k, tau = 8192, 3, 0.51
+@pytest.mark.parametrize("k,count", [(3, 150), (100, 40)])
+def test_full_size_8192_sampled(storage, k, count):
+    """150 sampled nodes (plus corners and an edge node) after 3 steps, and
+    40 after 100 steps (oracle patches of 201^2 nodes)."""
+    n, tau = 8192, 0.51
     note(f"full size {n}^2 {storage}, {k} steps, sampled")
     u, b = inputs.turbulence(n, 0.04)
     R = rrmhd()
@@ -433,7 +436,7 @@ def test_full_size_8192_sampled(storage):
     s.init(dev(u), dev(b))
     s.step(k)
     rho, uu, bb = s.moments()
-    pts = sample_nodes(n, 150, seed=3)
+    pts = sample_nodes(n, count, seed=3)
     xs = torch.tensor([p[0] for p in pts], device="cuda")
     ys = torch.tensor([p[1] for p in pts], device="cuda")
     got = torch.stack([rho[ys, xs], uu[0, ys, xs], uu[1, ys, xs],
@@ -445,7 +448,7 @@ def test_full_size_8192_sampled(storage):
     scale = np.array([1.0, 0.04, 0.04, 0.04, 0.04])
     err = np.max(np.abs(got - ref) / scale, axis=0)
     note(f"  max |err| / field scale: {err}")
-    tol = 1e-6 if storage == "f32" else 3e-3
+    tol = (1e-6 if k < 10 else 1e-5) if storage == "f32" else (3e-3 if k < 10 else 1e-2)
     assert np.all(err < tol), err
 
 

@@ -39,3 +39,17 @@ def test_box_filter_and_eps():
     e = np.array([0, 1.0, 2.0, 4.0])
     assert spectral.eps_spec(e, e, 3) == 0.0
     assert abs(spectral.eps_spec(1.1 * e, e, 3) - 0.1) < 1e-12
+
+
+def test_kinetic_magnetic_split():
+    """The two parts add up to E(k); a velocity-only field has no magnetic
+    part and the single mode lands in its shell on the right side."""
+    n = 32
+    x = np.arange(n)
+    u = np.zeros((2, n, n)); b = np.zeros((2, n, n))
+    u[0] = 0.1 * np.cos(2 * np.pi * 3 * x / n)[None, :]
+    b[1] = 0.2 * np.sin(2 * np.pi * (4 * x[:, None] + 3 * x[None, :]) / n)
+    eu, eb = spectral.kinetic_magnetic_spectra(u, b)
+    assert np.allclose(eu + eb, spectral.shell_spectrum(u, b), rtol=0, atol=1e-16)
+    assert abs(eu[3] - 0.5 * 0.1 ** 2 / 2) < 1e-15 and eu[5] < 1e-30
+    assert abs(eb[5] - 0.5 * 0.2 ** 2 / 2) < 1e-15 and eb[3] < 1e-30
