@@ -112,23 +112,30 @@ def launch_sweep(torch, rrmhd, inputs, args):
     del u, b
     st = torch.cuda.current_stream()
     shapes = [(256, 1), (128, 2), (64, 4), (128, 1), (64, 1)]
+    if args.inplace:
+        shapes += [(32, 8), (256, 1), (32, 4), (16, 16)]
+        shapes = list(dict.fromkeys(shapes))
+    # single-buffer steps alternate two kernels: time an even number
+    steps = args.steps + (args.steps % 2 if args.inplace else 0)
     for storage in ("f32", "f16"):
-        for gap in (0, 256, 4352, 65792):
+        for gap in ((256,) if args.inplace else (0, 256, 4352, 65792)):
             os.environ["RRMHD_PLANE_PAD_BYTES"] = str(gap)
-            s = rrmhd.Solver(n, n, args.tau, args.tau, storage=storage)
+            s = rrmhd.Solver(n, n, args.tau, args.tau, storage=storage, inplace=args.inplace)
             s.init(ud, bd)
             s.step(4)
-            for (bx, by), xcd, nt in itertools.product(shapes, (0, 1, 2), (0, 1)):
+            for (bx, by), xcd, nt in itertools.product(shapes, (0, 1, 2),
+                                                       (0, 1)):
                 s.set_launch(bx, by, 1, xcd, nt)
                 s.step(2)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(st)
-                s.step(args.steps)
+                s.step(steps)
                 e1.record(st)
                 torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / args.steps
-                print(json.dumps({"storage": storage, "plane_gap_bytes": gap,
+                ms = e0.elapsed_time(e1) / steps
+                print(json.dumps({"storage": storage, "inplace": args.inplace,
+                                  "plane_gap_bytes": gap,
                                   "bx": bx, "by": by, "xcd": xcd, "nt": nt,
                                   "ms": round(ms, 4),
                                   "GBs": round(BYTES_PER_NODE[storage] * n * n
@@ -393,6 +400,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tau", type=float, default=0.52)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--inplace", action="store_true",
+                    help="single-buffer streaming (one population buffer)")
     ap.add_argument("--equilibrium", choices=["algorithm", "full_maxwell"],
                     default="algorithm",
                     help="fluid equilibrium of the turbulence step: the method's "
@@ -458,11 +467,14 @@ def main():
     bd = torch.from_numpy(b).cuda()
     del u, b
     s = rrmhd.Solver(n, n, args.tau, args.tau, storage=args.storage,
-                     equilibrium=args.equilibrium)
+                     equilibrium=args.equilibrium, inplace=args.inplace)
     launch = ("library default (f32: 128x2 threads; f16: 128x1 threads, two nodes "
               "per thread; NT stores)")
     if args.equilibrium != "algorithm":
         launch = "library default block shape, one node per thread, NT stores"
+    if args.inplace:
+        launch = ("library default for one buffer (f32: 64x1, f16: 128x1 threads, XCD-local "
+                  "order, NT stores); steps alternate pull+push and own-slot forms")
     s.init(ud, bd)
     del ud, bd
     s.step(args.warmup)
@@ -496,7 +508,8 @@ def main():
     bpn = BYTES_PER_NODE[args.storage]
     achieved = bpn * nodes / per_launch / 1e9
     # the stored counter readings belong to the method's own step kernel
-    traffic = measured_traffic(args.storage, n) if args.equilibrium == "algorithm" else None
+    traffic = (measured_traffic(args.storage, n)
+               if args.equilibrium == "algorithm" and not args.inplace else None)
     out = {
         "metric": "MLUPS & % HBM roofline (fused RR-MHD step)",
         "value": round(mlups, 1),
@@ -515,6 +528,7 @@ def main():
                    "nodes": nodes, "tau_f": args.tau, "tau_m": args.tau,
                    "storage": f"{args.storage}-shifted (f - w)",
                    "equilibrium": args.equilibrium,
+                   "population_buffers": 1 if args.inplace else 2,
                    "launch": launch,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),

@@ -42,8 +42,19 @@ enum {
 };
 
 /* Population storage.  Both store f_i - w_i for the fluid populations and
- * g_j for the magnetic ones, times the codec scale; arithmetic is FP32. */
-enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1 };
+ * g_j for the magnetic ones, times the codec scale; arithmetic is FP32.
+ * RRMHD_STORE_INPLACE may be OR-ed into rrmhd_grid.storage: the handle then
+ * holds one population buffer instead of two (half the device memory).  Its
+ * steps alternate between two forms that each write only the locations they
+ * have just read: a pull of the upstream populations whose results go into
+ * the slots just read for the opposite directions, then a read of the node's
+ * own (swapped) slots with a local store, which restores the usual layout.
+ * The per-node arithmetic is unchanged, so a single-buffer handle evolves
+ * bit for bit as a two-buffer one; moments, diagnostics, fields and
+ * rrmhd_save_state read either layout (save returns the usual one).  Not
+ * with the learned closure or the equilibrium ablation (EINVAL); of the
+ * launch shape's nt bits only bit 0 (non-temporal stores) applies. */
+enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
 
 /* Boundary kinds.  PERIODIC: doubly periodic.  WALLS_Y: periodic in x,
  * walls half-way at y = -1/2 and y = ny - 1/2 (half-way bounce-back for f,
@@ -52,7 +63,7 @@ enum { RRMHD_BC_PERIODIC = 0, RRMHD_BC_WALLS_Y = 1 };
 
 typedef struct {
   int32_t nx, ny;    /* nodes in x and y, >= 1 (ny >= 2 with walls) */
-  int32_t storage;   /* RRMHD_STORE_* */
+  int32_t storage;   /* RRMHD_STORE_F32 or _F16, optionally | _INPLACE */
   float codec_scale; /* power-of-two storage scale S; 0 selects 1 */
 } rrmhd_grid;
 

@@ -42,6 +42,8 @@ struct rrmhd {
   void *buf[2] = {nullptr, nullptr};
   int cur = 0;
   int64_t steps = 0;
+  bool inplace = false;  // one population buffer (alternating step phases)
+  int phase = 0;         // in-place: 0 pull layout, 1 swapped layout
   bool ready = false;
   rr::LaunchShape shape{};
   void *diag_work = nullptr;
@@ -91,8 +93,9 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   *out = nullptr;
   if (!grid) return RRMHD_EINVAL;
   if (grid->nx < 1 || grid->ny < 1) return RRMHD_EINVAL;
-  if (grid->storage != RRMHD_STORE_F32 && grid->storage != RRMHD_STORE_F16)
-    return RRMHD_EINVAL;
+  const int kind = grid->storage & 0xff, flags = grid->storage & ~0xff;
+  if (kind != RRMHD_STORE_F32 && kind != RRMHD_STORE_F16) return RRMHD_EINVAL;
+  if (flags != 0 && flags != RRMHD_STORE_INPLACE) return RRMHD_EINVAL;
   if (!(std::isfinite(tau_f) && std::isfinite(tau_m)) || tau_f <= 0.5 || tau_m <= 0.5)
     return RRMHD_EINVAL;
   rrmhd_bc b{};
@@ -111,8 +114,9 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
 
   rrmhd *h = new (std::nothrow) rrmhd();
   if (!h) return RRMHD_ENOMEM;
-  h->storage = grid->storage;
-  h->elem = grid->storage == RRMHD_STORE_F16 ? 2 : 4;
+  h->storage = kind;
+  h->inplace = flags == RRMHD_STORE_INPLACE;
+  h->elem = kind == RRMHD_STORE_F16 ? 2 : 4;
   h->tau_f = tau_f;
   h->tau_m = tau_m;
   h->bc = b;
@@ -139,14 +143,23 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   D.Gy = (float)b.force[1];
   D.bw2x = (float)(b.b_wall[0] / 3.0);
   D.bw2y = (float)(b.b_wall[1] / 3.0);
-  D.s = grid->storage == RRMHD_STORE_F16 ? S : 1.0f;
+  D.s = kind == RRMHD_STORE_F16 ? S : 1.0f;
   D.inv_s = 1.0f / D.s;
   D.elem = (int)h->elem;
   h->shape = rr::default_shape(D);
+  if (h->inplace) {
+    // measured best for the alternating single-buffer steps at 8192^2: one
+    // row per workgroup, eight neighbouring tiles per XCD
+    h->shape.bx = h->elem == 2 ? 128 : 64;
+    h->shape.by = 1;
+    h->shape.ry = 1;
+    h->shape.xcd = 2;
+    h->shape.nt = 1;
+  }
 
   const size_t bytes = (size_t)D.plane * rr::kStatePlanes * h->elem;
   int rc = RRMHD_OK;
-  for (int k = 0; k < 2 && rc == RRMHD_OK; ++k) {
+  for (int k = 0; k < (h->inplace ? 1 : 2) && rc == RRMHD_OK; ++k) {
     hipError_t e = hipMalloc(&h->buf[k], bytes);
     if (e != hipSuccess) rc = dev_err(e, "hipMalloc(populations)");
   }
@@ -184,7 +197,7 @@ int rrmhd_set_stream(rrmhd *h, void *hip_stream) {
 
 int rrmhd_set_equilibrium(rrmhd *h, int kind) {
   if (!h || (kind != RRMHD_FEQ_ALGORITHM && kind != RRMHD_FEQ_FULL_MAXWELL)) return RRMHD_EINVAL;
-  if (kind == RRMHD_FEQ_FULL_MAXWELL && h->closure_on) return RRMHD_EINVAL;
+  if (kind == RRMHD_FEQ_FULL_MAXWELL && (h->closure_on || h->inplace)) return RRMHD_EINVAL;
   h->D.feq = kind;
   return RRMHD_OK;
 }
@@ -194,6 +207,7 @@ int rrmhd_init(rrmhd *h, const double *u, const double *b) {
   HIP_OR_RETURN(rr::launch_init(h->storage, h->D, u, b, h->bc.b_wall[0],
                                 h->bc.b_wall[1], h->buf[0], h->stream));
   h->cur = 0;
+  h->phase = 0;
   h->steps = 0;
   h->ready = true;
   return RRMHD_OK;
@@ -203,6 +217,13 @@ int rrmhd_step(rrmhd *h, int64_t n) {
   if (!h || n < 0) return RRMHD_EINVAL;
   if (!h->ready) return RRMHD_ESTATE;
   for (int64_t k = 0; k < n; ++k) {
+    if (h->inplace) {
+      HIP_OR_RETURN(rr::launch_step_inplace(h->storage, h->D, h->buf[0], h->phase, h->shape,
+                                            h->stream));
+      h->phase ^= 1;
+      h->steps++;
+      continue;
+    }
     if (h->closure_on) {
       HIP_OR_RETURN(rr::launch_step_closure(h->storage, h->D, (const rr::MlpDev *)h->mlp,
                                             h->buf[h->cur], h->buf[h->cur ^ 1],
@@ -222,7 +243,7 @@ int rrmhd_moments(rrmhd *h, double *rho, double *u, double *b) {
   if (!h->ready) return RRMHD_ESTATE;
   if (!rho && !u && !b) return RRMHD_OK;
   HIP_OR_RETURN(rr::launch_moments(h->storage, h->D, h->buf[h->cur], rho, u, b,
-                                   h->stream));
+                                   h->stream, h->inplace ? h->phase : 0));
   return RRMHD_OK;
 }
 
@@ -231,7 +252,8 @@ static int run_diag(rrmhd *h) {
     HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
   }
   HIP_OR_RETURN(rr::launch_diagnostics(h->storage, h->D, h->buf[h->cur],
-                                       h->diag_work, h->diag_out, h->stream));
+                                       h->diag_work, h->diag_out, h->stream,
+                                       h->inplace ? h->phase : 0));
   HIP_OR_RETURN(hipMemcpyAsync(h->diag_host, h->diag_out, 8 * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream));
   HIP_OR_RETURN(hipStreamSynchronize(h->stream));
@@ -275,6 +297,10 @@ int64_t rrmhd_state_bytes(const rrmhd *h) {
 int rrmhd_save_state(rrmhd *h, void *dst, int64_t bytes) {
   if (!h || !dst || bytes < rrmhd_state_bytes(h)) return RRMHD_EINVAL;
   if (!h->ready) return RRMHD_ESTATE;
+  if (h->inplace && h->phase) {
+    HIP_OR_RETURN(rr::launch_swapped_to_pull(h->storage, h->D, h->buf[0], dst, h->stream));
+    return RRMHD_OK;
+  }
   const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
   const size_t pitch = (size_t)h->D.plane * h->elem;
   HIP_OR_RETURN(hipMemcpy2DAsync(dst, row, h->buf[h->cur], pitch, row, rr::kStatePlanes,
@@ -289,6 +315,7 @@ int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes, int64_t step_coun
   HIP_OR_RETURN(hipMemcpy2DAsync(h->buf[0], pitch, src, row, row, rr::kStatePlanes,
                                  hipMemcpyDeviceToDevice, h->stream));
   h->cur = 0;
+  h->phase = 0;
   h->steps = step_count;
   h->ready = true;
   return RRMHD_OK;
@@ -306,6 +333,8 @@ int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage, hipStream_t *
 }
 
 int rr_handle_walls(const rrmhd *h) { return h && h->D.walls ? 1 : 0; }
+
+int rr_handle_inplace(const rrmhd *h) { return h && h->inplace ? 1 : 0; }
 
 void rr_handle_set_ready(rrmhd *h, int ready) {
   if (h) h->ready = ready != 0;
@@ -331,7 +360,8 @@ int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm) {
 
 int rrmhd_closure_enable(rrmhd *h, int on) {
   if (!h) return RRMHD_EINVAL;
-  if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f || h->D.feq))
+  if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f || h->D.feq ||
+             h->inplace))
     return RRMHD_EINVAL;
   h->closure_on = on != 0;
   return RRMHD_OK;
@@ -360,7 +390,8 @@ int rrmhd_current_vorticity(rrmhd *h, double *jz, double *wz) {
   if (!h->diag_work) HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
   // the diagnostics workspace starts with 2 nx ny doubles: the velocity planes
   int rc = rr_launch_current_vorticity(h->storage, &h->D, h->buf[h->cur], 1.0 / h->tau_m, jz, wz,
-                                       (double *)h->diag_work, h->stream);
+                                       (double *)h->diag_work, h->stream,
+                                       h->inplace ? h->phase : 0);
   if (rc != RRMHD_OK) return dev_err(hipGetLastError(), "current/vorticity kernels");
   return RRMHD_OK;
 }

@@ -12,7 +12,9 @@
 
 namespace rr {
 
-template <class C>
+// SWAPPED: the layout a single-buffer handle holds after an odd number of
+// steps, f_i(x) in slot opp(i) of x itself.
+template <class C, bool SWAPPED>
 __global__ void k_current(PlaneGeom G, const typename C::T *__restrict__ src, double omega_m,
                           double Gx, double Gy, double *__restrict__ jz,
                           double *__restrict__ upl) {
@@ -25,25 +27,38 @@ __global__ void k_current(PlaneGeom G, const typename C::T *__restrict__ src, do
   const uint32_t b0 = y * pitch, bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
   const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
   float d[kQ], g[2 * kQm];
-  d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  if constexpr (SWAPPED) {
+    const uint32_t o = b0 + x0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      d[i] = C::dec(ld_at<T, false>(plane_ptr(src, opp_f(i), G.plane), o), G.inv_s);
+#pragma unroll
+    for (int j = 0; j < kQm; ++j)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        g[2 * j + c] =
+            C::dec(ld_at<T, false>(plane_ptr(src, gplane(opp_g(j), c), G.plane), o), G.inv_s);
+  } else {
+    d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
+    d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+    g[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  }
   double dr = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -97,15 +112,23 @@ __global__ void k_vorticity(int nx, int ny, const double *__restrict__ upl,
 // Launcher used by rrmhd_current_vorticity (rr_api.hip).
 extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Domain *D, const void *src,
                                            double omega_m, double *jz, double *wz,
-                                           double *upl, hipStream_t st) {
+                                           double *upl, hipStream_t st, int swapped) {
   const dim3 block(64), grid((D->nx + 63) / 64, D->ny);
   const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s};
-  if (storage == rr::kF16)
-    hipLaunchKernelGGL(rr::k_current<rr::CodecF16>, grid, block, 0, st, G,
-                       (const uint16_t *)src, omega_m, (double)D->Gx, (double)D->Gy, jz, upl);
-  else
-    hipLaunchKernelGGL(rr::k_current<rr::CodecF32>, grid, block, 0, st, G, (const float *)src,
-                       omega_m, (double)D->Gx, (double)D->Gy, jz, upl);
+  const double gx = D->Gx, gy = D->Gy;
+  auto s16 = (const uint16_t *)src;
+  auto s32 = (const float *)src;
+  if (storage == rr::kF16) {
+    if (swapped)
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, true>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
+    else
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, false>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
+  } else {
+    if (swapped)
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, true>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
+    else
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, false>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
+  }
   if (hipGetLastError() != hipSuccess) return RRMHD_EDEVICE;
   if (wz) {
     hipLaunchKernelGGL(rr::k_vorticity, grid, block, 0, st, D->nx, D->ny, upl, wz);

@@ -15,6 +15,8 @@ RR_HIDDEN int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage,
 RR_HIDDEN void rr_handle_set_ready(rrmhd *h, int ready);
 // 1 when the handle has walls (the paired FP16 update is periodic only)
 RR_HIDDEN int rr_handle_walls(const rrmhd *h);
+// 1 when the handle streams in place in one population buffer
+RR_HIDDEN int rr_handle_inplace(const rrmhd *h);
 // batch: domain sizes (arrays may be NULL to query n and storage)
 RR_HIDDEN int rr_batch_domains(const rrmhd_batch *b, int *n, int *storage, int *nx,
                                int *ny);
@@ -30,4 +32,4 @@ struct Domain;
 extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Domain *D,
                                                      const void *src, double omega_m,
                                                      double *jz, double *wz, double *upl,
-                                                     hipStream_t st);
+                                                     hipStream_t st, int swapped);

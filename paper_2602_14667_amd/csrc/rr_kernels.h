@@ -35,13 +35,25 @@ hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
 hipError_t launch_init(int storage, const Domain &D, const double *u,
                        const double *b, double bwx, double bwy, void *dst,
                        hipStream_t st);
+// swapped = 1 reads the layout a single-buffer handle holds after an odd
+// number of its steps (f_i(x) in slot opp(i) of x itself).
 hipError_t launch_moments(int storage, const Domain &D, const void *src,
-                          double *rho, double *u, double *b, hipStream_t st);
+                          double *rho, double *u, double *b, hipStream_t st,
+                          int swapped = 0);
 // Diagnostics: out_dev[8] = {E_kin, E_mag, max|div b|, mass, j_x, j_y, b_x,
 // b_y}.  work must hold diag_work_bytes(D) bytes.
 size_t diag_work_bytes(const Domain &D);
 hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
-                              void *work, double *out_dev, hipStream_t st);
+                              void *work, double *out_dev, hipStream_t st, int swapped = 0);
+
+// Single-buffer streaming: one step of the given phase (0: pull read, push
+// into the opposite slots; 1: read own swapped slots, store locally) on buf.
+hipError_t launch_step_inplace(int storage, const Domain &D, void *buf, int phase,
+                               const LaunchShape &L, hipStream_t st);
+// The swapped layout of buf rewritten in the pull layout into dst (dense
+// planes of nx * ny elements).
+hipError_t launch_swapped_to_pull(int storage, const Domain &D, const void *buf, void *dst,
+                                  hipStream_t st);
 
 LaunchShape default_shape(const Domain &D);
 

@@ -174,6 +174,141 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
 }
 
 // ---------------------------------------------------------------------------
+// Single-buffer (in-place) step: the two phases of the alternating update
+// (see rr_pull.h).  With walls, a population whose push target lies beyond
+// a wall stays in the node's own slot of the same direction (the slot its
+// bounce-back read came from), and the swapped read of phase 1 applies the
+// magnetic anti-bounce-back to the populations that arrive through a wall.
+// ---------------------------------------------------------------------------
+template <class T, bool NT>
+__device__ __forceinline__ void st_el(T *p, T v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <class C, bool FORCED, bool NT>
+__device__ __forceinline__ void update_walled_push(const Domain &D, typename C::T *buf, int x,
+                                                   int y, const CollideParams &P) {
+  float d[kQ], g[2 * kQm];
+  pull_node<C, true>(D, buf, x, y, d, g);
+  collide<FORCED>(d, g, P);
+  const Rows R = rows_of<true>(D, x, y);
+  const int own = R.r0 + x;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const bool out = (cy(i) > 0 && R.hi) || (cy(i) < 0 && R.lo);
+    const int tx = cx(i) == 0 ? x : (cx(i) > 0 ? R.xp : R.xm);
+    const int trow = cy(i) == 0 ? R.r0 : (cy(i) > 0 ? R.rp : R.rm);
+    const int plane = out ? i : opp_f(i);
+    const int off = out ? own : trow + tx;
+    st_el<typename C::T, NT>(&buf[(int64_t)plane * D.plane + off], C::enc(d[i], D.s));
+  }
+#pragma unroll
+  for (int j = 0; j < kQm; ++j) {
+    const bool out = (ey(j) > 0 && R.hi) || (ey(j) < 0 && R.lo);
+    const int tx = ex(j) == 0 ? x : (ex(j) > 0 ? R.xp : R.xm);
+    const int trow = ey(j) == 0 ? R.r0 : (ey(j) > 0 ? R.rp : R.rm);
+    const int jj = out ? j : opp_g(j);
+    const int off = out ? own : trow + tx;
+    st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 0) * D.plane + off], C::enc(g[2 * j], D.s));
+    st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 1) * D.plane + off],
+                             C::enc(g[2 * j + 1], D.s));
+  }
+}
+
+// Pre-collision populations of node (x, y) from the swapped layout of phase
+// 1: f_i(x) = buf[opp(i)][x]; with walls, a magnetic population arriving
+// through a wall is the anti-bounce-back of the value stored there.
+template <class C, bool WALLS>
+__device__ __forceinline__ void own_node(const Domain &D, const typename C::T *buf, int x, int y,
+                                         float (&d)[kQ], float (&g)[2 * kQm]) {
+  const int64_t o = (int64_t)y * D.nx + x;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) d[i] = C::dec(buf[(int64_t)opp_f(i) * D.plane + o], D.inv_s);
+#pragma unroll
+  for (int j = 0; j < kQm; ++j) {
+    float gx = C::dec(buf[(int64_t)gplane(opp_g(j), 0) * D.plane + o], D.inv_s);
+    float gy = C::dec(buf[(int64_t)gplane(opp_g(j), 1) * D.plane + o], D.inv_s);
+    if constexpr (WALLS) {
+      const bool in = (ey(j) > 0 && y == 0) || (ey(j) < 0 && y == D.ny - 1);
+      if (in) {
+        gx = D.bw2x - gx;
+        gy = D.bw2y - gy;
+      }
+    }
+    g[2 * j] = gx;
+    g[2 * j + 1] = gy;
+  }
+}
+
+template <class C, bool WALLS, bool FORCED, int PHASE, bool NT>
+__global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int ry, int xcd,
+                                                      typename C::T *buf) {
+  const int ntiles = gridDim.x;
+  const int L = xcd == 1 ? xcd_remap(blockIdx.x, ntiles)
+                         : (xcd == 2 ? xcd_local(blockIdx.x, ntiles) : (int)blockIdx.x);
+  const int tx = L % tiles_x, ty = L / tiles_x;
+  const int x = tx * blockDim.x + threadIdx.x;
+  const int y0 = (ty * blockDim.y + threadIdx.y) * ry;
+  if (x >= D.nx) return;
+  CollideParams P;
+  P.om_c = D.om_c;
+  P.omm_c = D.omm_c;
+  P.Gx = D.Gx;
+  P.Gy = D.Gy;
+  P.src_c = D.src_c;
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+  for (int r = 0; r < ry; ++r) {
+    const int y = y0 + r;
+    if (y >= D.ny) return;
+    if constexpr (PHASE == 0) {
+      if constexpr (WALLS)
+        update_walled_push<C, FORCED, NT>(D, buf, x, y, P);
+      else
+        update_periodic_push<C, FORCED, NT>(G, buf, x, y, P);
+    } else {
+      if constexpr (WALLS) {
+        float d[kQ], g[2 * kQm];
+        own_node<C, true>(D, buf, x, y, d, g);
+        collide<FORCED>(d, g, P);
+        const int o = y * D.nx + x;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+          st_el<typename C::T, NT>(&buf[(int64_t)i * D.plane + o], C::enc(d[i], D.s));
+#pragma unroll
+        for (int k = 0; k < 2 * kQm; ++k)
+          st_el<typename C::T, NT>(&buf[(int64_t)(kQ + k) * D.plane + o], C::enc(g[k], D.s));
+      } else {
+        update_periodic_own<C, FORCED, NT>(G, buf, x, y, P);
+      }
+    }
+  }
+}
+
+// Swapped layout -> pull layout, into a dense copy (planes of nx * ny):
+// dst[i][x] = f*_i(x), found at buf[opp(i)][x + c_i], or in the node's own
+// slot i when x + c_i lies beyond a wall.
+template <class T>
+__global__ void k_swapped_to_pull(Domain D, const T *__restrict__ buf, T *__restrict__ dst) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= D.nx) return;
+  const int64_t N = (int64_t)D.nx * D.ny, o = (int64_t)y * D.nx + x;
+  auto src_of = [&](int p, int op, int cxv, int cyv) -> T {
+    int tx = x + cxv, ty = y + cyv;
+    tx = tx < 0 ? tx + D.nx : (tx >= D.nx ? tx - D.nx : tx);
+    if (D.walls && (ty < 0 || ty >= D.ny)) return buf[(int64_t)p * D.plane + o];
+    ty = ty < 0 ? ty + D.ny : (ty >= D.ny ? ty - D.ny : ty);
+    return buf[(int64_t)op * D.plane + (int64_t)ty * D.nx + tx];
+  };
+  for (int i = 0; i < kQ; ++i) dst[(int64_t)i * N + o] = src_of(i, opp_f(i), cx(i), cy(i));
+  for (int j = 0; j < kQm; ++j)
+    for (int c = 0; c < 2; ++c)
+      dst[(int64_t)gplane(j, c) * N + o] = src_of(gplane(j, c), gplane(opp_g(j), c), ex(j), ey(j));
+}
+
+// ---------------------------------------------------------------------------
 // Initialisation at equilibrium (rho = 1), written for the pull layout: the
 // value stored in plane p at node n is read by node n + c_p as population p,
 // or, beyond a wall, by n itself as the opposite population.  It is set so
@@ -265,12 +400,15 @@ struct MomD {
   double rho, jx, jy, ux, uy, bx, by;
 };
 
-template <class C, bool WALLS>
+template <class C, bool WALLS, bool SWAPPED = false>
 __device__ __forceinline__ MomD moments_d(const Domain &D,
                                           const typename C::T *__restrict__ s,
                                           int x, int y) {
   float d[kQ], g[2 * kQm];
-  pull_node<C, WALLS>(D, s, x, y, d, g);
+  if constexpr (SWAPPED)
+    own_node<C, WALLS>(D, s, x, y, d, g);
+  else
+    pull_node<C, WALLS>(D, s, x, y, d, g);
   MomD m;
   double dr = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
@@ -295,14 +433,14 @@ __device__ __forceinline__ MomD moments_d(const Domain &D,
   return m;
 }
 
-template <class C, bool WALLS>
+template <class C, bool WALLS, bool SWAPPED>
 __global__ void k_moments(Domain D, const typename C::T *__restrict__ src,
                           double *__restrict__ rho, double *__restrict__ u,
                           double *__restrict__ b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= D.nx) return;
-  const MomD m = moments_d<C, WALLS>(D, src, x, y);
+  const MomD m = moments_d<C, WALLS, SWAPPED>(D, src, x, y);
   const int64_t N = (int64_t)D.nx * D.ny, o = (int64_t)y * D.nx + x;
   if (rho) rho[o] = m.rho;
   if (u) {
@@ -350,7 +488,7 @@ __device__ double block_reduce(double v, double *lds) {
   return r;
 }
 
-template <class C, bool WALLS>
+template <class C, bool WALLS, bool SWAPPED>
 __global__ __launch_bounds__(kDiagBlock) void k_diag_sums(
     Domain D, const typename C::T *__restrict__ src, double *__restrict__ bpl,
     double *__restrict__ part) {
@@ -360,7 +498,7 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_sums(
   for (int64_t n = (int64_t)blockIdx.x * kDiagBlock + threadIdx.x; n < N;
        n += (int64_t)gridDim.x * kDiagBlock) {
     const int y = (int)(n / D.nx), x = (int)(n - (int64_t)y * D.nx);
-    const MomD m = moments_d<C, WALLS>(D, src, x, y);
+    const MomD m = moments_d<C, WALLS, SWAPPED>(D, src, x, y);
     acc[0] += m.ux * m.ux + m.uy * m.uy;
     acc[1] += m.bx * m.bx + m.by * m.by;
     acc[2] += m.rho;
@@ -603,23 +741,81 @@ hipError_t launch_init(int storage, const Domain &D, const double *u,
   return hipGetLastError();
 }
 
-template <class C>
+template <class C, bool SW>
 static void moments_t(const Domain &D, const void *src, double *rho, double *u,
                       double *b, hipStream_t st) {
   const dim3 block(64), grid((D.nx + 63) / 64, D.ny);
   auto s = (const typename C::T *)src;
   if (D.walls)
-    hipLaunchKernelGGL((k_moments<C, true>), grid, block, 0, st, D, s, rho, u, b);
+    hipLaunchKernelGGL((k_moments<C, true, SW>), grid, block, 0, st, D, s, rho, u, b);
   else
-    hipLaunchKernelGGL((k_moments<C, false>), grid, block, 0, st, D, s, rho, u, b);
+    hipLaunchKernelGGL((k_moments<C, false, SW>), grid, block, 0, st, D, s, rho, u, b);
 }
 
 hipError_t launch_moments(int storage, const Domain &D, const void *src,
-                          double *rho, double *u, double *b, hipStream_t st) {
+                          double *rho, double *u, double *b, hipStream_t st, int swapped) {
   if (storage == kF16)
-    moments_t<CodecF16>(D, src, rho, u, b, st);
+    swapped ? moments_t<CodecF16, true>(D, src, rho, u, b, st)
+            : moments_t<CodecF16, false>(D, src, rho, u, b, st);
   else
-    moments_t<CodecF32>(D, src, rho, u, b, st);
+    swapped ? moments_t<CodecF32, true>(D, src, rho, u, b, st)
+            : moments_t<CodecF32, false>(D, src, rho, u, b, st);
+  return hipGetLastError();
+}
+
+template <class C, int PHASE, bool NT>
+static void inplace_t(const Domain &D, void *buf, const LaunchShape &L, hipStream_t st) {
+  const int tiles_x = (D.nx + L.bx - 1) / L.bx;
+  const int rows_per_tile = L.by * L.ry;
+  const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
+  const dim3 grid(tiles_x * tiles_y), block(L.bx, L.by);
+  const bool forced = D.Gx != 0.0f || D.Gy != 0.0f;
+  auto b = (typename C::T *)buf;
+  if (D.walls) {
+    if (forced)
+      hipLaunchKernelGGL((k_step_inplace<C, true, true, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+    else
+      hipLaunchKernelGGL((k_step_inplace<C, true, false, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+  } else {
+    if (forced)
+      hipLaunchKernelGGL((k_step_inplace<C, false, true, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+    else
+      hipLaunchKernelGGL((k_step_inplace<C, false, false, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+  }
+}
+
+template <class C>
+static void inplace_phase(const Domain &D, void *buf, int phase, const LaunchShape &L,
+                          hipStream_t st) {
+  const bool nt = L.nt & 1;
+  if (phase)
+    nt ? inplace_t<C, 1, true>(D, buf, L, st) : inplace_t<C, 1, false>(D, buf, L, st);
+  else
+    nt ? inplace_t<C, 0, true>(D, buf, L, st) : inplace_t<C, 0, false>(D, buf, L, st);
+}
+
+hipError_t launch_step_inplace(int storage, const Domain &D, void *buf, int phase,
+                               const LaunchShape &L, hipStream_t st) {
+  if (L.bx <= 0 || L.by <= 0 || L.bx * L.by > 256 || L.ry <= 0) return hipErrorInvalidValue;
+  if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
+    return hipErrorInvalidValue;
+  if (storage == kF16)
+    D.s == 1.0f ? inplace_phase<CodecF16U>(D, buf, phase, L, st)
+                : inplace_phase<CodecF16>(D, buf, phase, L, st);
+  else
+    inplace_phase<CodecF32>(D, buf, phase, L, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_swapped_to_pull(int storage, const Domain &D, const void *buf, void *dst,
+                                  hipStream_t st) {
+  const dim3 block(64), grid((D.nx + 63) / 64, D.ny);
+  if (storage == kF16)
+    hipLaunchKernelGGL(k_swapped_to_pull<uint16_t>, grid, block, 0, st, D,
+                       (const uint16_t *)buf, (uint16_t *)dst);
+  else
+    hipLaunchKernelGGL(k_swapped_to_pull<float>, grid, block, 0, st, D, (const float *)buf,
+                       (float *)dst);
   return hipGetLastError();
 }
 
@@ -634,27 +830,29 @@ size_t diag_work_bytes(const Domain &D) {
   return sizeof(double) * (size_t)(2 * N + kDiagGrid * kSums + kDiagGrid);
 }
 
-template <class C>
+template <class C, bool SW>
 static void diag_t(const Domain &D, const void *src, double *bpl, double *ps,
                    double *pm, int nb, hipStream_t st) {
   auto s = (const typename C::T *)src;
   if (D.walls)
-    hipLaunchKernelGGL((k_diag_sums<C, true>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
+    hipLaunchKernelGGL((k_diag_sums<C, true, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
   else
-    hipLaunchKernelGGL((k_diag_sums<C, false>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
+    hipLaunchKernelGGL((k_diag_sums<C, false, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
 }
 
 hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
-                              void *work, double *out_dev, hipStream_t st) {
+                              void *work, double *out_dev, hipStream_t st, int swapped) {
   const int64_t N = (int64_t)D.nx * D.ny;
   double *bpl = (double *)work;
   double *ps = bpl + 2 * N;
   double *pm = ps + kDiagGrid * kSums;
   const int nb = diag_grid(D);
   if (storage == kF16)
-    diag_t<CodecF16>(D, src, bpl, ps, pm, nb, st);
+    swapped ? diag_t<CodecF16, true>(D, src, bpl, ps, pm, nb, st)
+            : diag_t<CodecF16, false>(D, src, bpl, ps, pm, nb, st);
   else
-    diag_t<CodecF32>(D, src, bpl, ps, pm, nb, st);
+    swapped ? diag_t<CodecF32, true>(D, src, bpl, ps, pm, nb, st)
+            : diag_t<CodecF32, false>(D, src, bpl, ps, pm, nb, st);
   hipLaunchKernelGGL(k_diag_divb, dim3(nb), dim3(kDiagBlock), 0, st, D, bpl, pm);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, st, ps, nb, pm, nb,
                      1.0 / (2.0 * (double)N), out_dev);

@@ -127,6 +127,120 @@ __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
   store_planes<C, NT>(G, dst, b0 + x0, d, g);
 }
 
+// ---- single-buffer (in-place) streaming --------------------------------------
+// One buffer instead of two.  Steps alternate between two forms, each of
+// which writes only the locations its own thread has just read, so one
+// buffer suffices without races:
+//  * phase 0 (buffer in the pull layout, stored value of plane i at node y is
+//    f*_i(y)): pull f_i(x) = buf[i][x - c_i] as the two-buffer step does,
+//    collide, and write f*_i(x) into the slot just read for the opposite
+//    direction, buf[opp(i)][x + c_i];
+//  * phase 1 (swapped layout, buf[opp(i)][x] = f_i(x), the pre-collision
+//    population of x itself): read the node's own slots, collide, and store
+//    f*_i(x) at buf[i][x], which restores the pull layout.
+// The arithmetic per node is the two-buffer step's, so both give the same
+// bits.  buf points at plane 0 and is read and written through one pointer.
+template <class C, int P, bool NT>
+__device__ __forceinline__ void store_plane_at(const PlaneGeom &G, typename C::T *buf,
+                                               uint32_t o, float v) {
+  st_at<typename C::T, NT>(buf + (int64_t)P * G.plane, o, C::enc(v, G.s));
+}
+
+template <class C, bool FORCED, bool NT>
+__device__ __forceinline__ void update_periodic_push(const PlaneGeom &G, typename C::T *buf,
+                                                     int x, int y, const CollideParams &P) {
+  using T = typename C::T;
+  constexpr uint32_t E = sizeof(T);
+  const uint32_t pitch = G.nx * E;
+  const uint32_t x0 = x * E;
+  const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
+  const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
+  const uint32_t b0 = y * pitch;
+  const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
+  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
+  const T *src = buf;
+  float d[kQ], g[2 * kQm];
+  d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
+  d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
+  g[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  collide<FORCED>(d, g, P);
+  // f*_i(x) -> buf[opp(i)][x + c_i]: the slot read for direction opp(i)
+  auto at = [&](int cxv, int cyv) {
+    return (cyv == 0 ? b0 : (cyv > 0 ? bp : bm)) + (cxv == 0 ? x0 : (cxv > 0 ? xp : xm));
+  };
+  store_plane_at<C, opp_f(0), NT>(G, buf, at(cx(0), cy(0)), d[0]);
+  store_plane_at<C, opp_f(1), NT>(G, buf, at(cx(1), cy(1)), d[1]);
+  store_plane_at<C, opp_f(2), NT>(G, buf, at(cx(2), cy(2)), d[2]);
+  store_plane_at<C, opp_f(3), NT>(G, buf, at(cx(3), cy(3)), d[3]);
+  store_plane_at<C, opp_f(4), NT>(G, buf, at(cx(4), cy(4)), d[4]);
+  store_plane_at<C, opp_f(5), NT>(G, buf, at(cx(5), cy(5)), d[5]);
+  store_plane_at<C, opp_f(6), NT>(G, buf, at(cx(6), cy(6)), d[6]);
+  store_plane_at<C, opp_f(7), NT>(G, buf, at(cx(7), cy(7)), d[7]);
+  store_plane_at<C, opp_f(8), NT>(G, buf, at(cx(8), cy(8)), d[8]);
+  store_plane_at<C, gplane(opp_g(0), 0), NT>(G, buf, at(ex(0), ey(0)), g[0]);
+  store_plane_at<C, gplane(opp_g(0), 1), NT>(G, buf, at(ex(0), ey(0)), g[1]);
+  store_plane_at<C, gplane(opp_g(1), 0), NT>(G, buf, at(ex(1), ey(1)), g[2]);
+  store_plane_at<C, gplane(opp_g(1), 1), NT>(G, buf, at(ex(1), ey(1)), g[3]);
+  store_plane_at<C, gplane(opp_g(2), 0), NT>(G, buf, at(ex(2), ey(2)), g[4]);
+  store_plane_at<C, gplane(opp_g(2), 1), NT>(G, buf, at(ex(2), ey(2)), g[5]);
+  store_plane_at<C, gplane(opp_g(3), 0), NT>(G, buf, at(ex(3), ey(3)), g[6]);
+  store_plane_at<C, gplane(opp_g(3), 1), NT>(G, buf, at(ex(3), ey(3)), g[7]);
+  store_plane_at<C, gplane(opp_g(4), 0), NT>(G, buf, at(ex(4), ey(4)), g[8]);
+  store_plane_at<C, gplane(opp_g(4), 1), NT>(G, buf, at(ex(4), ey(4)), g[9]);
+}
+
+template <class C, int P>
+__device__ __forceinline__ float ld_own(const PlaneGeom &G, const typename C::T *buf,
+                                        uint32_t o) {
+  return C::dec(ld_at<typename C::T, false>(plane_ptr(buf, P, G.plane), o), G.inv_s);
+}
+
+template <class C, bool FORCED, bool NT>
+__device__ __forceinline__ void update_periodic_own(const PlaneGeom &G, typename C::T *buf,
+                                                    int x, int y, const CollideParams &P) {
+  constexpr uint32_t E = sizeof(typename C::T);
+  const uint32_t o = y * (G.nx * E) + x * E;
+  const typename C::T *src = buf;
+  float d[kQ], g[2 * kQm];
+  d[0] = ld_own<C, opp_f(0)>(G, src, o);
+  d[1] = ld_own<C, opp_f(1)>(G, src, o);
+  d[2] = ld_own<C, opp_f(2)>(G, src, o);
+  d[3] = ld_own<C, opp_f(3)>(G, src, o);
+  d[4] = ld_own<C, opp_f(4)>(G, src, o);
+  d[5] = ld_own<C, opp_f(5)>(G, src, o);
+  d[6] = ld_own<C, opp_f(6)>(G, src, o);
+  d[7] = ld_own<C, opp_f(7)>(G, src, o);
+  d[8] = ld_own<C, opp_f(8)>(G, src, o);
+  g[0] = ld_own<C, gplane(opp_g(0), 0)>(G, src, o);
+  g[1] = ld_own<C, gplane(opp_g(0), 1)>(G, src, o);
+  g[2] = ld_own<C, gplane(opp_g(1), 0)>(G, src, o);
+  g[3] = ld_own<C, gplane(opp_g(1), 1)>(G, src, o);
+  g[4] = ld_own<C, gplane(opp_g(2), 0)>(G, src, o);
+  g[5] = ld_own<C, gplane(opp_g(2), 1)>(G, src, o);
+  g[6] = ld_own<C, gplane(opp_g(3), 0)>(G, src, o);
+  g[7] = ld_own<C, gplane(opp_g(3), 1)>(G, src, o);
+  g[8] = ld_own<C, gplane(opp_g(4), 0)>(G, src, o);
+  g[9] = ld_own<C, gplane(opp_g(4), 1)>(G, src, o);
+  collide<FORCED>(d, g, P);
+  store_planes<C, NT>(G, buf, o, d, g);
+}
+
 // ---- 16-bit storage, two neighbouring nodes per thread -----------------------
 // Nodes (x, x + 1), x even, nx even: every plane moves as one 32-bit word per
 // thread (low half node x, high half node x + 1), which halves the memory

@@ -154,7 +154,8 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
   int rc = rr_handle_info(h, &nx, &ny, &storage, &st, &ready);
   if (rc != RRMHD_OK) return rc;
   auto cache = read_cache(cache_path);
-  const std::string key = key_of("step", nx, ny, storage);
+  const bool inplace = rr_handle_inplace(h) != 0;
+  const std::string key = key_of(inplace ? "step_inplace" : "step", nx, ny, storage);
   Entry best;
   auto it = cache.find(key);
   if (it != cache.end()) {
@@ -181,7 +182,8 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
                            {64, 1, 0, 1},  {32, 8, 0, 1},  {256, 1, 2, 1}, {128, 2, 2, 1},
                            {64, 4, 2, 1},  {128, 1, 0, 5}, {128, 2, 0, 5}, {64, 4, 0, 5},
                            {256, 1, 0, 5}, {64, 2, 0, 5}};
-    const bool pair_ok = storage == RRMHD_STORE_F16 && nx % 2 == 0 && !rr_handle_walls(h);
+    const bool pair_ok =
+        storage == RRMHD_STORE_F16 && nx % 2 == 0 && !rr_handle_walls(h) && !inplace;
     best.ms = 1e30;
     for (const Shape &c : cands) {
       if (rc != RRMHD_OK) break;

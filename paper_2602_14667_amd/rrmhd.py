@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librrmhd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
-STORE_F32, STORE_F16 = 0, 1
+STORE_F32, STORE_F16, STORE_INPLACE = 0, 1, 0x100
 BC_PERIODIC, BC_WALLS_Y = 0, 1
 FEQ_ALGORITHM, FEQ_FULL_MAXWELL = 0, 1
 
@@ -198,16 +198,18 @@ class Solver:
     per unit mass; b_wall: field imposed by the magnetic walls.
     equilibrium: "algorithm" (the method's) or "full_maxwell" (ablation with
     the u.M cross terms of the third and fourth orders).
+    inplace: one population buffer instead of two (single-buffer streaming).
     """
 
     def __init__(self, nx, ny, tau_f, tau_m, storage="f32", walls=False,
                  force=(0.0, 0.0), b_wall=(0.0, 0.0), codec_scale=0.0,
-                 stream=None, equilibrium="algorithm"):
+                 stream=None, equilibrium="algorithm", inplace=False):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.storage = storage
         self._stream = stream
-        g = Grid(self.nx, self.ny, STORE_F16 if storage == "f16" else STORE_F32,
+        kind = STORE_F16 if storage == "f16" else STORE_F32
+        g = Grid(self.nx, self.ny, kind | (STORE_INPLACE if inplace else 0),
                  float(codec_scale))
         bc = BC(BC_WALLS_Y if walls else BC_PERIODIC,
                 (ctypes.c_double * 2)(*force), (ctypes.c_double * 2)(*b_wall))

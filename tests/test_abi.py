@@ -91,3 +91,13 @@ def test_null_handle_calls_are_rejected():
                                  None) == rrmhd.EINVAL
     assert L.rrmhd_closure_enable(None, 1) == rrmhd.EINVAL
     assert L.rrmhd_autotune(None, None, 3, None, None, None, None) == rrmhd.EINVAL
+
+
+def test_create_rejects_unknown_storage_flags():
+    L = rrmhd.lib()
+    for storage in (0x200, 0x101 | 0x400, 2, 0x102):
+        g = rrmhd.Grid(4, 4, storage, 0.0)
+        h = ctypes.c_void_p()
+        assert L.rrmhd_create(ctypes.byref(g), 0.6, 0.6, None, None,
+                              ctypes.byref(h)) == rrmhd.EINVAL
+        assert not h.value
