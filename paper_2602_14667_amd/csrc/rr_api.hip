@@ -47,6 +47,7 @@ struct rrmhd {
   bool ready = false;
   rr::LaunchShape shape{};
   void *diag_work = nullptr;
+  void *fields_work = nullptr;  // 2 nx ny doubles for the j_z / w_z fields
   double *diag_out = nullptr;   // device, 8 doubles
   double *diag_host = nullptr;  // pinned, 8 doubles
   void *mlp = nullptr;          // prepared closure parameters (device)
@@ -80,6 +81,7 @@ int rrmhd_destroy(rrmhd *h) {
   for (void *&p : h->buf)
     if (p) (void)hipFree(p), p = nullptr;
   if (h->diag_work) (void)hipFree(h->diag_work);
+  if (h->fields_work) (void)hipFree(h->fields_work);
   if (h->diag_out) (void)hipFree(h->diag_out);
   if (h->diag_host) (void)hipHostFree(h->diag_host);
   if (h->mlp) (void)hipFree(h->mlp);
@@ -387,10 +389,11 @@ int rrmhd_current_vorticity(rrmhd *h, double *jz, double *wz) {
   if (!h->ready) return RRMHD_ESTATE;
   if (h->D.walls) return RRMHD_EINVAL;
   if (!jz && !wz) return RRMHD_OK;
-  if (!h->diag_work) HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
-  // the diagnostics workspace starts with 2 nx ny doubles: the velocity planes
+  if (!h->fields_work)
+    HIP_OR_RETURN(hipMalloc(&h->fields_work, sizeof(double) * 2 * (size_t)h->D.nx * h->D.ny));
+  // velocity planes for the vorticity's gradient
   int rc = rr_launch_current_vorticity(h->storage, &h->D, h->buf[h->cur], 1.0 / h->tau_m, jz, wz,
-                                       (double *)h->diag_work, h->stream,
+                                       (double *)h->fields_work, h->stream,
                                        h->inplace ? h->phase : 0);
   if (rc != RRMHD_OK) return dev_err(hipGetLastError(), "current/vorticity kernels");
   return RRMHD_OK;

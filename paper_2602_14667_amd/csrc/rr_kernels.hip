@@ -459,7 +459,7 @@ __global__ void k_moments(Domain D, const typename C::T *__restrict__ src,
 // d_a phi = 3 sum_i w_i phi(x + c_i) c_ia.
 // ---------------------------------------------------------------------------
 constexpr int kDiagBlock = 256;
-constexpr int kDiagGrid = 1024;
+constexpr int kDiagGrid = 1024;  // persistent workgroups of the diagnostics (2048-8192 equal)
 constexpr int kSums = 7;  // |u|^2, |b|^2, rho, j_x, j_y, b_x, b_y
 
 __device__ __forceinline__ double nanmax(double a, double b) {
@@ -488,59 +488,116 @@ __device__ double block_reduce(double v, double *lds) {
   return r;
 }
 
+// b = sum_j g_j of node (x, y) in FP64, summed as moments_d sums it.
 template <class C, bool WALLS, bool SWAPPED>
-__global__ __launch_bounds__(kDiagBlock) void k_diag_sums(
-    Domain D, const typename C::T *__restrict__ src, double *__restrict__ bpl,
-    double *__restrict__ part) {
-  __shared__ double lds[kDiagBlock / 64];
-  const int64_t N = (int64_t)D.nx * D.ny;
-  double acc[kSums] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t n = (int64_t)blockIdx.x * kDiagBlock + threadIdx.x; n < N;
-       n += (int64_t)gridDim.x * kDiagBlock) {
-    const int y = (int)(n / D.nx), x = (int)(n - (int64_t)y * D.nx);
-    const MomD m = moments_d<C, WALLS, SWAPPED>(D, src, x, y);
-    acc[0] += m.ux * m.ux + m.uy * m.uy;
-    acc[1] += m.bx * m.bx + m.by * m.by;
-    acc[2] += m.rho;
-    acc[3] += m.jx;
-    acc[4] += m.jy;
-    acc[5] += m.bx;
-    acc[6] += m.by;
-    bpl[n] = m.bx;
-    bpl[N + n] = m.by;
+__device__ __forceinline__ void b_at(const Domain &D, const typename C::T *__restrict__ s,
+                                     int x, int y, double &bx, double &by) {
+  float g[2 * kQm];
+  if constexpr (SWAPPED) {
+    float d[kQ];
+    own_node<C, WALLS>(D, s, x, y, d, g);  // the fluid loads are dead code
+  } else {
+    const Rows R = rows_of<WALLS>(D, x, y);
+    pull_g<C, WALLS, 0>(D, s, R, x, g[0], g[1]);
+    pull_g<C, WALLS, 1>(D, s, R, x, g[2], g[3]);
+    pull_g<C, WALLS, 2>(D, s, R, x, g[4], g[5]);
+    pull_g<C, WALLS, 3>(D, s, R, x, g[6], g[7]);
+    pull_g<C, WALLS, 4>(D, s, R, x, g[8], g[9]);
   }
-  for (int k = 0; k < kSums; ++k) {
-    const double r = block_reduce<false>(acc[k], lds);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kSums + k] = r;
+  bx = 0.0;
+  by = 0.0;
+#pragma unroll
+  for (int j = 0; j < kQm; ++j) {
+    bx += (double)g[2 * j];
+    by += (double)g[2 * j + 1];
   }
 }
 
-__global__ __launch_bounds__(kDiagBlock) void k_diag_divb(Domain D,
-                                                          const double *__restrict__ bpl,
-                                                          double *__restrict__ part) {
+// One pass over the state: per-node moments and their FP64 sums, and
+// max |div b| from b staged in LDS.  Persistent workgroups of 4 waves take
+// tiles of kDTX x kDTY nodes; each tile's b, plus a one-node ring around it
+// (periodic wrap; zero beyond a wall, where div b is not evaluated), goes
+// to LDS, so every node's populations are read once for its moments and
+// only the ring's magnetic planes are read again.  Tile cells that lie past
+// a ragged edge hold the b of the node they wrap to.
+constexpr int kDTX = 64, kDTY = 16;
+template <class C, bool WALLS, bool SWAPPED>
+__global__ __launch_bounds__(kDiagBlock) void k_diag_tile(Domain D,
+                                                          const typename C::T *__restrict__ src,
+                                                          double *__restrict__ part_s,
+                                                          double *__restrict__ part_m) {
+  __shared__ double2 bt[kDTY + 2][kDTX + 2];
   __shared__ double lds[kDiagBlock / 64];
-  const int64_t N = (int64_t)D.nx * D.ny;
-  const int ylo = D.walls ? 1 : 0, yhi = D.walls ? D.ny - 1 : D.ny;
+  const int tiles_x = (D.nx + kDTX - 1) / kDTX, tiles_y = (D.ny + kDTY - 1) / kDTY;
+  const int ntiles = tiles_x * tiles_y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kRing = 2 * (kDTX + 2) + 2 * kDTY;
+  auto wrap = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+  double acc[kSums] = {0, 0, 0, 0, 0, 0, 0};
   double mx = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * kDiagBlock + threadIdx.x; n < N;
-       n += (int64_t)gridDim.x * kDiagBlock) {
-    const int y = (int)(n / D.nx), x = (int)(n - (int64_t)y * D.nx);
-    if (y < ylo || y >= yhi) continue;
-    double s = 0.0;
-#pragma unroll
-    for (int i = 1; i < kQ; ++i) {
-      int xx = x + cx(i), yy = y + cy(i);
-      xx = xx < 0 ? xx + D.nx : (xx >= D.nx ? xx - D.nx : xx);
-      yy = yy < 0 ? yy + D.ny : (yy >= D.ny ? yy - D.ny : yy);
-      const int64_t o = (int64_t)yy * D.nx + xx;
-      const double w = (i & 1) ? 1.0 / 36.0 : 1.0 / 9.0;
-      s += w * (cx(i) * bpl[o] + cy(i) * bpl[N + o]);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int x0 = (t % tiles_x) * kDTX, y0 = (t / tiles_x) * kDTY;
+    // tile cells: moments of the real nodes, b of every cell
+    for (int r = wave; r < kDTY; r += kDiagBlock / 64) {
+      const int x = x0 + lane, y = y0 + r;
+      double2 bv = make_double2(0.0, 0.0);
+      if (x < D.nx && y < D.ny) {
+        const MomD m = moments_d<C, WALLS, SWAPPED>(D, src, x, y);
+        acc[0] += m.ux * m.ux + m.uy * m.uy;
+        acc[1] += m.bx * m.bx + m.by * m.by;
+        acc[2] += m.rho;
+        acc[3] += m.jx;
+        acc[4] += m.jy;
+        acc[5] += m.bx;
+        acc[6] += m.by;
+        bv = make_double2(m.bx, m.by);
+      } else if (!(WALLS && y >= D.ny)) {
+        b_at<C, WALLS, SWAPPED>(D, src, wrap(x, D.nx), wrap(y, D.ny), bv.x, bv.y);
+      }
+      bt[r + 1][lane + 1] = bv;
     }
-    const double dv = fabs(3.0 * s);
-    mx = nanmax(mx, dv);
+    // the ring
+    for (int h = threadIdx.x; h < kRing; h += kDiagBlock) {
+      int lx, ly;
+      if (h < kDTX + 2) {
+        lx = h - 1;
+        ly = -1;
+      } else if (h < 2 * (kDTX + 2)) {
+        lx = h - (kDTX + 2) - 1;
+        ly = kDTY;
+      } else {
+        const int k = h - 2 * (kDTX + 2);
+        lx = k < kDTY ? -1 : kDTX;
+        ly = k % kDTY;
+      }
+      const int y = y0 + ly;
+      double2 bv = make_double2(0.0, 0.0);
+      if (!(WALLS && (y < 0 || y >= D.ny)))
+        b_at<C, WALLS, SWAPPED>(D, src, wrap(x0 + lx, D.nx), wrap(y, D.ny), bv.x, bv.y);
+      bt[ly + 1][lx + 1] = bv;
+    }
+    __syncthreads();
+    for (int r = wave; r < kDTY; r += kDiagBlock / 64) {
+      const int x = x0 + lane, y = y0 + r;
+      if (x >= D.nx || y >= D.ny) continue;
+      if (WALLS && (y < 1 || y > D.ny - 2)) continue;
+      double sum = 0.0;
+#pragma unroll
+      for (int i = 1; i < kQ; ++i) {
+        const double2 v = bt[r + 1 + cy(i)][lane + 1 + cx(i)];
+        const double w = (i & 1) ? 1.0 / 36.0 : 1.0 / 9.0;
+        sum += w * (cx(i) * v.x + cy(i) * v.y);
+      }
+      mx = nanmax(mx, fabs(3.0 * sum));
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < kSums; ++k) {
+    const double r = block_reduce<false>(acc[k], lds);
+    if (threadIdx.x == 0) part_s[(int64_t)blockIdx.x * kSums + k] = r;
   }
   const double r = block_reduce<true>(mx, lds);
-  if (threadIdx.x == 0) part[blockIdx.x] = r;
+  if (threadIdx.x == 0) part_m[blockIdx.x] = r;
 }
 
 __global__ __launch_bounds__(kDiagBlock) void k_diag_final(
@@ -820,40 +877,36 @@ hipError_t launch_swapped_to_pull(int storage, const Domain &D, const void *buf,
 }
 
 static int diag_grid(const Domain &D) {
-  const int64_t N = (int64_t)D.nx * D.ny;
-  const int64_t need = (N + kDiagBlock - 1) / kDiagBlock;
-  return (int)(need < kDiagGrid ? need : kDiagGrid);
+  const int64_t tiles = (int64_t)((D.nx + kDTX - 1) / kDTX) * ((D.ny + kDTY - 1) / kDTY);
+  return (int)(tiles < kDiagGrid ? tiles : kDiagGrid);
 }
 
-size_t diag_work_bytes(const Domain &D) {
-  const int64_t N = (int64_t)D.nx * D.ny;
-  return sizeof(double) * (size_t)(2 * N + kDiagGrid * kSums + kDiagGrid);
+size_t diag_work_bytes(const Domain &) {
+  return sizeof(double) * (size_t)(kDiagGrid * kSums + kDiagGrid);
 }
 
 template <class C, bool SW>
-static void diag_t(const Domain &D, const void *src, double *bpl, double *ps,
-                   double *pm, int nb, hipStream_t st) {
+static void diag_t(const Domain &D, const void *src, double *ps, double *pm, int nb,
+                   hipStream_t st) {
   auto s = (const typename C::T *)src;
   if (D.walls)
-    hipLaunchKernelGGL((k_diag_sums<C, true, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
+    hipLaunchKernelGGL((k_diag_tile<C, true, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, ps, pm);
   else
-    hipLaunchKernelGGL((k_diag_sums<C, false, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, bpl, ps);
+    hipLaunchKernelGGL((k_diag_tile<C, false, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, ps, pm);
 }
 
 hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
                               void *work, double *out_dev, hipStream_t st, int swapped) {
   const int64_t N = (int64_t)D.nx * D.ny;
-  double *bpl = (double *)work;
-  double *ps = bpl + 2 * N;
+  double *ps = (double *)work;
   double *pm = ps + kDiagGrid * kSums;
   const int nb = diag_grid(D);
   if (storage == kF16)
-    swapped ? diag_t<CodecF16, true>(D, src, bpl, ps, pm, nb, st)
-            : diag_t<CodecF16, false>(D, src, bpl, ps, pm, nb, st);
+    swapped ? diag_t<CodecF16, true>(D, src, ps, pm, nb, st)
+            : diag_t<CodecF16, false>(D, src, ps, pm, nb, st);
   else
-    swapped ? diag_t<CodecF32, true>(D, src, bpl, ps, pm, nb, st)
-            : diag_t<CodecF32, false>(D, src, bpl, ps, pm, nb, st);
-  hipLaunchKernelGGL(k_diag_divb, dim3(nb), dim3(kDiagBlock), 0, st, D, bpl, pm);
+    swapped ? diag_t<CodecF32, true>(D, src, ps, pm, nb, st)
+            : diag_t<CodecF32, false>(D, src, ps, pm, nb, st);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, st, ps, nb, pm, nb,
                      1.0 / (2.0 * (double)N), out_dev);
   return hipGetLastError();
