@@ -8,6 +8,11 @@ PROF_DIR holds the rocprofv3 output directories written by
 Counter values (KiB per dispatch) are calibrated against the plain copy
 kernel of known size: factor = true bytes / counted bytes for that kernel.
 
+Single-buffer (in-place) steps, per phase, from the same copy calibration:
+  rocprofv3 --kernel-trace --stats ... -d PROF_DIR/ip_stats_{f32,f16} ... bench.py --inplace ...
+  rocprofv3 --pmc <ctr> ... -d PROF_DIR/ip_pmc_<ctr>_{f32,f16} ... bench.py --inplace ...
+  python -m paper_2602_14667_amd.profsum inplace PROF_DIR OUT_DIR N
+
 Second form, kernel-trace statistics of any workload:
   python -m paper_2602_14667_amd.profsum stats STATS_DIR OUT.md KERNEL BYTES TITLE COMMAND [LAST]
 writes the per-kernel table and, for the kernel whose name contains KERNEL,
@@ -18,6 +23,7 @@ bench run, after any autotuning launches).
 import csv
 import json
 import os
+import re
 import sys
 
 from . import kernel_hash
@@ -103,6 +109,65 @@ def main(prof, out, n):
     print("ok")
 
 
+def _calibration(prof):
+    fac = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        kib = counter_mean(os.path.join(prof, f"pmc_{ctr}_copy"), "k_copy16")
+        fac[ctr] = COPY_BYTES / (kib * 1024.0)
+    return fac
+
+
+def inplace_summary(prof, out, n):
+    """Per-phase time and calibrated HBM traffic of the single-buffer step."""
+    n = int(n)
+    nodes = n * n
+    fac = _calibration(prof)
+    for st, bpn in (("f32", 152), ("f16", 76)):
+        stats = kernel_stats(os.path.join(prof, f"ip_stats_{st}"))
+        alg = bpn * nodes
+        lines = [
+            f"# single-buffer (in-place) step kernels, {st.upper()} storage, turbulence {n}x{n}",
+            "",
+            f"Source hash {kernel_hash()}. The two phases alternate; one step of either moves "
+            f"{alg / 1e9:.3f} GB algorithmically ({bpn} B/node).",
+            "",
+            "Commands (from the repository root, on the MI355X host; calibration runs as for the "
+            "two-buffer step summaries):",
+            "```",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/ip_stats_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 50 --warmup 6 --no-cpu-baseline",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/ip_pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 6 --warmup 2 --no-cpu-baseline",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/ip_pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 6 --warmup 2 --no-cpu-baseline",
+            f"python -m paper_2602_14667_amd.profsum inplace {prof} profiles {n}",
+            "```",
+            "",
+            "| kernel | calls | avg ns | min ns | max ns |",
+            "|---|---|---|---|---|",
+        ]
+        for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+            lines.append(f"| `{k[:100]}` | {v['calls']} | {v['avg_ns']:.0f} | {v['min_ns']:.0f} "
+                         f"| {v['max_ns']:.0f} |")
+        lines.append("")
+        tot = 0.0
+        for ph in (0, 1):
+            # k_step_inplace<codec, walls, forced, phase, nt>
+            pat = re.compile(r"k_step_inplace<[^,<>]+, \w+, \w+, %d," % ph)
+            name = [k for k in stats if pat.search(k)][0]
+            avg = stats[name]["avg_ns"]
+            tot += avg
+            rd = counter_mean(os.path.join(prof, f"ip_pmc_FETCH_SIZE_{st}"), name) * 1024 * fac["FETCH_SIZE"]
+            wr = counter_mean(os.path.join(prof, f"ip_pmc_WRITE_SIZE_{st}"), name) * 1024 * fac["WRITE_SIZE"]
+            lines.append(f"* phase {ph}: average launch {avg / 1e3:.1f} us -> {alg / avg:.1f} GB/s "
+                         f"algorithmic = {alg / avg / 8000 * 100:.1f} % of 8 TB/s; HBM traffic (PMC, "
+                         f"calibrated) read {rd / 1e9:.3f} GB ({rd / (alg / 2):.3f}x), write "
+                         f"{wr / 1e9:.3f} GB ({wr / (alg / 2):.3f}x)")
+        avg2 = tot / 2
+        lines.append(f"* both phases: {avg2 / 1e3:.1f} us per step -> {nodes / avg2 * 1e3:.0f} MLUPS, "
+                     f"{alg / avg2 / 8000 * 100:.1f} % of 8 TB/s")
+        with open(os.path.join(out, f"step_inplace_{st}_{n}.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    print("ok")
+
+
 def last_dispatches(stats_dir, kernel, count):
     """Average duration (ns) of the last `count` dispatches of the kernel
     whose name contains `kernel` (the timed region of a bench run)."""
@@ -144,5 +209,7 @@ def stats_summary(stats_dir, out_md, kernel, bytes_per_launch, title, command, l
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats_summary(*sys.argv[2:9])
+    elif sys.argv[1] == "inplace":
+        inplace_summary(*sys.argv[2:5])
     else:
         main(*sys.argv[1:4])
