@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rrmhd_oracle.c")
+_SRC3 = os.path.join(_HERE, "rrmhd3d_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FEQ_ALGORITHM = 0  # equilibrium of the algorithm (Maxwell stress at 2nd order)
@@ -33,7 +34,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp",
-               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+               "-Wall", "-Wno-unused-function", _SRC, _SRC3, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -73,6 +74,24 @@ def lib():
         L.orc_node_collide.argtypes = [_dp, _dp, ctypes.c_double,
                                        ctypes.c_double, _dp, ctypes.c_int,
                                        _dp, _dp, _dp]
+        L.orc3d_create.restype = ctypes.c_void_p
+        L.orc3d_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_double]
+        L.orc3d_destroy.argtypes = [ctypes.c_void_p]
+        L.orc3d_init.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc3d_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.orc3d_step_count.restype = ctypes.c_long
+        L.orc3d_step_count.argtypes = [ctypes.c_void_p]
+        L.orc3d_moments.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.orc3d_diagnostics.argtypes = [ctypes.c_void_p, _dp]
+        L.orc3d_invariants.argtypes = [ctypes.c_void_p, _dp]
+        L.orc3d_hermite.restype = ctypes.c_double
+        L.orc3d_hermite.argtypes = [ctypes.c_int, _ip, ctypes.c_int]
+        L.orc3d_lattice.argtypes = [_ip, _dp]
+        L.orc3d_aux_size.restype = ctypes.c_int
+        L.orc3d_node_equilibrium.argtypes = [ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.orc3d_node_collide.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double,
+                                         _dp, _dp, _dp]
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_closure_nparams.restype = ctypes.c_int
@@ -386,3 +405,108 @@ class Oracle:
         assert f.shape == (9, self.ny, self.nx)
         assert g.shape == (5, 2, self.ny, self.nx)
         lib().orc_set_state(self._h, _ptr(f), _ptr(g))
+
+
+# ---- three-dimensional extension (D3Q27 fluid, D3Q7 magnetic lattice) -------
+def lattice3d():
+    """(c[27][3], w[27]) in the oracle's velocity order
+    i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1)."""
+    c = np.zeros(81, dtype=np.int32)
+    w = np.zeros(27)
+    lib().orc3d_lattice(c.ctypes.data_as(_ip), _ptr(w))
+    return c.reshape(27, 3).astype(int), w
+
+
+MAG3D_E = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                    [0, 0, 1], [0, 0, -1]])
+MAG3D_PSI = np.array([0.25] + [0.125] * 6)
+
+
+def hermite3d(n: int, idx, i: int) -> float:
+    arr = (ctypes.c_int * max(n, 1))(*idx)
+    return float(lib().orc3d_hermite(n, arr, i))
+
+
+def node_equilibrium3d(rho, u, b):
+    """(f_eq[27], g_eq[7][3]) of one node."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    feq = np.zeros(27)
+    geq = np.zeros(21)
+    lib().orc3d_node_equilibrium(float(rho), _ptr(u), _ptr(b), _ptr(feq), _ptr(geq))
+    return feq, geq.reshape(7, 3)
+
+
+def node_collide3d(f, g, omega, omega_m):
+    """Collide one node.  Returns (f*[27], g*[7][3], aux dict with rho, u,
+    b, the full tensors a2..a6, feq, geq, fneq_reg)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(21)
+    fs = np.zeros(27)
+    gs = np.zeros(21)
+    aux = np.zeros(int(lib().orc3d_aux_size()))
+    lib().orc3d_node_collide(_ptr(f), _ptr(g), float(omega), float(omega_m), _ptr(fs),
+                             _ptr(gs), _ptr(aux))
+    names = [("rho", 1), ("u", 3), ("b", 3), ("a2", 9), ("a3", 27), ("a4", 81),
+             ("a5", 243), ("a6", 729), ("feq", 27), ("geq", 21), ("fneq_reg", 27)]
+    d, k = {}, 0
+    for nm, sz in names:
+        d[nm] = aux[k:k + sz].copy() if sz > 1 else float(aux[k])
+        k += sz
+    for n in range(2, 7):
+        d[f"a{n}"] = d[f"a{n}"].reshape((3,) * n)
+    d["geq"] = d["geq"].reshape(7, 3)
+    return fs, gs.reshape(7, 3), d
+
+
+class Oracle3D:
+    """FP64 three-dimensional periodic grid; state = pre-collision
+    populations; fields are [3][nz][ny][nx] (rho [nz][ny][nx])."""
+
+    def __init__(self, nx, ny, nz, tau_f, tau_m):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self._h = lib().orc3d_create(self.nx, self.ny, self.nz, float(tau_f), float(tau_m))
+        if not self._h:
+            raise ValueError("oracle: invalid grid or relaxation times")
+
+    def close(self):
+        if self._h:
+            lib().orc3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, u, b):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        assert u.shape == (3, self.nz, self.ny, self.nx) and b.shape == u.shape
+        lib().orc3d_init(self._h, _ptr(u), _ptr(b))
+
+    def step(self, n=1):
+        lib().orc3d_step(self._h, int(n))
+
+    @property
+    def step_count(self):
+        return int(lib().orc3d_step_count(self._h))
+
+    def moments(self):
+        shp = (self.nz, self.ny, self.nx)
+        rho = np.zeros(shp)
+        u = np.zeros((3,) + shp)
+        b = np.zeros((3,) + shp)
+        lib().orc3d_moments(self._h, _ptr(rho), _ptr(u), _ptr(b))
+        return rho, u, b
+
+    def diagnostics(self):
+        out = np.zeros(3)
+        lib().orc3d_diagnostics(self._h, _ptr(out))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def invariants(self):
+        out = np.zeros(7)
+        lib().orc3d_invariants(self._h, _ptr(out))
+        return out

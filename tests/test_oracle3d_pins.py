@@ -1,0 +1,304 @@
+"""Pins of the three-dimensional FP64 oracle (D3Q27 fluid, D3Q7 magnetic
+lattice), the direct generalisation of the algorithm of Sec. II.B that the
+Conclusions name as the next step.  Every check is derived independently of
+the oracle's generic-tensor code: the tensor-product (D1Q3 x D1Q3 x D1Q3)
+form of the equilibrium and of the Hermite basis, the hand-expanded Maxwell
+term, moment identities, the pair form of the recursion, conservation and
+symmetries, and the analytic decay rates of a shear wave, a magnetic
+diffusion mode and an Alfven wave.  CPU only."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+C, W = oracle.lattice3d()
+E, PSI = oracle.MAG3D_E, oracle.MAG3D_PSI
+RNG = np.random.default_rng(31)
+
+
+def w1(c):
+    return 2 / 3 if c == 0 else 1 / 6
+
+
+def h1d(n, c):
+    """1-D Hermite polynomial of order n <= 2 at lattice speed c (c_s^2 = 1/3)."""
+    return (1.0, float(c), c * c - 1 / 3)[n]
+
+
+def H(idx):
+    """H^(n) at every velocity for a supported tuple: the product of 1-D
+    polynomials of the per-direction counts."""
+    cnt = [list(idx).count(a) for a in range(3)]
+    return np.array([np.prod([h1d(cnt[a], C[i, a]) for a in range(3)]) for i in range(27)])
+
+
+def rand_state(scale=0.05):
+    rho = 1 + 0.1 * RNG.standard_normal()
+    u = scale * RNG.standard_normal(3)
+    b = scale * RNG.standard_normal(3)
+    return rho, u, b
+
+
+def maxwell(b):
+    return 0.5 * (b @ b) * np.eye(3) - np.outer(b, b)
+
+
+def supported_tuples(n):
+    return [t for t in itertools.product(range(3), repeat=n)
+            if max(t.count(a) for a in range(3)) <= 2]
+
+
+# ---------------------------------------------------------------------------
+def test_lattices():
+    assert sorted(map(tuple, C)) == sorted(itertools.product((-1, 0, 1), repeat=3))
+    assert np.allclose(W, [w1(c[0]) * w1(c[1]) * w1(c[2]) for c in C], rtol=0, atol=1e-17)
+    assert abs(W.sum() - 1) < 1e-15
+    assert np.allclose(np.einsum("i,ia,ib->ab", W, C, C), np.eye(3) / 3, rtol=0, atol=1e-16)
+    assert abs((W * C[:, 0] ** 4).sum() - 1 / 3) < 1e-16
+    assert abs((W * C[:, 0] ** 2 * C[:, 1] ** 2).sum() - 1 / 9) < 1e-16
+    assert abs((W * (C[:, 0] * C[:, 1] * C[:, 2]) ** 2).sum() - 1 / 27) < 1e-16
+    assert abs(PSI.sum() - 1) < 1e-16
+    assert np.allclose(np.einsum("j,ja,jb->ab", PSI, E, E), np.eye(3) / 4, rtol=0, atol=1e-16)
+
+
+def test_hermite_values_and_aliasing():
+    for n in range(0, 7):
+        for t in supported_tuples(n)[:40]:
+            got = np.array([oracle.hermite3d(n, t, i) for i in range(27)])
+            assert np.allclose(got, H(t), rtol=0, atol=1e-15), t
+    # a direction three times aliases to zero on the lattice
+    for idx in ((0, 0, 0), (1, 1, 1, 2), (2, 2, 2, 0, 1)):
+        got = np.array([oracle.hermite3d(len(idx), idx, i) for i in range(27)])
+        assert np.allclose(got, 0, atol=1e-15)
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_feq_is_d1q3_product_without_field(trial):
+    rho, u, _ = rand_state(0.08)
+    feq, _ = oracle.node_equilibrium3d(rho, u, np.zeros(3))
+
+    def phi(c, v):
+        return 2 / 3 - v * v if c == 0 else 1 / 6 + c * v / 2 + v * v / 2
+
+    expect = np.array([rho * phi(c[0], u[0]) * phi(c[1], u[1]) * phi(c[2], u[2]) for c in C])
+    assert np.allclose(feq, expect, rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_maxwell_term_closed_form(trial):
+    """f_eq(b) - f_eq(0) = w_i (9/2) [M_ab c_a c_b - tr(M)/3] with
+    M = |b|^2/2 I - b b (tr M = |b|^2/2 in three dimensions)."""
+    rho, u, b = rand_state()
+    f1, _ = oracle.node_equilibrium3d(rho, u, b)
+    f0, _ = oracle.node_equilibrium3d(rho, u, np.zeros(3))
+    M = maxwell(b)
+    expect = np.array([W[i] * 4.5 * (C[i] @ M @ C[i] - np.trace(M) / 3) for i in range(27)])
+    assert np.allclose(f1 - f0, expect, rtol=0, atol=2e-16)  # ~2 ulp of f
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_feq_hermite_moments(trial):
+    rho, u, b = rand_state()
+    feq, _ = oracle.node_equilibrium3d(rho, u, b)
+    M = maxwell(b)
+    assert abs(feq.sum() - rho) < 1e-15
+    assert np.allclose(feq @ C, rho * u, rtol=0, atol=1e-15)
+    for n in range(2, 7):
+        for t in supported_tuples(n):
+            want = rho * np.prod([u[a] for a in t]) + (M[t[0], t[1]] if n == 2 else 0.0)
+            assert abs(feq @ H(t) - want) < 1e-15, t
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_geq_moments(trial):
+    _, u, b = rand_state()
+    _, geq = oracle.node_equilibrium3d(1.0, u, b)
+    assert np.allclose(geq.sum(0), b, rtol=0, atol=1e-16)
+    first = np.einsum("ja,jb->ab", E, geq)
+    assert np.allclose(first, np.outer(u, b) - np.outer(b, u), rtol=0, atol=1e-16)
+    second = np.einsum("ja,jb,jc->abc", E, E, geq)
+    assert np.allclose(second, np.einsum("ab,c->abc", np.eye(3), b) / 4, rtol=0, atol=1e-16)
+
+
+def node_state():
+    rho, u, b = rand_state()
+    feq, geq = oracle.node_equilibrium3d(rho, u, b)
+    f = feq * (1 + 0.03 * RNG.standard_normal(27))
+    g = geq + 0.002 * RNG.standard_normal((7, 3))
+    return f, g
+
+
+@pytest.mark.parametrize("trial", range(3))
+def test_a1_projection_and_pair_recursion(trial):
+    """a1^(2) = P - (drho/3) I - rho u u - M from the raw moments, and
+    a1^(n) = sum over index pairs (p, q) of (prod_{k != p, q} u_k) a1^(2)_pq
+    for n = 3..6 (the closed form the recursion produces)."""
+    f, g = node_state()
+    _, _, d = oracle.node_collide3d(f, g, 1 / 0.55, 1 / 0.6)
+    rho = f.sum()
+    u = (f @ C) / rho
+    b = g.sum(0)
+    P = np.einsum("i,ia,ib->ab", f, C, C)
+    a2 = P - rho / 3 * np.eye(3) - rho * np.outer(u, u) - maxwell(b)
+    assert np.allclose(d["a2"], a2, rtol=0, atol=1e-15)
+    for n in range(3, 7):
+        for t in supported_tuples(n):
+            want = 0.0
+            for p, q in itertools.combinations(range(n), 2):
+                want += np.prod([u[t[k]] for k in range(n) if k not in (p, q)]) * a2[t[p], t[q]]
+            assert abs(d[f"a{n}"][t] - want) < 1e-16, t
+
+
+@pytest.mark.parametrize("trial", range(3))
+def test_regularised_part_moments(trial):
+    """f_neq,reg has zero mass and momentum and returns a1^(n) as its
+    Hermite moment on every supported component (n = 2..6)."""
+    f, g = node_state()
+    _, _, d = oracle.node_collide3d(f, g, 1 / 0.55, 1 / 0.6)
+    fr = d["fneq_reg"]
+    assert abs(fr.sum()) < 1e-16 and np.allclose(fr @ C, 0, atol=1e-16)
+    for n in range(2, 7):
+        for t in supported_tuples(n):
+            assert abs(fr @ H(t) - d[f"a{n}"][t]) < 1e-16, t
+
+
+@pytest.mark.parametrize("trial", range(3))
+def test_post_collision_moments(trial):
+    f, g = node_state()
+    om, omm = 1 / 0.55, 1 / 0.6
+    fs, gs, d = oracle.node_collide3d(f, g, om, omm)
+    rho = f.sum()
+    assert abs(fs.sum() - rho) < 1e-15
+    assert np.allclose(fs @ C, f @ C, rtol=0, atol=1e-16)
+    assert np.allclose(gs.sum(0), g.sum(0), rtol=0, atol=1e-16)
+    u, b = d["u"], d["b"]
+    for a, c in itertools.product(range(3), repeat=2):
+        want = rho * u[a] * u[c] + maxwell(b)[a, c] + (1 - om) * d["a2"][a, c]
+        assert abs(fs @ H((a, c)) - want) < 1e-15
+    # magnetic: g* = g_eq + (1 - omega_m)(g - g_eq)
+    assert np.allclose(gs, d["geq"] + (1 - omm) * (g - d["geq"]), rtol=0, atol=1e-17)
+
+
+def random_fields(nx, ny, nz, amp, seed):
+    r = np.random.default_rng(seed)
+    return amp * r.standard_normal((3, nz, ny, nx)), amp * r.standard_normal((3, nz, ny, nx))
+
+
+def test_conservation_and_fixed_point():
+    u, b = random_fields(6, 5, 4, 0.03, 1)
+    o = oracle.Oracle3D(6, 5, 4, 0.56, 0.62)
+    o.init(u, b)
+    i0 = o.invariants()
+    o.step(20)
+    assert np.allclose(o.invariants(), i0, rtol=0, atol=1e-12)
+    uu = np.zeros((3, 3, 4, 5)) + np.array([0.03, -0.02, 0.01])[:, None, None, None]
+    bb = np.zeros_like(uu) + np.array([0.02, 0.01, -0.03])[:, None, None, None]
+    o = oracle.Oracle3D(5, 4, 3, 0.6, 0.7)
+    o.init(uu, bb)
+    o.step(10)
+    rho, u1, b1 = o.moments()
+    assert np.allclose(rho, 1, atol=1e-14) and np.allclose(u1, uu, atol=1e-15)
+    assert np.allclose(b1, bb, atol=1e-16)
+
+
+def test_translation_and_axis_permutation_equivariance():
+    u, b = random_fields(5, 5, 5, 0.04, 2)
+    o = oracle.Oracle3D(5, 5, 5, 0.57, 0.6)
+    o.init(u, b)
+    o.step(6)
+    r0, u0, b0 = o.moments()
+    sh = (2, 1, 3)  # roll in z, y, x
+    o2 = oracle.Oracle3D(5, 5, 5, 0.57, 0.6)
+    o2.init(np.roll(u, sh, (1, 2, 3)), np.roll(b, sh, (1, 2, 3)))
+    o2.step(6)
+    r1, u1, b1 = o2.moments()
+    assert np.allclose(r1, np.roll(r0, sh, (0, 1, 2)), rtol=0, atol=1e-15)
+    assert np.allclose(u1, np.roll(u0, sh, (1, 2, 3)), rtol=0, atol=1e-15)
+    # cyclic relabelling x -> y -> z -> x of axes and components
+    def rot(v):  # v[c][z][y][x] -> new field with components (z, x, y) and axes permuted
+        return np.stack([v[2], v[0], v[1]]).transpose(0, 2, 3, 1)
+    o3 = oracle.Oracle3D(5, 5, 5, 0.57, 0.6)
+    o3.init(rot(u), rot(b))
+    o3.step(6)
+    _, u2, b2 = o3.moments()
+    assert np.allclose(u2, rot(u0), rtol=0, atol=1e-15)
+    assert np.allclose(b2, rot(b0), rtol=0, atol=1e-15)
+
+
+def test_no_field_keeps_field_zero():
+    u, _ = random_fields(4, 4, 4, 0.04, 3)
+    o = oracle.Oracle3D(4, 4, 4, 0.56, 0.6)
+    o.init(u, np.zeros_like(u))
+    o.step(10)
+    _, _, b = o.moments()
+    assert np.abs(b).max() == 0.0
+
+
+def decay_rate(series, dt):
+    return -math.log(series[1] / series[0]) / dt
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8])
+def test_shear_wave_decay(tau):
+    """u_x = U sin(k z) decays at nu k^2 with nu = c_s^2 (tau - 1/2)."""
+    n, U, steps = 32, 1e-4, 200
+    k = 2 * np.pi / n
+    z = np.arange(n)
+    u = np.zeros((3, n, 1, 1))
+    u[0, :, 0, 0] = U * np.sin(k * z)
+    o = oracle.Oracle3D(1, 1, n, tau, 0.6)
+    o.init(u, np.zeros_like(u))
+    o.step(20)
+    a0 = np.abs(np.fft.fft(o.moments()[1][0, :, 0, 0])[1])
+    o.step(steps)
+    a1 = np.abs(np.fft.fft(o.moments()[1][0, :, 0, 0])[1])
+    nu = (tau - 0.5) / 3
+    assert abs(decay_rate((a0, a1), steps) / (nu * k * k) - 1) < 1e-2
+
+
+@pytest.mark.parametrize("tau_m", [0.55, 0.8])
+def test_magnetic_diffusion_decay(tau_m):
+    """b_y = B sin(k x) with u = 0 decays at eta k^2, eta = c_m^2 (tau_m - 1/2)
+    with the D3Q7 lattice's c_m^2 = 1/4."""
+    n, B, steps = 32, 1e-4, 200
+    k = 2 * np.pi / n
+    x = np.arange(n)
+    b = np.zeros((3, 1, 1, n))
+    b[1, 0, 0, :] = B * np.sin(k * x)
+    o = oracle.Oracle3D(n, 1, 1, 0.6, tau_m)
+    o.init(np.zeros_like(b), b)
+    o.step(20)
+    a0 = np.abs(np.fft.fft(o.moments()[2][1, 0, 0, :])[1])
+    o.step(steps)
+    a1 = np.abs(np.fft.fft(o.moments()[2][1, 0, 0, :])[1])
+    eta = (tau_m - 0.5) / 4
+    assert abs(decay_rate((a0, a1), steps) / (eta * k * k) - 1) < 1e-2
+
+
+def test_alfven_wave():
+    """Along a uniform field B0 y with nu = eta, the Elsaesser variable
+    z+ = u_z + b_z of a transverse perturbation travels in -y at speed B0
+    and decays as exp(-nu k^2 t); eta = nu needs tau_m = 1/2 + 4 nu on the
+    D3Q7 lattice (c_m^2 = 1/4)."""
+    N, A, B0, tau = 128, 1e-4, 0.05, 0.56
+    nu = (tau - 0.5) / 3
+    tau_m = 0.5 + 4 * nu
+    k = 2 * np.pi / N
+    y = np.arange(N)
+    u = np.zeros((3, 1, N, 1))
+    b = np.zeros_like(u)
+    u[2, 0, :, 0] = A * np.sin(k * y)
+    b[1] = B0
+    b[2, 0, :, 0] = A * np.sin(k * y)
+    T = 600
+    o = oracle.Oracle3D(1, N, 1, tau, tau_m)
+    o.init(u, b)
+    o.step(T)
+    _, v, c = o.moments()
+    zp = v[2, 0, :, 0] + c[2, 0, :, 0]
+    ratio = (np.fft.fft(zp)[1] / N) / (2 * A / 2j)
+    assert abs(-math.log(abs(ratio)) / T / (nu * k * k) - 1) < 0.01
+    assert abs(np.angle(ratio) / (k * B0 * T) - 1) < 0.01
