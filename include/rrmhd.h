@@ -168,6 +168,39 @@ int rrmhd_set_equilibrium(rrmhd *h, int kind);
 
 int rrmhd_destroy(rrmhd *h);
 
+/* ---- Three-dimensional extension ----------------------------------------
+ * The paper is two-dimensional and names three-dimensional lattices as the
+ * next step (Conclusions).  This handle advances the direct generalisation
+ * of the algorithm of Sec. II.B on a periodic nx x ny x nz box:
+ *  - fluid D3Q27, c_s^2 = 1/3: equilibrium = the D3Q27 Hermite series up to
+ *    sixth order (the product of three D1Q3 factors) with the Maxwell stress
+ *    M = |b|^2/2 I - b b at second order only; a1^(2) by projection; every
+ *    D3Q27-supported coefficient of orders 3 to 6 from the recursion of task
+ *    3 in general form (a sum over index pairs of a1^(2) times the other
+ *    velocities); collision f* = f_eq + (1 - 1/tau_f) f_neq,reg;
+ *  - magnetic D3Q7 vector BGK, weights 1/4 (rest) and 1/8, so
+ *    eta = (tau_m - 1/2)/4; g_eq,j = psi_j [b + 4 e_j.(u b - b u)].
+ * nu = (tau_f - 1/2)/3.  Storage RRMHD_STORE_F32 or _F16 (f - w and g, S = 1),
+ * FP32 arithmetic, two buffers of 48 planes.  Fields are [3][nz][ny][nx]
+ * (component, z, y, x) FP64 device arrays, rho [nz][ny][nx].  Errors as for
+ * the two-dimensional handle (EINVAL also for ny or nz above 65535 or
+ * nx ny nz * element size >= 2^32).  Diagnostics: E = sum |u|^2 / (2N),
+ * sum |b|^2 / (2N), max |div b| with the isotropic D3Q27 gradient;
+ * invariants: mass, sum rho u (3), sum b (3). */
+typedef struct rrmhd3d rrmhd3d;
+int rrmhd3d_create(int32_t nx, int32_t ny, int32_t nz, int32_t storage, double tau_f,
+                   double tau_m, void *hip_stream, rrmhd3d **out);
+int rrmhd3d_init(rrmhd3d *h, const double *u, const double *b);
+int rrmhd3d_step(rrmhd3d *h, int64_t n);
+int rrmhd3d_step_count(const rrmhd3d *h, int64_t *out);
+int rrmhd3d_moments(rrmhd3d *h, double *rho, double *u, double *b);
+int rrmhd3d_diagnostics(rrmhd3d *h, double *E_kin, double *E_mag, double *max_div_b);
+int rrmhd3d_invariants(rrmhd3d *h, double out[7]);
+/* bx x by threads per workgroup over x and y (bx * by <= 256); results do
+ * not depend on it.  Host-side only. */
+int rrmhd3d_set_launch(rrmhd3d *h, int bx, int by);
+int rrmhd3d_destroy(rrmhd3d *h);
+
 /* ---- Batched ensemble --------------------------------------------------
  * Many independent doubly periodic domains of uneven sizes and relaxation
  * times, all advanced together: one persistent kernel launch per time step

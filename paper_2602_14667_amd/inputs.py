@@ -12,6 +12,7 @@ drawn.
 """
 from __future__ import annotations
 
+import itertools
 import math
 from dataclasses import dataclass
 
@@ -257,3 +258,81 @@ def batch_fields(dom: dict):
     if dom["kind"] == "ot":
         return orszag_tang(s, 0.05, 0.05, perturb=1e-4, seed=dom["seed"])
     return turbulence(s, 0.04, seed_psi=dom["seed"], seed_a=dom["seed"] + 1)
+
+
+# --------------------------------------------------------------------------
+# Three-dimensional fields (the three-dimensional extension)
+# --------------------------------------------------------------------------
+TURB3D_KMAX = 12
+
+
+def _gauss(seed: int, stream: int, index: np.ndarray) -> np.ndarray:
+    """Standard normal values from two counter streams (Box-Muller)."""
+    u1 = counter_uniform(seed, stream, index)
+    u2 = counter_uniform(seed, stream + 1, index)
+    return np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def _solenoidal3d(n: int, seed: int):
+    """u = curl A on an n^3 grid for a random vector potential A with the
+    modes |kappa| <= TURB3D_KMAX, |A(kappa)| ~ sqrt(E(k) / 4 pi) / k^2 and
+    E(k) ~ k^4 exp(-2 (k/4)^2), so that the shell spectrum of u follows
+    E(k); real by Hermitian symmetry (irfftn).  Returns u [3][n][n][n]
+    (component, z, y, x) with unit vector rms."""
+    K = min(TURB3D_KMAX, n // 2 - 1) if n > 2 else 0
+    kz = np.fft.fftfreq(n, 1.0 / n)[:, None, None]
+    ky = np.fft.fftfreq(n, 1.0 / n)[None, :, None]
+    kx = np.arange(n // 2 + 1, dtype=float)[None, None, :]
+    kk = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2)
+    keep = (kk > 0) & (kk <= K)
+    E = np.where(keep, kk ** 4 * np.exp(-2.0 * (kk / 4.0) ** 2), 0.0)
+    amp = np.where(keep, np.sqrt(E / (4.0 * np.pi)) / np.maximum(kk, 1.0) ** 2, 0.0)
+    shape = amp.shape
+    # a counter index per (component, kappa) that does not depend on n
+    kzi = np.rint(np.broadcast_to(kz, shape)).astype(np.int64) + 64
+    kyi = np.rint(np.broadcast_to(ky, shape)).astype(np.int64) + 64
+    kxi = np.rint(np.broadcast_to(kx, shape)).astype(np.int64)
+    base = ((kzi * 129 + kyi) * 129 + kxi).astype(np.uint64)
+    A = []
+    for comp in range(3):
+        idx = base + np.uint64(comp * 129 ** 3)
+        re = _gauss(seed, 11, idx.ravel()).reshape(shape)
+        im = _gauss(seed, 13, idx.ravel()).reshape(shape)
+        A.append(amp * (re + 1j * im))
+    ik = (1j * kx, 1j * ky, 1j * kz)
+    uh = (ik[1] * A[2] - ik[2] * A[1], ik[2] * A[0] - ik[0] * A[2], ik[0] * A[1] - ik[1] * A[0])
+    u = np.stack([np.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2)) for c in uh])
+    rms = math.sqrt(float(np.mean(np.sum(u * u, axis=0))))
+    return u / (rms if rms > 0 else 1.0)
+
+
+def turbulence3d(n: int, rms: float = 0.04, seed_u: int = 101, seed_b: int = 102):
+    """Decaying 3D MHD turbulence on a periodic n^3 box: divergence-free
+    random-phase u and b with shell spectrum ~ k^4 exp(-2 (k/4)^2) (modes
+    |kappa| <= 12), each rescaled to vector rms ``rms``.  Returns u, b
+    [3][n][n][n] float64 (component, z, y, x)."""
+    u = rms * _solenoidal3d(n, seed_u)
+    b = rms * _solenoidal3d(n, seed_b)
+    return np.ascontiguousarray(u), np.ascontiguousarray(b)
+
+
+def random_modes3d(nx: int, ny: int, nz: int, amp: float, seed: int, kmax: int = 2):
+    """Smooth periodic test fields on a box: each component of u and b is a
+    sum of Fourier modes with |k_a| <= kmax and counter-based random
+    coefficients, scaled to max |component| ~ amp.  Returns u, b
+    [3][nz][ny][nx]."""
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    stream = 40
+    for _ in range(6):
+        f = np.zeros((nz, ny, nx))
+        for k3 in itertools.product(range(-kmax, kmax + 1), repeat=3):
+            if k3 == (0, 0, 0):
+                continue
+            r = counter_uniform(seed, stream, np.arange(2, dtype=np.uint64))
+            stream += 1
+            ph = 2 * np.pi * (k3[0] * x / nx + k3[1] * y / ny + k3[2] * z / nz)
+            f += (r[0] - 0.5) * np.cos(ph + 2 * np.pi * r[1])
+        m = np.abs(f).max()
+        out.append(f * (amp / m) if m > 0 else f)
+    return np.stack(out[:3]), np.stack(out[3:])

@@ -35,6 +35,9 @@ EXPORTED = [
     "rrmhd_train_onestep_samples", "rrmhd_train_onestep_loss_grad",
     "rrmhd_train_adam", "rrmhd_train_destroy", "rrmhd_train_last_error_detail",
     "rrmhd_current_vorticity",
+    "rrmhd3d_create", "rrmhd3d_init", "rrmhd3d_step", "rrmhd3d_step_count",
+    "rrmhd3d_moments", "rrmhd3d_diagnostics", "rrmhd3d_invariants",
+    "rrmhd3d_set_launch", "rrmhd3d_destroy",
 ]
 
 
@@ -90,6 +93,18 @@ def lib():
         ci = ctypes.c_int
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
         L.rrmhd_set_equilibrium.argtypes = [vp, ci]
+        L.rrmhd3d_create.argtypes = [ci, ci, ci, ci, ctypes.c_double, ctypes.c_double, vp,
+                                     ctypes.POINTER(vp)]
+        L.rrmhd3d_init.argtypes = [vp, dp, dp]
+        L.rrmhd3d_step.argtypes = [vp, i64]
+        L.rrmhd3d_step_count.argtypes = [vp, ctypes.POINTER(i64)]
+        L.rrmhd3d_moments.argtypes = [vp, dp, dp, dp]
+        L.rrmhd3d_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]
+        L.rrmhd3d_invariants.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.rrmhd3d_set_launch.argtypes = [vp, ci, ci]
+        L.rrmhd3d_destroy.argtypes = [vp]
         L.rrmhd_destroy.argtypes = [vp]
         L.rrmhd_bandwidth_probe.argtypes = [vp, vp, i64, vp]
         dbl = ctypes.POINTER(ctypes.c_double)
@@ -351,6 +366,75 @@ class Solver:
         self._stream = stream
         _check(lib().rrmhd_set_stream(self._h, _stream_handle(stream)),
                "rrmhd_set_stream")
+
+
+class Solver3D:
+    """Periodic nx x ny x nz box of the three-dimensional extension (D3Q27
+    fluid, D3Q7 magnetic lattice) on the current device.  Fields are FP64
+    device tensors [3][nz][ny][nx]."""
+
+    def __init__(self, nx, ny, nz, tau_f, tau_m, storage="f32", stream=None):
+        L = lib()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(L.rrmhd3d_create(self.nx, self.ny, self.nz,
+                                STORE_F16 if storage == "f16" else STORE_F32,
+                                float(tau_f), float(tau_m), _stream_handle(stream),
+                                ctypes.byref(h)), "rrmhd3d_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().rrmhd3d_destroy(self._h), "rrmhd3d_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, u, b):
+        shp = (3, self.nz, self.ny, self.nx)
+        _check(lib().rrmhd3d_init(self._h, _dev_f64(u, shp, "u"), _dev_f64(b, shp, "b")),
+               "rrmhd3d_init")
+
+    def step(self, n=1):
+        _check(lib().rrmhd3d_step(self._h, int(n)), "rrmhd3d_step")
+
+    @property
+    def step_count(self):
+        v = ctypes.c_int64()
+        _check(lib().rrmhd3d_step_count(self._h, ctypes.byref(v)), "rrmhd3d_step_count")
+        return v.value
+
+    def moments(self):
+        import torch
+        shp = (self.nz, self.ny, self.nx)
+        rho = torch.empty(shp, dtype=torch.float64, device="cuda")
+        u = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
+        b = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
+        _check(lib().rrmhd3d_moments(self._h, _dev_f64(rho, shp, "rho"),
+                                     _dev_f64(u, (3,) + shp, "u"), _dev_f64(b, (3,) + shp, "b")),
+               "rrmhd3d_moments")
+        return rho, u, b
+
+    def diagnostics(self, allow_nonfinite=False):
+        ek, em, dv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().rrmhd3d_diagnostics(self._h, ctypes.byref(ek), ctypes.byref(em),
+                                       ctypes.byref(dv))
+        if not (allow_nonfinite and rc == ENONFINITE):
+            _check(rc, "rrmhd3d_diagnostics")
+        return ek.value, em.value, dv.value
+
+    def invariants(self):
+        out = (ctypes.c_double * 7)()
+        _check(lib().rrmhd3d_invariants(self._h, out), "rrmhd3d_invariants")
+        return list(out)
+
+    def set_launch(self, bx, by):
+        _check(lib().rrmhd3d_set_launch(self._h, int(bx), int(by)), "rrmhd3d_set_launch")
 
 
 def bandwidth_probe(dst, src, stream=None):
