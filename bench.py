@@ -293,6 +293,52 @@ def ot64_bench(torch, rrmhd, inputs, args):
         "us_per_step": out}), flush=True)
 
 
+def turbulence3d_bench(torch, rrmhd, inputs, args):
+    """The three-dimensional extension (D3Q27 fluid, D3Q7 magnetic lattice)
+    on a periodic n^3 box of random-phase MHD turbulence (rms u = b = 0.04),
+    tau 0.52, both storages; roofline against the algorithmic bytes, 48
+    planes read and written per node."""
+    n = args.n3d
+    u, b = inputs.turbulence3d(n, 0.04)
+    ud, bd = torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda()
+    del u, b
+    st = torch.cuda.current_stream()
+    nodes = n ** 3
+    res = {}
+    for storage in ("f32", "f16"):
+        s = rrmhd.Solver3D(n, n, n, args.tau, args.tau, storage=storage)
+        s.init(ud, bd)
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.step(args.steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        diag = s.diagnostics(allow_nonfinite=True)
+        s.close()
+        bpn = 2 * 48 * (4 if storage == "f32" else 2)
+        gbs = bpn * nodes / ms / 1e6
+        res[storage] = dict(mlups=round(nodes / ms / 1e3, 1), ms_per_step=round(ms, 4),
+                            bytes_per_node=bpn, achieved_GBs=round(gbs, 1),
+                            frac=round(gbs / PEAK_HBM_GBS, 4),
+                            diagnostics_after=[v if math.isfinite(v) else None for v in diag])
+    r = res["f32"]
+    print(json.dumps({
+        "metric": "MLUPS & % HBM roofline (fused 3D RR-MHD step, D3Q27 + D3Q7)",
+        "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"decaying 3D MHD turbulence {n}^3 periodic, random-phase "
+                               "solenoidal u and b, rms 0.04", "nodes": nodes,
+                   "tau_f": args.tau, "tau_m": args.tau, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": r["frac"], "traffic": None},
+        "storages": res}), flush=True)
+
+
 def closure_step_bench(torch, rrmhd, inputs, args):
     """The fused step with the closure network (BF16 MFMA inside the
     collision) against the plain step on the same grid, FP32 storage, a
@@ -398,6 +444,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps before timing (default 100; 5 for copy/sweep)")
     ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--n3d", type=int, default=256, help="box side of --workload turbulence3d")
     ap.add_argument("--tau", type=float, default=0.52)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--inplace", action="store_true",
@@ -415,7 +462,8 @@ def main():
                          "time launch shapes, XCD block orders and plane gaps")
     ap.add_argument("--copy-bytes", type=int, default=4 << 30)
     ap.add_argument("--workload", choices=["turbulence", "batch", "closure",
-                                           "closure-step", "hartmann", "ot64"],
+                                           "closure-step", "hartmann", "ot64",
+                                           "turbulence3d"],
                     default="turbulence",
                     help="batch: the 256-domain ensemble; closure: the "
                          "learned-closure protocol (coarse vs fine spectra); "
@@ -427,7 +475,8 @@ def main():
     args = ap.parse_args()
     if args.steps is None:
         args.steps = (20 if args.mode != "step" else
-                      {"batch": 2000, "closure-step": 200}.get(args.workload, 10000))
+                      {"batch": 2000, "closure-step": 200,
+                       "turbulence3d": 1000}.get(args.workload, 10000))
     if args.warmup is None:
         args.warmup = 5 if args.mode != "step" else 100
     if args.gpus != 1:
@@ -460,6 +509,9 @@ def main():
         return
     if args.workload == "ot64":
         ot64_bench(torch, rrmhd, inputs, args)
+        return
+    if args.workload == "turbulence3d":
+        turbulence3d_bench(torch, rrmhd, inputs, args)
         return
     n = args.n
     u, b = inputs.turbulence(n, 0.04)
