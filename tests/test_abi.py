@@ -101,3 +101,32 @@ def test_create_rejects_unknown_storage_flags():
         assert L.rrmhd_create(ctypes.byref(g), 0.6, 0.6, None, None,
                               ctypes.byref(h)) == rrmhd.EINVAL
         assert not h.value
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, 4, 0), (4, 4, 0, 0), (4, 70000, 2, 0), (4, 2, 70000, 0), (4, 4, 4, 2),
+    (4, 4, 4, 0x100), (2048, 2048, 256, 0),  # 2^30 nodes x 4 B does not fit 32-bit offsets
+])
+def test_create3d_rejects_bad_arguments_before_touching_the_device(args):
+    L = rrmhd.lib()
+    nx, ny, nz, storage = args
+    h = ctypes.c_void_p(1234)
+    rc = L.rrmhd3d_create(nx, ny, nz, storage, 0.6, 0.6, None, ctypes.byref(h))
+    assert rc == rrmhd.EINVAL
+    assert not h.value
+
+
+def test_create3d_rejects_bad_relaxation_times():
+    L = rrmhd.lib()
+    for tf, tm in ((0.5, 0.6), (0.6, 0.5), (float("nan"), 0.6)):
+        h = ctypes.c_void_p()
+        assert L.rrmhd3d_create(4, 4, 4, 0, tf, tm, None, ctypes.byref(h)) == rrmhd.EINVAL
+
+
+def test_null_3d_handle_calls_are_rejected():
+    L = rrmhd.lib()
+    assert L.rrmhd3d_step(None, 1) == rrmhd.EINVAL
+    assert L.rrmhd3d_init(None, None, None) == rrmhd.EINVAL
+    assert L.rrmhd3d_moments(None, None, None, None) == rrmhd.EINVAL
+    assert L.rrmhd3d_set_launch(None, 64, 4) == rrmhd.EINVAL
+    assert L.rrmhd3d_destroy(None) == rrmhd.OK
