@@ -151,6 +151,17 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 /* Stream used by the handle; NULL is the null stream. */
 int rrmhd_set_stream(rrmhd *h, void *hip_stream);
 
+/* Graph replay for launch-bound grids: with chunk > 0, rrmhd_step(n) runs
+ * whole runs of `chunk` steps as one captured hipGraph each (captured on
+ * first use, one graph per starting buffer or in-place phase, replayed on
+ * an internal stream that is ordered after the handle's stream with events)
+ * and launches the remaining n mod chunk steps directly.  Results are
+ * bitwise those of plain launches.  Changing the launch shape, the
+ * equilibrium or the closure's on/off state drops the graphs; new closure
+ * parameters do not (the graph reads them at run time).  chunk = 0 (the
+ * default) launches every step directly.  EINVAL for chunk < 0. */
+int rrmhd_set_graph_chunk(rrmhd *h, int chunk);
+
 /* Equilibrium of the fluid populations.  RRMHD_FEQ_ALGORITHM (the default)
  * is the fourth-order Hermite equilibrium the algorithm uses (Eq. feq_4th,
  * task 2 of the algorithm in Sec. II.B), with the Maxwell stress in the

@@ -53,7 +53,19 @@ struct rrmhd {
   void *mlp = nullptr;          // prepared closure parameters (device)
   bool closure_on = false;
   int closure_grid = 0;         // persistent blocks of the closure kernel
+  // graph replay of runs of graph_chunk steps (0: plain launches); one graph
+  // per starting buffer (or in-place phase), on an internal stream ordered
+  // after the caller's stream with events
+  int graph_chunk = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipStream_t own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
+
+static void free_graphs(rrmhd *h) {
+  for (auto &g : h->graph)
+    if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+}
 
 extern "C" {
 
@@ -85,6 +97,10 @@ int rrmhd_destroy(rrmhd *h) {
   if (h->diag_out) (void)hipFree(h->diag_out);
   if (h->diag_host) (void)hipHostFree(h->diag_host);
   if (h->mlp) (void)hipFree(h->mlp);
+  free_graphs(h);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  if (h->own) (void)hipStreamDestroy(h->own);
   delete h;
   return rc;
 }
@@ -183,6 +199,7 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
 
 int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
   if (!h || bx < 1 || by < 1 || bx * by > 256 || ry < 1) return RRMHD_EINVAL;
+  free_graphs(h);
   h->shape.bx = bx;
   h->shape.by = by;
   h->shape.ry = ry;
@@ -200,6 +217,7 @@ int rrmhd_set_stream(rrmhd *h, void *hip_stream) {
 int rrmhd_set_equilibrium(rrmhd *h, int kind) {
   if (!h || (kind != RRMHD_FEQ_ALGORITHM && kind != RRMHD_FEQ_FULL_MAXWELL)) return RRMHD_EINVAL;
   if (kind == RRMHD_FEQ_FULL_MAXWELL && (h->closure_on || h->inplace)) return RRMHD_EINVAL;
+  free_graphs(h);
   h->D.feq = kind;
   return RRMHD_OK;
 }
@@ -215,28 +233,80 @@ int rrmhd_init(rrmhd *h, const double *u, const double *b) {
   return RRMHD_OK;
 }
 
+static int plain_steps(rrmhd *h, int64_t n, hipStream_t st) {
+  for (int64_t k = 0; k < n; ++k) {
+    if (h->inplace) {
+      HIP_OR_RETURN(rr::launch_step_inplace(h->storage, h->D, h->buf[0], h->phase, h->shape, st));
+      h->phase ^= 1;
+    } else if (h->closure_on) {
+      HIP_OR_RETURN(rr::launch_step_closure(h->storage, h->D, (const rr::MlpDev *)h->mlp,
+                                            h->buf[h->cur], h->buf[h->cur ^ 1],
+                                            h->closure_grid, st));
+      h->cur ^= 1;
+    } else {
+      HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur], h->buf[h->cur ^ 1],
+                                    h->shape, st));
+      h->cur ^= 1;
+    }
+    h->steps++;
+  }
+  return RRMHD_OK;
+}
+
 int rrmhd_step(rrmhd *h, int64_t n) {
   if (!h || n < 0) return RRMHD_EINVAL;
   if (!h->ready) return RRMHD_ESTATE;
-  for (int64_t k = 0; k < n; ++k) {
-    if (h->inplace) {
-      HIP_OR_RETURN(rr::launch_step_inplace(h->storage, h->D, h->buf[0], h->phase, h->shape,
-                                            h->stream));
-      h->phase ^= 1;
-      h->steps++;
-      continue;
+  const int64_t chunk = h->graph_chunk;
+  if (chunk <= 0 || n < chunk) return plain_steps(h, n, h->stream);
+  HIP_OR_RETURN(hipEventRecord(h->ev_in, h->stream));
+  HIP_OR_RETURN(hipStreamWaitEvent(h->own, h->ev_in, 0));
+  int64_t left = n;
+  while (left >= chunk) {
+    const int state = h->inplace ? h->phase : h->cur;
+    hipGraphExec_t &g = h->graph[state];
+    if (!g) {
+      hipGraph_t graph = nullptr;
+      const int c0 = h->cur, p0 = h->phase;
+      const int64_t s0 = h->steps;
+      HIP_OR_RETURN(hipStreamBeginCapture(h->own, hipStreamCaptureModeThreadLocal));
+      int rc = plain_steps(h, chunk, h->own);
+      hipError_t ee = hipStreamEndCapture(h->own, &graph);
+      h->cur = c0;  // the capture recorded the launches; nothing ran yet
+      h->phase = p0;
+      h->steps = s0;
+      if (rc != RRMHD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ee != hipSuccess) return dev_err(ee, "hipStreamEndCapture");
+      hipError_t ei = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return dev_err(ei, "hipGraphInstantiate");
     }
-    if (h->closure_on) {
-      HIP_OR_RETURN(rr::launch_step_closure(h->storage, h->D, (const rr::MlpDev *)h->mlp,
-                                            h->buf[h->cur], h->buf[h->cur ^ 1],
-                                            h->closure_grid, h->stream));
-    } else {
-      HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur], h->buf[h->cur ^ 1],
-                                    h->shape, h->stream));
+    HIP_OR_RETURN(hipGraphLaunch(g, h->own));
+    if (chunk & 1) {
+      h->cur ^= h->inplace ? 0 : 1;
+      h->phase ^= h->inplace ? 1 : 0;
     }
-    h->cur ^= 1;
-    h->steps++;
+    h->steps += chunk;
+    left -= chunk;
   }
+  int rc = plain_steps(h, left, h->own);
+  if (rc != RRMHD_OK) return rc;
+  HIP_OR_RETURN(hipEventRecord(h->ev_out, h->own));
+  HIP_OR_RETURN(hipStreamWaitEvent(h->stream, h->ev_out, 0));
+  return RRMHD_OK;
+}
+
+int rrmhd_set_graph_chunk(rrmhd *h, int chunk) {
+  if (!h || chunk < 0) return RRMHD_EINVAL;
+  free_graphs(h);
+  if (chunk > 0 && !h->own) {
+    HIP_OR_RETURN(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+    HIP_OR_RETURN(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    HIP_OR_RETURN(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+  }
+  h->graph_chunk = chunk;
   return RRMHD_OK;
 }
 
@@ -345,6 +415,7 @@ void rr_handle_set_ready(rrmhd *h, int ready) {
 int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm) {
   if (!h) return RRMHD_EINVAL;
   if (!params) {
+    if (h->closure_on) free_graphs(h);
     h->closure_on = false;
     return RRMHD_OK;
   }
@@ -365,6 +436,7 @@ int rrmhd_closure_enable(rrmhd *h, int on) {
   if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f || h->D.feq ||
              h->inplace))
     return RRMHD_EINVAL;
+  if (h->closure_on != (on != 0)) free_graphs(h);
   h->closure_on = on != 0;
   return RRMHD_OK;
 }

@@ -22,7 +22,7 @@ EXPORTED = [
     "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
     "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
-    "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium",
+    "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium", "rrmhd_set_graph_chunk",
     "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
     "rrmhd_batch_create", "rrmhd_batch_init", "rrmhd_batch_step",
@@ -93,6 +93,7 @@ def lib():
         ci = ctypes.c_int
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
         L.rrmhd_set_equilibrium.argtypes = [vp, ci]
+        L.rrmhd_set_graph_chunk.argtypes = [vp, ci]
         L.rrmhd3d_create.argtypes = [ci, ci, ci, ci, ctypes.c_double, ctypes.c_double, vp,
                                      ctypes.POINTER(vp)]
         L.rrmhd3d_init.argtypes = [vp, dp, dp]
@@ -356,6 +357,10 @@ class Solver:
     def closure_enable(self, on=True):
         _check(lib().rrmhd_closure_enable(self._h, int(bool(on))),
                "rrmhd_closure_enable")
+
+    def set_graph_chunk(self, chunk):
+        """Replay runs of `chunk` steps as captured hipGraphs (0: off)."""
+        _check(lib().rrmhd_set_graph_chunk(self._h, int(chunk)), "rrmhd_set_graph_chunk")
 
     def set_equilibrium(self, kind):
         """"algorithm" or "full_maxwell"; applies to later init and steps."""

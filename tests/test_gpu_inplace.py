@@ -231,3 +231,40 @@ def test_inplace_full_size_8192_bitwise(storage):
         s.close()
     for x, y in zip(*out):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_inplace_walls_plain_stores_bitwise(storage):
+    """Walls and forcing with plain (not non-temporal) stores and another
+    tile shape: still the two-buffer state bit for bit."""
+    note(f"in-place walls, plain stores {storage}")
+    nx, ny = 33, 20
+    h = inputs.Hartmann(nx=nx, ny=ny, tau_f=0.7, tau_m=0.65, G=1e-4, Ha=3.0)
+    u, b = inputs.random_modes(nx, ny, 0.03, seed=8)
+    b[1] += h.B0
+    kw = dict(walls=True, force=(h.G, 0.0), b_wall=(0.0, h.B0))
+    two, one = pair(nx, ny, h.tau_f, h.tau_m, storage, **kw)
+    one.set_launch(16, 4, 2, 1, 0)
+    for s in (two, one):
+        s.init(dev(u), dev(b))
+    for k in (3, 8):
+        two.step(k - two.step_count)
+        one.step(k - one.step_count)
+        assert_same(two, one, k)
+    two.close(); one.close()
+
+
+def test_inplace_scaled_f16_codec_bitwise():
+    """FP16 storage with a codec scale S = 4 (the scaled codec): the single
+    buffer still evolves as the two-buffer handle with the same scale."""
+    note("in-place f16 codec scale 4")
+    n = 48
+    u, b = inputs.turbulence(n, 0.04)
+    two, one = pair(n, n, 0.53, 0.56, "f16", codec_scale=4.0)
+    for s in (two, one):
+        s.init(dev(u), dev(b))
+    for k in (5, 12):
+        two.step(k - two.step_count)
+        one.step(k - one.step_count)
+        assert_same(two, one, k)
+    two.close(); one.close()
