@@ -417,6 +417,21 @@ def closure_bench(args):
              for side in ("plain", "closure")}
     ms = {k: sum(t[k] for t in tests) / len(tests)
           for k in ("fine_gpu_ms", "plain_gpu_ms", "closure_gpu_ms")}
+
+    def within_until(rows):
+        # last coarse step up to which every comparison time meets the bar
+        last = 0
+        for r in rows:
+            if r["eps_spec"] <= 0.05 and abs(r["ekin_err"]) <= 0.05 and abs(r["emag_err"]) <= 0.05:
+                last = r["step"]
+            else:
+                break
+        return last
+
+    horizon = {side: {str(t["seed"]): within_until(t[side + "_rows"]) for t in tests}
+               for side in ("plain", "closure")}
+    eps_t = {side: {str(t["seed"]): [round(r["eps_spec"], 4) for r in t[side + "_rows"]]
+                    for t in tests} for side in ("plain", "closure")}
     print(json.dumps({
         "metric": "closure-vs-fine wall time at 5% spectral error",
         "value": round(ms["closure_gpu_ms"] / 1e3, 3), "unit": "s (GPU, coarse+closure run)",
@@ -429,6 +444,11 @@ def closure_bench(args):
         "within_5pct": {side: all(t[side]["within_5pct"] for t in tests)
                         for side in ("plain", "closure")},
         "gpu_s": {k: round(v / 1e3, 3) for k, v in ms.items()},
+        "fine_over_coarse_gpu_time": {"plain": round(ms["fine_gpu_ms"] / ms["plain_gpu_ms"], 1),
+                                      "closure": round(ms["fine_gpu_ms"] / ms["closure_gpu_ms"], 1)},
+        "within_5pct_until_coarse_step": horizon,
+        "comparison_steps": [r["step"] for r in tests[0]["plain_rows"]],
+        "eps_spec_per_time": eps_t,
         "train_s": round(res["train_s"], 2), "data_s": round(res["data_s"], 2),
         "train_loss_first_last": [res["train_loss"][0], res["train_loss"][-1]],
         "onestep_objective": {"train": res["onestep_objective"],
