@@ -302,3 +302,31 @@ def test_alfven_wave():
     ratio = (np.fft.fft(zp)[1] / N) / (2 * A / 2j)
     assert abs(-math.log(abs(ratio)) / T / (nu * k * k) - 1) < 0.01
     assert abs(np.angle(ratio) / (k * B0 * T) - 1) < 0.01
+
+
+def test_turbulence3d_generator():
+    """The seeded 3D turbulence field (inputs, no method arithmetic): u and b
+    are divergence-free, have vector rms 0.04, differ from each other, and
+    their shell spectrum follows k^4 exp(-2 (k/4)^2) on average over shells
+    (modes up to |kappa| = 12)."""
+    from paper_2602_14667_amd import inputs
+    n = 32
+    u, b = inputs.turbulence3d(n, 0.04)
+    k = np.fft.fftfreq(n, 1.0 / n)
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    for f in (u, b):
+        assert abs(math.sqrt(np.mean(np.sum(f * f, axis=0))) - 0.04) < 1e-12
+        fh = [np.fft.fftn(f[a]) for a in range(3)]
+        div = KX * fh[0] + KY * fh[1] + KZ * fh[2]
+        assert np.abs(div).max() < 1e-10 * np.abs(fh[0]).max()
+    assert np.abs(u - b).max() > 0.01
+    # shell spectrum of u against the prescribed shape, shells 2..10
+    e = sum(np.abs(np.fft.fftn(u[a]) / n ** 3) ** 2 for a in range(3))
+    kk = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    shell = np.floor(kk + 0.5).astype(int)
+    E = np.bincount(shell.ravel(), weights=e.ravel())
+    ks = np.arange(2, 11)
+    model = ks ** 4 * np.exp(-2 * (ks / 4.0) ** 2)
+    ratio = E[ks] / model
+    assert ratio.std() / ratio.mean() < 0.35  # random amplitudes, ~4 pi k^2 modes per shell
+    assert E[13:].sum() < 1e-6 * E.sum()      # nothing beyond the cut
