@@ -80,6 +80,29 @@ def cpu_baseline(n_sample=2048, steps=60):
                               "sample": f"{n1}^2, {s1} steps", "seconds": dt1}}
 
 
+def cpu_baseline_c1():
+    """The FP64 oracle on the whole Orszag-Tang 64^2 case (1000 steps), with
+    all host threads and with one."""
+    import oracle
+    from paper_2602_14667_amd import inputs
+    u, b = inputs.orszag_tang(64, 0.05, 0.05, perturb=1e-4, seed=0)
+    cores = oracle.threads()
+    out = {}
+    for label, th in (("all_threads", cores), ("single_thread", 1)):
+        oracle.set_threads(th)
+        o = oracle.Oracle(64, 64, 0.56, 0.56)
+        o.init(u, b)
+        t0 = time.perf_counter()
+        o.step(1000)
+        dt = time.perf_counter() - t0
+        o.close()
+        out[label] = {"seconds": round(dt, 3), "MLUPS": round(64 * 64 * 1000 / dt / 1e6, 3),
+                      "threads": th}
+    oracle.set_threads(cores)
+    out["kind"] = "oracle"
+    return out
+
+
 def copy_reference(torch, rrmhd, args):
     """Plain streaming copy of a known byte count (bandwidth reference and
     calibration of memory-traffic counters)."""
@@ -293,7 +316,9 @@ def ot64_bench(torch, rrmhd, inputs, args):
         "value": out["f32"], "unit": "us/step", "n_gpus": 1, "steps": 1000,
         "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
         "data": "synthetic", "config": {"workload": "Orszag-Tang 64x64, tau 0.56"},
-        "us_per_step": out, "us_per_step_graph_chunk_100": graphed}), flush=True)
+        "us_per_step": out, "us_per_step_graph_chunk_100": graphed,
+        **({} if args.no_cpu_baseline else {"cpu_baseline_c1_1000_steps": cpu_baseline_c1()})}),
+        flush=True)
 
 
 def turbulence3d_bench(torch, rrmhd, inputs, args):
