@@ -36,6 +36,7 @@
 #include <utility>
 
 #include "../../include/rrmhd.h"
+#include "rr_internal.h"
 #include "rr_node.h"
 #include "rr_pull.h"
 
@@ -535,11 +536,10 @@ struct rrmhd3d {
   double *diag_host = nullptr;
 };
 
-static int dev_err3(hipError_t) { return RRMHD_EDEVICE; }
-#define HIP3(x)                                 \
-  do {                                          \
-    hipError_t e_ = (x);                        \
-    if (e_ != hipSuccess) return dev_err3(e_);  \
+#define HIP3(x)                                         \
+  do {                                                  \
+    hipError_t e_ = (x);                                \
+    if (e_ != hipSuccess) return rr_device_error(e_, #x); \
   } while (0)
 
 extern "C" {

@@ -22,6 +22,13 @@ int dev_err(hipError_t e, const char *what) {
   return e == hipErrorOutOfMemory ? RRMHD_ENOMEM : RRMHD_EDEVICE;
 }
 
+}  // namespace
+
+// shared with the three-dimensional handle (rr_3d.hip)
+int rr_device_error(hipError_t e, const char *what) { return dev_err(e, what); }
+
+namespace {
+
 #define HIP_OR_RETURN(expr)                          \
   do {                                               \
     hipError_t e_ = (expr);                          \

@@ -17,6 +17,11 @@ RR_HIDDEN void rr_handle_set_ready(rrmhd *h, int ready);
 RR_HIDDEN int rr_handle_walls(const rrmhd *h);
 // 1 when the handle streams in place in one population buffer
 RR_HIDDEN int rr_handle_inplace(const rrmhd *h);
+}
+// record the HIP message of a device error for rrmhd_last_error_detail and
+// map it to RRMHD_ENOMEM or RRMHD_EDEVICE
+RR_HIDDEN int rr_device_error(hipError_t e, const char *what);
+extern "C" {
 // batch: domain sizes (arrays may be NULL to query n and storage)
 RR_HIDDEN int rr_batch_domains(const rrmhd_batch *b, int *n, int *storage, int *nx,
                                int *ny);
