@@ -327,14 +327,33 @@ def turbulence3d_bench(torch, rrmhd, inputs, args):
     tau 0.52, both storages; roofline against the algorithmic bytes, 48
     planes read and written per node."""
     n = args.n3d
-    u, b = inputs.turbulence3d(n, 0.04)
-    ud, bd = torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda()
-    del u, b
+    if args.ic3d == "abc":
+        # analytic Arnold-Beltrami-Childress fields built on the device (for
+        # boxes whose host-side FFT synthesis would take minutes): u with one
+        # wavelength per side, b with two, each scaled to vector rms 0.04
+        x = torch.arange(n, dtype=torch.float64, device="cuda") * (2 * math.pi / n)
+
+        def abc(m):
+            s1, c1 = torch.sin(m * x), torch.cos(m * x)
+            f = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+            f[0] = s1[:, None, None] + c1[None, :, None]   # sin z + cos y
+            f[1] = s1[None, None, :] + c1[:, None, None]   # sin x + cos z
+            f[2] = s1[None, :, None] + c1[None, None, :]   # sin y + cos x
+            return f * (0.04 / math.sqrt(3.0))
+
+        ud, bd = abc(1), abc(2)
+        workload = f"ABC flow and field on a {n}^3 periodic box, rms 0.04"
+    else:
+        u, b = inputs.turbulence3d(n, 0.04)
+        ud, bd = torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda()
+        del u, b
+        workload = (f"decaying 3D MHD turbulence {n}^3 periodic, random-phase "
+                    "solenoidal u and b, rms 0.04")
     st = torch.cuda.current_stream()
     nodes = n ** 3
     res = {}
     for storage in ("f32", "f16"):
-        s = rrmhd.Solver3D(n, n, n, args.tau, args.tau, storage=storage)
+        s = rrmhd.Solver3D(n, n, n, args.tau, args.tau, storage=storage, inplace=args.inplace)
         s.init(ud, bd)
         s.step(args.warmup)
         torch.cuda.synchronize()
@@ -359,9 +378,10 @@ def turbulence3d_bench(torch, rrmhd, inputs, args):
         "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"decaying 3D MHD turbulence {n}^3 periodic, random-phase "
-                               "solenoidal u and b, rms 0.04", "nodes": nodes,
-                   "tau_f": args.tau, "tau_m": args.tau, "parallelism": "single GPU"},
+        "config": {"workload": workload, "nodes": nodes, "tau_f": args.tau, "tau_m": args.tau,
+                   "population_buffers": 1 if args.inplace else 2,
+                   "state_GB": round(nodes * 48 * 4 * (1 if args.inplace else 2) / 1e9, 1),
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": r["frac"], "traffic": None},
         "storages": res}), flush=True)
@@ -493,6 +513,8 @@ def main():
                     help="untimed steps before timing (default 100; 5 for copy/sweep)")
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--n3d", type=int, default=256, help="box side of --workload turbulence3d")
+    ap.add_argument("--ic3d", choices=["turbulence", "abc"], default="turbulence",
+                    help="initial field of --workload turbulence3d")
     ap.add_argument("--tau", type=float, default=0.52)
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--inplace", action="store_true",

@@ -192,7 +192,10 @@ int rrmhd_destroy(rrmhd *h);
  *  - magnetic D3Q7 vector BGK, weights 1/4 (rest) and 1/8, so
  *    eta = (tau_m - 1/2)/4; g_eq,j = psi_j [b + 4 e_j.(u b - b u)].
  * nu = (tau_f - 1/2)/3.  Storage RRMHD_STORE_F32 or _F16 (f - w and g, S = 1),
- * FP32 arithmetic, two buffers of 48 planes.  Fields are [3][nz][ny][nx]
+ * FP32 arithmetic, two buffers of 48 planes, or one with RRMHD_STORE_INPLACE
+ * OR-ed into storage (the alternating single-buffer steps of the
+ * two-dimensional handle; bitwise the same results; moments and
+ * diagnostics read either layout).  Fields are [3][nz][ny][nx]
  * (component, z, y, x) FP64 device arrays, rho [nz][ny][nx].  Errors as for
  * the two-dimensional handle (EINVAL also for ny or nz above 65535 or
  * nx ny nz * element size >= 2^32).  Diagnostics: E = sum |u|^2 / (2N),

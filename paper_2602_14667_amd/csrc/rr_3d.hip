@@ -324,6 +324,76 @@ __global__ __launch_bounds__(256) void k_step3(Dom3 D, int tiles_x,
                std::make_integer_sequence<int, kPlanes>{});
 }
 
+// ---- single-buffer (in-place) streaming ---------------------------------------
+// Steps alternate between two forms that each write only the locations their
+// own thread has just read: phase 0 pulls as k_step3 does and writes f*_i(x)
+// into the slot just read for the opposite direction, buf[opp(i)][x + c_i];
+// phase 1 reads the node's own swapped slots (buf[opp(i)][x] = f_i(x)) and
+// stores locally, which restores the pull layout.  Slot (p, x) is read and
+// written only by node x + c_p, for any box.
+__host__ __device__ constexpr int opp_plane(int P) {
+  if (P < kQ) return kQ - 1 - P;
+  const int j = (P - kQ) / 3, a = (P - kQ) % 3;
+  const int oj = j == 0 ? 0 : ((j & 1) ? j + 1 : j - 1);
+  return kQ + 3 * oj + a;
+}
+
+template <class C, int P>
+__device__ __forceinline__ void st_push(typename C::T *buf, const Dom3 &D, const Src3 &S,
+                                        const float *v) {
+  int a, b, c;
+  if constexpr (P < kQ) {
+    a = cx(P);
+    b = cy(P);
+    c = cz(P);
+  } else {
+    constexpr int j = (P - kQ) / 3;
+    a = ecomp(j, 0);
+    b = ecomp(j, 1);
+    c = ecomp(j, 2);
+  }
+  // the source entry of -c is the node x + c
+  const uint32_t off = S.slab[1 - c] + S.row[1 - b] + S.col[1 - a];
+  rr::st_at<typename C::T, true>(buf + (int64_t)opp_plane(P) * D.plane, off, C::enc(v[P], 1.0f));
+}
+template <class C, int... P>
+__device__ __forceinline__ void push_all(typename C::T *buf, const Dom3 &D, const Src3 &S,
+                                         const float *v, std::integer_sequence<int, P...>) {
+  (st_push<C, P>(buf, D, S, v), ...);
+}
+
+template <class C, int... P>
+__device__ __forceinline__ void load_own(const typename C::T *buf, const Dom3 &D, uint32_t o,
+                                         float *v, std::integer_sequence<int, P...>) {
+  ((v[P] = C::dec(rr::ld_at<typename C::T, false>(buf + (int64_t)opp_plane(P) * D.plane, o),
+                  1.0f)),
+   ...);
+}
+
+template <class C, int PHASE>
+__global__ __launch_bounds__(256) void k_step3_inplace(Dom3 D, int tiles_x, typename C::T *buf) {
+  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int x = tx * blockDim.x + threadIdx.x;
+  const int y = ty * blockDim.y + threadIdx.y;
+  const int z = blockIdx.y;
+  if (x >= D.nx || y >= D.ny) return;
+  constexpr uint32_t E = sizeof(typename C::T);
+  const Src3 S = sources(D, x, y, z, E);
+  const uint32_t own = S.slab[1] + S.row[1] + S.col[1];
+  float v[kPlanes];
+  if constexpr (PHASE == 0)
+    load_all<C>(buf, D, S, v, std::make_integer_sequence<int, kPlanes>{});
+  else
+    load_own<C>(buf, D, own, v, std::make_integer_sequence<int, kPlanes>{});
+  float(&d)[kQ] = *reinterpret_cast<float(*)[kQ]>(v);
+  float(&g)[3 * kQm] = *reinterpret_cast<float(*)[3 * kQm]>(v + kQ);
+  collide3(d, g, D.om_c, D.omm_c);
+  if constexpr (PHASE == 0)
+    push_all<C>(buf, D, S, v, std::make_integer_sequence<int, kPlanes>{});
+  else
+    store_all<C>(buf, D, own, v, std::make_integer_sequence<int, kPlanes>{});
+}
+
 // ---- initialisation at equilibrium (FP64), pull layout ----------------------
 __device__ double feq3_d(int i, const double u[3], const double b[3]) {
   const int c[3] = {cx(i), cy(i), cz(i)};
@@ -378,13 +448,17 @@ struct Mom3 {
   double rho, j[3], u[3], b[3];
 };
 
-template <class C>
+template <class C, bool SW>
 __device__ Mom3 moments3(const Dom3 &D, const typename C::T *__restrict__ s, int x, int y,
                          int z) {
   constexpr uint32_t E = sizeof(typename C::T);
   const Src3 S = sources(D, x, y, z, E);
   float v[kPlanes];
-  load_all<C>(s, D, S, v, std::make_integer_sequence<int, kPlanes>{});
+  if constexpr (SW)
+    load_own<C>(s, D, S.slab[1] + S.row[1] + S.col[1], v,
+                std::make_integer_sequence<int, kPlanes>{});
+  else
+    load_all<C>(s, D, S, v, std::make_integer_sequence<int, kPlanes>{});
   Mom3 m;
   double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -405,12 +479,12 @@ __device__ Mom3 moments3(const Dom3 &D, const typename C::T *__restrict__ s, int
   return m;
 }
 
-template <class C>
+template <class C, bool SW>
 __global__ void k_moments3(Dom3 D, const typename C::T *__restrict__ src, double *rho, double *u,
                            double *b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= D.nx) return;
-  const Mom3 m = moments3<C>(D, src, x, y, z);
+  const Mom3 m = moments3<C, SW>(D, src, x, y, z);
   const int64_t N = (int64_t)D.nx * D.ny * D.nz;
   const int64_t o = ((int64_t)z * D.ny + y) * D.nx + x;
   if (rho) rho[o] = m.rho;
@@ -447,7 +521,7 @@ __device__ double block_red(double v, double *lds) {
   return r;
 }
 
-template <class C>
+template <class C, bool SW>
 __global__ __launch_bounds__(kDB) void k_diag3_sums(Dom3 D, const typename C::T *__restrict__ src,
                                                     double *__restrict__ bpl,
                                                     double *__restrict__ part) {
@@ -457,7 +531,7 @@ __global__ __launch_bounds__(kDB) void k_diag3_sums(Dom3 D, const typename C::T 
   for (int64_t n = (int64_t)blockIdx.x * kDB + threadIdx.x; n < N; n += (int64_t)gridDim.x * kDB) {
     const int x = (int)(n % D.nx), y = (int)((n / D.nx) % D.ny),
               z = (int)(n / ((int64_t)D.nx * D.ny));
-    const Mom3 m = moments3<C>(D, src, x, y, z);
+    const Mom3 m = moments3<C, SW>(D, src, x, y, z);
     acc[0] += m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
     acc[1] += m.b[0] * m.b[0] + m.b[1] * m.b[1] + m.b[2] * m.b[2];
     acc[2] += m.rho;
@@ -530,6 +604,8 @@ struct rrmhd3d {
   int cur = 0;
   int64_t steps = 0;
   bool ready = false;
+  bool inplace = false;  // one buffer, alternating phases
+  int phase = 0;         // in-place: 0 pull layout, 1 swapped layout
   int bx = 64, by = 4;
   double *diag_work = nullptr;
   double *diag_out = nullptr;
@@ -541,6 +617,36 @@ struct rrmhd3d {
     hipError_t e_ = (x);                                \
     if (e_ != hipSuccess) return rr_device_error(e_, #x); \
   } while (0)
+
+template <class C>
+static void launch_inplace3(rrmhd3d *h, dim3 grid, dim3 block, int tiles_x) {
+  auto b = (typename C::T *)h->buf[0];
+  if (h->phase == 0)
+    hipLaunchKernelGGL((rr3::k_step3_inplace<C, 0>), grid, block, 0, h->stream, h->D, tiles_x, b);
+  else
+    hipLaunchKernelGGL((rr3::k_step3_inplace<C, 1>), grid, block, 0, h->stream, h->D, tiles_x, b);
+}
+
+template <class C>
+static void launch_moments3(rrmhd3d *h, bool sw, dim3 grid, dim3 block, double *rho, double *u,
+                            double *b) {
+  auto s = (const typename C::T *)h->buf[h->cur];
+  if (sw)
+    hipLaunchKernelGGL((rr3::k_moments3<C, true>), grid, block, 0, h->stream, h->D, s, rho, u, b);
+  else
+    hipLaunchKernelGGL((rr3::k_moments3<C, false>), grid, block, 0, h->stream, h->D, s, rho, u, b);
+}
+
+template <class C>
+static void launch_diag3(rrmhd3d *h, bool sw, int nb, double *bpl, double *ps) {
+  auto s = (const typename C::T *)h->buf[h->cur];
+  if (sw)
+    hipLaunchKernelGGL((rr3::k_diag3_sums<C, true>), dim3(nb), dim3(rr3::kDB), 0, h->stream, h->D,
+                       s, bpl, ps);
+  else
+    hipLaunchKernelGGL((rr3::k_diag3_sums<C, false>), dim3(nb), dim3(rr3::kDB), 0, h->stream, h->D,
+                       s, bpl, ps);
+}
 
 extern "C" {
 
@@ -563,15 +669,18 @@ int rrmhd3d_create(int32_t nx, int32_t ny, int32_t nz, int32_t storage, double t
   *out = nullptr;
   if (nx < 1 || ny < 1 || nz < 1) return RRMHD_EINVAL;
   if (ny > 65535 || nz > 65535) return RRMHD_EINVAL;  // grid dimensions of the launches
-  if (storage != RRMHD_STORE_F32 && storage != RRMHD_STORE_F16) return RRMHD_EINVAL;
+  const int kind = storage & 0xff, flags = storage & ~0xff;
+  if (kind != RRMHD_STORE_F32 && kind != RRMHD_STORE_F16) return RRMHD_EINVAL;
+  if (flags != 0 && flags != RRMHD_STORE_INPLACE) return RRMHD_EINVAL;
   if (!(std::isfinite(tau_f) && std::isfinite(tau_m)) || tau_f <= 0.5 || tau_m <= 0.5)
     return RRMHD_EINVAL;
-  const int64_t elem = storage == RRMHD_STORE_F16 ? 2 : 4;
+  const int64_t elem = kind == RRMHD_STORE_F16 ? 2 : 4;
   const int64_t N = (int64_t)nx * ny * nz;
   if (N * elem >= ((int64_t)1 << 32)) return RRMHD_EINVAL;  // 32-bit in-plane byte offsets
   rrmhd3d *h = new (std::nothrow) rrmhd3d();
   if (!h) return RRMHD_ENOMEM;
-  h->storage = storage;
+  h->storage = kind;
+  h->inplace = flags == RRMHD_STORE_INPLACE;
   h->elem = elem;
   h->stream = (hipStream_t)hip_stream;
   h->D.nx = nx;
@@ -585,9 +694,15 @@ int rrmhd3d_create(int32_t nx, int32_t ny, int32_t nz, int32_t storage, double t
   // it (FP16 +6 % over 64 x 4); narrow boxes stack rows to fill 128 threads
   h->bx = nx >= 128 ? 128 : ((nx + 15) / 16) * 16;
   h->by = 128 / h->bx;
+  if (h->inplace && nx >= 256) {
+    // the alternating single-buffer steps: one row of 256 threads measured
+    // best at 256^3 (FP32 61 %, FP16 64 % of 8 TB/s against 56 %, 60 % at 128)
+    h->bx = 256;
+    h->by = 1;
+  }
   const size_t bytes = (size_t)h->D.plane * rr3::kPlanes * elem;
   int rc = RRMHD_OK;
-  for (int k = 0; k < 2 && rc == RRMHD_OK; ++k)
+  for (int k = 0; k < (h->inplace ? 1 : 2) && rc == RRMHD_OK; ++k)
     if (hipMalloc(&h->buf[k], bytes) != hipSuccess) rc = RRMHD_ENOMEM;
   if (rc == RRMHD_OK && hipMalloc((void **)&h->diag_out, 10 * sizeof(double)) != hipSuccess)
     rc = RRMHD_ENOMEM;
@@ -620,6 +735,7 @@ int rrmhd3d_init(rrmhd3d *h, const double *u, const double *b) {
                        (float *)h->buf[0]);
   HIP3(hipGetLastError());
   h->cur = 0;
+  h->phase = 0;
   h->steps = 0;
   h->ready = true;
   return RRMHD_OK;
@@ -630,6 +746,16 @@ int rrmhd3d_step(rrmhd3d *h, int64_t n) {
   if (!h->ready) return RRMHD_ESTATE;
   const int tiles_x = (h->D.nx + h->bx - 1) / h->bx, tiles_y = (h->D.ny + h->by - 1) / h->by;
   const dim3 grid(tiles_x * tiles_y, h->D.nz), block(h->bx, h->by);
+  for (int64_t k = 0; k < n && h->inplace; ++k) {
+    if (h->storage == RRMHD_STORE_F16)
+      launch_inplace3<rr3::CodecF16U>(h, grid, block, tiles_x);
+    else
+      launch_inplace3<rr3::CodecF32>(h, grid, block, tiles_x);
+    HIP3(hipGetLastError());
+    h->phase ^= 1;
+    h->steps++;
+  }
+  if (h->inplace) return RRMHD_OK;
   for (int64_t k = 0; k < n; ++k) {
     const void *s = h->buf[h->cur];
     void *d = h->buf[h->cur ^ 1];
@@ -657,12 +783,11 @@ int rrmhd3d_moments(rrmhd3d *h, double *rho, double *u, double *b) {
   if (!h->ready) return RRMHD_ESTATE;
   if (!rho && !u && !b) return RRMHD_OK;
   const dim3 block(64), grid((h->D.nx + 63) / 64, h->D.ny, h->D.nz);
+  const bool sw = h->inplace && h->phase;
   if (h->storage == RRMHD_STORE_F16)
-    hipLaunchKernelGGL(rr3::k_moments3<rr3::CodecF16U>, grid, block, 0, h->stream, h->D,
-                       (const uint16_t *)h->buf[h->cur], rho, u, b);
+    launch_moments3<rr3::CodecF16U>(h, sw, grid, block, rho, u, b);
   else
-    hipLaunchKernelGGL(rr3::k_moments3<rr3::CodecF32>, grid, block, 0, h->stream, h->D,
-                       (const float *)h->buf[h->cur], rho, u, b);
+    launch_moments3<rr3::CodecF32>(h, sw, grid, block, rho, u, b);
   HIP3(hipGetLastError());
   return RRMHD_OK;
 }
@@ -675,12 +800,11 @@ static int run_diag3(rrmhd3d *h) {
   double *bpl = h->diag_work, *ps = bpl + 3 * N, *pm = ps + rr3::kDG * rr3::kS3;
   const int64_t need = (N + rr3::kDB - 1) / rr3::kDB;
   const int nb = (int)(need < rr3::kDG ? need : rr3::kDG);
+  const bool sw = h->inplace && h->phase;
   if (h->storage == RRMHD_STORE_F16)
-    hipLaunchKernelGGL(rr3::k_diag3_sums<rr3::CodecF16U>, dim3(nb), dim3(rr3::kDB), 0, h->stream,
-                       h->D, (const uint16_t *)h->buf[h->cur], bpl, ps);
+    launch_diag3<rr3::CodecF16U>(h, sw, nb, bpl, ps);
   else
-    hipLaunchKernelGGL(rr3::k_diag3_sums<rr3::CodecF32>, dim3(nb), dim3(rr3::kDB), 0, h->stream,
-                       h->D, (const float *)h->buf[h->cur], bpl, ps);
+    launch_diag3<rr3::CodecF32>(h, sw, nb, bpl, ps);
   hipLaunchKernelGGL(rr3::k_diag3_divb, dim3(nb), dim3(rr3::kDB), 0, h->stream, h->D, bpl, pm);
   hipLaunchKernelGGL(rr3::k_diag3_final, dim3(1), dim3(rr3::kDB), 0, h->stream, ps, pm, nb,
                      1.0 / (2.0 * (double)N), h->diag_out);

@@ -378,13 +378,14 @@ class Solver3D:
     fluid, D3Q7 magnetic lattice) on the current device.  Fields are FP64
     device tensors [3][nz][ny][nx]."""
 
-    def __init__(self, nx, ny, nz, tau_f, tau_m, storage="f32", stream=None):
+    def __init__(self, nx, ny, nz, tau_f, tau_m, storage="f32", stream=None, inplace=False):
         L = lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self._stream = stream
         h = ctypes.c_void_p()
+        kind = STORE_F16 if storage == "f16" else STORE_F32
         _check(L.rrmhd3d_create(self.nx, self.ny, self.nz,
-                                STORE_F16 if storage == "f16" else STORE_F32,
+                                kind | (STORE_INPLACE if inplace else 0),
                                 float(tau_f), float(tau_m), _stream_handle(stream),
                                 ctypes.byref(h)), "rrmhd3d_create")
         self._h = h

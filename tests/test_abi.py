@@ -105,7 +105,8 @@ def test_create_rejects_unknown_storage_flags():
 
 @pytest.mark.parametrize("args", [
     (0, 4, 4, 0), (4, 4, 0, 0), (4, 70000, 2, 0), (4, 2, 70000, 0), (4, 4, 4, 2),
-    (4, 4, 4, 0x100), (2048, 2048, 256, 0),  # 2^30 nodes x 4 B does not fit 32-bit offsets
+    (4, 4, 4, 0x200), (4, 4, 4, 0x102), (2048, 2048, 256, 0x100),
+    (2048, 2048, 256, 0),  # 2^30 nodes x 4 B does not fit 32-bit offsets
 ])
 def test_create3d_rejects_bad_arguments_before_touching_the_device(args):
     L = rrmhd.lib()

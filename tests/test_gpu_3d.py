@@ -191,3 +191,43 @@ def test_3d_full_size_sampled(storage):
     err = np.max(np.abs(got - ref) / scale, axis=0)
     note(f"  max |err| / field scale: {err}")
     assert np.all(err < (1e-6 if storage == "f32" else 3e-3)), err
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("shape", [(7, 5, 3), (1, 1, 9), (2, 2, 2), (1, 1, 1), (37, 11, 5)])
+def test_3d_inplace_bitwise(storage, shape):
+    """One buffer, alternating step forms: the moments and diagnostics equal
+    the two-buffer handle's bit for bit at odd and even step counts."""
+    note(f"3D in-place {shape} {storage}")
+    R = rrmhd()
+    u, b = inputs.random_modes3d(*shape, 0.04, seed=sum(shape) + 3)
+    two = R.Solver3D(*shape, 0.55, 0.6, storage=storage)
+    one = R.Solver3D(*shape, 0.55, 0.6, storage=storage, inplace=True)
+    for s in (two, one):
+        s.init(dev(u), dev(b))
+    for k in (1, 2, 5, 6):
+        two.step(k - two.step_count)
+        one.step(k - one.step_count)
+        ga, gb = gpu_fields(two), gpu_fields(one)
+        for f in FIELDS:
+            assert np.array_equal(ga[f], gb[f]), (k, f)
+        assert two.diagnostics() == one.diagnostics()
+    two.close(); one.close()
+
+
+def test_3d_inplace_holds_one_buffer():
+    R = rrmhd()
+    n = 192
+    torch.cuda.synchronize()
+    taken = []
+    for inplace in (False, True):
+        free0 = torch.cuda.mem_get_info()[0]
+        s = R.Solver3D(n, n, n, 0.55, 0.6, inplace=inplace)
+        torch.cuda.synchronize()
+        taken.append(free0 - torch.cuda.mem_get_info()[0])
+        s.close()
+        torch.cuda.synchronize()
+    state = n ** 3 * 48 * 4
+    note(f"  device bytes: two buffers {taken[0]}, one buffer {taken[1]} (state {state})")
+    assert abs(taken[0] - 2 * state) < 0.02 * state
+    assert abs(taken[1] - state) < 0.02 * state
