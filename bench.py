@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_NODE = {"f32": 152, "f16": 76}
+BYTES_PER_NODE = {"f32": 152, "f16": 76, "f16sr": 76}
 def kernel_hash():
     from paper_2602_14667_amd import kernel_hash as kh
     return kh()
@@ -237,7 +237,13 @@ def hartmann_bench(torch, rrmhd, inputs, args):
     tau_f 0.6, tau_m 0.55) from rest, FP32 and FP16 storage: steps and GPU
     time until the u_x and b_x profiles are within rel L2 1e-3 of the
     analytic steady state (checked every 10^4 steps, at most 1.2e7 steps),
-    or until the stored state stops changing (a rounding fixed point)."""
+    or until the stored state stops changing (a rounding fixed point).
+    Stochastically rounded FP16 never stops changing: it runs a fixed 10^6
+    steps and reports the error band of the x-averaged profile over the
+    second half, on an 8-wide channel: its noise breaks the x-invariance
+    that the deterministic storages keep exactly, and the 512-wide channel
+    has a long-wavelength mode in x that grows from any such perturbation
+    (FP32 storage included), while every mode of the narrow one decays."""
     import numpy as np
     h = inputs.hartmann_c2()
     u, b = h.initial_fields()
@@ -245,14 +251,17 @@ def hartmann_bench(torch, rrmhd, inputs, args):
     ue, be = h.profile(np.arange(h.ny))
     st = torch.cuda.current_stream()
     out = {}
-    for storage in ("f32", "f16"):
-        s = rrmhd.Solver(h.nx, h.ny, h.tau_f, h.tau_m, storage=storage, walls=True,
+    for storage in ("f32", "f16", "f16sr"):
+        nx = 8 if storage == "f16sr" else h.nx
+        s = rrmhd.Solver(nx, h.ny, h.tau_f, h.tau_m, storage=storage, walls=True,
                          force=(h.G, 0.0), b_wall=(0.0, h.B0))
-        s.init(ud, bd)
+        s.init(ud[:, :, :nx].contiguous(), bd[:, :, :nx].contiguous())
         prev = None
         gpu_ms = 0.0
         status = "cap"
-        while s.step_count < 12_000_000:
+        cap = 1_000_000 if storage == "f16sr" else 12_000_000
+        hist = []
+        while s.step_count < cap:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(st)
@@ -261,9 +270,12 @@ def hartmann_bench(torch, rrmhd, inputs, args):
             _, uu, bb = s.moments()
             torch.cuda.synchronize()
             gpu_ms += e0.elapsed_time(e1)
-            gu, gb = uu[0, :, 0].cpu().numpy(), bb[0, :, 0].cpu().numpy()
+            gu, gb = uu[0].mean(1).cpu().numpy(), bb[0].mean(1).cpu().numpy()
             eu = np.linalg.norm(gu - ue) / np.linalg.norm(ue)
             eb = np.linalg.norm(gb - be) / np.linalg.norm(be)
+            hist.append((s.step_count, float(eu), float(eb)))
+            if storage == "f16sr":
+                continue
             if eu <= 1e-3 and eb <= 1e-3:
                 status = "converged"
                 break
@@ -278,6 +290,16 @@ def hartmann_bench(torch, rrmhd, inputs, args):
                         "gpu_s": round(gpu_ms / 1e3, 2),
                         "us_per_step": round(1e3 * gpu_ms / s.step_count, 3),
                         "rel_l2_u": float(eu), "rel_l2_bx": float(eb)}
+        if storage == "f16sr":
+            late = [r for r in hist if r[0] > cap // 2]
+            out[storage]["status"] = "fixed step budget"
+            out[storage]["grid"] = f"{nx}x{h.ny}"
+            out[storage]["second_half_rel_l2_u"] = [min(r[1] for r in late),
+                                                    max(r[1] for r in late)]
+            out[storage]["second_half_rel_l2_bx"] = [min(r[2] for r in late),
+                                                     max(r[2] for r in late)]
+            out[storage]["first_step_u_below_1e-2"] = next(
+                (r[0] for r in hist if r[1] < 1e-2), None)
         s.close()
     print(json.dumps({
         "metric": "GPU time to steady state (Hartmann channel)",
@@ -286,7 +308,7 @@ def hartmann_bench(torch, rrmhd, inputs, args):
         "data": "synthetic",
         "config": {"workload": "Hartmann channel 512x256, walls in y, G=1e-6, Ha=10, "
                                "tau_f=0.6, tau_m=0.55, from rest",
-                   "criterion": "rel L2 of u_x and b_x vs the analytic profile <= 1e-3"},
+                   "criterion": "rel L2 of the x-averaged u_x and b_x vs the analytic profile <= 1e-3"},
         "storage": out}), flush=True)
 
 
@@ -516,7 +538,8 @@ def main():
     ap.add_argument("--ic3d", choices=["turbulence", "abc"], default="turbulence",
                     help="initial field of --workload turbulence3d")
     ap.add_argument("--tau", type=float, default=0.52)
-    ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--storage", choices=["f32", "f16", "f16sr"], default="f32",
+                    help="f16sr: FP16 with stochastically rounded step stores (variant)")
     ap.add_argument("--inplace", action="store_true",
                     help="single-buffer streaming (one population buffer)")
     ap.add_argument("--equilibrium", choices=["algorithm", "full_maxwell"],

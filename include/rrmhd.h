@@ -55,6 +55,18 @@ enum {
  * with the learned closure or the equilibrium ablation (EINVAL); of the
  * launch shape's nt bits only bit 0 (non-temporal stores) applies. */
 enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
+/* RRMHD_STORE_F16_SR: FP16 storage whose step stores round stochastically
+ * (each value goes to one of its two FP16 neighbours, away from zero with
+ * probability equal to its distance from the neighbour toward zero in units
+ * of the gap, exactly for magnitudes >= 2^-32; smaller ones store zero, and
+ * results beyond the FP16 range, NaN included, store infinity),
+ * with random bits from a counter-based hash of the step count, the node
+ * and the plane, so runs are reproducible and independent of the launch
+ * shape.  An optional variant of the prescribed round-to-nearest-even
+ * codec, reported separately; initialisation still rounds to nearest.  Not
+ * with RRMHD_STORE_INPLACE, graph replay, the learned closure or the
+ * equilibrium ablation (EINVAL); the two-node FP16 update is not used. */
+enum { RRMHD_STORE_F16_SR = 2 };
 
 /* Boundary kinds.  PERIODIC: doubly periodic.  WALLS_Y: periodic in x,
  * walls half-way at y = -1/2 and y = ny - 1/2 (half-way bounce-back for f,

@@ -12,6 +12,7 @@
 #include "rr_closure.h"
 #include "rr_internal.h"
 #include "rr_kernels.h"
+#include "rr_node.h"
 
 namespace {
 
@@ -119,8 +120,10 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   if (!grid) return RRMHD_EINVAL;
   if (grid->nx < 1 || grid->ny < 1) return RRMHD_EINVAL;
   const int kind = grid->storage & 0xff, flags = grid->storage & ~0xff;
-  if (kind != RRMHD_STORE_F32 && kind != RRMHD_STORE_F16) return RRMHD_EINVAL;
+  if (kind != RRMHD_STORE_F32 && kind != RRMHD_STORE_F16 && kind != RRMHD_STORE_F16_SR)
+    return RRMHD_EINVAL;
   if (flags != 0 && flags != RRMHD_STORE_INPLACE) return RRMHD_EINVAL;
+  if (kind == RRMHD_STORE_F16_SR && flags) return RRMHD_EINVAL;
   if (!(std::isfinite(tau_f) && std::isfinite(tau_m)) || tau_f <= 0.5 || tau_m <= 0.5)
     return RRMHD_EINVAL;
   rrmhd_bc b{};
@@ -139,9 +142,10 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
 
   rrmhd *h = new (std::nothrow) rrmhd();
   if (!h) return RRMHD_ENOMEM;
-  h->storage = kind;
+  // the stochastic-rounding variant is FP16 storage for every read path
+  h->storage = kind == RRMHD_STORE_F16_SR ? RRMHD_STORE_F16 : kind;
   h->inplace = flags == RRMHD_STORE_INPLACE;
-  h->elem = kind == RRMHD_STORE_F16 ? 2 : 4;
+  h->elem = kind == RRMHD_STORE_F32 ? 4 : 2;
   h->tau_f = tau_f;
   h->tau_m = tau_m;
   h->bc = b;
@@ -168,7 +172,8 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   D.Gy = (float)b.force[1];
   D.bw2x = (float)(b.b_wall[0] / 3.0);
   D.bw2y = (float)(b.b_wall[1] / 3.0);
-  D.s = kind == RRMHD_STORE_F16 ? S : 1.0f;
+  D.s = kind != RRMHD_STORE_F32 ? S : 1.0f;
+  D.sr = kind == RRMHD_STORE_F16_SR;
   D.inv_s = 1.0f / D.s;
   D.elem = (int)h->elem;
   h->shape = rr::default_shape(D);
@@ -223,7 +228,8 @@ int rrmhd_set_stream(rrmhd *h, void *hip_stream) {
 
 int rrmhd_set_equilibrium(rrmhd *h, int kind) {
   if (!h || (kind != RRMHD_FEQ_ALGORITHM && kind != RRMHD_FEQ_FULL_MAXWELL)) return RRMHD_EINVAL;
-  if (kind == RRMHD_FEQ_FULL_MAXWELL && (h->closure_on || h->inplace)) return RRMHD_EINVAL;
+  if (kind == RRMHD_FEQ_FULL_MAXWELL && (h->closure_on || h->inplace || h->D.sr))
+    return RRMHD_EINVAL;
   free_graphs(h);
   h->D.feq = kind;
   return RRMHD_OK;
@@ -242,6 +248,8 @@ int rrmhd_init(rrmhd *h, const double *u, const double *b) {
 
 static int plain_steps(rrmhd *h, int64_t n, hipStream_t st) {
   for (int64_t k = 0; k < n; ++k) {
+    // random bits of the stochastic-rounding codec: keyed by the step count
+    h->D.sr_key = rr::mix32((uint32_t)h->steps * 0x27d4eb2fu + 0x165667b1u);
     if (h->inplace) {
       HIP_OR_RETURN(rr::launch_step_inplace(h->storage, h->D, h->buf[0], h->phase, h->shape, st));
       h->phase ^= 1;
@@ -307,6 +315,7 @@ int rrmhd_step(rrmhd *h, int64_t n) {
 
 int rrmhd_set_graph_chunk(rrmhd *h, int chunk) {
   if (!h || chunk < 0) return RRMHD_EINVAL;
+  if (chunk > 0 && h->D.sr) return RRMHD_EINVAL;  // a graph would freeze the step key
   free_graphs(h);
   if (chunk > 0 && !h->own) {
     HIP_OR_RETURN(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
@@ -441,7 +450,7 @@ int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm) {
 int rrmhd_closure_enable(rrmhd *h, int on) {
   if (!h) return RRMHD_EINVAL;
   if (on && (!h->mlp || h->D.walls || h->D.Gx != 0.0f || h->D.Gy != 0.0f || h->D.feq ||
-             h->inplace))
+             h->inplace || h->D.sr))
     return RRMHD_EINVAL;
   if (h->closure_on != (on != 0)) free_graphs(h);
   h->closure_on = on != 0;

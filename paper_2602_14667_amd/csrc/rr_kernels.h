@@ -20,6 +20,8 @@ struct Domain {
   int elem;          // bytes per stored value (4 or 2)
   int feq;           // 0: the algorithm's equilibrium; 1: with the u.M
                      // cross terms of the third and fourth orders (ablation)
+  int sr = 0;             // FP16 storage written with stochastic rounding
+  uint32_t sr_key = 0;    // its per-step key (set before each step)
 };
 
 struct LaunchShape {

@@ -161,13 +161,21 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
       pull_node<C, true>(D, src, x, y, d, g);
       collide<FORCED, NoCorrection, FULLM>(d, g, P);
       const int o = y * D.nx + x;
+      uint32_t seed = 0;
+      if constexpr (codec_sr<C>::value)
+        seed = sr_seed(D.sr_key, (uint32_t)o * (uint32_t)sizeof(typename C::T));
+      auto enc = [&](float v, int p) {
+        if constexpr (codec_sr<C>::value)
+          return C::enc_sr(v, D.s, sr_plane(seed, p));
+        else
+          return C::enc(v, D.s);
+      };
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) dst[(int64_t)i * D.plane + o] = C::enc(d[i], D.s);
+      for (int i = 0; i < kQ; ++i) dst[(int64_t)i * D.plane + o] = enc(d[i], i);
 #pragma unroll
-      for (int k = 0; k < 2 * kQm; ++k)
-        dst[(int64_t)(kQ + k) * D.plane + o] = C::enc(g[k], D.s);
+      for (int k = 0; k < 2 * kQm; ++k) dst[(int64_t)(kQ + k) * D.plane + o] = enc(g[k], kQ + k);
     } else {
-      const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+      const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key};
       update_periodic<C, FORCED, NT, NTL, FULLM>(G, src, dst, x, y, P);
     }
   }
@@ -747,7 +755,7 @@ static hipError_t step_t(const Domain &D, const void *src, void *dst,
     step_fullm<C>(D, src, dst, L, st);
     return hipGetLastError();
   }
-  if constexpr (sizeof(typename C::T) == 2) {
+  if constexpr (sizeof(typename C::T) == 2 && !codec_sr<C>::value) {
     if ((L.nt & 4) && !D.walls && D.nx % 2 == 0) {
       if (nts && ntl)
         step_pair_nt<C, true, true>(D, src, dst, L, st);
@@ -777,6 +785,7 @@ hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
   // byte offsets inside one plane are 32-bit
   if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
     return hipErrorInvalidValue;
+  if (storage == kF16 && D.sr) return step_t<CodecF16SR>(D, src, dst, L, st);
   if (storage == kF16)  // S = 1 (the default) needs no scaling of the stored values
     return D.s == 1.0f ? step_t<CodecF16U>(D, src, dst, L, st) : step_t<CodecF16>(D, src, dst, L, st);
   return step_t<CodecF32>(D, src, dst, L, st);

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rr {
 
 // ---- Sec. II.A lattices -------------------------------------------------
@@ -99,6 +101,74 @@ struct CodecF16U {
     return __half_as_ushort(__float2half_rn(v));
   }
 };
+
+// FP16 storage with stochastic rounding (an optional variant of the codec):
+// a value is rounded to one of its two FP16 neighbours, away from zero with
+// probability equal to its distance from the one toward zero in units of the
+// gap, so the stored value is unbiased.  The random bits come from the caller
+// (a counter-based hash of step, node and plane).  Decoding and the plain
+// encode (used at initialisation) are those of CodecF16.
+//
+// The rounding is done on the FP32 bit pattern, where magnitudes are ordered
+// as integers.  With e the biased FP32 exponent and m the significand with
+// its leading one, the FP16 grid below |x| has spacing 2^(e-150+d) where
+// d = max(126 - e, 13) bits of m are dropped (13 in FP16's normal range,
+// more below 2^-14 where the grid is 2^-24).  Adding d random bits before the
+// shift carries into the kept part with probability (dropped bits) / 2^d,
+// the exact probability.  The kept integer k is the FP16 pattern less the
+// exponent field ((e - 113) << 10 for normal values, nothing for subnormals:
+// 1024 <= k <= 2048 in the normal range, and k = 1024 is the smallest normal
+// 2^-14 where a subnormal rounds up).  d is clamped at 31: magnitudes below
+// 2^-32 give zero.  Results past the largest finite value, and NaN, saturate
+// to infinity.
+struct CodecF16SR {
+  using T = uint16_t;
+  static constexpr bool kSR = true;
+  __device__ __forceinline__ static float dec(T v, float inv_s) {
+    return __half2float(__ushort_as_half(v)) * inv_s;
+  }
+  __device__ __forceinline__ static T enc(float v, float s) {
+    return __half_as_ushort(__float2half_rn(v * s));
+  }
+  __device__ __forceinline__ static T enc_sr(float v, float s, uint32_t r) {
+    const uint32_t b = __float_as_uint(v * s);
+    const uint32_t a = b & 0x7fffffffu;
+    const int e = (int)(a >> 23);
+    const uint32_t d = (uint32_t)min(max(126 - e, 13), 31);
+    const uint32_t m = e > 94 ? ((a & 0x7fffffu) | 0x800000u) : 0u;
+    const uint32_t k = (m + (r & ((1u << d) - 1u))) >> d;
+    const uint32_t h = min(((uint32_t)(max(e, 113) - 113) << 10) + k, 0x7c00u);
+    return (T)(((b >> 16) & 0x8000u) | h);
+  }
+};
+
+// Whether a codec rounds stochastically.
+template <class C, class = void>
+struct codec_sr : std::false_type {};
+template <class C>
+struct codec_sr<C, std::void_t<decltype(C::kSR)>> : std::bool_constant<C::kSR> {};
+
+// 32-bit mixer (the MurmurHash3 finaliser) for counter-based random bits.
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+// Random bits for the plane p of a node: a node seed from the step key k and
+// the node's in-plane byte offset o (computed once per node), then one
+// multiply-xorshift round over a Weyl sequence in the plane number.
+__device__ __forceinline__ uint32_t sr_seed(uint32_t k, uint32_t o) {
+  return mix32(k ^ (o * 0x9e3779b1u));
+}
+__device__ __forceinline__ uint32_t sr_plane(uint32_t seed, int p) {
+  uint32_t h = seed + (uint32_t)(p + 1) * 0x9e3779b9u;
+  h ^= h >> 16;
+  h *= 0x21f0aaadu;
+  return h ^ (h >> 15);
+}
 
 // ---- parameters of the collision ------------------------------------------
 struct CollideParams {

@@ -15,6 +15,7 @@ struct PlaneGeom {
   int64_t plane;  // elements between plane starts
   int nx, ny;
   float s, inv_s;  // storage scale
+  uint32_t sr_key = 0;  // per-step key of the stochastic-rounding codec
 };
 
 template <class T>
@@ -70,21 +71,27 @@ __device__ __forceinline__ float pull_g_per(const PlaneGeom &G,
 // pointer) so each store keeps a scalar plane base and the 32-bit offset.
 template <class C, bool NT, int P>
 __device__ __forceinline__ void store_plane(const PlaneGeom &G, typename C::T *__restrict__ dst,
-                                            uint32_t o, const float *d, const float *g) {
+                                            uint32_t o, uint32_t seed, const float *d,
+                                            const float *g) {
   const float v = P < kQ ? d[P] : g[P - kQ];
-  st_at<typename C::T, NT>(dst + (int64_t)P * G.plane, o, C::enc(v, G.s));
+  if constexpr (codec_sr<C>::value)
+    st_at<typename C::T, NT>(dst + (int64_t)P * G.plane, o, C::enc_sr(v, G.s, sr_plane(seed, P)));
+  else
+    st_at<typename C::T, NT>(dst + (int64_t)P * G.plane, o, C::enc(v, G.s));
 }
 template <class C, bool NT, int... P>
 __device__ __forceinline__ void store_planes_seq(const PlaneGeom &G,
                                                  typename C::T *__restrict__ dst, uint32_t o,
-                                                 const float *d, const float *g,
+                                                 uint32_t seed, const float *d, const float *g,
                                                  std::integer_sequence<int, P...>) {
-  (store_plane<C, NT, P>(G, dst, o, d, g), ...);
+  (store_plane<C, NT, P>(G, dst, o, seed, d, g), ...);
 }
 template <class C, bool NT>
 __device__ __forceinline__ void store_planes(const PlaneGeom &G, typename C::T *__restrict__ dst,
                                              uint32_t o, const float *d, const float *g) {
-  store_planes_seq<C, NT>(G, dst, o, d, g, std::make_integer_sequence<int, kPlanes>{});
+  uint32_t seed = 0;
+  if constexpr (codec_sr<C>::value) seed = sr_seed(G.sr_key, o);
+  store_planes_seq<C, NT>(G, dst, o, seed, d, g, std::make_integer_sequence<int, kPlanes>{});
 }
 
 // Pull, collide and store one node of a doubly periodic domain.  src/dst

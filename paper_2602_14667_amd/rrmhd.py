@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "librrmhd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
 STORE_F32, STORE_F16, STORE_INPLACE = 0, 1, 0x100
+STORE_F16_SR = 2
 BC_PERIODIC, BC_WALLS_Y = 0, 1
 FEQ_ALGORITHM, FEQ_FULL_MAXWELL = 0, 1
 
@@ -209,7 +210,8 @@ def closure_eval(params, norm, x, stream=None):
 class Solver:
     """One lattice on the current device.
 
-    storage: "f32" or "f16" (populations stored as offsets f - w).
+    storage: "f32", "f16" (populations stored as offsets f - w) or "f16sr"
+    (FP16 with stochastically rounded step stores).
     walls: half-way bounce-back walls in y (periodic x); force: body force
     per unit mass; b_wall: field imposed by the magnetic walls.
     equilibrium: "algorithm" (the method's) or "full_maxwell" (ablation with
@@ -224,7 +226,7 @@ class Solver:
         self.nx, self.ny = int(nx), int(ny)
         self.storage = storage
         self._stream = stream
-        kind = STORE_F16 if storage == "f16" else STORE_F32
+        kind = {"f32": STORE_F32, "f16": STORE_F16, "f16sr": STORE_F16_SR}[storage]
         g = Grid(self.nx, self.ny, kind | (STORE_INPLACE if inplace else 0),
                  float(codec_scale))
         bc = BC(BC_WALLS_Y if walls else BC_PERIODIC,

@@ -553,3 +553,171 @@ def test_near_half_tau_instability_tracks_oracle():
     assert rc == R.ENONFINITE
     assert not all(math.isfinite(v) for v in o.diagnostics())
     s.close()
+
+
+def hartmann_run(h, nx, storage, u, b, checkpoints):
+    """x-averaged rel L2 of u_x and b_x against the closed form, and the
+    largest spread of u_x across x, at each checkpoint."""
+    R = rrmhd()
+    ue, be = hartmann_closed_form(h, np.arange(h.ny))
+    s = R.Solver(nx, h.ny, h.tau_f, h.tau_m, storage=storage, walls=True,
+                 force=(h.G, 0.0), b_wall=(0.0, h.B0))
+    s.init(dev(u), dev(b))
+    out = []
+    for n in checkpoints:
+        s.step(n - s.step_count)
+        g = gpu_moments(s)
+        gu, gb = g["ux"].mean(1), g["bx"].mean(1)
+        out.append((np.linalg.norm(gu - ue) / np.linalg.norm(ue),
+                    np.linalg.norm(gb - be) / np.linalg.norm(be),
+                    float(g["ux"].std(1).max())))
+    s.close()
+    return out
+
+
+def test_hartmann_c2_long_wave_instability_fp32():
+    """The C2 channel started from the closed-form profile plus a random
+    perturbation of 1e-5 in u, FP32 storage: on the 512-wide channel the
+    spread of u_x across x grows by about 10x per 5e4 steps (a mode of
+    wavelength >= 256 in x is unstable), on a 64-wide channel it stays at the
+    perturbation's level.  Runs started x-invariant keep every column
+    identical, bit for bit, and never excite the mode; the noise of
+    stochastic rounding does."""
+    note("C2 long-wave instability, FP32, nx 512 and 64")
+    h = inputs.hartmann_c2()
+    ue, be = hartmann_closed_form(h, np.arange(h.ny))
+    spread = {}
+    for nx in (512, 64):
+        rng = np.random.default_rng(5)
+        u = np.zeros((2, h.ny, nx)); u[0] = ue[:, None]
+        u += 1e-5 * rng.standard_normal(u.shape)
+        b = np.zeros((2, h.ny, nx)); b[0] = be[:, None]; b[1] = h.B0
+        spread[nx] = [r[2] for r in hartmann_run(h, nx, "f32", u, b, [50_000, 200_000])]
+        note(f"  nx {nx}: spread of u_x across x at 5e4 / 2e5 steps {spread[nx]}")
+    assert spread[512][1] > 100 * spread[512][0]
+    assert spread[64][1] < 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f16sr", "f16"])
+def test_hartmann_from_rest_fp16_narrow(storage):
+    """FP16 storage from rest on an 8-wide section of the C2 channel (the
+    same profile in y; every x-mode decays).  Round-to-nearest rounds every
+    per-step increment of the body force away and the state freezes far
+    from the profile; stochastic rounding keeps the increments on average
+    and the x-averaged profile converges to within its noise (a few 1e-3)
+    of the closed form."""
+    h = inputs.hartmann_c2()
+    nx = 8
+    note(f"C2 from rest, {nx}x{h.ny}, {storage}")
+    u = np.zeros((2, h.ny, nx))
+    b = np.zeros((2, h.ny, nx)); b[1] = h.B0
+    if storage == "f16sr":
+        res = hartmann_run(h, nx, storage, u, b, [500_000])
+        note(f"  rel L2 u {res[0][0]:.3e}  b_x {res[0][1]:.3e}")
+        assert res[0][0] < 1e-2 and res[0][1] < 1e-2
+    else:
+        res = hartmann_run(h, nx, storage, u, b, [100_000])
+        note(f"  rel L2 u {res[0][0]:.3e}  b_x {res[0][1]:.3e} (frozen)")
+        assert res[0][0] > 0.5
+
+
+# ---------------------------------------------------------------------------
+# FP16 storage with stochastic rounding (optional codec variant)
+# ---------------------------------------------------------------------------
+def test_c1_fp16_stochastic_rounding_per_field():
+    """Orszag-Tang 64^2, 1000 steps: the stochastically rounded FP16 codec
+    against the FP64 oracle, next to the prescribed round-to-nearest-even
+    codec on the same case.  Stochastic rounding removes the systematic part
+    of the per-step rounding, so its accumulated error is expected to be the
+    smaller of the two; both stay within the FP16 arithmetic bound."""
+    note("C1 OT 64^2 fp16 stochastic rounding")
+    u, b = c1_inputs()
+    cps = list(range(100, 1001, 100))
+    sr = run_pair(64, 64, u, b, 0.56, 0.56, cps, storage="f16sr")
+    rne = run_pair(64, 64, u, b, 0.56, 0.56, cps, storage="f16")
+    for k in FIELDS:
+        note(f"  {k}: SR {max(e[k] for e in sr):.3e}  RNE {max(e[k] for e in rne):.3e}")
+    assert worst(sr) < 1e-2
+    assert worst(sr, ("ux", "uy", "bx", "by")) < worst(rne, ("ux", "uy", "bx", "by"))
+
+
+@pytest.mark.parametrize("shape", [(130, 66), (129, 40)])
+def test_stochastic_rounding_is_reproducible_and_shape_independent(shape):
+    """The random bits are a hash of (step, node, plane): two runs, and runs
+    with other launch shapes, give the same state bit for bit; walls and
+    forcing included."""
+    nx, ny = shape
+    R = rrmhd()
+    u, b = inputs.random_modes(nx, ny, 0.03, seed=11)
+    ref = None
+    for bx, by, ry, xcd, nt in ((0, 0, 0, 0, 0), (64, 4, 1, 0, 0), (32, 2, 3, 1, 1),
+                                (256, 1, 1, 2, 3), (0, 0, 0, 0, 0)):
+        s = R.Solver(nx, ny, 0.53, 0.57, storage="f16sr")
+        if bx:
+            s.set_launch(bx, by, ry, xcd, nt)
+        s.init(dev(u), dev(b))
+        s.step(9)
+        g = gpu_moments(s)
+        s.close()
+        if ref is None:
+            ref = g
+        for k in FIELDS:
+            assert np.array_equal(g[k], ref[k]), (bx, by, k)
+    # the rounding is not round-to-nearest: the result differs from the codec
+    s = R.Solver(nx, ny, 0.53, 0.57, storage="f16")
+    s.init(dev(u), dev(b))
+    s.step(9)
+    g = gpu_moments(s)
+    s.close()
+    assert any(not np.array_equal(g[k], ref[k]) for k in FIELDS)
+
+
+def test_stochastic_rounding_walls_force_parity():
+    note("walls+force 9x24 f16sr")
+    h = inputs.Hartmann(nx=9, ny=24, tau_f=0.8, tau_m=0.75, G=1e-4, Ha=4.0)
+    u, b = inputs.random_modes(9, 24, 0.03, seed=4)
+    b[1] += h.B0
+    errs = run_pair(9, 24, u, b, h.tau_f, h.tau_m, [1, 10, 100], storage="f16sr",
+                    walls=True, force=(h.G, 0.0), b_wall=(0.0, h.B0), initial_norm=True)
+    assert worst(errs) < 1e-2, errs
+
+
+def test_stochastic_rounding_keeps_small_increments():
+    """A uniform flow (u = (0.05, 0.03), b = (0.02, 0.01)) driven by a body
+    force too small to move any FP16 population by half a step: with
+    round-to-nearest every increment is rounded away (the flow stagnates);
+    with stochastic rounding the increments survive on average, and the mean
+    momentum gained over k steps is k times the force (Guo forcing conserves
+    mass and adds rho G per step), as with FP32 storage.  The mean field is
+    conserved by the induction collision and stays put within the rounding
+    noise."""
+    R = rrmhd()
+    n, k, G = 128, 200, 1e-6
+    u = np.zeros((2, n, n))
+    u[0], u[1] = 0.05, 0.03
+    b = np.zeros((2, n, n))
+    b[0], b[1] = 0.02, 0.01
+    gain, drift = {}, {}
+    for storage in ("f32", "f16", "f16sr"):
+        s = R.Solver(n, n, 0.6, 0.6, storage=storage, force=(G, 0.0))
+        s.init(dev(u), dev(b))
+        m0 = gpu_moments(s)
+        s.step(k)
+        m1 = gpu_moments(s)
+        s.close()
+        gain[storage] = float(np.mean(m1["rho"] * m1["ux"]) - np.mean(m0["rho"] * m0["ux"]))
+        drift[storage] = max(abs(float(np.mean(m1[f]) - np.mean(m0[f]))) for f in ("bx", "by"))
+        note(f"  {storage}: momentum gain / (k G) = {gain[storage] / (k * G):.4f}, "
+             f"mean-field drift {drift[storage]:.2e}")
+    assert abs(gain["f32"] / (k * G) - 1) < 0.02
+    assert abs(gain["f16sr"] / (k * G) - 1) < 0.1
+    assert abs(gain["f16"]) < 0.5 * k * G
+    assert drift["f16sr"] < 2e-6
+
+
+def test_stochastic_rounding_refusals():
+    R = rrmhd()
+    s = R.Solver(32, 32, 0.56, 0.56, storage="f16sr")
+    assert R.lib().rrmhd_set_graph_chunk(s._h, 4) == R.EINVAL
+    assert R.lib().rrmhd_set_equilibrium(s._h, R.FEQ_FULL_MAXWELL) == R.EINVAL
+    s.close()
