@@ -32,15 +32,17 @@ def kernel_hash():
     return kh()
 
 
-def measured_traffic(storage, n):
+def measured_traffic(storage, n, dims=2):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on another kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_{storage}_{n}.json")
+    from paper_2602_14667_amd import kernel3d_hash
+    tag = "step" if dims == 2 else "step3d"
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}_{storage}_{n}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != (kernel_hash() if dims == 2 else kernel3d_hash()):
         return None
     return t.get("bytes_per_launch")
 
@@ -100,6 +102,39 @@ def cpu_baseline_c1():
                       "threads": th}
     oracle.set_threads(cores)
     out["kind"] = "oracle"
+    return out
+
+
+def cpu_baseline_c2(steps=40_000, to_steady=490_000):
+    """The FP64 oracle on the Hartmann channel's x-invariant section (a
+    1 x 256 column, the same profile in y) from rest, timed on a bounded
+    sample of steps with all host threads and with one; the projected time
+    to the step count at which the GPU run meets the 1e-3 criterion."""
+    import numpy as np
+    import oracle
+    from paper_2602_14667_amd import inputs
+    h = inputs.hartmann_c2()
+    u = np.zeros((2, h.ny, 1))
+    b = np.zeros((2, h.ny, 1))
+    b[1] = h.B0
+    cores = oracle.threads()
+    out = {}
+    for label, th in (("all_threads", cores), ("single_thread", 1)):
+        oracle.set_threads(th)
+        o = oracle.Oracle(1, h.ny, h.tau_f, h.tau_m, walls=True, force=(h.G, 0.0),
+                          b_wall=(0.0, h.B0))
+        o.init(u, b)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        o.close()
+        out[label] = {"seconds": round(dt, 3), "MLUPS": round(h.ny * steps / dt / 1e6, 3),
+                      "threads": th,
+                      "projected_s_to_steady": round(dt * to_steady / steps, 1)}
+    oracle.set_threads(cores)
+    out["kind"] = "oracle"
+    out["sample"] = f"1x{h.ny} column from rest, {steps} steps, FP64"
+    out["steady_steps"] = to_steady
     return out
 
 
@@ -309,7 +344,9 @@ def hartmann_bench(torch, rrmhd, inputs, args):
         "config": {"workload": "Hartmann channel 512x256, walls in y, G=1e-6, Ha=10, "
                                "tau_f=0.6, tau_m=0.55, from rest",
                    "criterion": "rel L2 of the x-averaged u_x and b_x vs the analytic profile <= 1e-3"},
-        "storage": out}), flush=True)
+        "storage": out,
+        **({} if args.no_cpu_baseline else {"cpu_baseline_c2": cpu_baseline_c2()})}),
+        flush=True)
 
 
 def ot64_bench(torch, rrmhd, inputs, args):
@@ -393,6 +430,7 @@ def turbulence3d_bench(torch, rrmhd, inputs, args):
         res[storage] = dict(mlups=round(nodes / ms / 1e3, 1), ms_per_step=round(ms, 4),
                             bytes_per_node=bpn, achieved_GBs=round(gbs, 1),
                             frac=round(gbs / PEAK_HBM_GBS, 4),
+                            traffic=None if args.inplace else measured_traffic(storage, n, dims=3),
                             diagnostics_after=[v if math.isfinite(v) else None for v in diag])
     r = res["f32"]
     print(json.dumps({
@@ -405,7 +443,8 @@ def turbulence3d_bench(torch, rrmhd, inputs, args):
                    "state_GB": round(nodes * 48 * 4 * (1 if args.inplace else 2) / 1e9, 1),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": r["frac"], "traffic": None},
+                     "unit": "GB/s", "frac": r["frac"],
+                     "traffic": None if args.inplace else measured_traffic("f32", n, dims=3)},
         "storages": res}), flush=True)
 
 

@@ -6,17 +6,22 @@ binding loads the library on first use and raises if it is missing.
 """
 __all__ = ["rrmhd", "inputs"]
 
-# Sources of the step kernel; their hash tags measured traffic figures so a
+# Sources of the step kernels; their hash tags measured traffic figures so a
 # figure taken on another kernel version is not reported.
 KERNEL_SOURCES = ("csrc/rr_node.h", "csrc/rr_pull.h", "csrc/rr_kernels.hip")
+KERNEL3D_SOURCES = ("csrc/rr_node.h", "csrc/rr_pull.h", "csrc/rr_3d.hip")
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     import os
     here = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(here, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel3d_hash() -> str:
+    return kernel_hash(KERNEL3D_SOURCES)

@@ -13,6 +13,11 @@ Single-buffer (in-place) steps, per phase, from the same copy calibration:
   rocprofv3 --pmc <ctr> ... -d PROF_DIR/ip_pmc_<ctr>_{f32,f16} ... bench.py --inplace ...
   python -m paper_2602_14667_amd.profsum inplace PROF_DIR OUT_DIR N
 
+Three-dimensional step (both storages in one bench run), same calibration:
+  rocprofv3 --kernel-trace --stats ... -d PROF_DIR/s3_stats ... bench.py --workload turbulence3d ...
+  rocprofv3 --pmc <ctr> ... -d PROF_DIR/s3_pmc_<ctr> ... bench.py --workload turbulence3d ...
+  python -m paper_2602_14667_amd.profsum step3d PROF_DIR OUT_DIR N
+
 Second form, kernel-trace statistics of any workload:
   python -m paper_2602_14667_amd.profsum stats STATS_DIR OUT.md KERNEL BYTES TITLE COMMAND [LAST]
 writes the per-kernel table and, for the kernel whose name contains KERNEL,
@@ -26,7 +31,7 @@ import os
 import re
 import sys
 
-from . import kernel_hash
+from . import kernel3d_hash, kernel_hash
 
 COPY_BYTES = 4 << 30  # bench.py --mode copy default
 
@@ -168,6 +173,61 @@ def inplace_summary(prof, out, n):
     print("ok")
 
 
+def step3d_summary(prof, out, n):
+    """Time and calibrated HBM traffic of the 3D step kernel, per storage."""
+    n = int(n)
+    nodes = n ** 3
+    fac = _calibration(prof)
+    stats = kernel_stats(os.path.join(prof, "s3_stats"))
+    cmd = f"python3 bench.py --workload turbulence3d --n3d {n}"
+    for st, codec, bpn in (("f32", "CodecF32>", 384), ("f16", "CodecF16U>", 192)):
+        name = [k for k in stats if "k_step3<" in k and codec in k][0]
+        avg = stats[name]["avg_ns"]
+        rd = counter_mean(os.path.join(prof, "s3_pmc_FETCH_SIZE"), name) * 1024 * fac["FETCH_SIZE"]
+        wr = counter_mean(os.path.join(prof, "s3_pmc_WRITE_SIZE"), name) * 1024 * fac["WRITE_SIZE"]
+        alg = bpn * nodes
+        traffic = {"kernel": name, "kernel_hash": kernel3d_hash(), "n": n, "storage": st,
+                   "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+                   "algorithmic_bytes": alg, "fetch_factor": fac["FETCH_SIZE"],
+                   "write_factor": fac["WRITE_SIZE"]}
+        with open(os.path.join(out, f"traffic_step3d_{st}_{n}.json"), "w") as fh:
+            json.dump(traffic, fh, indent=1)
+        lines = [
+            f"# 3D step kernel (D3Q27 + D3Q7), {st.upper()} storage, turbulence {n}^3",
+            "",
+            f"Kernel: `{name}`  (source hash {kernel3d_hash()}); both storages come from the same runs.",
+            "",
+            "Commands (from the repository root, on the MI355X host; the copy calibration runs as "
+            "for the two-dimensional step summaries):",
+            "```",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/s3_stats -o run -- {cmd} --steps 50 --warmup 5",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/s3_pmc_FETCH_SIZE -o run -- {cmd} --steps 5 --warmup 1",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/s3_pmc_WRITE_SIZE -o run -- {cmd} --steps 5 --warmup 1",
+            f"python -m paper_2602_14667_amd.profsum step3d {prof} profiles {n}",
+            "```",
+            "",
+            "| kernel | calls | avg ns | min ns | max ns |",
+            "|---|---|---|---|---|",
+        ]
+        for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+            lines.append(f"| `{k[:90]}` | {v['calls']} | {v['avg_ns']:.0f} | {v['min_ns']:.0f} "
+                         f"| {v['max_ns']:.0f} |")
+        lines += [
+            "",
+            f"* nodes per launch: {nodes}; algorithmic bytes per launch: {alg / 1e9:.3f} GB ({bpn} B/node)",
+            f"* average launch: {avg / 1e3:.1f} us -> {nodes / avg * 1e3:.0f} MLUPS, "
+            f"{alg / avg:.1f} GB/s algorithmic = {alg / avg / 8000 * 100:.1f} % of 8 TB/s",
+            f"* HBM traffic per launch (PMC, calibrated): read {rd / 1e9:.3f} GB "
+            f"({rd / (alg / 2):.3f}x algorithmic), write {wr / 1e9:.3f} GB ({wr / (alg / 2):.3f}x); "
+            f"{(rd + wr) / avg:.1f} GB/s actual",
+            f"* calibration: FETCH_SIZE x {fac['FETCH_SIZE']:.4f}, WRITE_SIZE x {fac['WRITE_SIZE']:.4f} "
+            f"(plain copy of {COPY_BYTES} B)",
+        ]
+        with open(os.path.join(out, f"step3d_{st}_{n}.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    print("ok")
+
+
 def last_dispatches(stats_dir, kernel, count):
     """Average duration (ns) of the last `count` dispatches of the kernel
     whose name contains `kernel` (the timed region of a bench run)."""
@@ -211,5 +271,7 @@ if __name__ == "__main__":
         stats_summary(*sys.argv[2:9])
     elif sys.argv[1] == "inplace":
         inplace_summary(*sys.argv[2:5])
+    elif sys.argv[1] == "step3d":
+        step3d_summary(*sys.argv[2:5])
     else:
         main(*sys.argv[1:4])
