@@ -23,8 +23,10 @@
 // Storage and arithmetic follow the two-dimensional kernels: f_i - w_i and
 // g_j stored in FP32 or FP16 (round to nearest even), FP32 arithmetic with
 // exactly representable constants and w_i applied as a correctly rounded
-// quotient by 1/w_i in {3.375, 13.5, 54, 216}.  Pull streaming, periodic in
-// x, y and z; two buffers.
+// quotient by 1/w_i in {3.375, 13.5, 54, 216}.  Periodic in x, y and z.
+// Pull streaming with two buffers, or one buffer with alternating steps: a
+// pull whose results go to the opposite-direction slots at x + c_i, then a
+// read of the node's own (swapped) slots with local stores.
 //
 // Velocity order (this library): i = 9 (c_z + 1) + 3 (c_y + 1) + (c_x + 1);
 // magnetic j = 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z.  Planes: f_0..f_26,

@@ -500,7 +500,7 @@ def test_launch_shapes_bitwise(storage, shape):
     ref.close()
     for bx, by, ry, xcd, nt in ((64, 4, 1, 0, 0), (32, 2, 3, 1, 1), (256, 1, 1, 2, 3),
                                 (128, 1, 1, 0, 5), (64, 2, 2, 2, 7), (16, 16, 1, 0, 4),
-                                (1, 1, 1, 0, 5)):
+                                (1, 1, 1, 0, 5), (32, 2, 2, 1, 5)):
         s = R.Solver(nx, ny, 0.53, 0.57, storage=storage)
         s.set_launch(bx, by, ry, xcd, nt)
         s.init(dev(u), dev(b))

@@ -115,3 +115,13 @@ def test_bench_traffic_gate(tmp_path, monkeypatch):
     assert bench.measured_traffic("f32", 16, dims=3) is None
     p3.write_text(json.dumps({"kernel_hash": kernel3d_hash(), "bytes_per_launch": 7.0}))
     assert bench.measured_traffic("f32", 16, dims=3) == 7.0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
