@@ -317,29 +317,20 @@ def test_post_collision_moments(trial):
     assert np.allclose(gs.reshape(5, 2).sum(0), b, atol=1e-16)
 
 
-def _exact_collide(f, g, omega, omega_m):
-    """Single-node collision in exact rational arithmetic from the hand
-    expansion: D1Q3 product equilibrium + Maxwell term, closed-form a1,
-    closed-form recursion, reconstruction with 9/2, 27/2 and 81/4."""
-    f = [Fr(x) for x in f]
-    g = [Fr(x) for x in g]
-    om, omm = Fr(omega), Fr(omega_m)
-    t = Fr(1, 3)
-    rho = sum(f)
-    ux = sum(fi * c for fi, c in zip(f, CX)) / rho
-    uy = sum(fi * c for fi, c in zip(f, CY)) / rho
-    bx = sum(g[0::2])
-    by = sum(g[1::2])
+def _frac(p, q=1):
+    return Fr(p, q)
 
+
+def _exact_equilibria(rho, ux, uy, bx, by, K=_frac):
+    """f_eq (D1Q3 product form + hand-expanded Maxwell term) and g_eq of one
+    node; K(p, q) makes the constant p/q in the arithmetic in use."""
     def ph(c, v):
-        return Fr(2, 3) - v * v if c == 0 else Fr(1, 6) + c * v / 2 + v * v / 2
+        return K(2, 3) - v * v if c == 0 else K(1, 6) + c * v / 2 + v * v / 2
 
-    W = [Fr(4, 9), Fr(1, 36), Fr(1, 9), Fr(1, 36), Fr(1, 9), Fr(1, 36),
-         Fr(1, 9), Fr(1, 36), Fr(1, 9)]
     feq = []
     for i in range(9):
         cx, cy = int(CX[i]), int(CY[i])
-        m = Fr(0)
+        m = K(0)
         if i in (2, 6):
             m = (by * by - bx * bx) / 4
         elif i in (4, 8):
@@ -347,31 +338,52 @@ def _exact_collide(f, g, omega, omega_m):
         elif i != 0:
             m = -cx * cy * bx * by / 4
         feq.append(rho * ph(cx, ux) * ph(cy, uy) + m)
+    E = ux * by - uy * bx
+    psi = [K(1, 3)] + [K(1, 6)] * 4
+    geq = []
+    for j in range(5):
+        geq.append(psi[j] * (bx - 3 * int(EY[j]) * E))
+        geq.append(psi[j] * (by + 3 * int(EX[j]) * E))
+    return feq, geq
+
+
+def _exact_collide_k(f, g, om, omm, K=_frac):
+    """Single-node collision from the hand expansion in the arithmetic of K:
+    closed-form a1, closed-form recursion, reconstruction with 9/2, 27/2 and
+    81/4.  f, g, om, omm are already numbers of that arithmetic."""
+    t = K(1, 3)
+    rho = sum(f)
+    ux = sum(fi * c for fi, c in zip(f, CX)) / rho
+    uy = sum(fi * c for fi, c in zip(f, CY)) / rho
+    bx = sum(g[0::2])
+    by = sum(g[1::2])
+    W = [K(4, 9), K(1, 36), K(1, 9), K(1, 36), K(1, 9), K(1, 36),
+         K(1, 9), K(1, 36), K(1, 9)]
+    feq, geq = _exact_equilibria(rho, ux, uy, bx, by, K)
     Mxx = (by * by - bx * bx) / 2
     Myy = -Mxx
     Mxy = -bx * by
-    axx = sum(fi * c * c for fi, c in zip(f, CX)) - rho * t - rho * ux * ux - Mxx
-    ayy = sum(fi * c * c for fi, c in zip(f, CY)) - rho * t - rho * uy * uy - Myy
-    axy = sum(fi * a * c for fi, a, c in zip(f, CX, CY)) - rho * ux * uy - Mxy
+    axx = sum(fi * int(c) * int(c) for fi, c in zip(f, CX)) - rho * t - rho * ux * ux - Mxx
+    ayy = sum(fi * int(c) * int(c) for fi, c in zip(f, CY)) - rho * t - rho * uy * uy - Myy
+    axy = sum(fi * int(a) * int(c) for fi, a, c in zip(f, CX, CY)) - rho * ux * uy - Mxy
     axxy = 2 * ux * axy + uy * axx
     axyy = 2 * uy * axy + ux * ayy
     axxyy = ux * ux * ayy + uy * uy * axx + 4 * ux * uy * axy
     fs = []
     for i in range(9):
         cx, cy = int(CX[i]), int(CY[i])
-        hxx, hyy, hxy = cx * cx - t, cy * cy - t, Fr(cx * cy)
-        r = (Fr(9, 2) * (hxx * axx + 2 * hxy * axy + hyy * ayy)
-             + Fr(27, 2) * (cy * hxx * axxy + cx * hyy * axyy)
-             + Fr(81, 4) * hxx * hyy * axxyy)
+        hxx, hyy, hxy = cx * cx - t, cy * cy - t, K(cx * cy)
+        r = (K(9, 2) * (hxx * axx + 2 * hxy * axy + hyy * ayy)
+             + K(27, 2) * (cy * hxx * axxy + cx * hyy * axyy)
+             + K(81, 4) * hxx * hyy * axxyy)
         fs.append(feq[i] + (1 - om) * W[i] * r)
-    E = ux * by - uy * bx
-    psi = [Fr(1, 3)] + [Fr(1, 6)] * 4
-    gs = []
-    for j in range(5):
-        gx = psi[j] * (bx - 3 * int(EY[j]) * E)
-        gy = psi[j] * (by + 3 * int(EX[j]) * E)
-        gs.append(gx + (1 - omm) * (g[2 * j] - gx))
-        gs.append(gy + (1 - omm) * (g[2 * j + 1] - gy))
+    gs = [geq[k] + (1 - omm) * (g[k] - geq[k]) for k in range(10)]
+    return fs, gs
+
+
+def _exact_collide(f, g, omega, omega_m):
+    """Single-node collision in exact rational arithmetic."""
+    fs, gs = _exact_collide_k([Fr(x) for x in f], [Fr(x) for x in g], Fr(omega), Fr(omega_m))
     return [float(x) for x in fs], [float(x) for x in gs]
 
 
@@ -383,6 +395,90 @@ def test_collision_exact_rational(trial):
     efs, egs = _exact_collide(f, g, om, omm)
     assert np.allclose(fs, efs, rtol=0, atol=1e-15)
     assert np.allclose(gs, egs, rtol=0, atol=1e-16)
+
+
+def _grid_run_hand(u, b, tau_f, tau_m, steps, K, num):
+    """Whole periodic grid from the hand expansion: equilibrium
+    initialisation at rho = 1, then collide and push-stream (f*_i(x) moves to
+    x + c_i, g*_j(x) to x + e_j), in the arithmetic of K (constants) and num
+    (float inputs, converted exactly).  Returns the pre-collision moments
+    (rho, u, b) after each step as floats."""
+    ny, nx = u.shape[1:]
+    om, omm = 1 / num(tau_f), 1 / num(tau_m)
+    F = [[None] * nx for _ in range(ny)]
+    G = [[None] * nx for _ in range(ny)]
+    for y in range(ny):
+        for x in range(nx):
+            F[y][x], G[y][x] = _exact_equilibria(K(1), num(u[0, y, x]), num(u[1, y, x]),
+                                                 num(b[0, y, x]), num(b[1, y, x]), K)
+    out = []
+    for _ in range(steps):
+        Fn = [[[None] * 9 for _ in range(nx)] for _ in range(ny)]
+        Gn = [[[None] * 10 for _ in range(nx)] for _ in range(ny)]
+        for y in range(ny):
+            for x in range(nx):
+                fs, gs = _exact_collide_k(F[y][x], G[y][x], om, omm, K)
+                for i in range(9):
+                    Fn[(y + int(CY[i])) % ny][(x + int(CX[i])) % nx][i] = fs[i]
+                for j in range(5):
+                    yy, xx = (y + int(EY[j])) % ny, (x + int(EX[j])) % nx
+                    Gn[yy][xx][2 * j] = gs[2 * j]
+                    Gn[yy][xx][2 * j + 1] = gs[2 * j + 1]
+        F, G = Fn, Gn
+        rho = np.zeros((ny, nx)); uu = np.zeros((2, ny, nx)); bb = np.zeros((2, ny, nx))
+        for y in range(ny):
+            for x in range(nx):
+                f, g = F[y][x], G[y][x]
+                r = sum(f)
+                rho[y, x] = float(r)
+                uu[0, y, x] = float(sum(fi * int(c) for fi, c in zip(f, CX)) / r)
+                uu[1, y, x] = float(sum(fi * int(c) for fi, c in zip(f, CY)) / r)
+                bb[0, y, x] = float(sum(g[0::2]))
+                bb[1, y, x] = float(sum(g[1::2]))
+        out.append((rho, uu, bb))
+    return out
+
+
+@pytest.mark.parametrize("shape,steps", [((3, 3), 5), ((5, 4), 5), ((1, 1), 3), ((2, 1), 3)])
+def test_tiny_grid_high_precision(shape, steps):
+    """Tiny periodic grids, 1 to 5 steps: the oracle (generic Hermite
+    tensors, FP64) against the hand expansion run in 50-digit decimal
+    arithmetic, field by field."""
+    from decimal import Decimal, localcontext
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 10 + ny)
+    u = 0.05 * rng.standard_normal((2, ny, nx))
+    b = 0.05 * rng.standard_normal((2, ny, nx))
+    with localcontext() as ctx:
+        ctx.prec = 50
+        ref = _grid_run_hand(u, b, 0.53, 0.57, steps, lambda p, q=1: Decimal(p) / Decimal(q),
+                             lambda v: Decimal(float(v)))
+    o = oracle.Oracle(nx, ny, 0.53, 0.57)
+    o.init(u, b)
+    for k in range(steps):
+        o.step(1)
+        rho, uu, bb = o.moments()
+        r_rho, r_u, r_b = ref[k]
+        assert np.max(np.abs(rho - r_rho)) < 1e-14, k
+        assert np.max(np.abs(uu - r_u)) < 1e-15, k
+        assert np.max(np.abs(bb - r_b)) < 1e-15, k
+    o.close()
+
+
+def test_tiny_grid_decimal_equals_exact():
+    """The 50-digit run of the hand expansion equals the exact-rational one
+    on a 3 x 3 grid over 2 steps (to far below FP64 resolution)."""
+    from decimal import Decimal, localcontext
+    rng = np.random.default_rng(7)
+    u = 0.05 * rng.standard_normal((2, 3, 3))
+    b = 0.05 * rng.standard_normal((2, 3, 3))
+    exact = _grid_run_hand(u, b, 0.53, 0.57, 2, _frac, Fr)
+    with localcontext() as ctx:
+        ctx.prec = 50
+        dec = _grid_run_hand(u, b, 0.53, 0.57, 2, lambda p, q=1: Decimal(p) / Decimal(q),
+                             lambda v: Decimal(float(v)))
+    for (a0, a1, a2), (b0, b1, b2) in zip(exact, dec):
+        assert np.array_equal(a0, b0) and np.array_equal(a1, b1) and np.array_equal(a2, b2)
 
 
 # --------------------------------------------------------------------------
