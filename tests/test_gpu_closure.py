@@ -121,3 +121,26 @@ def test_fused_closure_step_vs_oracle(shape):
         # proportion to the effect's size
         assert de < 5e-2
         assert e < 5e-2 * eff / np.linalg.norm(r) + 1e-6
+
+
+def test_runtime_fallback_to_plain():
+    """A closure whose weights are scaled by 1e6 drives the state non-finite
+    within its first chunk of steps: the run reloads the last checkpoint
+    (here the initial state), turns the closure off, reports the step, and
+    from then on is the plain run, bit for bit."""
+    from paper_2602_14667_amd import closure_pipeline as cp
+    note("closure runtime fallback")
+    rng = np.random.default_rng(3)
+    p = init_params(rng) * 1e6
+    nm = norm_of(features(rng, 4096))
+    n = 64
+    u, b = inputs.turbulence(n, 0.04)
+    cps = [500, 1500]
+    plain, _, fb0 = cp.spectra_run(n, 0.56, u, b, cps, fallback_every=500)
+    got, _, fb = cp.spectra_run(n, 0.56, u, b, cps, params=dev32(p), norm=dev32(nm),
+                                fallback_every=500)
+    note(f"  fell back at step {fb}")
+    assert fb0 is None and fb == 500
+    for c in cps:
+        assert np.array_equal(got[c][0], plain[c][0])
+        assert got[c][1] == plain[c][1] and got[c][2] == plain[c][2]
