@@ -92,7 +92,10 @@ typedef struct rrmhd rrmhd;
  * collision of algorithm task 5), both > 1/2 and finite.  bc may be NULL
  * (periodic, no force).  hip_stream may be NULL (the null stream) or a
  * hipStream_t such as torch's current stream.  Allocates the two population
- * buffers (19 planes each) and a diagnostics workspace. */
+ * buffers (19 planes each) and a diagnostics workspace.  A plane of
+ * nx * ny stored values must stay below 4 GiB (in-plane offsets are 32-bit
+ * byte offsets): nx * ny < 2^30 for FP32 storage, < 2^31 for FP16 (EINVAL
+ * otherwise). */
 int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
                  const rrmhd_bc *bc, void *hip_stream, rrmhd **out);
 

@@ -134,7 +134,8 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   for (int k = 0; k < 2; ++k)
     if (!finite_pos(b.force[k]) || !finite_pos(b.b_wall[k])) return RRMHD_EINVAL;
   const int64_t N = (int64_t)grid->nx * grid->ny;
-  if (N > ((int64_t)1 << 31) - 1) return RRMHD_EINVAL;  // in-plane offsets are int32
+  // in-plane offsets are 32-bit byte offsets: a plane stays below 4 GiB
+  if (N * (kind == RRMHD_STORE_F32 ? 4 : 2) >= ((int64_t)1 << 32)) return RRMHD_EINVAL;
   float S = grid->codec_scale;
   if (S == 0.0f) S = 1.0f;
   int ex = 0;

@@ -66,6 +66,19 @@ def test_create_rejects_bad_arguments_before_touching_the_device(args):
     assert not h.value
 
 
+@pytest.mark.parametrize("nx,ny,storage", [(32768, 32768, 0), (65536, 16384, 0),
+                                            (65536, 32768, 1), (46341, 46341, 1)])
+def test_create_rejects_planes_of_4_gib(nx, ny, storage):
+    """In-plane offsets are 32-bit byte offsets: a plane of 2^32 bytes or
+    more is refused before any allocation."""
+    L = rrmhd.lib()
+    g = rrmhd.Grid(nx, ny, storage, 0.0)
+    h = ctypes.c_void_p(1234)
+    assert L.rrmhd_create(ctypes.byref(g), 0.6, 0.6, None, None,
+                          ctypes.byref(h)) == rrmhd.EINVAL
+    assert not h.value
+
+
 def test_create_rejects_non_power_of_two_scale():
     L = rrmhd.lib()
     g = rrmhd.Grid(4, 4, 1, 3.0)

@@ -455,7 +455,7 @@ def test_full_size_8192_sampled(storage, k, count):
 # ---------------------------------------------------------------------------
 # Checkpoint / resume
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
 def test_save_load_resume_bitwise(storage):
     note(f"resume {storage}")
     R = rrmhd()
