@@ -38,7 +38,8 @@ enum {
   RRMHD_ENOMEM = -2,     /* device allocation failed */
   RRMHD_EDEVICE = -3,    /* a HIP call failed */
   RRMHD_ENONFINITE = -4, /* a diagnostic came out NaN or infinite */
-  RRMHD_ESTATE = -5      /* e.g. rrmhd_step before rrmhd_init */
+  RRMHD_ESTATE = -5,     /* e.g. rrmhd_step before rrmhd_init */
+  RRMHD_EIO = -6         /* a checkpoint file could not be opened, read or written */
 };
 
 /* Population storage.  Both store f_i - w_i for the fluid populations and
@@ -150,6 +151,27 @@ int rrmhd_save_state(rrmhd *h, void *dst, int64_t bytes);
 int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes,
                      int64_t step_count);
 
+/* Checkpoint files.  rrmhd_save writes a 104-byte header, then the state of
+ * rrmhd_save_state (19 planes in the pull layout).  The header is the magic
+ * "RRMHDCK1", then int32 version (1), nx, ny, storage kind (RRMHD_STORE_F32,
+ * _F16 or _F16_SR; the single-buffer flag is not recorded, the layout
+ * being the same), float codec scale, int32 boundary kind, int32
+ * equilibrium kind, int32 zero, then double tau_f, tau_m, force[2],
+ * b_wall[2], then int64 step count and payload bytes, little-endian.  It
+ * synchronises the handle's stream and copies one plane at a time through
+ * host memory.  A single-buffer handle between its two step forms also
+ * needs a device buffer of the state's size for the gather.
+ * rrmhd_load reads such a file into a handle with the same nx, ny, element
+ * size, codec scale, relaxation times, boundary conditions and equilibrium
+ * kind; the stochastic-rounding flag may differ, since the rounding applies
+ * only to later steps.  It then continues exactly as the saved run would
+ * have (bitwise).  A mismatch or a malformed file gives EINVAL (the handle
+ * is unchanged; rrmhd_last_error_detail names the field); I/O failures give
+ * RRMHD_EIO (a read that fails part-way leaves the handle uninitialised:
+ * ESTATE until rrmhd_init or a load succeeds).  Synchronous. */
+int rrmhd_save(rrmhd *h, const char *path);
+int rrmhd_load(rrmhd *h, const char *path);
+
 /* Launch shape of the step kernel (the tuning knob of the autotuner; the
  * default is picked from the grid).  bx x by threads per workgroup
  * (bx * by <= 256, bx >= 1, by >= 1), ry consecutive rows per thread (>= 1),
@@ -176,6 +198,15 @@ int rrmhd_set_stream(rrmhd *h, void *hip_stream);
  * parameters do not (the graph reads them at run time).  chunk = 0 (the
  * default) launches every step directly.  EINVAL for chunk < 0. */
 int rrmhd_set_graph_chunk(rrmhd *h, int chunk);
+
+/* Debug aid: with on != 0, every later step first fills the buffer it
+ * writes with a NaN pattern (all planes, padding included), so a stored
+ * value that a step fails to write shows up as NaN in the moments and as
+ * RRMHD_ENONFINITE from the diagnostics.  Results are otherwise unchanged
+ * (a step reads only the other buffer); each step costs one more write of
+ * the whole buffer.  For the callers that check kernel coverage (tests);
+ * EINVAL for a single-buffer handle, whose steps read what they write. */
+int rrmhd_set_debug_poison(rrmhd *h, int on);
 
 /* Equilibrium of the fluid populations.  RRMHD_FEQ_ALGORITHM (the default)
  * is the fourth-order Hermite equilibrium the algorithm uses (Eq. feq_4th,

@@ -2,6 +2,7 @@
 // handle, A/B population buffers, stream ordering, error mapping.
 #include <hip/hip_runtime.h>
 
+#include <cerrno>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -65,10 +66,25 @@ struct rrmhd {
   // per starting buffer (or in-place phase), on an internal stream ordered
   // after the caller's stream with events
   int graph_chunk = 0;
+  bool poison = false;  // debug: NaN-fill the destination buffer before each step
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   hipStream_t own = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
+
+// Debug fill of a population buffer with a NaN pattern (32-bit words).
+__global__ void k_poison(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static hipError_t poison_buffer(const rrmhd *h, void *buf, hipStream_t st) {
+  const int64_t words = (int64_t)h->D.plane * rr::kStatePlanes * h->elem / 4;
+  const uint32_t nan = h->elem == 4 ? 0x7fc00000u : 0x7e007e00u;
+  hipLaunchKernelGGL(k_poison, dim3(2048), dim3(256), 0, st, (uint32_t *)buf, words, nan);
+  return hipGetLastError();
+}
 
 static void free_graphs(rrmhd *h) {
   for (auto &g : h->graph)
@@ -85,6 +101,7 @@ const char *rrmhd_strerror(int code) {
     case RRMHD_EDEVICE: return "HIP device error";
     case RRMHD_ENONFINITE: return "non-finite diagnostic";
     case RRMHD_ESTATE: return "invalid state (not initialised)";
+    case RRMHD_EIO: return "checkpoint file I/O error";
     default: return "unknown error";
   }
 }
@@ -254,14 +271,15 @@ static int plain_steps(rrmhd *h, int64_t n, hipStream_t st) {
     if (h->inplace) {
       HIP_OR_RETURN(rr::launch_step_inplace(h->storage, h->D, h->buf[0], h->phase, h->shape, st));
       h->phase ^= 1;
-    } else if (h->closure_on) {
-      HIP_OR_RETURN(rr::launch_step_closure(h->storage, h->D, (const rr::MlpDev *)h->mlp,
-                                            h->buf[h->cur], h->buf[h->cur ^ 1],
-                                            h->closure_grid, st));
-      h->cur ^= 1;
     } else {
-      HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur], h->buf[h->cur ^ 1],
-                                    h->shape, st));
+      if (h->poison) HIP_OR_RETURN(poison_buffer(h, h->buf[h->cur ^ 1], st));
+      if (h->closure_on)
+        HIP_OR_RETURN(rr::launch_step_closure(h->storage, h->D, (const rr::MlpDev *)h->mlp,
+                                              h->buf[h->cur], h->buf[h->cur ^ 1],
+                                              h->closure_grid, st));
+      else
+        HIP_OR_RETURN(rr::launch_step(h->storage, h->D, h->buf[h->cur], h->buf[h->cur ^ 1],
+                                      h->shape, st));
       h->cur ^= 1;
     }
     h->steps++;
@@ -311,6 +329,13 @@ int rrmhd_step(rrmhd *h, int64_t n) {
   if (rc != RRMHD_OK) return rc;
   HIP_OR_RETURN(hipEventRecord(h->ev_out, h->own));
   HIP_OR_RETURN(hipStreamWaitEvent(h->stream, h->ev_out, 0));
+  return RRMHD_OK;
+}
+
+int rrmhd_set_debug_poison(rrmhd *h, int on) {
+  if (!h || (on && h->inplace)) return RRMHD_EINVAL;
+  if (h->poison != (on != 0)) free_graphs(h);
+  h->poison = on != 0;
   return RRMHD_OK;
 }
 
@@ -406,6 +431,167 @@ int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes, int64_t step_coun
   h->cur = 0;
   h->phase = 0;
   h->steps = step_count;
+  h->ready = true;
+  return RRMHD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint file header (little-endian, as written by x86 and read back on
+// the same platform).
+struct CkHeader {
+  char magic[8];
+  int32_t version, nx, ny, storage;
+  float codec_scale;
+  int32_t bc_kind, equilibrium, zero;
+  double tau_f, tau_m, force[2], b_wall[2];
+  int64_t steps, payload;
+};
+static_assert(sizeof(CkHeader) == 104, "checkpoint header layout");
+constexpr char kCkMagic[8] = {'R', 'R', 'M', 'H', 'D', 'C', 'K', '1'};
+
+CkHeader ck_header(const rrmhd *h) {
+  CkHeader c{};
+  std::memcpy(c.magic, kCkMagic, 8);
+  c.version = 1;
+  c.nx = h->D.nx;
+  c.ny = h->D.ny;
+  c.storage = h->storage == RRMHD_STORE_F32 ? RRMHD_STORE_F32
+                                            : (h->D.sr ? RRMHD_STORE_F16_SR : RRMHD_STORE_F16);
+  c.codec_scale = h->D.s;
+  c.bc_kind = h->bc.kind;
+  c.equilibrium = h->D.feq;
+  c.tau_f = h->tau_f;
+  c.tau_m = h->tau_m;
+  for (int k = 0; k < 2; ++k) {
+    c.force[k] = h->bc.force[k];
+    c.b_wall[k] = h->bc.b_wall[k];
+  }
+  c.steps = h->steps;
+  c.payload = (int64_t)h->D.nx * h->D.ny * h->elem * rr::kStatePlanes;
+  return c;
+}
+
+int io_err(const char *what, const char *path) {
+  std::snprintf(g_detail, sizeof g_detail, "%s %s: %s", what, path, std::strerror(errno));
+  return RRMHD_EIO;
+}
+
+int ck_mismatch(const char *field) {
+  std::snprintf(g_detail, sizeof g_detail, "checkpoint does not match the handle: %s", field);
+  return RRMHD_EINVAL;
+}
+
+// Bitwise comparison of doubles: the file must carry exactly the handle's
+// parameters.
+bool same(double a, double b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int rrmhd_save(rrmhd *h, const char *path) {
+  if (!h || !path) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  const CkHeader hd = ck_header(h);
+  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
+  void *tmp = nullptr;
+  const char *base = (const char *)h->buf[h->cur];
+  size_t pitch = (size_t)h->D.plane * h->elem;
+  if (h->inplace && h->phase) {
+    // between the two step forms: gather the swapped layout first
+    HIP_OR_RETURN(hipMalloc(&tmp, row * rr::kStatePlanes));
+    hipError_t e = rr::launch_swapped_to_pull(h->storage, h->D, h->buf[0], tmp, h->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return dev_err(e, "launch_swapped_to_pull");
+    }
+    base = (const char *)tmp;
+    pitch = row;
+  }
+  int rc = RRMHD_OK;
+  char *host = nullptr;
+  FILE *f = nullptr;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) rc = dev_err(e, "hipStreamSynchronize");
+  if (rc == RRMHD_OK && !(host = new (std::nothrow) char[row])) rc = RRMHD_ENOMEM;
+  if (rc == RRMHD_OK && !(f = std::fopen(path, "wb"))) rc = io_err("cannot open", path);
+  if (rc == RRMHD_OK && std::fwrite(&hd, sizeof hd, 1, f) != 1) rc = io_err("cannot write", path);
+  for (int p = 0; p < rr::kStatePlanes && rc == RRMHD_OK; ++p) {
+    e = hipMemcpy(host, base + (size_t)p * pitch, row, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
+    else if (std::fwrite(host, 1, row, f) != row) rc = io_err("cannot write", path);
+  }
+  if (f && std::fclose(f) != 0 && rc == RRMHD_OK) rc = io_err("cannot close", path);
+  delete[] host;
+  if (tmp) (void)hipFree(tmp);
+  return rc;
+}
+
+int rrmhd_load(rrmhd *h, const char *path) {
+  if (!h || !path) return RRMHD_EINVAL;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return io_err("cannot open", path);
+  CkHeader hd{};
+  int rc = RRMHD_OK;
+  if (std::fread(&hd, sizeof hd, 1, f) != 1) rc = ck_mismatch("file shorter than the header");
+  const CkHeader me = ck_header(h);
+  if (rc == RRMHD_OK) {
+    const bool mine16 = me.storage != RRMHD_STORE_F32, file16 = hd.storage != RRMHD_STORE_F32;
+    if (std::memcmp(hd.magic, kCkMagic, 8) != 0 || hd.version != 1) rc = ck_mismatch("magic/version");
+    else if (hd.nx != me.nx || hd.ny != me.ny) rc = ck_mismatch("grid size");
+    else if (hd.storage < RRMHD_STORE_F32 || hd.storage > RRMHD_STORE_F16_SR || mine16 != file16)
+      rc = ck_mismatch("storage");
+    else if (hd.codec_scale != me.codec_scale) rc = ck_mismatch("codec scale");
+    else if (!same(hd.tau_f, me.tau_f) || !same(hd.tau_m, me.tau_m)) rc = ck_mismatch("tau");
+    else if (hd.bc_kind != me.bc_kind || !same(hd.force[0], me.force[0]) ||
+             !same(hd.force[1], me.force[1]) || !same(hd.b_wall[0], me.b_wall[0]) ||
+             !same(hd.b_wall[1], me.b_wall[1]))
+      rc = ck_mismatch("boundary conditions");
+    else if (hd.equilibrium != me.equilibrium) rc = ck_mismatch("equilibrium");
+    else if (hd.payload != me.payload || hd.steps < 0) rc = ck_mismatch("payload size / step count");
+  }
+  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
+  const size_t pitch = (size_t)h->D.plane * h->elem;
+  char *host = nullptr;
+  if (rc == RRMHD_OK) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = dev_err(e, "hipStreamSynchronize");
+  }
+  if (rc == RRMHD_OK && !(host = new (std::nothrow) char[row])) rc = RRMHD_ENOMEM;
+  // the whole payload must be in the file before the device state is
+  // touched, so a short file leaves the handle unchanged
+  if (rc == RRMHD_OK) {
+    if (std::fseek(f, 0, SEEK_END) != 0) {
+      rc = io_err("cannot seek", path);
+    } else {
+      const long end = std::ftell(f);
+      if (end < 0) rc = io_err("cannot seek", path);
+      else if ((int64_t)end != (int64_t)sizeof hd + hd.payload) rc = ck_mismatch("file size");
+      else if (std::fseek(f, (long)sizeof hd, SEEK_SET) != 0) rc = io_err("cannot seek", path);
+    }
+  }
+  bool touched = false;
+  for (int p = 0; p < rr::kStatePlanes && rc == RRMHD_OK; ++p) {
+    if (std::fread(host, 1, row, f) != row) {
+      rc = io_err("cannot read", path);
+      break;
+    }
+    touched = true;
+    hipError_t e = hipMemcpy((char *)h->buf[0] + (size_t)p * pitch, host, row, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
+  }
+  std::fclose(f);
+  delete[] host;
+  if (rc != RRMHD_OK) {
+    if (touched) h->ready = false;  // part of the state was overwritten
+    return rc;
+  }
+  h->cur = 0;
+  h->phase = 0;
+  h->steps = hd.steps;
   h->ready = true;
   return RRMHD_OK;
 }

@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librrmhd.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6
 STORE_F32, STORE_F16, STORE_INPLACE = 0, 1, 0x100
 STORE_F16_SR = 2
 BC_PERIODIC, BC_WALLS_Y = 0, 1
@@ -22,8 +22,9 @@ FEQ_ALGORITHM, FEQ_FULL_MAXWELL = 0, 1
 EXPORTED = [
     "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
     "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
-    "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state",
+    "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state", "rrmhd_save", "rrmhd_load",
     "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium", "rrmhd_set_graph_chunk",
+    "rrmhd_set_debug_poison",
     "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
     "rrmhd_batch_create", "rrmhd_batch_init", "rrmhd_batch_step",
@@ -59,7 +60,7 @@ class RRMHDError(RuntimeError):
         msg = L.rrmhd_strerror(code).decode()
         det = L.rrmhd_last_error_detail().decode()
         super().__init__(f"{where}: {msg} ({code})" + (f" [{det}]" if det and
-                                                      code == EDEVICE else ""))
+                                                      code in (EDEVICE, EIO) else ""))
 
 
 _lib = None
@@ -90,6 +91,9 @@ def lib():
         L.rrmhd_state_bytes.restype = i64
         L.rrmhd_save_state.argtypes = [vp, vp, i64]
         L.rrmhd_load_state.argtypes = [vp, vp, i64, i64]
+        L.rrmhd_save.argtypes = [vp, ctypes.c_char_p]
+        L.rrmhd_set_debug_poison.argtypes = [vp, ctypes.c_int]
+        L.rrmhd_load.argtypes = [vp, ctypes.c_char_p]
         L.rrmhd_set_stream.argtypes = [vp, vp]
         ci = ctypes.c_int
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
@@ -331,6 +335,19 @@ class Solver:
         _check(lib().rrmhd_load_state(self._h, ctypes.c_void_p(src.data_ptr()),
                                       src.numel() * src.element_size(),
                                       int(step_count)), "rrmhd_load_state")
+
+    def set_debug_poison(self, on=True):
+        """NaN-fill the destination buffer before every step (debug)."""
+        _check(lib().rrmhd_set_debug_poison(self._h, int(bool(on))), "rrmhd_set_debug_poison")
+
+    def save(self, path):
+        """Write a checkpoint file (header + state); synchronous."""
+        _check(lib().rrmhd_save(self._h, os.fsencode(path)), "rrmhd_save")
+
+    def load(self, path):
+        """Read a checkpoint file written by save() into this handle (same
+        grid, storage, relaxation times, boundary conditions)."""
+        _check(lib().rrmhd_load(self._h, os.fsencode(path)), "rrmhd_load")
 
     def set_launch(self, bx, by, ry=1, xcd=1, nt=0):
         _check(lib().rrmhd_set_launch(self._h, int(bx), int(by), int(ry),

@@ -44,8 +44,9 @@ def test_binding_lists_every_declared_symbol():
 
 def test_strerror_without_device():
     L = rrmhd.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.rrmhd_strerror(code)
+    assert L.rrmhd_strerror(-6) != L.rrmhd_strerror(-99)
 
 
 @pytest.mark.parametrize("args", [
@@ -104,6 +105,8 @@ def test_null_handle_calls_are_rejected():
                                  None) == rrmhd.EINVAL
     assert L.rrmhd_closure_enable(None, 1) == rrmhd.EINVAL
     assert L.rrmhd_autotune(None, None, 3, None, None, None, None) == rrmhd.EINVAL
+    assert L.rrmhd_save(None, b"/nonexistent/x.ck") == rrmhd.EINVAL
+    assert L.rrmhd_load(None, b"/nonexistent/x.ck") == rrmhd.EINVAL
 
 
 def test_create_rejects_unknown_storage_flags():
