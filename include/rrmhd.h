@@ -260,6 +260,17 @@ int rrmhd3d_invariants(rrmhd3d *h, double out[7]);
  * not depend on it.  Host-side only. */
 int rrmhd3d_set_launch(rrmhd3d *h, int bx, int by);
 int rrmhd3d_destroy(rrmhd3d *h);
+/* Checkpoint files of the 3D handle, as rrmhd_save / rrmhd_load: a 64-byte
+ * header (magic "RRMHD3C1", int32 version 1, nx, ny, nz, storage kind,
+ * zero, double tau_f, tau_m, int64 step count, payload bytes) and the 48
+ * planes of nx*ny*nz stored values in the pull layout (a single-buffer
+ * handle between its two step forms gathers them through a temporary
+ * device buffer of the state's size).  Load requires the same box,
+ * storage kind and relaxation times (EINVAL otherwise, handle unchanged),
+ * accepts files of one- and two-buffer handles alike, and continues
+ * bitwise; RRMHD_EIO for I/O failures.  Synchronous. */
+int rrmhd3d_save(rrmhd3d *h, const char *path);
+int rrmhd3d_load(rrmhd3d *h, const char *path);
 
 /* ---- Batched ensemble --------------------------------------------------
  * Many independent doubly periodic domains of uneven sizes and relaxation

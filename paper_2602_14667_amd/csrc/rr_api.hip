@@ -479,16 +479,72 @@ int io_err(const char *what, const char *path) {
   return RRMHD_EIO;
 }
 
-int ck_mismatch(const char *field) {
-  std::snprintf(g_detail, sizeof g_detail, "checkpoint does not match the handle: %s", field);
-  return RRMHD_EINVAL;
-}
-
 // Bitwise comparison of doubles: the file must carry exactly the handle's
 // parameters.
 bool same(double a, double b) { return std::memcmp(&a, &b, sizeof a) == 0; }
 
 }  // namespace
+
+int rr_ck_mismatch(const char *field) {
+  std::snprintf(g_detail, sizeof g_detail, "checkpoint does not match the handle: %s", field);
+  return RRMHD_EINVAL;
+}
+
+int rr_ck_write(const char *path, const void *hdr, size_t hdr_bytes, const char *base,
+                size_t pitch, size_t row, int planes) {
+  char *host = new (std::nothrow) char[row];
+  if (!host) return RRMHD_ENOMEM;
+  int rc = RRMHD_OK;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) rc = io_err("cannot open", path);
+  if (rc == RRMHD_OK && std::fwrite(hdr, hdr_bytes, 1, f) != 1) rc = io_err("cannot write", path);
+  for (int p = 0; p < planes && rc == RRMHD_OK; ++p) {
+    hipError_t e = hipMemcpy(host, base + (size_t)p * pitch, row, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
+    else if (std::fwrite(host, 1, row, f) != row) rc = io_err("cannot write", path);
+  }
+  if (f && std::fclose(f) != 0 && rc == RRMHD_OK) rc = io_err("cannot close", path);
+  delete[] host;
+  return rc;
+}
+
+int rr_ck_open(const char *path, void *hdr, size_t hdr_bytes, FILE **out) {
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return io_err("cannot open", path);
+  if (std::fread(hdr, hdr_bytes, 1, f) != 1) {
+    std::fclose(f);
+    return rr_ck_mismatch("file shorter than the header");
+  }
+  *out = f;
+  return RRMHD_OK;
+}
+
+int rr_ck_read_planes(FILE *f, const char *path, size_t hdr_bytes, char *base, size_t pitch,
+                      size_t row, int planes, bool *touched) {
+  *touched = false;
+  // the whole payload must be in the file before the device state is
+  // touched, so a short file leaves the handle unchanged
+  if (std::fseek(f, 0, SEEK_END) != 0) return io_err("cannot seek", path);
+  const long end = std::ftell(f);
+  if (end < 0) return io_err("cannot seek", path);
+  if ((uint64_t)end != hdr_bytes + (uint64_t)row * planes) return rr_ck_mismatch("file size");
+  if (std::fseek(f, (long)hdr_bytes, SEEK_SET) != 0) return io_err("cannot seek", path);
+  char *host = new (std::nothrow) char[row];
+  if (!host) return RRMHD_ENOMEM;
+  int rc = RRMHD_OK;
+  for (int p = 0; p < planes && rc == RRMHD_OK; ++p) {
+    if (std::fread(host, 1, row, f) != row) {
+      rc = io_err("cannot read", path);
+      break;
+    }
+    *touched = true;
+    hipError_t e = hipMemcpy(base + (size_t)p * pitch, host, row, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
+  }
+  delete[] host;
+  return rc;
+}
 
 extern "C" {
 
@@ -511,80 +567,42 @@ int rrmhd_save(rrmhd *h, const char *path) {
     base = (const char *)tmp;
     pitch = row;
   }
-  int rc = RRMHD_OK;
-  char *host = nullptr;
-  FILE *f = nullptr;
   hipError_t e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) rc = dev_err(e, "hipStreamSynchronize");
-  if (rc == RRMHD_OK && !(host = new (std::nothrow) char[row])) rc = RRMHD_ENOMEM;
-  if (rc == RRMHD_OK && !(f = std::fopen(path, "wb"))) rc = io_err("cannot open", path);
-  if (rc == RRMHD_OK && std::fwrite(&hd, sizeof hd, 1, f) != 1) rc = io_err("cannot write", path);
-  for (int p = 0; p < rr::kStatePlanes && rc == RRMHD_OK; ++p) {
-    e = hipMemcpy(host, base + (size_t)p * pitch, row, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
-    else if (std::fwrite(host, 1, row, f) != row) rc = io_err("cannot write", path);
-  }
-  if (f && std::fclose(f) != 0 && rc == RRMHD_OK) rc = io_err("cannot close", path);
-  delete[] host;
+  int rc = e != hipSuccess ? dev_err(e, "hipStreamSynchronize")
+                           : rr_ck_write(path, &hd, sizeof hd, base, pitch, row, rr::kStatePlanes);
   if (tmp) (void)hipFree(tmp);
   return rc;
 }
 
 int rrmhd_load(rrmhd *h, const char *path) {
   if (!h || !path) return RRMHD_EINVAL;
-  FILE *f = std::fopen(path, "rb");
-  if (!f) return io_err("cannot open", path);
   CkHeader hd{};
-  int rc = RRMHD_OK;
-  if (std::fread(&hd, sizeof hd, 1, f) != 1) rc = ck_mismatch("file shorter than the header");
+  FILE *f = nullptr;
+  int rc = rr_ck_open(path, &hd, sizeof hd, &f);
+  if (rc != RRMHD_OK) return rc;
   const CkHeader me = ck_header(h);
-  if (rc == RRMHD_OK) {
-    const bool mine16 = me.storage != RRMHD_STORE_F32, file16 = hd.storage != RRMHD_STORE_F32;
-    if (std::memcmp(hd.magic, kCkMagic, 8) != 0 || hd.version != 1) rc = ck_mismatch("magic/version");
-    else if (hd.nx != me.nx || hd.ny != me.ny) rc = ck_mismatch("grid size");
-    else if (hd.storage < RRMHD_STORE_F32 || hd.storage > RRMHD_STORE_F16_SR || mine16 != file16)
-      rc = ck_mismatch("storage");
-    else if (hd.codec_scale != me.codec_scale) rc = ck_mismatch("codec scale");
-    else if (!same(hd.tau_f, me.tau_f) || !same(hd.tau_m, me.tau_m)) rc = ck_mismatch("tau");
-    else if (hd.bc_kind != me.bc_kind || !same(hd.force[0], me.force[0]) ||
-             !same(hd.force[1], me.force[1]) || !same(hd.b_wall[0], me.b_wall[0]) ||
-             !same(hd.b_wall[1], me.b_wall[1]))
-      rc = ck_mismatch("boundary conditions");
-    else if (hd.equilibrium != me.equilibrium) rc = ck_mismatch("equilibrium");
-    else if (hd.payload != me.payload || hd.steps < 0) rc = ck_mismatch("payload size / step count");
-  }
-  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
-  const size_t pitch = (size_t)h->D.plane * h->elem;
-  char *host = nullptr;
+  const bool mine16 = me.storage != RRMHD_STORE_F32, file16 = hd.storage != RRMHD_STORE_F32;
+  if (std::memcmp(hd.magic, kCkMagic, 8) != 0 || hd.version != 1) rc = rr_ck_mismatch("magic/version");
+  else if (hd.nx != me.nx || hd.ny != me.ny) rc = rr_ck_mismatch("grid size");
+  else if (hd.storage < RRMHD_STORE_F32 || hd.storage > RRMHD_STORE_F16_SR || mine16 != file16)
+    rc = rr_ck_mismatch("storage");
+  else if (hd.codec_scale != me.codec_scale) rc = rr_ck_mismatch("codec scale");
+  else if (!same(hd.tau_f, me.tau_f) || !same(hd.tau_m, me.tau_m)) rc = rr_ck_mismatch("tau");
+  else if (hd.bc_kind != me.bc_kind || !same(hd.force[0], me.force[0]) ||
+           !same(hd.force[1], me.force[1]) || !same(hd.b_wall[0], me.b_wall[0]) ||
+           !same(hd.b_wall[1], me.b_wall[1]))
+    rc = rr_ck_mismatch("boundary conditions");
+  else if (hd.equilibrium != me.equilibrium) rc = rr_ck_mismatch("equilibrium");
+  else if (hd.payload != me.payload || hd.steps < 0) rc = rr_ck_mismatch("payload size / step count");
   if (rc == RRMHD_OK) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = dev_err(e, "hipStreamSynchronize");
   }
-  if (rc == RRMHD_OK && !(host = new (std::nothrow) char[row])) rc = RRMHD_ENOMEM;
-  // the whole payload must be in the file before the device state is
-  // touched, so a short file leaves the handle unchanged
-  if (rc == RRMHD_OK) {
-    if (std::fseek(f, 0, SEEK_END) != 0) {
-      rc = io_err("cannot seek", path);
-    } else {
-      const long end = std::ftell(f);
-      if (end < 0) rc = io_err("cannot seek", path);
-      else if ((int64_t)end != (int64_t)sizeof hd + hd.payload) rc = ck_mismatch("file size");
-      else if (std::fseek(f, (long)sizeof hd, SEEK_SET) != 0) rc = io_err("cannot seek", path);
-    }
-  }
   bool touched = false;
-  for (int p = 0; p < rr::kStatePlanes && rc == RRMHD_OK; ++p) {
-    if (std::fread(host, 1, row, f) != row) {
-      rc = io_err("cannot read", path);
-      break;
-    }
-    touched = true;
-    hipError_t e = hipMemcpy((char *)h->buf[0] + (size_t)p * pitch, host, row, hipMemcpyHostToDevice);
-    if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
-  }
+  if (rc == RRMHD_OK)
+    rc = rr_ck_read_planes(f, path, sizeof hd, (char *)h->buf[0], (size_t)h->D.plane * h->elem,
+                           (size_t)h->D.nx * h->D.ny * h->elem, rr::kStatePlanes, &touched);
   std::fclose(f);
-  delete[] host;
   if (rc != RRMHD_OK) {
     if (touched) h->ready = false;  // part of the state was overwritten
     return rc;

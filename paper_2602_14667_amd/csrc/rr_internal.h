@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 
 #include "../../include/rrmhd.h"
 
@@ -21,6 +22,18 @@ RR_HIDDEN int rr_handle_inplace(const rrmhd *h);
 // record the HIP message of a device error for rrmhd_last_error_detail and
 // map it to RRMHD_ENOMEM or RRMHD_EDEVICE
 RR_HIDDEN int rr_device_error(hipError_t e, const char *what);
+// Checkpoint files (synchronous, through one plane of host memory):
+// write a header and `planes` planes of `row` bytes taken from device memory
+// at base + p * pitch; open a file and read its header; after the caller has
+// checked the header, check the file size and read the planes back
+// (*touched: some device memory was written before a failure); record a
+// header mismatch (RRMHD_EINVAL, the field named in the error detail).
+RR_HIDDEN int rr_ck_write(const char *path, const void *hdr, size_t hdr_bytes, const char *base,
+                          size_t pitch, size_t row, int planes);
+RR_HIDDEN int rr_ck_open(const char *path, void *hdr, size_t hdr_bytes, FILE **f);
+RR_HIDDEN int rr_ck_read_planes(FILE *f, const char *path, size_t hdr_bytes, char *base,
+                                size_t pitch, size_t row, int planes, bool *touched);
+RR_HIDDEN int rr_ck_mismatch(const char *field);
 extern "C" {
 // batch: domain sizes (arrays may be NULL to query n and storage)
 RR_HIDDEN int rr_batch_domains(const rrmhd_batch *b, int *n, int *storage, int *nx,

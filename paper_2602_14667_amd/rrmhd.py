@@ -39,7 +39,7 @@ EXPORTED = [
     "rrmhd_current_vorticity",
     "rrmhd3d_create", "rrmhd3d_init", "rrmhd3d_step", "rrmhd3d_step_count",
     "rrmhd3d_moments", "rrmhd3d_diagnostics", "rrmhd3d_invariants",
-    "rrmhd3d_set_launch", "rrmhd3d_destroy",
+    "rrmhd3d_set_launch", "rrmhd3d_destroy", "rrmhd3d_save", "rrmhd3d_load",
 ]
 
 
@@ -93,6 +93,8 @@ def lib():
         L.rrmhd_load_state.argtypes = [vp, vp, i64, i64]
         L.rrmhd_save.argtypes = [vp, ctypes.c_char_p]
         L.rrmhd_set_debug_poison.argtypes = [vp, ctypes.c_int]
+        L.rrmhd3d_save.argtypes = [vp, ctypes.c_char_p]
+        L.rrmhd3d_load.argtypes = [vp, ctypes.c_char_p]
         L.rrmhd_load.argtypes = [vp, ctypes.c_char_p]
         L.rrmhd_set_stream.argtypes = [vp, vp]
         ci = ctypes.c_int
@@ -460,6 +462,14 @@ class Solver3D:
 
     def set_launch(self, bx, by):
         _check(lib().rrmhd3d_set_launch(self._h, int(bx), int(by)), "rrmhd3d_set_launch")
+
+    def save(self, path):
+        """Write a checkpoint file (header + state); synchronous."""
+        _check(lib().rrmhd3d_save(self._h, os.fsencode(path)), "rrmhd3d_save")
+
+    def load(self, path):
+        """Read a checkpoint file written by save() into this handle."""
+        _check(lib().rrmhd3d_load(self._h, os.fsencode(path)), "rrmhd3d_load")
 
 
 def bandwidth_probe(dst, src, stream=None):

@@ -142,3 +142,62 @@ def test_save_before_init_is_refused(tmp_path):
     s = R.Solver(16, 16, 0.6, 0.6)
     assert R.lib().rrmhd_save(s._h, str(tmp_path / "x.ck").encode()) == R.ESTATE
     s.close()
+
+
+def moments3(s):
+    rho, u, b = s.moments()
+    torch.cuda.synchronize()
+    return [rho.cpu().numpy(), u.cpu().numpy(), b.cpu().numpy()]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("src_inplace,dst_inplace", [(False, False), (True, True), (True, False),
+                                                     (False, True)])
+def test_3d_save_load_continue_bitwise(tmp_path, storage, src_inplace, dst_inplace):
+    note(f"3D checkpoint {storage} inplace {src_inplace}->{dst_inplace}")
+    R = rrmhd()
+    shape = (9, 6, 5)
+    u, b = inputs.random_modes3d(*shape, 0.04, seed=3)
+    a = R.Solver3D(*shape, 0.55, 0.6, storage=storage, inplace=src_inplace)
+    a.init(dev(u), dev(b))
+    a.step(7)  # odd: a single-buffer handle sits between its two step forms
+    path = str(tmp_path / "box.ck")
+    a.save(path)
+    assert os.path.getsize(path) == 64 + 9 * 6 * 5 * 48 * (4 if storage == "f32" else 2)
+    a.step(4)
+    ref = moments3(a)
+    c = R.Solver3D(*shape, 0.55, 0.6, storage=storage, inplace=dst_inplace)
+    c.load(path)
+    assert c.step_count == 7
+    c.step(4)
+    got = moments3(c)
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
+    a.close(); c.close()
+
+
+def test_3d_checkpoint_refusals(tmp_path):
+    R = rrmhd()
+    L = R.lib()
+    shape = (6, 5, 4)
+    u, b = inputs.random_modes3d(*shape, 0.04, seed=4)
+    a = R.Solver3D(*shape, 0.55, 0.6)
+    a.init(dev(u), dev(b))
+    a.step(2)
+    path = str(tmp_path / "a.ck")
+    a.save(path)
+    for args in (((6, 5, 5), 0.55, "f32"), (shape, 0.56, "f32"), (shape, 0.55, "f16")):
+        o = R.Solver3D(*args[0], args[1], 0.6, storage=args[2])
+        assert L.rrmhd3d_load(o._h, path.encode()) == R.EINVAL, args
+        o.close()
+    # a two-dimensional checkpoint is not a three-dimensional one
+    s2 = R.Solver(8, 8, 0.55, 0.6)
+    u2, b2 = inputs.random_modes(8, 8, 0.04, seed=1)
+    s2.init(dev(u2), dev(b2))
+    p2 = str(tmp_path / "two.ck")
+    s2.save(p2)
+    assert L.rrmhd3d_load(a._h, p2.encode()) == R.EINVAL
+    assert L.rrmhd_load(s2._h, path.encode()) == R.EINVAL
+    assert L.rrmhd3d_load(a._h, str(tmp_path / "none.ck").encode()) == R.EIO
+    assert a.step_count == 2
+    a.close(); s2.close()
