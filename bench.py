@@ -47,6 +47,25 @@ def measured_traffic(storage, n, dims=2):
     return t.get("bytes_per_launch")
 
 
+def environment(torch):
+    """Where the numbers were taken: GPU, HIP runtime and torch versions, host
+    CPU model and thread count."""
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    prop = torch.cuda.get_device_properties(0)
+    return {"gpu": torch.cuda.get_device_name(0), "arch": getattr(prop, "gcnArchName", None),
+            "device_memory_GiB": round(prop.total_memory / 2 ** 30, 1),
+            "compute_units": prop.multi_processor_count, "hip": torch.version.hip,
+            "torch": torch.__version__, "cpu_model": cpu, "host_threads": os.cpu_count()}
+
+
 def cpu_baseline(n_sample=2048, steps=60):
     """The FP64 oracle on a bounded sample of the same workload: all host
     threads on 2048^2 x 60 steps, and one thread on 512^2 x 20 steps."""
@@ -724,6 +743,7 @@ def main():
                               (("E_kin", ek), ("E_mag", em), ("max_div_b", dv))},
         "diagnostics_ms_per_call": round(diag_ms, 4),
         "kernel_hash": kernel_hash(),
+        "env": environment(torch),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

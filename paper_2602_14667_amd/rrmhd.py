@@ -338,6 +338,41 @@ class Solver:
                                       src.numel() * src.element_size(),
                                       int(step_count)), "rrmhd_load_state")
 
+    def run(self, n, every, log=None):
+        """Advance n steps, taking the diagnostics and invariants after every
+        `every` steps (and after the last).  Returns the records; with `log`
+        (a path, appended to, or an open text file) each record is also
+        written as one JSON line.  Non-finite values are recorded as null."""
+        import json
+        import math
+
+        def fin(v):
+            return v if math.isfinite(v) else None
+
+        own = isinstance(log, (str, bytes, os.PathLike))
+        fh = open(log, "a") if own else log
+        recs = []
+        try:
+            left = int(n)
+            while left > 0:
+                k = min(int(every), left)
+                self.step(k)
+                left -= k
+                ek, em, dv = self.diagnostics(allow_nonfinite=True)
+                inv = self.invariants()
+                rec = {"step": self.step_count, "E_kin": fin(ek), "E_mag": fin(em),
+                       "max_div_b": fin(dv), "mass": fin(inv[0]),
+                       "momentum": [fin(inv[1]), fin(inv[2])],
+                       "sum_b": [fin(inv[3]), fin(inv[4])]}
+                recs.append(rec)
+                if fh is not None:
+                    fh.write(json.dumps(rec) + "\n")
+                    fh.flush()
+        finally:
+            if own:
+                fh.close()
+        return recs
+
     def set_debug_poison(self, on=True):
         """NaN-fill the destination buffer before every step (debug)."""
         _check(lib().rrmhd_set_debug_poison(self._h, int(bool(on))), "rrmhd_set_debug_poison")
