@@ -1,0 +1,80 @@
+"""The largest two-dimensional grid the library accepts in FP32 storage:
+32768 x 32767 nodes (each plane just under 4 GiB, the limit of the 32-bit
+in-plane byte offsets; 163 GB of populations in two buffers).  After three
+steps, sampled nodes, including the last nodes of the grid at the top of the
+offset range, match the FP64 oracle run on 7 x 7 patches around them (after
+k steps a node depends only on nodes within distance k).  The fields are
+built on the device; the test is skipped when the card has less free memory
+than it needs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_14667_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NX, NY, K, TAU, A = 32768, 32767, 3, 0.52, 0.04
+
+
+def fields_np(xs, ys):
+    """u, b of the test at node coordinates (arrays of x and y indices)."""
+    x = 2 * math.pi * xs / NX
+    y = 2 * math.pi * ys / NY
+    u = np.stack([-A * np.sin(y) + 0.01 * np.cos(3 * x + y), A * np.sin(x) + 0.01 * np.sin(2 * y)])
+    b = np.stack([-A * np.sin(y), A * np.sin(2 * x) + 0.01 * np.cos(x - 2 * y)])
+    return u, b
+
+
+def test_largest_fp32_grid_sampled():
+    from paper_2602_14667_amd import rrmhd as R
+    R.lib()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 215 * 2 ** 30:
+        pytest.skip(f"needs ~215 GiB of free device memory, {free / 2 ** 30:.0f} GiB free")
+    print(f"[gpu] largest FP32 grid {NX}x{NY}", flush=True)
+    s = R.Solver(NX, NY, TAU, TAU)
+    X = (torch.arange(NX, dtype=torch.float64, device="cuda") * (2 * math.pi / NX))[None, :]
+    ys = torch.arange(NY, dtype=torch.float64, device="cuda") * (2 * math.pi / NY)
+    u = torch.empty((2, NY, NX), dtype=torch.float64, device="cuda")
+    b = torch.empty_like(u)
+    for r0 in range(0, NY, 2048):  # row chunks keep the temporaries small
+        Y = ys[r0:r0 + 2048, None]
+        u[0, r0:r0 + 2048] = -A * torch.sin(Y) + 0.01 * torch.cos(3 * X + Y)
+        u[1, r0:r0 + 2048] = A * torch.sin(X) + 0.01 * torch.sin(2 * Y)
+        b[0, r0:r0 + 2048] = -A * torch.sin(Y) + 0.0 * X
+        b[1, r0:r0 + 2048] = A * torch.sin(2 * X) + 0.01 * torch.cos(X - 2 * Y)
+    s.init(u, b)
+    del u, b, X, Y, ys
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    s.step(K)
+    rho, uu, bb = s.moments()
+    idx = inputs.counter_u64(11, 5, np.arange(60))
+    pts = [(int(idx[2 * i] % NX), int(idx[2 * i + 1] % NY)) for i in range(30)]
+    pts += [(0, 0), (NX - 1, NY - 1), (NX - 1, 0), (0, NY - 1), (NX - 2, NY - 1)]
+    got = np.array([[float(rho[y, x])] + [float(uu[a, y, x]) for a in range(2)]
+                    + [float(bb[a, y, x]) for a in range(2)] for x, y in pts])
+    s.close()
+    del rho, uu, bb
+    torch.cuda.empty_cache()
+    w = 2 * K + 1
+    ref = []
+    for x, y in pts:
+        px = (np.arange(x - K, x + K + 1) % NX)[None, :].repeat(w, 0)
+        py = (np.arange(y - K, y + K + 1) % NY)[:, None].repeat(w, 1)
+        pu, pb = fields_np(px, py)
+        o = oracle.Oracle(w, w, TAU, TAU)
+        o.init(pu, pb)
+        o.step(K)
+        r, ou, ob = o.moments()
+        o.close()
+        ref.append([r[K, K], ou[0, K, K], ou[1, K, K], ob[0, K, K], ob[1, K, K]])
+    ref = np.array(ref)
+    err = np.max(np.abs(got - ref) / np.array([1.0, A, A, A, A]), axis=0)
+    print(f"[gpu]   max |err| / field scale: {err}", flush=True)
+    assert np.all(err < 1e-6), err
