@@ -1,6 +1,7 @@
-"""The largest two-dimensional grid the library accepts in FP32 storage:
-32768 x 32767 nodes (each plane just under 4 GiB, the limit of the 32-bit
-in-plane byte offsets; 163 GB of populations in two buffers).  After three
+"""The largest two-dimensional grids the library accepts: 32768 x 32767
+nodes in FP32 storage and 46340 x 46340 in FP16 (each plane just under
+4 GiB, the limit of the 32-bit in-plane byte offsets; 163 GB of populations
+in two buffers; FP16 runs the two-node kernel).  After three
 steps, sampled nodes, including the last nodes of the grid at the top of the
 offset range, match the FP64 oracle run on 7 x 7 patches around them (after
 k steps a node depends only on nodes within distance k).  The fields are
@@ -17,10 +18,10 @@ from paper_2602_14667_amd import inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-NX, NY, K, TAU, A = 32768, 32767, 3, 0.52, 0.04
+K, TAU, A = 3, 0.52, 0.04
 
 
-def fields_np(xs, ys):
+def fields_np(xs, ys, NX, NY):
     """u, b of the test at node coordinates (arrays of x and y indices)."""
     x = 2 * math.pi * xs / NX
     y = 2 * math.pi * ys / NY
@@ -29,15 +30,17 @@ def fields_np(xs, ys):
     return u, b
 
 
-def test_largest_fp32_grid_sampled():
+@pytest.mark.parametrize("storage,NX,NY,need_gib,tol", [("f32", 32768, 32767, 215, 1e-6),
+                                                      ("f16", 46340, 46340, 245, 3e-3)])
+def test_largest_grid_sampled(storage, NX, NY, need_gib, tol):
     from paper_2602_14667_amd import rrmhd as R
     R.lib()
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    if free < 215 * 2 ** 30:
-        pytest.skip(f"needs ~215 GiB of free device memory, {free / 2 ** 30:.0f} GiB free")
-    print(f"[gpu] largest FP32 grid {NX}x{NY}", flush=True)
-    s = R.Solver(NX, NY, TAU, TAU)
+    if free < need_gib * 2 ** 30:
+        pytest.skip(f"needs ~{need_gib} GiB of free device memory, {free / 2 ** 30:.0f} GiB free")
+    print(f"[gpu] largest {storage} grid {NX}x{NY}", flush=True)
+    s = R.Solver(NX, NY, TAU, TAU, storage=storage)
     X = (torch.arange(NX, dtype=torch.float64, device="cuda") * (2 * math.pi / NX))[None, :]
     ys = torch.arange(NY, dtype=torch.float64, device="cuda") * (2 * math.pi / NY)
     u = torch.empty((2, NY, NX), dtype=torch.float64, device="cuda")
@@ -67,7 +70,7 @@ def test_largest_fp32_grid_sampled():
     for x, y in pts:
         px = (np.arange(x - K, x + K + 1) % NX)[None, :].repeat(w, 0)
         py = (np.arange(y - K, y + K + 1) % NY)[:, None].repeat(w, 1)
-        pu, pb = fields_np(px, py)
+        pu, pb = fields_np(px, py, NX, NY)
         o = oracle.Oracle(w, w, TAU, TAU)
         o.init(pu, pb)
         o.step(K)
@@ -77,4 +80,4 @@ def test_largest_fp32_grid_sampled():
     ref = np.array(ref)
     err = np.max(np.abs(got - ref) / np.array([1.0, A, A, A, A]), axis=0)
     print(f"[gpu]   max |err| / field scale: {err}", flush=True)
-    assert np.all(err < 1e-6), err
+    assert np.all(err < tol), err
