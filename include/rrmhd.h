@@ -64,9 +64,12 @@ enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
  * with random bits from a counter-based hash of the step count, the node
  * and the plane, so runs are reproducible and independent of the launch
  * shape.  An optional variant of the prescribed round-to-nearest-even
- * codec, reported separately; initialisation still rounds to nearest.  Not
- * with RRMHD_STORE_INPLACE, graph replay, the learned closure or the
- * equilibrium ablation (EINVAL); the two-node FP16 update is not used. */
+ * codec, reported separately; initialisation still rounds to nearest.  It
+ * combines with RRMHD_STORE_INPLACE (each value draws the bits of the node
+ * that computes it and of its own plane, whichever slot receives it, so the
+ * single-buffer handle stays bitwise equal to the two-buffer one); not with
+ * graph replay, the learned closure or the equilibrium ablation (EINVAL);
+ * the two-node FP16 update is not used. */
 enum { RRMHD_STORE_F16_SR = 2 };
 
 /* Boundary kinds.  PERIODIC: doubly periodic.  WALLS_Y: periodic in x,

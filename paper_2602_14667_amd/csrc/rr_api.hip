@@ -140,7 +140,6 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   if (kind != RRMHD_STORE_F32 && kind != RRMHD_STORE_F16 && kind != RRMHD_STORE_F16_SR)
     return RRMHD_EINVAL;
   if (flags != 0 && flags != RRMHD_STORE_INPLACE) return RRMHD_EINVAL;
-  if (kind == RRMHD_STORE_F16_SR && flags) return RRMHD_EINVAL;
   if (!(std::isfinite(tau_f) && std::isfinite(tau_m)) || tau_f <= 0.5 || tau_m <= 0.5)
     return RRMHD_EINVAL;
   rrmhd_bc b{};

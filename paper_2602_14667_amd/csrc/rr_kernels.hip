@@ -204,6 +204,17 @@ __device__ __forceinline__ void update_walled_push(const Domain &D, typename C::
   collide<FORCED>(d, g, P);
   const Rows R = rows_of<true>(D, x, y);
   const int own = R.r0 + x;
+  // stochastic rounding: the bits of this node and of the population's own
+  // plane, as in the two-buffer step
+  uint32_t seed = 0;
+  if constexpr (codec_sr<C>::value)
+    seed = sr_seed(D.sr_key, (uint32_t)own * (uint32_t)sizeof(typename C::T));
+  auto enc = [&](float v, int p) {
+    if constexpr (codec_sr<C>::value)
+      return C::enc_sr(v, D.s, sr_plane(seed, p));
+    else
+      return C::enc(v, D.s);
+  };
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const bool out = (cy(i) > 0 && R.hi) || (cy(i) < 0 && R.lo);
@@ -211,7 +222,7 @@ __device__ __forceinline__ void update_walled_push(const Domain &D, typename C::
     const int trow = cy(i) == 0 ? R.r0 : (cy(i) > 0 ? R.rp : R.rm);
     const int plane = out ? i : opp_f(i);
     const int off = out ? own : trow + tx;
-    st_el<typename C::T, NT>(&buf[(int64_t)plane * D.plane + off], C::enc(d[i], D.s));
+    st_el<typename C::T, NT>(&buf[(int64_t)plane * D.plane + off], enc(d[i], i));
   }
 #pragma unroll
   for (int j = 0; j < kQm; ++j) {
@@ -220,9 +231,10 @@ __device__ __forceinline__ void update_walled_push(const Domain &D, typename C::
     const int trow = ey(j) == 0 ? R.r0 : (ey(j) > 0 ? R.rp : R.rm);
     const int jj = out ? j : opp_g(j);
     const int off = out ? own : trow + tx;
-    st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 0) * D.plane + off], C::enc(g[2 * j], D.s));
+    st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 0) * D.plane + off],
+                             enc(g[2 * j], gplane(j, 0)));
     st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 1) * D.plane + off],
-                             C::enc(g[2 * j + 1], D.s));
+                             enc(g[2 * j + 1], gplane(j, 1)));
   }
 }
 
@@ -267,7 +279,7 @@ __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
-  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key};
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
@@ -282,12 +294,21 @@ __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int
         own_node<C, true>(D, buf, x, y, d, g);
         collide<FORCED>(d, g, P);
         const int o = y * D.nx + x;
+        uint32_t seed = 0;
+        if constexpr (codec_sr<C>::value)
+          seed = sr_seed(D.sr_key, (uint32_t)o * (uint32_t)sizeof(typename C::T));
+        auto enc = [&](float v, int p) {
+          if constexpr (codec_sr<C>::value)
+            return C::enc_sr(v, D.s, sr_plane(seed, p));
+          else
+            return C::enc(v, D.s);
+        };
 #pragma unroll
         for (int i = 0; i < kQ; ++i)
-          st_el<typename C::T, NT>(&buf[(int64_t)i * D.plane + o], C::enc(d[i], D.s));
+          st_el<typename C::T, NT>(&buf[(int64_t)i * D.plane + o], enc(d[i], i));
 #pragma unroll
         for (int k = 0; k < 2 * kQm; ++k)
-          st_el<typename C::T, NT>(&buf[(int64_t)(kQ + k) * D.plane + o], C::enc(g[k], D.s));
+          st_el<typename C::T, NT>(&buf[(int64_t)(kQ + k) * D.plane + o], enc(g[k], kQ + k));
       } else {
         update_periodic_own<C, FORCED, NT>(G, buf, x, y, P);
       }
@@ -865,7 +886,9 @@ hipError_t launch_step_inplace(int storage, const Domain &D, void *buf, int phas
   if (L.bx <= 0 || L.by <= 0 || L.bx * L.by > 256 || L.ry <= 0) return hipErrorInvalidValue;
   if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
     return hipErrorInvalidValue;
-  if (storage == kF16)
+  if (storage == kF16 && D.sr)
+    inplace_phase<CodecF16SR>(D, buf, phase, L, st);
+  else if (storage == kF16)
     D.s == 1.0f ? inplace_phase<CodecF16U>(D, buf, phase, L, st)
                 : inplace_phase<CodecF16>(D, buf, phase, L, st);
   else

@@ -149,8 +149,15 @@ __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
 // bits.  buf points at plane 0 and is read and written through one pointer.
 template <class C, int P, bool NT>
 __device__ __forceinline__ void store_plane_at(const PlaneGeom &G, typename C::T *buf,
-                                               uint32_t o, float v) {
-  st_at<typename C::T, NT>(buf + (int64_t)P * G.plane, o, C::enc(v, G.s));
+                                               uint32_t o, float v, uint32_t seed, int src_plane) {
+  // stochastic rounding draws the bits of the computing node and of the
+  // population's own plane, whichever slot receives it, so the result is
+  // the two-buffer step's bit for bit
+  if constexpr (codec_sr<C>::value)
+    st_at<typename C::T, NT>(buf + (int64_t)P * G.plane, o,
+                             C::enc_sr(v, G.s, sr_plane(seed, src_plane)));
+  else
+    st_at<typename C::T, NT>(buf + (int64_t)P * G.plane, o, C::enc(v, G.s));
 }
 
 template <class C, bool FORCED, bool NT>
@@ -191,25 +198,37 @@ __device__ __forceinline__ void update_periodic_push(const PlaneGeom &G, typenam
   auto at = [&](int cxv, int cyv) {
     return (cyv == 0 ? b0 : (cyv > 0 ? bp : bm)) + (cxv == 0 ? x0 : (cxv > 0 ? xp : xm));
   };
-  store_plane_at<C, opp_f(0), NT>(G, buf, at(cx(0), cy(0)), d[0]);
-  store_plane_at<C, opp_f(1), NT>(G, buf, at(cx(1), cy(1)), d[1]);
-  store_plane_at<C, opp_f(2), NT>(G, buf, at(cx(2), cy(2)), d[2]);
-  store_plane_at<C, opp_f(3), NT>(G, buf, at(cx(3), cy(3)), d[3]);
-  store_plane_at<C, opp_f(4), NT>(G, buf, at(cx(4), cy(4)), d[4]);
-  store_plane_at<C, opp_f(5), NT>(G, buf, at(cx(5), cy(5)), d[5]);
-  store_plane_at<C, opp_f(6), NT>(G, buf, at(cx(6), cy(6)), d[6]);
-  store_plane_at<C, opp_f(7), NT>(G, buf, at(cx(7), cy(7)), d[7]);
-  store_plane_at<C, opp_f(8), NT>(G, buf, at(cx(8), cy(8)), d[8]);
-  store_plane_at<C, gplane(opp_g(0), 0), NT>(G, buf, at(ex(0), ey(0)), g[0]);
-  store_plane_at<C, gplane(opp_g(0), 1), NT>(G, buf, at(ex(0), ey(0)), g[1]);
-  store_plane_at<C, gplane(opp_g(1), 0), NT>(G, buf, at(ex(1), ey(1)), g[2]);
-  store_plane_at<C, gplane(opp_g(1), 1), NT>(G, buf, at(ex(1), ey(1)), g[3]);
-  store_plane_at<C, gplane(opp_g(2), 0), NT>(G, buf, at(ex(2), ey(2)), g[4]);
-  store_plane_at<C, gplane(opp_g(2), 1), NT>(G, buf, at(ex(2), ey(2)), g[5]);
-  store_plane_at<C, gplane(opp_g(3), 0), NT>(G, buf, at(ex(3), ey(3)), g[6]);
-  store_plane_at<C, gplane(opp_g(3), 1), NT>(G, buf, at(ex(3), ey(3)), g[7]);
-  store_plane_at<C, gplane(opp_g(4), 0), NT>(G, buf, at(ex(4), ey(4)), g[8]);
-  store_plane_at<C, gplane(opp_g(4), 1), NT>(G, buf, at(ex(4), ey(4)), g[9]);
+  uint32_t seed = 0;
+  if constexpr (codec_sr<C>::value) seed = sr_seed(G.sr_key, b0 + x0);
+  store_plane_at<C, opp_f(0), NT>(G, buf, at(cx(0), cy(0)), d[0], seed, 0);
+  store_plane_at<C, opp_f(1), NT>(G, buf, at(cx(1), cy(1)), d[1], seed, 1);
+  store_plane_at<C, opp_f(2), NT>(G, buf, at(cx(2), cy(2)), d[2], seed, 2);
+  store_plane_at<C, opp_f(3), NT>(G, buf, at(cx(3), cy(3)), d[3], seed, 3);
+  store_plane_at<C, opp_f(4), NT>(G, buf, at(cx(4), cy(4)), d[4], seed, 4);
+  store_plane_at<C, opp_f(5), NT>(G, buf, at(cx(5), cy(5)), d[5], seed, 5);
+  store_plane_at<C, opp_f(6), NT>(G, buf, at(cx(6), cy(6)), d[6], seed, 6);
+  store_plane_at<C, opp_f(7), NT>(G, buf, at(cx(7), cy(7)), d[7], seed, 7);
+  store_plane_at<C, opp_f(8), NT>(G, buf, at(cx(8), cy(8)), d[8], seed, 8);
+  store_plane_at<C, gplane(opp_g(0), 0), NT>(G, buf, at(ex(0), ey(0)), g[0], seed,
+                                             gplane(0, 0));
+  store_plane_at<C, gplane(opp_g(0), 1), NT>(G, buf, at(ex(0), ey(0)), g[1], seed,
+                                             gplane(0, 1));
+  store_plane_at<C, gplane(opp_g(1), 0), NT>(G, buf, at(ex(1), ey(1)), g[2], seed,
+                                             gplane(1, 0));
+  store_plane_at<C, gplane(opp_g(1), 1), NT>(G, buf, at(ex(1), ey(1)), g[3], seed,
+                                             gplane(1, 1));
+  store_plane_at<C, gplane(opp_g(2), 0), NT>(G, buf, at(ex(2), ey(2)), g[4], seed,
+                                             gplane(2, 0));
+  store_plane_at<C, gplane(opp_g(2), 1), NT>(G, buf, at(ex(2), ey(2)), g[5], seed,
+                                             gplane(2, 1));
+  store_plane_at<C, gplane(opp_g(3), 0), NT>(G, buf, at(ex(3), ey(3)), g[6], seed,
+                                             gplane(3, 0));
+  store_plane_at<C, gplane(opp_g(3), 1), NT>(G, buf, at(ex(3), ey(3)), g[7], seed,
+                                             gplane(3, 1));
+  store_plane_at<C, gplane(opp_g(4), 0), NT>(G, buf, at(ex(4), ey(4)), g[8], seed,
+                                             gplane(4, 0));
+  store_plane_at<C, gplane(opp_g(4), 1), NT>(G, buf, at(ex(4), ey(4)), g[9], seed,
+                                             gplane(4, 1));
 }
 
 template <class C, int P>

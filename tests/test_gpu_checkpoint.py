@@ -41,8 +41,6 @@ def moments(s):
 @pytest.mark.parametrize("src_inplace,dst_inplace", [(False, False), (True, True), (True, False),
                                                      (False, True)])
 def test_save_load_continue_bitwise(tmp_path, storage, src_inplace, dst_inplace):
-    if storage == "f16sr" and (src_inplace or dst_inplace):
-        pytest.skip("stochastic rounding has no single-buffer form")
     note(f"checkpoint {storage} inplace {src_inplace}->{dst_inplace}")
     R = rrmhd()
     nx, ny = 70, 33

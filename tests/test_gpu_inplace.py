@@ -29,7 +29,7 @@ def assert_same(a, b, where):
         assert np.array_equal(ga[k], gb[k]), (where, k)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
 @pytest.mark.parametrize("shape", [(130, 66), (67, 45), (1, 37), (40, 1), (2, 2), (3, 5),
                                    (512, 33)])
 def test_inplace_bitwise_periodic(storage, shape):
@@ -47,7 +47,7 @@ def test_inplace_bitwise_periodic(storage, shape):
     two.close(); one.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
 @pytest.mark.parametrize("shape", [(9, 24), (64, 17), (5, 2)])
 def test_inplace_bitwise_walls_force(storage, shape):
     nx, ny = shape
@@ -86,7 +86,7 @@ def test_inplace_diagnostics_fields_invariants(storage):
     two.close(); one.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
 def test_inplace_save_resume(storage):
     """A state saved at an odd step count (swapped layout) is returned in the
     usual layout: resumed on a two-buffer or a single-buffer handle it
@@ -140,7 +140,7 @@ def test_inplace_c1_oracle_per_field():
     s.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
 def test_inplace_launch_shapes_bitwise(storage):
     note(f"in-place launch shapes {storage}")
     R = rrmhd()
