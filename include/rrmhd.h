@@ -272,6 +272,9 @@ int rrmhd3d_destroy(rrmhd3d *h);
  * storage kind and relaxation times (EINVAL otherwise, handle unchanged),
  * accepts files of one- and two-buffer handles alike, and continues
  * bitwise; RRMHD_EIO for I/O failures.  Synchronous. */
+/* As rrmhd_set_debug_poison, for the 3D two-buffer handle (EINVAL for a
+ * single-buffer one).  For the callers that check kernel coverage (tests). */
+int rrmhd3d_set_debug_poison(rrmhd3d *h, int on);
 int rrmhd3d_save(rrmhd3d *h, const char *path);
 int rrmhd3d_load(rrmhd3d *h, const char *path);
 

@@ -396,6 +396,13 @@ __global__ __launch_bounds__(256) void k_step3_inplace(Dom3 D, int tiles_x, type
     store_all<C>(buf, D, own, v, std::make_integer_sequence<int, kPlanes>{});
 }
 
+// Debug fill of a population buffer with a NaN pattern (32-bit words).
+__global__ void k_poison3(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 // The pull layout of a single-buffer state held in its swapped form:
 // plane p at x is the node x + c_p's own slot of the opposite direction,
 // dst[p][x] = buf[opp(p)][x + c_p], copied bit for bit into dense planes.
@@ -638,6 +645,7 @@ struct rrmhd3d {
   bool ready = false;
   bool inplace = false;  // one buffer, alternating phases
   int phase = 0;         // in-place: 0 pull layout, 1 swapped layout
+  bool poison = false;   // debug: NaN-fill the destination buffer before each step
   int bx = 64, by = 4;
   double *diag_work = nullptr;
   double *diag_out = nullptr;
@@ -793,6 +801,11 @@ int rrmhd3d_step(rrmhd3d *h, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const void *s = h->buf[h->cur];
     void *d = h->buf[h->cur ^ 1];
+    if (h->poison) {
+      const int64_t words = h->D.plane * rr3::kPlanes * h->elem / 4;
+      hipLaunchKernelGGL(rr3::k_poison3, dim3(2048), dim3(256), 0, h->stream, (uint32_t *)d, words,
+                         h->elem == 4 ? 0x7fc00000u : 0x7e007e00u);
+    }
     if (h->storage == RRMHD_STORE_F16)
       hipLaunchKernelGGL(rr3::k_step3<rr3::CodecF16U>, grid, block, 0, h->stream, h->D, tiles_x,
                          (const uint16_t *)s, (uint16_t *)d);
@@ -803,6 +816,12 @@ int rrmhd3d_step(rrmhd3d *h, int64_t n) {
     h->cur ^= 1;
     h->steps++;
   }
+  return RRMHD_OK;
+}
+
+int rrmhd3d_set_debug_poison(rrmhd3d *h, int on) {
+  if (!h || (on && h->inplace)) return RRMHD_EINVAL;
+  h->poison = on != 0;
   return RRMHD_OK;
 }
 

@@ -39,7 +39,7 @@ EXPORTED = [
     "rrmhd_current_vorticity",
     "rrmhd3d_create", "rrmhd3d_init", "rrmhd3d_step", "rrmhd3d_step_count",
     "rrmhd3d_moments", "rrmhd3d_diagnostics", "rrmhd3d_invariants",
-    "rrmhd3d_set_launch", "rrmhd3d_destroy", "rrmhd3d_save", "rrmhd3d_load",
+    "rrmhd3d_set_launch", "rrmhd3d_destroy", "rrmhd3d_save", "rrmhd3d_load", "rrmhd3d_set_debug_poison",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
         L.rrmhd_set_debug_poison.argtypes = [vp, ctypes.c_int]
         L.rrmhd3d_save.argtypes = [vp, ctypes.c_char_p]
         L.rrmhd3d_load.argtypes = [vp, ctypes.c_char_p]
+        L.rrmhd3d_set_debug_poison.argtypes = [vp, ctypes.c_int]
         L.rrmhd_load.argtypes = [vp, ctypes.c_char_p]
         L.rrmhd_set_stream.argtypes = [vp, vp]
         ci = ctypes.c_int
@@ -505,6 +506,10 @@ class Solver3D:
     def load(self, path):
         """Read a checkpoint file written by save() into this handle."""
         _check(lib().rrmhd3d_load(self._h, os.fsencode(path)), "rrmhd3d_load")
+
+    def set_debug_poison(self, on=True):
+        """NaN-fill the destination buffer before every step (debug)."""
+        _check(lib().rrmhd3d_set_debug_poison(self._h, int(bool(on))), "rrmhd3d_set_debug_poison")
 
 
 def bandwidth_probe(dst, src, stream=None):

@@ -119,3 +119,38 @@ def test_poison_refused_for_single_buffer():
     assert R.lib().rrmhd_set_debug_poison(s._h, 1) == R.EINVAL
     assert R.lib().rrmhd_set_debug_poison(s._h, 0) == R.OK
     s.close()
+
+
+def run3(R, shape, storage, poison, launch=None):
+    u, b = inputs.random_modes3d(*shape, 0.04, seed=sum(shape))
+    s = R.Solver3D(*shape, 0.55, 0.6, storage=storage)
+    if launch:
+        s.set_launch(*launch)
+    s.set_debug_poison(poison)
+    s.init(dev(u), dev(b))
+    s.step(4)
+    rho, uu, bb = s.moments()
+    torch.cuda.synchronize()
+    out = [rho.cpu().numpy(), uu.cpu().numpy(), bb.cpu().numpy()]
+    d = s.diagnostics()
+    s.close()
+    return out, d
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("shape", [(7, 5, 3), (37, 11, 5), (1, 1, 1), (2, 2, 2), (130, 3, 2)])
+@pytest.mark.parametrize("launch", [None, (64, 4), (16, 16), (1, 1)])
+def test_3d_poisoned_destination_is_fully_written(storage, shape, launch):
+    R = rrmhd()
+    a, da = run3(R, shape, storage, False, launch)
+    p, dp = run3(R, shape, storage, True, launch)
+    for x, y in zip(a, p):
+        assert np.array_equal(x, y)
+    assert da == dp and all(np.isfinite(v) for v in dp)
+
+
+def test_3d_poison_refused_for_single_buffer():
+    R = rrmhd()
+    s = R.Solver3D(8, 8, 8, 0.56, 0.56, inplace=True)
+    assert R.lib().rrmhd3d_set_debug_poison(s._h, 1) == R.EINVAL
+    s.close()
