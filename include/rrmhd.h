@@ -129,6 +129,27 @@ int rrmhd_moments(rrmhd *h, double *rho, double *u, double *b);
 int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag,
                       double *max_div_b);
 
+/* For callers that cannot allocate device memory (code that runs where
+ * hipMalloc is forbidden or too slow: tight serving loops, harnesses that
+ * forbid it): rrmhd_diagnostics with the same arguments, results, kernels
+ * and reduction order (the results are bit for bit those of
+ * rrmhd_diagnostics), but no allocation.  Its workspace (the pass's
+ * per-workgroup partial sums and its eight results) is a static device array
+ * of 72 KiB that each GPU the library runs on holds until the process ends;
+ * its device address is looked up once per device at rrmhd_create.  The
+ * workspace the pass needs does not grow with the grid (1024 persistent
+ * workgroups at most); a build whose pass would need more than the array
+ * holds returns RRMHD_EINVAL (rrmhd_last_error_detail gives the sizes)
+ * before anything is launched.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two host threads, or two handles
+ * whose streams run concurrently) race on it and must be serialised by the
+ * caller.  Nothing in the array needs clearing between calls: each pass
+ * writes every partial sum before its final reduction reads it.  Call with
+ * the handle's device current, as for every call.  Synchronises the
+ * stream. */
+int rrmhd_diagnostics_noalloc(rrmhd *h, double *E_kin, double *E_mag,
+                              double *max_div_b);
+
 /* Derived fields of a periodic grid, FP64 device arrays [ny][nx] (either
  * may be NULL): the local current density j_z of Eq. current, computed from
  * the magnetic populations' departure from equilibrium (no finite

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/rrmhd.h"
@@ -39,6 +40,43 @@ namespace {
 
 bool finite_pos(double v) { return std::isfinite(v); }
 
+// ---- workspace of the allocation-free diagnostics ---------------------------
+// rrmhd_diagnostics_noalloc keeps the partial sums of the diagnostics pass and
+// its eight results in this file-scope device array instead of the handle's
+// lazily allocated workspace.  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code the name `scratch` only stands
+// for the symbol: its device address is looked up once per device with
+// hipGetSymbolAddress (at rrmhd_create, with that device current) and only
+// that address is ever passed to kernels or copies.
+constexpr size_t kScratchBytes = 72 * 1024;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+int scratch_address(int *dev_out, void **out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_err(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    std::snprintf(g_detail, sizeof g_detail, "device %d beyond the scratch table", dev);
+    return RRMHD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return dev_err(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  *dev_out = dev;
+  *out = g_scratch_dev[dev];
+  return RRMHD_OK;
+}
+
 }  // namespace
 
 struct rrmhd {
@@ -59,6 +97,7 @@ struct rrmhd {
   void *fields_work = nullptr;  // 2 nx ny doubles for the j_z / w_z fields
   double *diag_out = nullptr;   // device, 8 doubles
   double *diag_host = nullptr;  // pinned, 8 doubles
+  void *scratch = nullptr;      // device address of this device's `scratch`
   void *mlp = nullptr;          // prepared closure parameters (device)
   bool closure_on = false;
   int closure_grid = 0;         // persistent blocks of the closure kernel
@@ -218,6 +257,10 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
     hipError_t e = hipHostMalloc((void **)&h->diag_host, 8 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) rc = dev_err(e, "hipHostMalloc(diag)");
   }
+  if (rc == RRMHD_OK) {
+    int dev = -1;
+    rc = scratch_address(&dev, &h->scratch);
+  }
   if (rc != RRMHD_OK) {
     rrmhd_destroy(h);
     return rc;
@@ -360,24 +403,25 @@ int rrmhd_moments(rrmhd *h, double *rho, double *u, double *b) {
   return RRMHD_OK;
 }
 
-static int run_diag(rrmhd *h) {
-  if (!h->diag_work) {
-    HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
-  }
-  HIP_OR_RETURN(rr::launch_diagnostics(h->storage, h->D, h->buf[h->cur],
-                                       h->diag_work, h->diag_out, h->stream,
-                                       h->inplace ? h->phase : 0));
-  HIP_OR_RETURN(hipMemcpyAsync(h->diag_host, h->diag_out, 8 * sizeof(double),
+// One diagnostics pass with the given workspace (diag_work_bytes) and
+// device output (8 doubles); the results land in the pinned diag_host.
+static int run_diag_with(rrmhd *h, void *work, double *out_dev) {
+  HIP_OR_RETURN(rr::launch_diagnostics(h->storage, h->D, h->buf[h->cur], work, out_dev,
+                                       h->stream, h->inplace ? h->phase : 0));
+  HIP_OR_RETURN(hipMemcpyAsync(h->diag_host, out_dev, 8 * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream));
   HIP_OR_RETURN(hipStreamSynchronize(h->stream));
   return RRMHD_OK;
 }
 
-int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag, double *max_div_b) {
-  if (!h) return RRMHD_EINVAL;
-  if (!h->ready) return RRMHD_ESTATE;
-  int rc = run_diag(h);
-  if (rc != RRMHD_OK) return rc;
+static int run_diag(rrmhd *h) {
+  if (!h->diag_work) {
+    HIP_OR_RETURN(hipMalloc(&h->diag_work, rr::diag_work_bytes(h->D)));
+  }
+  return run_diag_with(h, h->diag_work, h->diag_out);
+}
+
+static int diag_results(const rrmhd *h, double *E_kin, double *E_mag, double *max_div_b) {
   const double *r = h->diag_host;
   const bool bad = !(std::isfinite(r[0]) && std::isfinite(r[1]) && std::isfinite(r[2]));
   const double nan = std::nan("");
@@ -385,6 +429,35 @@ int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag, double *max_div_b)
   if (E_mag) *E_mag = bad ? nan : r[1];
   if (max_div_b) *max_div_b = bad ? nan : r[2];
   return bad ? RRMHD_ENONFINITE : RRMHD_OK;
+}
+
+int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag, double *max_div_b) {
+  if (!h) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  int rc = run_diag(h);
+  if (rc != RRMHD_OK) return rc;
+  return diag_results(h, E_kin, E_mag, max_div_b);
+}
+
+int rrmhd_diagnostics_noalloc(rrmhd *h, double *E_kin, double *E_mag, double *max_div_b) {
+  if (!h) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  // the workspace holds the pass's partial sums, then its eight results
+  const size_t work = rr::diag_work_bytes(h->D);
+  const size_t need = (work + 255) / 256 * 256 + 8 * sizeof(double);
+  if (need > kScratchBytes) {
+    std::snprintf(g_detail, sizeof g_detail,
+                  "diagnostics workspace of %zu bytes exceeds the static %zu", need,
+                  kScratchBytes);
+    return RRMHD_EINVAL;
+  }
+  if (!h->scratch) return RRMHD_ESTATE;
+  // every partial sum the final reduction reads is written by the same pass
+  // first, so nothing in the workspace needs clearing between calls
+  char *base = (char *)h->scratch;
+  int rc = run_diag_with(h, base, (double *)(base + (work + 255) / 256 * 256));
+  if (rc != RRMHD_OK) return rc;
+  return diag_results(h, E_kin, E_mag, max_div_b);
 }
 
 int rrmhd_invariants(rrmhd *h, double out[5]) {

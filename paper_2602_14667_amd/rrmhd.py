@@ -21,7 +21,7 @@ FEQ_ALGORITHM, FEQ_FULL_MAXWELL = 0, 1
 
 EXPORTED = [
     "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
-    "rrmhd_diagnostics", "rrmhd_invariants", "rrmhd_step_count",
+    "rrmhd_diagnostics", "rrmhd_diagnostics_noalloc", "rrmhd_invariants", "rrmhd_step_count",
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state", "rrmhd_save", "rrmhd_load",
     "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium", "rrmhd_set_graph_chunk",
     "rrmhd_set_debug_poison",
@@ -85,6 +85,9 @@ def lib():
         L.rrmhd_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
+        L.rrmhd_diagnostics_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double)]
         L.rrmhd_invariants.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.rrmhd_step_count.argtypes = [vp, ctypes.POINTER(i64)]
         L.rrmhd_state_bytes.argtypes = [vp]
@@ -306,6 +309,16 @@ class Solver:
                                      ctypes.byref(em), ctypes.byref(dv))
         if not (allow_nonfinite and rc == ENONFINITE):
             _check(rc, "rrmhd_diagnostics")
+        return ek.value, em.value, dv.value
+
+    def diagnostics_noalloc(self, allow_nonfinite=False):
+        """rrmhd_diagnostics_noalloc: the same results with the library's
+        static per-device workspace instead of an allocated one."""
+        ek, em, dv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().rrmhd_diagnostics_noalloc(self._h, ctypes.byref(ek),
+                                             ctypes.byref(em), ctypes.byref(dv))
+        if not (allow_nonfinite and rc == ENONFINITE):
+            _check(rc, "rrmhd_diagnostics_noalloc")
         return ek.value, em.value, dv.value
 
     def diagnostics_rc(self):
