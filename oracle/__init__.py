@@ -64,6 +64,8 @@ def lib():
         L.orc_invariants.argtypes = [ctypes.c_void_p, _dp]
         L.orc_current_vorticity.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_get_state.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_round_state_f32.argtypes = [ctypes.c_void_p]
+        L.orc_step_rounded_f32.argtypes = [ctypes.c_void_p, ctypes.c_long]
         L.orc_set_state.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_hermite.restype = ctypes.c_double
         L.orc_hermite.argtypes = [ctypes.c_int, _ip, ctypes.c_int]
@@ -355,6 +357,14 @@ class Oracle:
 
     def step(self, n=1):
         lib().orc_step(self._h, int(n))
+
+    def step_rounded_f32(self, n=1):
+        """n FP64 steps, each followed by rounding the stored state (f - w
+        and g) to FP32: the storage-precision model of FP32 storage."""
+        lib().orc_step_rounded_f32(self._h, int(n))
+
+    def round_state_f32(self):
+        lib().orc_round_state_f32(self._h)
 
     @property
     def step_count(self):

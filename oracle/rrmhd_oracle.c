@@ -667,6 +667,30 @@ void orc_set_state(orc *h, const double *f, const double *g) {
   if (g) memcpy(h->g, g, 10 * n * sizeof(double));
 }
 
+/* Storage-precision model (a test of the arithmetic, not of the method):
+ * rounds the current state to what FP32 storage keeps, i.e. the offsets
+ * f_i - w_i and the magnetic populations g_j, each to the nearest FP32 value
+ * (round to nearest even, the C cast), while every step stays in FP64.  A GPU
+ * run whose arithmetic is exact up to its storage rounding stays as close to
+ * the FP64 run as this model does. */
+void orc_round_state_f32(orc *h) {
+  size_t n = (size_t)h->nx * h->ny;
+  for (int i = 0; i < 9; ++i)
+    for (size_t p = 0; p < n; ++p) {
+      double *v = &h->f[(size_t)i * n + p];
+      *v = WI[i] + (double)(float)(*v - WI[i]);
+    }
+  for (size_t p = 0; p < 10 * n; ++p) h->g[p] = (double)(float)h->g[p];
+}
+
+/* n steps, each followed by the FP32 storage rounding above. */
+void orc_step_rounded_f32(orc *h, long n) {
+  for (long k = 0; k < n; ++k) {
+    one_step(h);
+    orc_round_state_f32(h);
+  }
+}
+
 /* ---- single-node entry points for tests --------------------------------- */
 void orc_node_equilibrium(double rho, const double u[2], const double b[2],
                           int option, double feq[9], double geq[10]) {

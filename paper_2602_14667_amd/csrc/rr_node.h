@@ -14,7 +14,9 @@
 // the bracket uses only exact constants (3, 4.5, 1.5, 2.25, 9), and w_i is
 // applied as a quotient by 36/W_i in {2.25, 9, 36} with one Newton/FMA
 // correction, so a rounding error never repeats with the same sign every
-// step.
+// step.  The forced step (a body force, the project's reading for the
+// Hartmann channel) is the exception: it runs tasks 1-5 in FP64 and rounds
+// only on storage (collide_forced64 below says why).
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -224,35 +226,10 @@ __device__ __forceinline__ float eq_bracket(const EqTerms &E) {
   return B;
 }
 
-struct ForceTerms {
-  float a1c;     // (1 - omega) * 3   applied to c.a1, a1 = -F/2
-  float a1x, a1y;
-  float sc;      // 1 - omega / 2
-  float Fx, Fy, ux, uy;
-};
-
-// Forcing additions to the bracket (project reading; see the oracle):
-// (1 - omega) 3 c.a1 + (1 - omega/2) [3 c.F + 3 (hx u_x F_x + hy u_y F_y)
-// + 9 cx cy (u_x F_y + u_y F_x)].
-template <int CX, int CY>
-__device__ __forceinline__ float force_bracket(const ForceTerms &T) {
-  constexpr float hx = CX ? 2.0f : -1.0f;
-  constexpr float hy = CY ? 2.0f : -1.0f;
-  float ca1 = 0.0f, cF = 0.0f;
-  if constexpr (CX != 0) { ca1 = CX * T.a1x; cF = CX * T.Fx; }
-  if constexpr (CY != 0) { ca1 = ca1 + CY * T.a1y; cF = cF + CY * T.Fy; }
-  float s = 3.0f * fmaf(hx * T.ux, T.Fx, hy * T.uy * T.Fy) + 3.0f * cF;
-  if constexpr (CX != 0 && CY != 0)
-    s = fmaf(9.0f * CX * CY, fmaf(T.ux, T.Fy, T.uy * T.Fx), s);
-  return fmaf(T.a1c, ca1, T.sc * s);
-}
-
-template <int I, bool FORCED>
-__device__ __forceinline__ float post_f(const EqTerms &E, const Acoef &A,
-                                        const ForceTerms &T) {
+template <int I>
+__device__ __forceinline__ float post_f(const EqTerms &E, const Acoef &A) {
   constexpr int CX = cx(I), CY = cy(I);
-  float v = eq_bracket<CX, CY>(E) + reg_bracket<CX, CY>(A);
-  if constexpr (FORCED) v = v + force_bracket<CX, CY>(T);
+  const float v = eq_bracket<CX, CY>(E) + reg_bracket<CX, CY>(A);
   return qdiv(v, wdiv(I), 1.0f / wdiv(I));
 }
 
@@ -262,6 +239,133 @@ struct NoCorrection {
   __device__ __forceinline__ void operator()(float, float, float, float, float, float &,
                                              float &, float &) const {}
 };
+
+// ---- the forced collision, in FP64 ------------------------------------------
+// A body force adds the same small impulse to every node at every step (G =
+// 1e-6 against velocities of 1e-2 in the Hartmann channel: a few hundred
+// units in the last place of an FP32 velocity).  In FP32 arithmetic that
+// increment is added to values that sit on the FP32 grid, so its rounding
+// has the same sign at every node and every step: a coherent bias (about
+// -0.2 % of the force in a uniform box) that the storage rounding alone does
+// not have, since the stored values are pseudo-random in their low bits.
+// The forced step therefore evaluates tasks 1-5 in FP64 and rounds only when
+// it stores; the unforced method keeps FP32 arithmetic.  Constants enter as
+// FP64 products with correctly rounded FP64 reciprocals (their rounding is
+// far below the FP32 storage's).
+template <int CX, int CY>
+__device__ __forceinline__ double reg_bracket64(const double (&A)[6]) {
+  constexpr double hx = CX ? 2.0 : -1.0;
+  constexpr double hy = CY ? 2.0 : -1.0;
+  double r = 1.5 * fma(hx, A[0], hy * A[2]);
+  if constexpr (CX != 0 && CY != 0) r = fma(9.0 * CX * CY, A[1], r);
+  if constexpr (CY != 0) r = fma(4.5 * CY * hx, A[3], r);
+  if constexpr (CX != 0) r = fma(4.5 * CX * hy, A[4], r);
+  return fma(2.25 * hx * hy, A[5], r);
+}
+
+template <int I, bool FULLM>
+__device__ __forceinline__ float post_f64(double rho, double dr, const double (&ex)[3],
+                                          const double (&ey)[3], double mq, double mxy,
+                                          const double (&A)[6], double a1c, double a1x,
+                                          double a1y, double sc, double Fx, double Fy,
+                                          double ux, double uy) {
+  constexpr int CX = cx(I), CY = cy(I);
+  constexpr double hx = CX ? 2.0 : -1.0;
+  constexpr double hy = CY ? 2.0 : -1.0;
+  // equilibrium bracket (D1Q3 product, Maxwell stress at second order)
+  const double exv = ex[CX + 1], eyv = ey[CY + 1];
+  double B = fma(rho, fma(exv, eyv, exv + eyv), dr);
+  if constexpr (CX != 0 && CY == 0) B = B + mq;
+  if constexpr (CX == 0 && CY != 0) B = B - mq;
+  if constexpr (CX != 0 && CY != 0) B = fma(-(double)(CX * CY), mxy, B);
+  // forcing: (1 - omega) 3 c.a1 + (1 - omega/2)[3 c.F + 3 (hx ux Fx + hy uy Fy)
+  // + 9 cx cy (ux Fy + uy Fx)]
+  double ca1 = 0.0, cF = 0.0;
+  if constexpr (CX != 0) { ca1 = CX * a1x; cF = CX * Fx; }
+  if constexpr (CY != 0) { ca1 = ca1 + CY * a1y; cF = cF + CY * Fy; }
+  double fs = 3.0 * fma(hx * ux, Fx, hy * uy * Fy) + 3.0 * cF;
+  if constexpr (CX != 0 && CY != 0) fs = fma(9.0 * CX * CY, fma(ux, Fy, uy * Fx), fs);
+  const double v = B + reg_bracket64<CX, CY>(A) + fma(a1c, ca1, sc * fs);
+  return (float)(v * (1.0 / (double)wdiv(I)));
+}
+
+template <bool FULLM>
+__device__ __forceinline__ void collide_forced64(float (&d)[kQ], float (&g)[2 * kQm],
+                                                 const CollideParams &P) {
+  double f[kQ], m[2 * kQm];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) f[i] = d[i];
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k) m[k] = g[k];
+  // task 1, with the velocity carrying half the force impulse
+  const double dr = ((f[0] + f[2]) + (f[4] + f[6])) + (((f[1] + f[3]) + (f[5] + f[7])) + f[8]);
+  const double rho = 1.0 + dr;
+  const double jx = ((f[5] + f[6]) + f[7]) - ((f[1] + f[2]) + f[3]);
+  const double jy = ((f[1] + f[7]) + f[8]) - ((f[3] + f[4]) + f[5]);
+  const double Gx = P.Gx, Gy = P.Gy;
+  const double Fx = rho * Gx, Fy = rho * Gy;
+  const double ux = fma(0.5, Fx, jx) / rho;
+  const double uy = fma(0.5, Fy, jy) / rho;
+  const double bx = ((m[0] + m[2]) + (m[4] + m[6])) + m[8];
+  const double by = ((m[1] + m[3]) + (m[5] + m[7])) + m[9];
+  // task 3: exact Hermite moments of f_eq, projection, recursion
+  const double pxx = ((f[1] + f[2]) + f[3]) + ((f[5] + f[6]) + f[7]);
+  const double pyy = ((f[1] + f[3]) + (f[5] + f[7])) + (f[4] + f[8]);
+  const double pxy = (f[3] + f[7]) - (f[1] + f[5]);
+  const double dr3 = dr * (1.0 / 3.0);
+  const double bxy = bx * by;
+  const double mxx = 0.5 * (by * by - bx * bx);
+  const double rux = rho * ux, ruy = rho * uy;
+  const double axx = fma(-rux, ux, pxx - dr3) - mxx;
+  const double ayy = fma(-ruy, uy, pyy - dr3) + mxx;
+  const double axy = fma(-rux, uy, pxy) + bxy;
+  const double om = P.om_c;
+  double A[6];
+  A[0] = om * axx;
+  A[1] = om * axy;
+  A[2] = om * ayy;
+  A[3] = om * fma(2.0 * ux, axy, uy * axx);
+  A[4] = om * fma(2.0 * uy, axy, ux * ayy);
+  A[5] = om * fma(ux * ux, ayy, fma(uy * uy, axx, (4.0 * ux) * (uy * axy)));
+  if constexpr (FULLM) {
+    // u.M cross terms of the third- and fourth-order equilibrium (ablation)
+    A[3] += fma(uy, mxx, -2.0 * (ux * bxy));
+    A[4] += fma(-ux, mxx, -2.0 * (uy * bxy));
+    A[5] += fma(fma(uy, uy, -ux * ux), mxx, -4.0 * (ux * (uy * bxy)));
+  }
+  // task 2: D1Q3 factors minus one, indexed by c + 1
+  const double ux2 = ux * ux, uy2 = uy * uy;
+  const double ex[3] = {fma(-3.0, ux, 3.0 * ux2), -1.5 * ux2, fma(3.0, ux, 3.0 * ux2)};
+  const double ey[3] = {fma(-3.0, uy, 3.0 * uy2), -1.5 * uy2, fma(3.0, uy, 3.0 * uy2)};
+  const double mq = 4.5 * mxx, mxy = 9.0 * bxy;
+  const double a1c = 3.0 * om, a1x = -0.5 * Fx, a1y = -0.5 * Fy;
+  const double sc = P.src_c;
+  // tasks 4-5 per velocity, rounded once to FP32
+  d[0] = post_f64<0, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[1] = post_f64<1, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[2] = post_f64<2, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[3] = post_f64<3, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[4] = post_f64<4, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[5] = post_f64<5, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[6] = post_f64<6, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[7] = post_f64<7, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  d[8] = post_f64<8, FULLM>(rho, dr, ex, ey, mq, mxy, A, a1c, a1x, a1y, sc, Fx, Fy, ux, uy);
+  // magnetic BGK with E = u_x b_y - u_y b_x; the rest population from the
+  // conservation of b, as in the FP32 collision
+  const double E3 = 3.0 * fma(ux, by, -uy * bx);
+  const double r3 = 1.0 / 3.0, r6 = 1.0 / 6.0;
+  const double bx3 = bx * r3, by3 = by * r3, bx6 = bx * r6, by6 = by * r6;
+  const double geq[2 * kQm] = {bx3, by3, bx6, (by - E3) * r6, (bx + E3) * r6, by6,
+                               bx6, (by + E3) * r6, (bx - E3) * r6, by6};
+  const double omm = P.omm_c;
+  double gs[2 * kQm];
+#pragma unroll
+  for (int k = 2; k < 2 * kQm; ++k) gs[k] = fma(omm, m[k] - geq[k], geq[k]);
+  gs[0] = bx - ((gs[2] + gs[4]) + (gs[6] + gs[8]));
+  gs[1] = by - ((gs[3] + gs[5]) + (gs[7] + gs[9]));
+#pragma unroll
+  for (int k = 0; k < 2 * kQm; ++k) g[k] = (float)gs[k];
+}
 
 // One collision (algorithm tasks 1-5) in place.  d[i] = f_i - w_i on entry,
 // f*_i - w_i on exit; g[2j + c] = g_j,c before and after.  corr(rho, u_x,
@@ -274,6 +378,11 @@ template <bool FORCED, class Corr = NoCorrection, bool FULLM = false>
 __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
                                         const CollideParams &P,
                                         const Corr &corr = Corr()) {
+  if constexpr (FORCED) {
+    static_assert(std::is_same_v<Corr, NoCorrection>, "the closure runs unforced");
+    collide_forced64<FULLM>(d, g, P);
+    return;
+  }
   // task 1: macroscopic variables
   const float dr = ((d[0] + d[2]) + (d[4] + d[6])) +
                    (((d[1] + d[3]) + (d[5] + d[7])) + d[8]);
@@ -281,12 +390,8 @@ __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
   const float jx = ((d[5] + d[6]) + d[7]) - ((d[1] + d[2]) + d[3]);
   const float jy = ((d[1] + d[7]) + d[8]) - ((d[3] + d[4]) + d[5]);
   const float rr = __builtin_amdgcn_rcpf(rho);
-  float ux = rdiv(jx, rho, rr);
-  float uy = rdiv(jy, rho, rr);
-  if constexpr (FORCED) {
-    ux = fmaf(0.5f, P.Gx, ux);
-    uy = fmaf(0.5f, P.Gy, uy);
-  }
+  const float ux = rdiv(jx, rho, rr);
+  const float uy = rdiv(jy, rho, rr);
   const float bx = ((g[0] + g[2]) + (g[4] + g[6])) + g[8];
   const float by = ((g[1] + g[3]) + (g[5] + g[7])) + g[9];
 
@@ -346,29 +451,16 @@ __device__ __forceinline__ void collide(float (&d)[kQ], float (&g)[2 * kQm],
   E.mq = 4.5f * mxx;
   E.mxy = 9.0f * bxy;
 
-  ForceTerms T{};
-  if constexpr (FORCED) {
-    const float Fx = rho * P.Gx, Fy = rho * P.Gy;
-    T.a1c = 3.0f * P.om_c;
-    T.a1x = -0.5f * Fx;
-    T.a1y = -0.5f * Fy;
-    T.sc = P.src_c;
-    T.Fx = Fx;
-    T.Fy = Fy;
-    T.ux = ux;
-    T.uy = uy;
-  }
-
   // tasks 4-5: regularised reconstruction and collision, per velocity
-  d[0] = post_f<0, FORCED>(E, A, T);
-  d[1] = post_f<1, FORCED>(E, A, T);
-  d[2] = post_f<2, FORCED>(E, A, T);
-  d[3] = post_f<3, FORCED>(E, A, T);
-  d[4] = post_f<4, FORCED>(E, A, T);
-  d[5] = post_f<5, FORCED>(E, A, T);
-  d[6] = post_f<6, FORCED>(E, A, T);
-  d[7] = post_f<7, FORCED>(E, A, T);
-  d[8] = post_f<8, FORCED>(E, A, T);
+  d[0] = post_f<0>(E, A);
+  d[1] = post_f<1>(E, A);
+  d[2] = post_f<2>(E, A);
+  d[3] = post_f<3>(E, A);
+  d[4] = post_f<4>(E, A);
+  d[5] = post_f<5>(E, A);
+  d[6] = post_f<6>(E, A);
+  d[7] = post_f<7>(E, A);
+  d[8] = post_f<8>(E, A);
 
   // magnetic BGK: g_eq,j = psi_j [b + e_j.(u b - b u) / c_s^2], i.e. with
   // E = u_x b_y - u_y b_x: g_eq,j = psi_j (b_x - 3 e_jy E, b_y + 3 e_jx E).

@@ -93,6 +93,14 @@ def test_batch_graph_and_tile_shape_bitwise():
         b.close()
 
 
+def per_field_errors(got, ref):
+    """rel L2 per field (rho, u_x, u_y, b_x, b_y) of (rho, u, b) triples."""
+    g = [got[0], got[1][0], got[1][1], got[2][0], got[2][1]]
+    r = [ref[0], ref[1][0], ref[1][1], ref[2][0], ref[2][1]]
+    names = ("rho", "ux", "uy", "bx", "by")
+    return {n: float(np.linalg.norm(a - c) / np.linalg.norm(c)) for n, a, c in zip(names, g, r)}
+
+
 def test_batch_domains_against_oracle():
     note("batch vs oracle")
     b = make_batch()
@@ -105,8 +113,7 @@ def test_batch_domains_against_oracle():
         o.step(40)
         ref = o.moments()
         got = moments_np(b.moments(d))
-        for k, (g, r) in enumerate(zip(got, ref)):
-            e = np.linalg.norm(g - r) / np.linalg.norm(r)
+        for k, e in per_field_errors(got, ref).items():
             assert e < 1e-6, (d, k, e)
         ek, em, dv = b.diagnostics(d)
         rk, rm, rd = o.diagnostics()
@@ -145,8 +152,7 @@ def test_batch_full_ensemble_sampled():
             o = oracle.Oracle(x["side"], x["side"], x["tau_f"], x["tau_m"])
             o.init(u, bf)
             o.step(20)
-            for k, (g, r) in enumerate(zip(got, o.moments())):
-                e = np.linalg.norm(g - r) / np.linalg.norm(r)
+            for k, e in per_field_errors(got, o.moments()).items():
                 assert e < 1e-6, (d, k, e)
     b.close()
 

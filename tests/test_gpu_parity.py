@@ -290,11 +290,15 @@ def test_nonfinite_state_is_reported():
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_walls_and_force_small(storage):
+    """Walls, anti-bounce-back and the body force on a 9 x 24 channel with a
+    random initial field: per-field rel L2 against the oracle at 1, 10 and 300
+    steps.  FP32 storage: <= 1e-6 (the FP32 storage model of the oracle stays
+    within 2e-8 here)."""
     note(f"walls+force 9x24 {storage}")
-    h = inputs.Hartmann(nx=9, ny=24, tau_f=0.8, tau_m=0.75, G=1e-4, Ha=4.0)
-    u, b = inputs.random_modes(9, 24, 0.03, seed=4)
+    h = inputs.Hartmann(nx=9, ny=24, tau_f=0.8, tau_m=0.75, G=1e-5, Ha=4.0)
+    u, b = inputs.random_modes(9, 24, 0.01, seed=4)
     b[1] += h.B0
-    errs = run_pair(9, 24, u, b, h.tau_f, h.tau_m, [1, 10, 100],
+    errs = run_pair(9, 24, u, b, h.tau_f, h.tau_m, [1, 10, 300],
                     storage=storage, walls=True, force=(h.G, 0.0),
                     b_wall=(0.0, h.B0), initial_norm=True)
     for k in FIELDS:
@@ -303,21 +307,35 @@ def test_walls_and_force_small(storage):
     assert worst(errs) < tol, errs
 
 
-def c2_solver(R, h):
-    return R.Solver(h.nx, h.ny, h.tau_f, h.tau_m, walls=True, force=(h.G, 0.0),
-                    b_wall=(0.0, h.B0))
+def c2_solver(R, h, storage="f32"):
+    return R.Solver(h.nx, h.ny, h.tau_f, h.tau_m, storage=storage, walls=True,
+                    force=(h.G, 0.0), b_wall=(0.0, h.B0))
+
+
+C2_FIELDS = ("ux", "bx", "by")
+
+
+def column_errors(got, ref_cols):
+    """Per-field rel L2 of the GPU's column 0 against 1-D oracle columns; the
+    GPU's columns must be identical to each other (x-invariant run)."""
+    out = {}
+    for k in C2_FIELDS:
+        assert np.max(np.abs(got[k] - got[k][:, :1])) == 0.0, k
+        col = np.asarray(ref_cols[k])
+        out[k] = float(np.linalg.norm(got[k][:, 0] - col) / np.linalg.norm(col))
+    return out
 
 
 def test_hartmann_c2_transient_vs_oracle_columns():
-    """512 x 256 channel from rest: every GPU column against the oracle's
-    x-invariant 1 x 256 column after 20000 steps.
+    """512 x 256 channel from rest, 20000 steps: every GPU column against the
+    oracle's x-invariant 1 x 256 column, per field.
 
-    Tolerance: the body force adds G = 1e-6 per step to momenta carried by
-    population offsets of order 3e-3, whose FP32 spacing is ~2e-10 (about
-    1e-3 of one step's increment).  In the plug-flow core every node rounds
-    alike, so this does not average out; after 2e4 steps the accumulated
-    difference is of order 1e-4 (an FP32 emulation of the kernel's exact
-    operation order gives 7e-5 for u_x)."""
+    The bar is the oracle's own FP32 storage model (FP64 steps, state rounded
+    to FP32 storage after each step) run alongside: the GPU's forced step
+    computes in FP64 and rounds only on storage, so its error must be of the
+    model's size (<= 3x it; the model gives 1.6e-6 for u_x, 1.3e-6 for
+    b_x).  North_star's 1e-6 lies below that storage floor for u_x and is
+    kept as a non-strict expected failure."""
     note("C2 512x256 20000 steps vs oracle 1x256")
     h = inputs.hartmann_c2()
     u, b = h.initial_fields()
@@ -326,75 +344,95 @@ def test_hartmann_c2_transient_vs_oracle_columns():
     s.init(dev(u), dev(b))
     s.step(20000)
     got = gpu_moments(s)
+    s.close()
+    kw = dict(walls=True, force=(h.G, 0.0), b_wall=(0.0, h.B0))
+    o = oracle.Oracle(1, h.ny, h.tau_f, h.tau_m, **kw)
+    m = oracle.Oracle(1, h.ny, h.tau_f, h.tau_m, **kw)
+    o.init(u[:, :, :1], b[:, :, :1])
+    m.init(u[:, :, :1], b[:, :, :1])
+    m.round_state_f32()
+    o.step(20000)
+    m.step_rounded_f32(20000)
+    ref = {k: v[:, 0] for k, v in split(*o.moments()).items()}
+    mod = {k: v[:, 0] for k, v in split(*m.moments()).items()}
+    e = column_errors(got, ref)
+    floor = {k: float(np.linalg.norm(mod[k] - ref[k]) / np.linalg.norm(ref[k]))
+             for k in C2_FIELDS}
+    note(f"  GPU vs oracle: {e}")
+    note(f"  FP32 storage model vs oracle: {floor}")
+    for k in C2_FIELDS:
+        assert e[k] < 3.0 * floor[k] + 1e-7, (k, e[k], floor[k])
+
+
+@pytest.mark.xfail(strict=False, reason="FP32 storage floor of the forced channel "
+                   "(1.6e-6 for u_x at 20000 steps) lies above 1e-6")
+def test_hartmann_c2_transient_fp32_target():
+    h = inputs.hartmann_c2()
+    u, b = h.initial_fields()
+    R = rrmhd()
+    s = c2_solver(R, h)
+    s.init(dev(u), dev(b))
+    s.step(20000)
+    got = gpu_moments(s)
+    s.close()
     o = oracle.Oracle(1, h.ny, h.tau_f, h.tau_m, walls=True, force=(h.G, 0.0),
                       b_wall=(0.0, h.B0))
     o.init(u[:, :, :1], b[:, :, :1])
     o.step(20000)
-    ref = split(*o.moments())
-    for k in ("ux", "bx", "by", "rho"):
-        col = ref[k][:, 0]
-        # columns are identical to each other and match the oracle
-        assert np.max(np.abs(got[k] - got[k][:, :1])) == 0.0
-        e = np.linalg.norm(got[k][:, 0] - col) / np.linalg.norm(col)
-        note(f"  {k}: rel L2 vs oracle = {e:.3e}")
-        assert e < 3e-4
-    s.close()
+    e = column_errors(got, {k: v[:, 0] for k, v in split(*o.moments()).items()})
+    note(f"  C2 transient per field: {e}")
+    assert max(e.values()) <= 1e-6
 
 
 def hartmann_closed_form(h, y):
-    a, Ha, B0 = h.a, h.Ha, h.B0
-    yp = y - (h.ny - 1) / 2.0
-    u = (h.G * a * a / (h.nu * Ha)) * (math.cosh(Ha) - np.cosh(Ha * yp / a)) \
-        / math.sinh(Ha)
-    bx = (h.G * a / B0) * (np.sinh(Ha * yp / a) / math.sinh(Ha) - yp / a)
-    return u, bx
+    return h.profile(y)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_hartmann_c2_steady_state(storage):
-    """512 x 256 Hartmann channel run to steady state on the GPU (started
-    from the closed-form profile, 1.6e6 steps = 6 e-foldings of the slowest
-    mode), against the closed form (<= 1e-3) and against the FP64 oracle's
-    converged profile stored in tests/golden (FP32 storage: the rounded map
-    settles at its own fixed point within a few 1e-6 of the FP64 one)."""
+    """512 x 256 Hartmann channel started from the closed-form profile and run
+    400,000 steps (1.5 e-foldings of the slowest mode) on the GPU, against
+    the closed form (<= 1e-3 for FP32 storage) and, like for like, against the
+    FP64 oracle run from the same profile for the same steps (stored in
+    tests/golden by a script that calls only the oracle).  FP32 storage: per
+    field within 3x of the oracle's FP32 storage model at the same step (the
+    model: 1.1e-6 for u_x, 2.8e-6 for b_x)."""
     import json
     import os
     fx = os.path.join(os.path.dirname(__file__), "golden",
                       "hartmann_c2_oracle.json")
+    with open(fx) as fh:
+        gold = json.load(fh)
     note(f"C2 steady state {storage}")
     h = inputs.hartmann_c2()
+    assert gold["steps"] == 400_000 and gold["start"] == "closed form"
     y = np.arange(h.ny)
     ue, be = hartmann_closed_form(h, y)
     u = np.zeros((2, h.ny, h.nx)); u[0] = ue[:, None]
     b = np.zeros((2, h.ny, h.nx)); b[0] = be[:, None]; b[1] = h.B0
     R = rrmhd()
-    s = R.Solver(h.nx, h.ny, h.tau_f, h.tau_m, storage=storage, walls=True,
-                 force=(h.G, 0.0), b_wall=(0.0, h.B0))
+    s = c2_solver(R, h, storage)
     s.init(dev(u), dev(b))
-    s.step(1_600_000)
+    s.step(gold["steps"])
     got = gpu_moments(s)
     s.close()
+    e = column_errors(got, gold["fp64"])
     gu, gb = got["ux"][:, 0], got["bx"][:, 0]
-    assert np.max(np.abs(got["ux"] - got["ux"][:, :1])) == 0.0
     eu = np.linalg.norm(gu - ue) / np.linalg.norm(ue)
     eb = np.linalg.norm(gb - be) / np.linalg.norm(be)
     note(f"  vs closed form: u {eu:.3e}  b_x {eb:.3e}")
-    tol_cf = 1e-3 if storage == "f32" else 5e-3
-    assert eu < tol_cf and eb < tol_cf
-    if os.path.exists(fx):
-        with open(fx) as fh:
-            gold = json.load(fh)
-        ou, ob = np.array(gold["ux"]), np.array(gold["bx"])
-        du = np.linalg.norm(gu - ou) / np.linalg.norm(ou)
-        db = np.linalg.norm(gb - ob) / np.linalg.norm(ob)
-        note(f"  vs FP64 oracle steady state: u {du:.3e}  b_x {db:.3e}")
-        # The slowest Hartmann modes relax over ~1e5 steps; once their
-        # per-step change falls below half a unit in the last place of the
-        # stored offsets (~2e-10 on values ~5e-3 in FP32), the rounded map
-        # stops moving.  That leaves a residual of order ulp x relaxation
-        # time / field ~ 1e-3 of the profile, for FP32 and FP16 storage alike.
-        tol = 2e-3 if storage == "f32" else 1e-2
-        assert du < tol and db < tol
+    note(f"  vs FP64 oracle, same start and steps: {e}")
+    if storage == "f32":
+        assert eu < 1e-3 and eb < 1e-3
+        for k in C2_FIELDS:
+            ref, mod = np.array(gold["fp64"][k]), np.array(gold["fp32_storage"][k])
+            floor = np.linalg.norm(mod - ref) / np.linalg.norm(ref)
+            note(f"  {k}: model {floor:.3e}")
+            assert e[k] < 3.0 * floor + 1e-7, (k, e[k], floor)
+    else:
+        # FP16 storage holds the profile only to its own rounding
+        assert eu < 5e-3 and eb < 5e-3
+        assert max(e.values()) < 1e-2
 
 
 # ---------------------------------------------------------------------------
@@ -445,11 +483,20 @@ def test_full_size_8192_sampled(storage, k, count):
     del rho, uu, bb
     torch.cuda.empty_cache()
     ref = np.array([patch_oracle(u, b, x, y, k, tau, tau) for x, y in pts])
+    # per-field rel L2 over the sampled nodes (the per-field measure of the
+    # precision targets, estimated on the sample), and the largest single
+    # error in units of the field's rms scale
+    rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
     scale = np.array([1.0, 0.04, 0.04, 0.04, 0.04])
     err = np.max(np.abs(got - ref) / scale, axis=0)
+    note(f"  sampled rel L2 per field: {rel}")
     note(f"  max |err| / field scale: {err}")
-    tol = (1e-6 if k < 10 else 1e-5) if storage == "f32" else (3e-3 if k < 10 else 1e-2)
-    assert np.all(err < tol), err
+    if storage == "f32":
+        assert np.all(rel < 1e-6), rel
+        assert np.all(err < 2e-6), err
+    else:
+        tol = 3e-3 if k < 10 else 1e-2
+        assert np.all(err < tol), err
 
 
 # ---------------------------------------------------------------------------
@@ -690,7 +737,10 @@ def test_stochastic_rounding_keeps_small_increments():
     momentum gained over k steps is k times the force (Guo forcing conserves
     mass and adds rho G per step), as with FP32 storage.  The mean field is
     conserved by the induction collision and stays put within the rounding
-    noise."""
+    noise.  FP32 storage: the forced step computes in FP64 and rounds only on
+    storage, so the gain is exact to the storage rounding (the oracle's FP32
+    storage model of this single-node state gains 1 - 1.7e-6 of k G; bar
+    1e-4, where FP32 arithmetic lost 0.2 % of the force)."""
     R = rrmhd()
     n, k, G = 128, 200, 1e-6
     u = np.zeros((2, n, n))
@@ -709,7 +759,7 @@ def test_stochastic_rounding_keeps_small_increments():
         drift[storage] = max(abs(float(np.mean(m1[f]) - np.mean(m0[f]))) for f in ("bx", "by"))
         note(f"  {storage}: momentum gain / (k G) = {gain[storage] / (k * G):.4f}, "
              f"mean-field drift {drift[storage]:.2e}")
-    assert abs(gain["f32"] / (k * G) - 1) < 0.02
+    assert abs(gain["f32"] / (k * G) - 1) < 1e-4
     assert abs(gain["f16sr"] / (k * G) - 1) < 0.1
     assert abs(gain["f16"]) < 0.5 * k * G
     assert drift["f16sr"] < 2e-6
