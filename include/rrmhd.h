@@ -354,7 +354,10 @@ const char *rrmhd_batch_last_error_detail(void);
  *   (a_xx, a_xy, a_yy) += sigma_out * y,
  * GELU(z) = z/2 (1 + tanh(sqrt(2/pi)(z + 0.044715 z^3))).  On the GPU the
  * layers run as BF16 MFMA (x_hat, weights, h1, h2 rounded to BF16, FP32
- * accumulation, FP32 biases and GELU) fused into the step kernel.
+ * accumulation and biases) fused into the step kernel; GELU is applied to
+ * the BF16-rounded pre-activation through a table holding, for each of the
+ * 65,536 BF16 bit patterns, the tanh-form GELU evaluated in FP64 and
+ * correctly rounded to BF16.
  * params: 4931 FP32 = W1[64][8], b1[64], W2[64][64], b2[64], W3[3][64],
  * b3[3]; norm: 19 FP32 = mu[8], sigma[8], sigma_out[3]; both DEVICE
  * pointers, read at the call (stream-ordered).  Zero weights and biases give
@@ -369,6 +372,10 @@ int rrmhd_closure_enable(rrmhd *h, int on);
  * step.  Synchronises hip_stream. */
 int rrmhd_closure_eval(const float *params, const float *norm, const float *x,
                        int64_t n, float *y, void *hip_stream);
+/* The GELU table the inference uses: out[v] (65,536 uint16, DEVICE) is the
+ * BF16 bit pattern of GELU(bf16 value with bit pattern v).  Stream-ordered on
+ * hip_stream, asynchronous. */
+int rrmhd_closure_gelu_table(uint16_t *out, void *hip_stream);
 
 /* Training of the closure (FP32 kernels).  Data (a-priori regression): fine
  * moments rho[nf][nf], u, b [2][nf][nf] (device FP64, e.g. from

@@ -719,7 +719,7 @@ int rrmhd_closure_set(rrmhd *h, const float *params, const float *norm) {
     int dev = 0, cus = 256;
     HIP_OR_RETURN(hipGetDevice(&dev));
     HIP_OR_RETURN(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    h->closure_grid = cus * 4;
+    h->closure_grid = cus;  // one 1024-thread block per CU (LDS-bound)
   }
   return RRMHD_OK;
 }
@@ -746,6 +746,12 @@ int rrmhd_closure_eval(const float *params, const float *norm, const float *x, i
   (void)hipFree(mlp);
   if (e != hipSuccess) return dev_err(e, "closure eval");
   if (e2 != hipSuccess) return dev_err(e2, "hipStreamSynchronize");
+  return RRMHD_OK;
+}
+
+int rrmhd_closure_gelu_table(uint16_t *out, void *hip_stream) {
+  if (!out) return RRMHD_EINVAL;
+  HIP_OR_RETURN(rr::launch_gelu_table(out, (hipStream_t)hip_stream));
   return RRMHD_OK;
 }
 

@@ -7,13 +7,24 @@
 // non-equilibrium coefficients before the recursion of algorithm task 3.
 // GELU is the tanh form (Hendrycks & Gimpel 2016).
 //
-// One wavefront evaluates 64 nodes (one per lane).  Layers 1 and 2 run as
-// BF16 MFMA 32x32x8 with FP32 accumulation, written transposed
-// (Z^T = W X^T): the accumulator layout of layer 1 (lane = node column,
-// registers = hidden rows) is exactly the B-operand layout layer 2 needs, so
-// activations never leave registers.  Layer 3 (3 outputs) is 32 FMAs per
-// lane plus one cross-half exchange.  x_hat, weights and h1/h2 are BF16
-// (round to nearest even); biases, GELU and accumulation are FP32.
+// One wavefront evaluates 64 nodes (one per lane) in two passes of 32 nodes.
+// All three layers run on the matrix cores, written transposed (Z^T = W X^T)
+// so that nodes are the MFMA columns: layer 1 as BF16 MFMA 32x32x8 (K = the 8
+// features), layers 2 and 3 as gfx950's BF16 MFMA 32x32x16 with FP32
+// accumulation.  The accumulator of a 32x32 MFMA holds, in lane (column c,
+// half s) and register r, row 8 (r / 4) + 4 s + r % 4; a layer's
+// activations are handed to the next layer as its B operand in exactly that
+// register order, and the next layer's weights are stored permuted to match
+// (the contraction does not depend on the order of its K index as long as A
+// and B agree), so activations never leave registers.  Biases enter as the
+// accumulators' initial values.
+//
+// GELU is a table lookup: the pre-activation is rounded to BF16 (as the next
+// layer's operands are), and the table, held in LDS, gives the correctly
+// rounded BF16 value of the tanh-form GELU for every one of the 65,536 BF16
+// bit patterns (computed once in FP64 when the parameters are prepared).  Two
+// VALU instructions and one LDS read per activation replace an exponential
+// and a reciprocal, which made the GELUs the kernel's largest cost.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,26 +38,55 @@ constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kNH * kNIN, kOffW2 = kOffB1 + kNH,
               kOffB2 = kOffW2 + kNH * kNH, kOffW3 = kOffB2 + kNH,
               kOffB3 = kOffW3 + kNOUT * kNH, kNParam = kOffB3 + kNOUT;
 constexpr int kNNorm = 2 * kNIN + kNOUT;
+constexpr int kGeluTable = 65536;
 
-// Prepared parameters (global memory and the LDS copy share this layout).
-struct MlpDev {
-  uint16_t w1[kNH * kNIN];  // BF16 bits
-  uint16_t w2[kNH * kNH];   // BF16 bits
+// Hidden unit held in slot j (0..7) of the 16-wide K block kb (0..3) by a
+// lane of half s: the accumulator rows of block kb / 2, registers
+// 8 (kb % 2) + j.
+__host__ __device__ constexpr int hid_of(int kb, int s, int j) {
+  return 32 * (kb >> 1) + 16 * (kb & 1) + 8 * (j >> 2) + 4 * s + (j & 3);
+}
+
+// Prepared parameters (global memory and the LDS copy share this layout;
+// every array used by 16-byte LDS reads starts on a 16-byte boundary).
+struct alignas(16) MlpDev {
+  uint16_t gelu[kGeluTable];          // BF16 bits: GELU of each BF16 value
+  uint16_t w1[kNH * kNIN];            // BF16 W1, row-major (layer-1 A operand)
+  uint16_t w2p[2 * 4 * 2 * 32 * 8];   // BF16 W2 in A-operand order [mb][kb][s][m][j]
+  uint16_t w3p[4 * 2 * kNOUT * 8];    // BF16 W3 in A-operand order [kb][s][o][j]
   float b1[kNH], b2[kNH];
-  float w3[kNOUT * kNH];  // BF16-rounded values
   float b3[kNOUT];
   float mu[kNIN], inv_sigma[kNIN], sigma_out[kNOUT];
   int zero;  // 1: all weights and biases zero (correction is exactly 0)
+  int pad_;
 };
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet).
 __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u;
   __builtin_memcpy(&u, &f, 4);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// FP64 -> BF16, correctly rounded to nearest even.  The FP32 rounding of v
+// can only create a BF16 tie that v itself does not sit on; that case is
+// decided by which side of the FP32 value v lies.
+__host__ __device__ __forceinline__ uint16_t d2bf(double v) {
+  const float f = (float)v;
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  if ((u & 0xffffu) == 0x8000u && (double)f != v) {
+    const bool away = (v > (double)f) == (f > 0.0f);
+    return (uint16_t)((u >> 16) + (away ? 1u : 0u));
+  }
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
@@ -63,25 +103,11 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return u;
 }
 
-__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
-
-__device__ __forceinline__ float bf2f(uint16_t h) {
+__host__ __device__ __forceinline__ float bf2f(uint16_t h) {
   const uint32_t u = (uint32_t)h << 16;
   float f;
   __builtin_memcpy(&f, &u, 4);
   return f;
-}
-
-// GELU in its tanh form, evaluated through the identity
-// z/2 (1 + tanh(v)) = z / (1 + exp(-2 v)), v = sqrt(2/pi) (z + 0.044715 z^3):
-// one hardware exp2 and one reciprocal instead of a tanh.  Large |v| give
-// exp2 -> inf (result -0 or 0) or -> 0 (result z), as the tanh form does.
-__device__ __forceinline__ float gelu_f(float z) {
-  const float k2 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) / ln 2
-  const float v = fmaf(0.044715f * z, z * z, z);
-  const float e = __builtin_amdgcn_exp2f(k2 * v);
-  return z * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
 __device__ __forceinline__ shortx4 ld4(const uint16_t *p) {
@@ -90,81 +116,111 @@ __device__ __forceinline__ shortx4 ld4(const uint16_t *p) {
   return v;
 }
 
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
+  bf16x8 v;
+  __builtin_memcpy(&v, p, 16);
+  return v;
+}
+
+__device__ __forceinline__ bf16x8 words8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const uint32_t w[4] = {a, b, c, d};
+  bf16x8 v;
+  __builtin_memcpy(&v, w, 16);
+  return v;
+}
+
+// Accumulator initialised with the bias of its rows (32 mb + 8 q + 4 s + i).
+__device__ __forceinline__ floatx16 bias_acc(const float *b, int mb, int s) {
+  floatx16 acc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    floatx4 v;
+    __builtin_memcpy(&v, b + 32 * mb + 8 * q + 4 * s, 16);
+    acc[4 * q + 0] = v[0];
+    acc[4 * q + 1] = v[1];
+    acc[4 * q + 2] = v[2];
+    acc[4 * q + 3] = v[3];
+  }
+  return acc;
+}
+
+// GELU of an accumulator block through the LDS table: eight words of two
+// BF16 activations each, in register order.
+__device__ __forceinline__ void gelu_block(const uint16_t *__restrict__ tab, const floatx16 &acc,
+                                           uint32_t (&w)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t p = pack_bf16x2(acc[2 * k], acc[2 * k + 1]);
+    w[k] = (uint32_t)tab[p & 0xffffu] | ((uint32_t)tab[p >> 16] << 16);
+  }
+}
+
 // Evaluate the network for the 64 nodes of the calling wavefront.  All 64
 // lanes must call it together.  xh: this lane's normalised features;
-// W: parameters (LDS); xs: 64 x 8 BF16 scratch of this wave (LDS).
-// Returns y[3] (normalised output) of this lane's node.
-__device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
-                                         uint16_t *__restrict__ xs,
-                                         const float (&xh)[kNIN], float (&y)[kNOUT]) {
+// W: parameters (LDS).  Returns y[3] (normalised output) of this lane's node.
+__device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W, const float (&xh)[kNIN],
+                                         float (&y)[kNOUT]) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5, col = lane & 31;
-  // stage this node's features as row `lane` of X (64 x 8)
-  uint32_t *xrow = reinterpret_cast<uint32_t *>(xs + lane * kNIN);
+  // this node's features as four words of two BF16; a pass over the nodes of
+  // half nb needs, in lane (c, s), features 4 s .. 4 s + 3 of node 32 nb + c:
+  // its own words when s == nb, else those of lane (c, 1 - s)
+  uint32_t fw[4];
 #pragma unroll
-  for (int k = 0; k < kNIN / 2; ++k) xrow[k] = pack_bf16x2(xh[2 * k], xh[2 * k + 1]);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = 0; k < 4; ++k) fw[k] = pack_bf16x2(xh[2 * k], xh[2 * k + 1]);
+  const uint32_t send0 = half ? fw[0] : fw[2], send1 = half ? fw[1] : fw[3];
+  const uint32_t recv0 = __shfl_xor(send0, 32, 64), recv1 = __shfl_xor(send1, 32, 64);
+  const uint32_t own0 = half ? fw[2] : fw[0], own1 = half ? fw[3] : fw[1];
   float own[kNOUT] = {0.0f, 0.0f, 0.0f};
 #pragma unroll 1
   for (int nb = 0; nb < 2; ++nb) {
-    // weights are re-read from LDS in each pass: hoisting them out of this
-    // loop would hold ~200 loop-invariant values in registers
+    // weights are re-read from LDS in each pass: hoisted out of this loop
+    // they would hold several hundred values in registers
     asm volatile("" ::: "memory");
-    // layer 1, transposed: Z1^T (64 hidden x 32 nodes) = W1 (64 x 8) X^T
-    const shortx4 bx = ld4(xs + (32 * nb + col) * kNIN + 4 * half);
-    shortx4 b2op[8];  // layer-2 B operands: h1 rows 8 kk + 4 half + q
+    const bool mine = nb == half;
+    uint32_t xw[2] = {mine ? own0 : recv0, mine ? own1 : recv1};
+    shortx4 bx;
+    __builtin_memcpy(&bx, xw, 8);
+    // layer 1: Z1^T (64 hidden x 32 nodes) = W1 (64 x 8) X^T
+    uint32_t h1[2][8];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
+      floatx16 acc = bias_acc(W->b1, mb, half);
       const shortx4 aw = ld4(W->w1 + (32 * mb + col) * kNIN + 4 * half);
-      floatx16 acc = {0};
       acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, bx, acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int h = 32 * mb + 8 * r + 4 * half;
-        uint32_t w[2];
-#pragma unroll
-        for (int q = 0; q < 4; q += 2)
-          w[q / 2] = pack_bf16x2(gelu_f(acc[4 * r + q] + W->b1[h + q]),
-                                 gelu_f(acc[4 * r + q + 1] + W->b1[h + q + 1]));
-        __builtin_memcpy(&b2op[4 * mb + r], w, 8);
-      }
+      gelu_block(W->gelu, acc, h1[mb]);
     }
-    // layer 2, transposed: Z2^T (64 x 32 nodes) = W2 (64 x 64) H1^T
-    float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f;
+    // layer 2: Z2^T (64 x 32 nodes) = W2 (64 x 64) H1^T, four 16-wide K blocks
+    uint32_t h2[2][8];
 #pragma unroll
-    for (int mb2 = 0; mb2 < 2; ++mb2) {
-      floatx16 acc = {0};
+    for (int mb = 0; mb < 2; ++mb) {
+      floatx16 acc = bias_acc(W->b2, mb, half);
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const shortx4 aw = ld4(W->w2 + (32 * mb2 + col) * kNH + 8 * kk + 4 * half);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, b2op[kk], acc, 0, 0, 0);
+      for (int kb = 0; kb < 4; ++kb) {
+        const bf16x8 aw = ld8(W->w2p + (((mb * 4 + kb) * 2 + half) * 32 + col) * 8);
+        const uint32_t *hw = h1[kb >> 1] + 4 * (kb & 1);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, words8(hw[0], hw[1], hw[2], hw[3]),
+                                                       acc, 0, 0, 0);
       }
-      // layer 3 partial sums over this lane's 16 rows of h2 (h2 rounded to
-      // BF16 like the layer inputs)
-#pragma unroll
-      for (int i = 0; i < 16; i += 2) {
-        const int h = 32 * mb2 + 8 * (i >> 2) + 4 * half + (i & 3);
-        const uint32_t u = pack_bf16x2(gelu_f(acc[i] + W->b2[h]), gelu_f(acc[i + 1] + W->b2[h + 1]));
-        const float ha = bf16_lo(u), hb = bf16_hi(u);
-        p0 = fmaf(W->w3[0 * kNH + h], ha, p0);
-        p1 = fmaf(W->w3[1 * kNH + h], ha, p1);
-        p2 = fmaf(W->w3[2 * kNH + h], ha, p2);
-        p0 = fmaf(W->w3[0 * kNH + h + 1], hb, p0);
-        p1 = fmaf(W->w3[1 * kNH + h + 1], hb, p1);
-        p2 = fmaf(W->w3[2 * kNH + h + 1], hb, p2);
-      }
+      gelu_block(W->gelu, acc, h2[mb]);
     }
-    // the other half of the wave holds the other 32 rows of the same nodes
-    const float s0 = p0 + __shfl_xor(p0, 32, 64);
-    const float s1 = p1 + __shfl_xor(p1, 32, 64);
-    const float s2 = p2 + __shfl_xor(p2, 32, 64);
-    // lane l's node is node 32 * (l / 32) + l % 32 = l: keep block nb = l / 32
-    if (nb == half) {
-      own[0] = s0;
-      own[1] = s1;
-      own[2] = s2;
+    // layer 3: rows 0..2 of a 32-row product carry the three outputs (the
+    // other rows' weights are zero)
+    floatx16 acc3 = {0};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      bf16x8 aw = {};
+      if (col < kNOUT) aw = ld8(W->w3p + ((kb * 2 + half) * kNOUT + col) * 8);
+      const uint32_t *hw = h2[kb >> 1] + 4 * (kb & 1);
+      acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, words8(hw[0], hw[1], hw[2], hw[3]),
+                                                      acc3, 0, 0, 0);
+    }
+    // output o of node 32 nb + c sits in lane c (half 0), register o; its
+    // owner is lane 32 nb + c
+#pragma unroll
+    for (int o = 0; o < kNOUT; ++o) {
+      const float v = __shfl(acc3[o], col, 64);
+      if (mine) own[o] = v;
     }
   }
 #pragma unroll
@@ -173,9 +229,10 @@ __device__ __forceinline__ void mlp_wave(const MlpDev *__restrict__ W,
 
 // Copy the prepared parameters into LDS (all threads of the block).
 __device__ __forceinline__ void mlp_to_lds(const MlpDev *__restrict__ g, MlpDev *s) {
-  const uint32_t *src = (const uint32_t *)g;
-  uint32_t *dst = (uint32_t *)s;
-  constexpr int n = sizeof(MlpDev) / 4;
+  const uint4 *src = (const uint4 *)g;
+  uint4 *dst = (uint4 *)s;
+  constexpr int n = sizeof(MlpDev) / 16;
+  static_assert(sizeof(MlpDev) % 16 == 0, "MlpDev is copied in 16-byte words");
   for (int k = threadIdx.x + threadIdx.y * blockDim.x; k < n; k += blockDim.x * blockDim.y)
     dst[k] = src[k];
   __syncthreads();

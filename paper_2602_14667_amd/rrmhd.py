@@ -33,6 +33,7 @@ EXPORTED = [
     "rrmhd_batch_destroy", "rrmhd_batch_last_error_detail",
     "rrmhd_autotune", "rrmhd_batch_autotune",
     "rrmhd_closure_set", "rrmhd_closure_enable", "rrmhd_closure_eval",
+    "rrmhd_closure_gelu_table",
     "rrmhd_train_samples", "rrmhd_train_create", "rrmhd_train_loss_grad",
     "rrmhd_train_onestep_samples", "rrmhd_train_onestep_loss_grad",
     "rrmhd_train_adam", "rrmhd_train_destroy", "rrmhd_train_last_error_detail",
@@ -141,6 +142,7 @@ def lib():
         L.rrmhd_closure_set.argtypes = [vp, vp, vp]
         L.rrmhd_closure_enable.argtypes = [vp, ci]
         L.rrmhd_closure_eval.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.rrmhd_closure_gelu_table.argtypes = [vp, vp]
         L.rrmhd_train_samples.argtypes = [vp, vp, vp, ci, ci, ctypes.c_double,
                                           vp, vp, vp, vp]
         L.rrmhd_train_create.argtypes = [i64, vp, ctypes.POINTER(vp)]
@@ -183,6 +185,34 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _own_stream(stream):
+    """The torch stream a handle is created on (torch's current one if None)."""
+    import torch
+    return torch.cuda.current_stream() if stream is None else stream
+
+
+def _before(stream):
+    """Before a call that reads or writes caller tensors: the handle's stream
+    waits for torch's current stream, where those tensors were produced."""
+    import torch
+    cur = torch.cuda.current_stream(stream.device)
+    if cur != stream:
+        stream.wait_stream(cur)
+
+
+def _after(stream, *tensors):
+    """After such a call: the caching allocator keeps the tensors until the
+    handle's stream is done with them, and torch's current stream waits for
+    the handle's stream before the caller uses the results."""
+    import torch
+    cur = torch.cuda.current_stream(stream.device)
+    if cur != stream:
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+        cur.wait_stream(stream)
+
+
 def _dev_f64(t, shape, name):
     import torch
     if t is None:
@@ -201,6 +231,16 @@ def _dev_f32(t, shape, name):
         raise ValueError(f"{name} must be a contiguous float32 device tensor "
                          f"of shape {shape}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def closure_gelu_table(stream=None):
+    """The inference's GELU table as an int16 device tensor [65536] holding
+    BF16 bit patterns: entry v is GELU of the BF16 value with pattern v."""
+    import torch
+    t = torch.empty(65536, dtype=torch.int16, device="cuda")
+    _check(lib().rrmhd_closure_gelu_table(ctypes.c_void_p(t.data_ptr()),
+                                          _stream_handle(stream)), "rrmhd_closure_gelu_table")
+    return t
 
 
 def closure_eval(params, norm, x, stream=None):
@@ -235,7 +275,7 @@ class Solver:
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.storage = storage
-        self._stream = stream
+        self._stream = _own_stream(stream)
         kind = {"f32": STORE_F32, "f16": STORE_F16, "f16sr": STORE_F16_SR}[storage]
         g = Grid(self.nx, self.ny, kind | (STORE_INPLACE if inplace else 0),
                  float(codec_scale))
@@ -243,7 +283,7 @@ class Solver:
                 (ctypes.c_double * 2)(*force), (ctypes.c_double * 2)(*b_wall))
         h = ctypes.c_void_p()
         _check(L.rrmhd_create(ctypes.byref(g), float(tau_f), float(tau_m),
-                              ctypes.byref(bc), _stream_handle(stream),
+                              ctypes.byref(bc), _stream_handle(self._stream),
                               ctypes.byref(h)), "rrmhd_create")
         self._h = h
         if equilibrium != "algorithm":
@@ -270,8 +310,10 @@ class Solver:
     # -- calls ---------------------------------------------------------------
     def init(self, u, b):
         shp = (2, self.ny, self.nx)
+        _before(self._stream)
         _check(lib().rrmhd_init(self._h, _dev_f64(u, shp, "u"),
                                 _dev_f64(b, shp, "b")), "rrmhd_init")
+        _after(self._stream, u, b)
 
     def step(self, n=1):
         _check(lib().rrmhd_step(self._h, int(n)), "rrmhd_step")
@@ -286,10 +328,12 @@ class Solver:
             u = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=dev)
         if b is None:
             b = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=dev)
+        _before(self._stream)
         _check(lib().rrmhd_moments(
             self._h, _dev_f64(rho, (self.ny, self.nx), "rho"),
             _dev_f64(u, (2, self.ny, self.nx), "u"),
             _dev_f64(b, (2, self.ny, self.nx), "b")), "rrmhd_moments")
+        _after(self._stream, rho, u, b)
         return rho, u, b
 
     def current_vorticity(self):
@@ -298,9 +342,11 @@ class Solver:
         dev = torch.device("cuda", torch.cuda.current_device())
         jz = torch.empty((self.ny, self.nx), dtype=torch.float64, device=dev)
         wz = torch.empty((self.ny, self.nx), dtype=torch.float64, device=dev)
+        _before(self._stream)
         _check(lib().rrmhd_current_vorticity(self._h, ctypes.c_void_p(jz.data_ptr()),
                                              ctypes.c_void_p(wz.data_ptr())),
                "rrmhd_current_vorticity")
+        _after(self._stream, jz, wz)
         return jz, wz
 
     def diagnostics(self, allow_nonfinite=False):
@@ -343,14 +389,18 @@ class Solver:
         return int(lib().rrmhd_state_bytes(self._h))
 
     def save_state(self, dst):
+        _before(self._stream)
         _check(lib().rrmhd_save_state(self._h, ctypes.c_void_p(dst.data_ptr()),
                                       dst.numel() * dst.element_size()),
                "rrmhd_save_state")
+        _after(self._stream, dst)
 
     def load_state(self, src, step_count):
+        _before(self._stream)
         _check(lib().rrmhd_load_state(self._h, ctypes.c_void_p(src.data_ptr()),
                                       src.numel() * src.element_size(),
                                       int(step_count)), "rrmhd_load_state")
+        _after(self._stream, src)
 
     def run(self, n, every, log=None):
         """Advance n steps, taking the diagnostics and invariants after every
@@ -438,8 +488,8 @@ class Solver:
         _check(lib().rrmhd_set_equilibrium(self._h, k), "rrmhd_set_equilibrium")
 
     def set_stream(self, stream):
-        self._stream = stream
-        _check(lib().rrmhd_set_stream(self._h, _stream_handle(stream)),
+        self._stream = _own_stream(stream)
+        _check(lib().rrmhd_set_stream(self._h, _stream_handle(self._stream)),
                "rrmhd_set_stream")
 
 
@@ -451,12 +501,12 @@ class Solver3D:
     def __init__(self, nx, ny, nz, tau_f, tau_m, storage="f32", stream=None, inplace=False):
         L = lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        self._stream = stream
+        self._stream = _own_stream(stream)
         h = ctypes.c_void_p()
         kind = STORE_F16 if storage == "f16" else STORE_F32
         _check(L.rrmhd3d_create(self.nx, self.ny, self.nz,
                                 kind | (STORE_INPLACE if inplace else 0),
-                                float(tau_f), float(tau_m), _stream_handle(stream),
+                                float(tau_f), float(tau_m), _stream_handle(self._stream),
                                 ctypes.byref(h)), "rrmhd3d_create")
         self._h = h
 
@@ -473,8 +523,10 @@ class Solver3D:
 
     def init(self, u, b):
         shp = (3, self.nz, self.ny, self.nx)
+        _before(self._stream)
         _check(lib().rrmhd3d_init(self._h, _dev_f64(u, shp, "u"), _dev_f64(b, shp, "b")),
                "rrmhd3d_init")
+        _after(self._stream, u, b)
 
     def step(self, n=1):
         _check(lib().rrmhd3d_step(self._h, int(n)), "rrmhd3d_step")
@@ -491,9 +543,11 @@ class Solver3D:
         rho = torch.empty(shp, dtype=torch.float64, device="cuda")
         u = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
         b = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
+        _before(self._stream)
         _check(lib().rrmhd3d_moments(self._h, _dev_f64(rho, shp, "rho"),
                                      _dev_f64(u, (3,) + shp, "u"), _dev_f64(b, (3,) + shp, "b")),
                "rrmhd3d_moments")
+        _after(self._stream, rho, u, b)
         return rho, u, b
 
     def diagnostics(self, allow_nonfinite=False):
@@ -547,9 +601,10 @@ class Batch:
         tf = (ctypes.c_double * n)(*map(float, tau_f))
         tm = (ctypes.c_double * n)(*map(float, tau_m))
         h = ctypes.c_void_p()
+        self._stream = _own_stream(stream)
         rc = L.rrmhd_batch_create(n, grids, tf, tm,
                                   STORE_F16 if storage == "f16" else STORE_F32,
-                                  _stream_handle(stream), ctypes.byref(h))
+                                  _stream_handle(self._stream), ctypes.byref(h))
         if rc != OK:
             raise RuntimeError(f"rrmhd_batch_create: {rc} "
                                f"{L.rrmhd_batch_last_error_detail().decode()}")
@@ -576,9 +631,11 @@ class Batch:
     def init(self, d, u, b):
         nx, ny = self.shapes[d]
         shp = (2, ny, nx)
+        _before(self._stream)
         self._chk(lib().rrmhd_batch_init(self._h, int(d), _dev_f64(u, shp, "u"),
                                          _dev_f64(b, shp, "b")),
                   "rrmhd_batch_init")
+        _after(self._stream, u, b)
 
     def step(self, n=1):
         self._chk(lib().rrmhd_batch_step(self._h, int(n)), "rrmhd_batch_step")
@@ -603,10 +660,12 @@ class Batch:
         rho = torch.empty((ny, nx), dtype=torch.float64, device=dev)
         u = torch.empty((2, ny, nx), dtype=torch.float64, device=dev)
         b = torch.empty((2, ny, nx), dtype=torch.float64, device=dev)
+        _before(self._stream)
         self._chk(lib().rrmhd_batch_moments(
             self._h, int(d), ctypes.c_void_p(rho.data_ptr()),
             ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(b.data_ptr())),
             "rrmhd_batch_moments")
+        _after(self._stream, rho, u, b)
         return rho, u, b
 
     def diagnostics(self, d):

@@ -144,3 +144,58 @@ def test_runtime_fallback_to_plain():
     for c in cps:
         assert np.array_equal(got[c][0], plain[c][0])
         assert got[c][1] == plain[c][1] and got[c][2] == plain[c][2]
+
+
+def _bf16_values(bits):
+    """Float64 values of uint16 BF16 bit patterns."""
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _round_to_bf16(v):
+    """Correctly rounded BF16 bit patterns (nearest, ties to even) of float64
+    values, by comparing the two BF16 neighbours found by truncating the
+    FP32 conversion toward zero and stepping one unit up."""
+    f = v.astype(np.float32)
+    u = f.view(np.uint32)
+    lo = (u >> 16).astype(np.uint32)
+    hi = lo + 1
+    with np.errstate(invalid="ignore"):
+        dl = np.abs(_bf16_values(lo.astype(np.uint16)) - v)
+        dh = np.abs(_bf16_values(hi.astype(np.uint16)) - v)
+        pick_hi = (dh < dl) | ((dh == dl) & (hi % 2 == 0))
+    out = np.where(pick_hi, hi, lo).astype(np.uint16)
+    nan = np.isnan(v)
+    out[nan] = ((u[nan] >> 16) | 0x40).astype(np.uint16)
+    return out
+
+
+def test_gelu_table_is_correctly_rounded():
+    """Every entry of the inference's GELU table is the tanh-form GELU of its
+    BF16 argument, evaluated in FP64 here by numpy and rounded to the nearest
+    BF16 (ties to even); infinities and NaN propagate as the formula does
+    (+inf -> +inf, -inf -> NaN, NaN -> NaN).  The reference uses the form
+    z / (1 + exp(-2 v)) of z/2 (1 + tanh v), which avoids the cancellation of
+    1 + tanh v for large negative z, where the tanh form itself carries a
+    relative error of a few per cent in FP64."""
+    rr = R()
+    tab = rr.closure_gelu_table().cpu().numpy().view(np.uint16)
+    bits = np.arange(65536, dtype=np.uint32).astype(np.uint16)
+    with np.errstate(invalid="ignore", over="ignore"):
+        z = _bf16_values(bits)
+        v = np.sqrt(2.0 / np.pi) * (z + 0.044715 * z ** 3)
+        g = z / (1.0 + np.exp(-2.0 * v))
+        # the two forms agree wherever 1 + tanh v does not cancel
+        t = 0.5 * z * (1.0 + np.tanh(v))
+        ok = np.isfinite(t) & (z > -2.0)
+        assert np.allclose(g[ok], t[ok], rtol=1e-12, atol=1e-300)
+        want = _round_to_bf16(g)
+    with np.errstate(invalid="ignore"):
+        got_v, want_v = _bf16_values(tab), _bf16_values(want)
+    both_nan = np.isnan(got_v) & np.isnan(want_v)
+    mism = ~both_nan & (tab != want)
+    note(f"  GELU table: {int(mism.sum())} mismatching entries of 65536")
+    assert not mism.any(), np.nonzero(mism)[0][:10]
+    # spot values: GELU(0) = 0, GELU(1) = 0.8412 -> BF16 0.84375, large z -> z
+    assert tab[0] == 0
+    assert abs(_bf16_values(tab[[0x3f80]])[0] - 0.8411920) < 4e-3
+    assert tab[0x4300] == 0x4300  # GELU(128) = 128
