@@ -47,6 +47,18 @@ def measured_traffic(storage, n, dims=2):
     return t.get("bytes_per_launch")
 
 
+def batch_traffic():
+    """HBM bytes per ensemble launch (default launch shape) from the committed
+    counter summary, or None when absent or taken on other kernel sources."""
+    from paper_2602_14667_amd import batch_hash
+    path = os.path.join(ROOT, "profiles", "traffic_batch_f32_256.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    return t.get("bytes_per_launch") if t.get("kernel_hash") == batch_hash() else None
+
+
 def environment(torch):
     """Where the numbers were taken: GPU, HIP runtime and torch versions, host
     CPU model and thread count."""
@@ -281,7 +293,8 @@ def batch_bench(torch, rrmhd, inputs, args):
                    "autotune_s": round(tune_s, 2)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+                     "frac": round(gbs / PEAK_HBM_GBS, 4),
+                     "traffic": batch_traffic() if args.no_autotune else None},
         "sequential_standalone_ms_per_step": round(seq_ms, 4),
         "speedup_vs_sequential": round(seq_ms / ms, 3)}), flush=True)
 
@@ -505,7 +518,8 @@ def closure_step_bench(torch, rrmhd, inputs, args):
     ms = res["closure"]
     nodes = n * n
     gbs = 152 * nodes / ms / 1e6
-    mfma_tf = 9216 * nodes / ms / 1e9
+    # the network's algorithmic work: 2 (8 x 64 + 64 x 64 + 64 x 3) FLOP per node
+    mfma_tf = 9600 * nodes / ms / 1e9
     print(json.dumps({
         "metric": "MLUPS (fused RR-MHD step with the closure network)",
         "value": round(nodes / ms / 1e3, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -582,6 +596,62 @@ def closure_bench(args):
         "fallbacks": [t["fallback_at"] for t in tests]}), flush=True)
 
 
+def time_turbulence_leg(torch, rrmhd, args, fields, storage):
+    """Warm-up, then args.steps fused steps of the turbulence workload timed with
+    HIP events on the handle's stream, then diagnostics (timed separately)."""
+    n = args.n
+    ud, bd = fields
+    s = rrmhd.Solver(n, n, args.tau, args.tau, storage=storage,
+                     equilibrium=args.equilibrium, inplace=args.inplace)
+    launch = ("library default (f32: 128x2 threads; f16: 128x1 threads, two nodes "
+              "per thread; NT stores)")
+    if args.equilibrium != "algorithm":
+        launch = "library default block shape, one node per thread, NT stores"
+    if args.inplace:
+        launch = ("library default for one buffer (f32: 64x1, f16: 128x1 threads, XCD-local "
+                  "order, NT stores); steps alternate pull+push and own-slot forms")
+    s.init(ud, bd)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    s.step(args.steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_launches = e0.elapsed_time(e1)
+    ek, em, dv = s.diagnostics(allow_nonfinite=True)
+    # diagnostics (every K steps in a run, not per step): timed separately
+    d0 = torch.cuda.Event(enable_timing=True)
+    d1 = torch.cuda.Event(enable_timing=True)
+    d0.record(st)
+    for _ in range(5):
+        s.diagnostics(allow_nonfinite=True)
+    d1.record(st)
+    torch.cuda.synchronize()
+    diag_ms = d0.elapsed_time(d1) / 5
+    s.close()
+    nodes = n * n
+    sec = ms_launches / 1e3
+    per_launch = sec / args.steps
+    achieved = BYTES_PER_NODE[storage] * nodes / per_launch / 1e9
+    # the stored counter readings belong to the method's own step kernel
+    traffic = (measured_traffic(storage, n)
+               if args.equilibrium == "algorithm" and not args.inplace else None)
+    return {"value": round(nodes * args.steps / sec / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(1e3 * per_launch, 4), "launch": launch,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
+            "wall_s_timed": round(wall, 4),
+            "diagnostics_after": {k: (v if math.isfinite(v) else None) for k, v in
+                                  (("E_kin", ek), ("E_mag", em), ("max_div_b", dv))},
+            "diagnostics_ms_per_call": round(diag_ms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +675,9 @@ def main():
                     help="fluid equilibrium of the turbulence step: the method's "
                          "(default) or the ablation with the u.M cross terms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f16-leg", action="store_true",
+                    help="turbulence workload with f32 storage: skip the FP16-storage "
+                         "leg timed after it")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch workload: keep the library's default launch "
                          "(one workgroup per 32x8 tile) instead of autotuning")
@@ -666,61 +739,17 @@ def main():
         return
     n = args.n
     u, b = inputs.turbulence(n, 0.04)
-    ud = torch.from_numpy(u).cuda()
-    bd = torch.from_numpy(b).cuda()
+    fields = (torch.from_numpy(u).cuda(), torch.from_numpy(b).cuda())
     del u, b
-    s = rrmhd.Solver(n, n, args.tau, args.tau, storage=args.storage,
-                     equilibrium=args.equilibrium, inplace=args.inplace)
-    launch = ("library default (f32: 128x2 threads; f16: 128x1 threads, two nodes "
-              "per thread; NT stores)")
-    if args.equilibrium != "algorithm":
-        launch = "library default block shape, one node per thread, NT stores"
-    if args.inplace:
-        launch = ("library default for one buffer (f32: 64x1, f16: 128x1 threads, XCD-local "
-                  "order, NT stores); steps alternate pull+push and own-slot forms")
-    s.init(ud, bd)
-    del ud, bd
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(st)
-    s.step(args.steps)
-    e1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_launches = e0.elapsed_time(e1)
-    ek, em, dv = s.diagnostics(allow_nonfinite=True)
-    # diagnostics (every K steps in a run, not per step): timed separately
-    d0 = torch.cuda.Event(enable_timing=True)
-    d1 = torch.cuda.Event(enable_timing=True)
-    d0.record(st)
-    for _ in range(5):
-        s.diagnostics(allow_nonfinite=True)
-    d1.record(st)
-    torch.cuda.synchronize()
-    diag_ms = d0.elapsed_time(d1) / 5
-    s.close()
-
-    nodes = n * n
-    sec = ms_launches / 1e3
-    mlups = nodes * args.steps / sec / 1e6
-    per_launch = sec / args.steps
-    bpn = BYTES_PER_NODE[args.storage]
-    achieved = bpn * nodes / per_launch / 1e9
-    # the stored counter readings belong to the method's own step kernel
-    traffic = (measured_traffic(args.storage, n)
-               if args.equilibrium == "algorithm" and not args.inplace else None)
+    leg = time_turbulence_leg(torch, rrmhd, args, fields, args.storage)
     out = {
         "metric": "MLUPS & % HBM roofline (fused RR-MHD step)",
-        "value": round(mlups, 1),
+        "value": leg["value"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * per_launch, 4),
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -728,23 +757,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"decaying 2D MHD turbulence {n}x{n} periodic, "
                                "random-phase psi/A, rms u=b=0.04",
-                   "nodes": nodes, "tau_f": args.tau, "tau_m": args.tau,
+                   "nodes": n * n, "tau_f": args.tau, "tau_m": args.tau,
                    "storage": f"{args.storage}-shifted (f - w)",
                    "equilibrium": args.equilibrium,
                    "population_buffers": 1 if args.inplace else 2,
-                   "launch": launch,
+                   "launch": leg["launch"],
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic},
-        "wall_s_timed": round(wall, 4),
-        "diagnostics_after": {k: (v if math.isfinite(v) else None) for k, v in
-                              (("E_kin", ek), ("E_mag", em), ("max_div_b", dv))},
-        "diagnostics_ms_per_call": round(diag_ms, 4),
+        "roofline": leg["roofline"],
+        "wall_s_timed": leg["wall_s_timed"],
+        "diagnostics_after": leg["diagnostics_after"],
+        "diagnostics_ms_per_call": leg["diagnostics_ms_per_call"],
         "kernel_hash": kernel_hash(),
         "env": environment(torch),
     }
+    # the FP16-offset storage of the same workload, timed the same way in the
+    # same run (the precision form the configuration compares against FP32)
+    if args.storage == "f32" and not args.no_f16_leg:
+        f16 = time_turbulence_leg(torch, rrmhd, args, fields, "f16")
+        out["storage_f16"] = {k: f16[k] for k in ("value", "unit", "ms_per_step", "roofline",
+                                                   "launch", "diagnostics_after")}
+    del fields
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

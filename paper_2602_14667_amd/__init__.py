@@ -10,6 +10,7 @@ __all__ = ["rrmhd", "inputs"]
 # figure taken on another kernel version is not reported.
 KERNEL_SOURCES = ("csrc/rr_node.h", "csrc/rr_pull.h", "csrc/rr_kernels.hip")
 KERNEL3D_SOURCES = ("csrc/rr_node.h", "csrc/rr_pull.h", "csrc/rr_3d.hip")
+BATCH_SOURCES = ("csrc/rr_node.h", "csrc/rr_pull.h", "csrc/rr_batch.hip")
 
 
 def kernel_hash(sources=KERNEL_SOURCES) -> str:
@@ -25,3 +26,7 @@ def kernel_hash(sources=KERNEL_SOURCES) -> str:
 
 def kernel3d_hash() -> str:
     return kernel_hash(KERNEL3D_SOURCES)
+
+
+def batch_hash() -> str:
+    return kernel_hash(BATCH_SOURCES)

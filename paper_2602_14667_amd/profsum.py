@@ -18,6 +18,11 @@ Three-dimensional step (both storages in one bench run), same calibration:
   rocprofv3 --pmc <ctr> ... -d PROF_DIR/s3_pmc_<ctr> ... bench.py --workload turbulence3d ...
   python -m paper_2602_14667_amd.profsum step3d PROF_DIR OUT_DIR N
 
+Batched ensemble step (256 domains), same calibration:
+  rocprofv3 --kernel-trace --stats ... -d PROF_DIR/batch_stats ... bench.py --workload batch --no-autotune ...
+  rocprofv3 --pmc <ctr> ... -d PROF_DIR/batch_pmc_<ctr> ... bench.py --workload batch --no-autotune ...
+  python -m paper_2602_14667_amd.profsum batch PROF_DIR OUT_DIR
+
 Second form, kernel-trace statistics of any workload:
   python -m paper_2602_14667_amd.profsum stats STATS_DIR OUT.md KERNEL BYTES TITLE COMMAND [LAST]
 writes the per-kernel table and, for the kernel whose name contains KERNEL,
@@ -84,9 +89,9 @@ def main(prof, out, n):
             "",
             "Commands (from the repository root, on the MI355X host):",
             "```",
-            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline",
-            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline --no-f16-leg",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline --no-f16-leg",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline --no-f16-leg",
             f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_copy -o run -- python3 bench.py --mode copy --steps 20",
             f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
             f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
@@ -228,6 +233,65 @@ def step3d_summary(prof, out, n):
     print("ok")
 
 
+def batch_summary(prof, out):
+    """Time and calibrated HBM traffic of the batched ensemble step (256
+    domains, default launch), with the copy calibration of the step
+    summaries."""
+    from . import batch_hash
+    fac = _calibration(prof)
+    stats = kernel_stats(os.path.join(prof, "batch_stats"))
+    name = [k for k in stats if "k_batch_step" in k][0]
+    avg, cnt, _ = last_dispatches(os.path.join(prof, "batch_stats"), "k_batch_step", 100)
+    rd = counter_mean(os.path.join(prof, "batch_pmc_FETCH_SIZE"), "k_batch_step") * 1024 * fac["FETCH_SIZE"]
+    wr = counter_mean(os.path.join(prof, "batch_pmc_WRITE_SIZE"), "k_batch_step") * 1024 * fac["WRITE_SIZE"]
+    from .inputs import batch_domains
+    nodes = sum(d["side"] ** 2 for d in batch_domains(256, seed=0))
+    alg = 152 * nodes
+    traffic = {"kernel": name, "kernel_hash": batch_hash(), "nodes": nodes, "storage": "f32",
+               "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+               "algorithmic_bytes": alg, "fetch_factor": fac["FETCH_SIZE"],
+               "write_factor": fac["WRITE_SIZE"]}
+    with open(os.path.join(out, "traffic_batch_f32_256.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    cmd = "python3 bench.py --workload batch --no-autotune --no-cpu-baseline"
+    lines = [
+        "# batched ensemble step, 256 domains (sides 64..1024), FP32, default launch "
+        "(one workgroup per 32x8 tile)",
+        "",
+        f"Kernel: `{name}`  (source hash {batch_hash()})",
+        "",
+        "Commands (from the repository root, on the MI355X host; the copy calibration runs as "
+        "for the two-dimensional step summaries):",
+        "```",
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/batch_stats -o run -- {cmd} --steps 100 --warmup 5",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/batch_pmc_FETCH_SIZE -o run -- {cmd} --steps 5 --warmup 1",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/batch_pmc_WRITE_SIZE -o run -- {cmd} --steps 5 --warmup 1",
+        f"python -m paper_2602_14667_amd.profsum batch {prof} profiles",
+        "```",
+        "",
+        "| kernel | calls | avg ns | min ns | max ns |",
+        "|---|---|---|---|---|",
+    ]
+    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+        lines.append(f"| `{k[:90]}` | {v['calls']} | {v['avg_ns']:.0f} | {v['min_ns']:.0f} "
+                     f"| {v['max_ns']:.0f} |")
+    lines += [
+        "",
+        f"* nodes per launch: {nodes}; algorithmic bytes per launch: {alg / 1e9:.3f} GB (152 B/node)",
+        f"* last {cnt} dispatches (the timed region): average {avg / 1e3:.1f} us -> "
+        f"{nodes / avg * 1e3:.0f} MLUPS, {alg / avg:.1f} GB/s algorithmic = "
+        f"{alg / avg / 8000 * 100:.1f} % of 8 TB/s",
+        f"* HBM traffic per launch (PMC, calibrated): read {rd / 1e9:.3f} GB "
+        f"({rd / (alg / 2):.3f}x algorithmic), write {wr / 1e9:.3f} GB ({wr / (alg / 2):.3f}x); "
+        f"{(rd + wr) / avg:.1f} GB/s actual",
+        f"* calibration: FETCH_SIZE x {fac['FETCH_SIZE']:.4f}, WRITE_SIZE x {fac['WRITE_SIZE']:.4f} "
+        f"(plain copy of {COPY_BYTES} B)",
+    ]
+    with open(os.path.join(out, "batch_step_256domains.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("ok")
+
+
 def last_dispatches(stats_dir, kernel, count):
     """Average duration (ns) of the last `count` dispatches of the kernel
     whose name contains `kernel` (the timed region of a bench run)."""
@@ -273,5 +337,7 @@ if __name__ == "__main__":
         inplace_summary(*sys.argv[2:5])
     elif sys.argv[1] == "step3d":
         step3d_summary(*sys.argv[2:5])
+    elif sys.argv[1] == "batch":
+        batch_summary(*sys.argv[2:4])
     else:
         main(*sys.argv[1:4])
