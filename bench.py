@@ -377,7 +377,8 @@ def hartmann_bench(torch, rrmhd, inputs, args):
                                "tau_f=0.6, tau_m=0.55, from rest",
                    "criterion": "rel L2 of the x-averaged u_x and b_x vs the analytic profile <= 1e-3"},
         "storage": out,
-        **({} if args.no_cpu_baseline else {"cpu_baseline_c2": cpu_baseline_c2()})}),
+        **({} if args.no_cpu_baseline else
+           {"cpu_baseline_c2": cpu_baseline_c2(to_steady=out["f32"]["steps"])})}),
         flush=True)
 
 
