@@ -21,6 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rrmhd_oracle.c")
 _SRC3 = os.path.join(_HERE, "rrmhd3d_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_SRC_REF = os.path.join(_HERE, "rrmhd_ref.c")
+_LIB_REF = os.path.join(_HERE, "librrmhd_ref.so")
 
 FEQ_ALGORITHM = 0  # equilibrium of the algorithm (Maxwell stress at 2nd order)
 FEQ_SERIES_FULL = 1  # full Hermite series incl. the u.M cross terms (ablation)
@@ -30,14 +32,31 @@ _ip = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp",
-               "-Wall", "-Wno-unused-function", _SRC, _SRC3, "-o", tmp, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc into ``oracle/liboracle.so``, and the
+    boundary's C-ABI over it (host pointers) into ``oracle/librrmhd_ref.so``."""
+    flags = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall",
+             "-Wno-unused-function"]
+    for lib_path, srcs in ((_LIB, [_SRC, _SRC3]), (_LIB_REF, [_SRC, _SRC_REF])):
+        if force or not os.path.exists(lib_path):
+            tmp = lib_path + ".tmp"
+            subprocess.run(flags + srcs + ["-o", tmp, "-lm"], check=True)
+            os.replace(tmp, lib_path)
     return _LIB
+
+
+_ref = None
+
+
+def ref_lib():
+    """The boundary's entry points (rrmhd_create, _init, _step, _moments,
+    _diagnostics, _invariants, _step_count, _destroy, _strerror) over the
+    oracle, with host pointers; the caller sets argument types."""
+    global _ref
+    if _ref is None:
+        if not os.path.exists(_LIB_REF):
+            build()
+        _ref = ctypes.CDLL(_LIB_REF)
+    return _ref
 
 
 _lib = None
