@@ -233,6 +233,108 @@ def step3d_summary(prof, out, n):
     print("ok")
 
 
+def counter_mean_named(d, match, counter):
+    """Mean over dispatches of one named counter for kernels matching `match`:
+    per dispatch, the sum over the counter's dimensions (the maximum for the
+    GPU-wide busy counter GRBM_GUI_ACTIVE, as rocprof's derived metrics take
+    it)."""
+    per = {}
+    use_max = counter.startswith("GRBM_")
+    for r in _rows(os.path.join(d, "run_counter_collection.csv")):
+        if match in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            key = r.get("Dispatch_Id") or r.get("Correlation_Id") or len(per)
+            v = float(r["Counter_Value"])
+            per[key] = max(per.get(key, 0.0), v) if use_max else per.get(key, 0.0) + v
+    return sum(per.values()) / len(per) if per else None
+
+
+def closure_summary(prof, out, n):
+    """The fused closure step against the plain step at n^2: launch times,
+    calibrated HBM traffic and the shader counters that locate its bound."""
+    n = int(n)
+    nodes = n * n
+    fac = _calibration(prof)
+    stats = kernel_stats(os.path.join(prof, "cl_stats"))
+    cl = [k for k in stats if "k_step_closure" in k][0]
+    pl = [k for k in stats if "k_step<" in k][0]
+    t_cl, t_pl = stats[cl]["avg_ns"], stats[pl]["avg_ns"]
+    rd = counter_mean(os.path.join(prof, "cl_pmc_FETCH_SIZE"), "k_step_closure") * 1024 * fac["FETCH_SIZE"]
+    wr = counter_mean(os.path.join(prof, "cl_pmc_WRITE_SIZE"), "k_step_closure") * 1024 * fac["WRITE_SIZE"]
+    sq = os.path.join(prof, "cl_pmc_sq")
+    ctr = {}
+    for kern, tag in ((cl, "closure"), (pl, "plain")):
+        m = "k_step_closure" if tag == "closure" else "k_step<"
+        ctr[tag] = {c: counter_mean_named(sq, m, c) for c in (
+            "SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU",
+            "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT",
+            "GRBM_GUI_ACTIVE")}
+    cus, simds = 256, 1024
+    alg = 152 * nodes
+    cmd = f"python3 bench.py --workload closure-step --n {n}"
+    lines = [
+        f"# fused step with the closure network vs the plain step, FP32 storage, turbulence {n}x{n}",
+        "",
+        f"Kernels: `{cl[:100]}` and `{pl[:100]}`",
+        "",
+        "Commands (from the repository root, on the MI355X host; the copy calibration runs as "
+        "for the two-dimensional step summaries):",
+        "```",
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/cl_stats -o run -- {cmd} --steps 50 --warmup 5",
+        f"rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_LDS SQ_ACTIVE_INST_VALU "
+        f"SQ_VALU_MFMA_BUSY_CYCLES SQ_LDS_IDX_ACTIVE SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE "
+        f"--output-format csv -d {prof}/cl_pmc_sq -o run -- {cmd} --steps 3 --warmup 1",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/cl_pmc_FETCH_SIZE -o run -- {cmd} --steps 3 --warmup 1",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/cl_pmc_WRITE_SIZE -o run -- {cmd} --steps 3 --warmup 1",
+        f"python -m paper_2602_14667_amd.profsum closure {prof} profiles {n}",
+        "```",
+        "",
+        "| kernel | calls | avg ns | min ns | max ns |",
+        "|---|---|---|---|---|",
+    ]
+    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["avg_ns"] * kv[1]["calls"]):
+        lines.append(f"| `{k[:90]}` | {v['calls']} | {v['avg_ns']:.0f} | {v['min_ns']:.0f} "
+                     f"| {v['max_ns']:.0f} |")
+    lines += [
+        "",
+        f"* closure step: average launch {t_cl / 1e3:.1f} us = {t_cl / t_pl:.2f}x the plain step "
+        f"({t_pl / 1e3:.1f} us); {nodes / t_cl * 1e3:.0f} MLUPS; {alg / t_cl:.1f} GB/s algorithmic "
+        f"= {alg / t_cl / 8000 * 100:.1f} % of 8 TB/s; network work 9600 FLOP/node -> "
+        f"{9600 * nodes / t_cl / 1e3:.1f} TFLOP/s = {9600 * nodes / t_cl / 1e3 / 2500 * 100:.1f} % of "
+        "the 2.5 PFLOP/s BF16 peak",
+        f"* HBM traffic per closure launch (PMC, calibrated): read {rd / 1e9:.3f} GB "
+        f"({rd / (alg / 2):.3f}x algorithmic), write {wr / 1e9:.3f} GB ({wr / (alg / 2):.3f}x)",
+        "",
+        "| counter (per launch) | closure step | plain step |",
+        "|---|---|---|",
+    ]
+    for c in ctr["closure"]:
+        a, b = ctr["closure"][c], ctr["plain"][c]
+        lines.append(f"| {c} | {a:.4g} | {b:.4g} |" if a is not None and b is not None
+                     else f"| {c} | {a} | {b} |")
+    lines.append("")
+    # busy fractions against the kernel's own duration at the 2.4 GHz peak
+    # clock: VALU quad-cycles x 4 and MFMA busy cycles over 1024 SIMDs, LDS
+    # active cycles over 256 CUs
+    clk = 2.4e9
+    for tag, t in (("closure", t_cl), ("plain", t_pl)):
+        c = ctr[tag]
+        if None in c.values():
+            continue
+        per = 64 / nodes  # wave instructions -> instructions per lane (one node per lane)
+        simd_cyc = simds * t * 1e-9 * clk
+        cu_cyc = cus * t * 1e-9 * clk
+        lines.append(
+            f"* {tag}: per lane (each lane updates one node) {c['SQ_INSTS_VALU'] * per:.0f} VALU, "
+            f"{c['SQ_INSTS_MFMA'] * per:.1f} MFMA and {c['SQ_INSTS_LDS'] * per:.0f} LDS instructions "
+            f"({c['SQ_WAVES']:.0f} waves); VALU busy {100 * 4 * c['SQ_ACTIVE_INST_VALU'] / simd_cyc:.0f} %, "
+            f"MFMA busy {100 * c['SQ_VALU_MFMA_BUSY_CYCLES'] / simd_cyc:.0f} %, LDS active "
+            f"{100 * c['SQ_LDS_IDX_ACTIVE'] / cu_cyc:.0f} % of the launch's cycles; LDS bank conflicts "
+            f"{100 * c['SQ_LDS_BANK_CONFLICT'] / max(c['SQ_LDS_IDX_ACTIVE'], 1):.0f} % of LDS-active cycles")
+    with open(os.path.join(out, f"closure_step_{n}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("ok")
+
+
 def batch_summary(prof, out):
     """Time and calibrated HBM traffic of the batched ensemble step (256
     domains, default launch), with the copy calibration of the step
@@ -339,5 +441,7 @@ if __name__ == "__main__":
         step3d_summary(*sys.argv[2:5])
     elif sys.argv[1] == "batch":
         batch_summary(*sys.argv[2:4])
+    elif sys.argv[1] == "closure":
+        closure_summary(*sys.argv[2:5])
     else:
         main(*sys.argv[1:4])
