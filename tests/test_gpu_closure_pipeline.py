@@ -110,3 +110,31 @@ def test_spectral_error_budget_of_the_plain_coarse_run():
           f"{[round(v, 4) for v in eps.values()]}", flush=True)
     assert eps[tc] <= 0.05
     assert eps[tc] < eps[tc - 0.001] and eps[tc] < eps[tc + 0.001]
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "measured on the full protocol (2048^2 -> 512^2, tau_f 0.56, 16 training seeds, "
+    "alpha 0.01 from the validation seeds): the closure lowers the worst-time eps_spec on "
+    "test seeds 21, 22, 23 (0.092 vs 0.108, 0.179 vs 0.207, 0.086 vs 0.106) but raises it "
+    "on seed 20 (0.161 vs 0.121)"))
+def test_closure_gain_on_held_out_seeds(capsys):
+    """The learned closure against the plain coarse run on the held-out test
+    seeds 20-23, full protocol: the closure run's spectral error (eps_spec,
+    worst over the five comparison times) must be lower than the plain run's
+    on every test seed."""
+    from paper_2602_14667_amd import closure_pipeline as cp, rrmhd
+    rrmhd.lib()
+
+    def log(m):
+        with capsys.disabled():
+            print("[gpu]  ", m, flush=True)
+
+    log("closure gain on held-out seeds: full protocol 2048 -> 512")
+    res = cp.pipeline(n_f=2048, factor=4, tau_f=0.56, fine_steps=64000, snaps=8,
+                      train_seeds=range(16), val_seeds=range(16, 20),
+                      test_seeds=range(20, 24), train_steps=3000, onestep_steps=2000,
+                      batch=65536, log=log)
+    gains = {t["seed"]: (t["plain"]["eps_spec"], t["closure"]["eps_spec"]) for t in res["tests"]}
+    log(f"eps_spec (plain, closure) per test seed: {gains}")
+    for sd, (p, c) in gains.items():
+        assert c < p, (sd, p, c)
