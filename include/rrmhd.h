@@ -22,6 +22,13 @@
  *    other failures leave the handle valid.  rrmhd_strerror gives the text,
  *    rrmhd_last_error_detail the HIP message of the last device error.
  *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Environment (read at rrmhd_create or rrmhd_*autotune): RRMHD_TILE =
+ *    "BXxBY" or "BXxBYxRY" replaces the default launch shape of the step
+ *    kernel (one node per thread; ignored unless BX*BY <= 256);
+ *    RRMHD_DEBUG_POISON = 1 turns on the debug poison mode of two-buffer
+ *    handles; RRMHD_AUTOTUNE_CACHE names the autotuner's cache file when the
+ *    call passes none; RRMHD_PLANE_PAD_BYTES (a multiple of 256) sets the
+ *    gap between population planes.
  */
 #ifndef RRMHD_H
 #define RRMHD_H
@@ -208,6 +215,8 @@ int rrmhd_load(rrmhd *h, const char *path);
  * otherwise).  Results do not depend on the shape (bitwise).  Host-side
  * only. */
 int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
+/* The handle's current launch shape (any pointer may be NULL). */
+int rrmhd_get_launch(const rrmhd *h, int *bx, int *by, int *ry, int *xcd, int *nt);
 
 /* Stream used by the handle; NULL is the null stream. */
 int rrmhd_set_stream(rrmhd *h, void *hip_stream);

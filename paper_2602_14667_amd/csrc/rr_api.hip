@@ -243,6 +243,20 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
     h->shape.nt = 1;
   }
 
+  // environment overrides of the launch shape ("BXxBY" or "BXxBYxRY") and of
+  // the debug poison mode (two-buffer handles), for runs driven from outside
+  if (const char *e = std::getenv("RRMHD_TILE")) {
+    int bx = 0, by = 0, ry = 1;
+    const int k = std::sscanf(e, "%dx%dx%d", &bx, &by, &ry);
+    if (k >= 2 && bx >= 1 && by >= 1 && bx * by <= 256 && ry >= 1) {
+      h->shape.bx = bx;
+      h->shape.by = by;
+      h->shape.ry = ry;
+      h->shape.nt &= 1;  // a tile given this way is for the one-node update
+    }
+  }
+  if (const char *e = std::getenv("RRMHD_DEBUG_POISON"))
+    h->poison = !h->inplace && std::atoi(e) != 0;
   const size_t bytes = (size_t)D.plane * rr::kStatePlanes * h->elem;
   int rc = RRMHD_OK;
   for (int k = 0; k < (h->inplace ? 1 : 2) && rc == RRMHD_OK; ++k) {
@@ -277,6 +291,16 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
   h->shape.ry = ry;
   h->shape.xcd = (xcd >= 0 && xcd <= 2) ? xcd : 0;
   h->shape.nt = nt & 7;
+  return RRMHD_OK;
+}
+
+int rrmhd_get_launch(const rrmhd *h, int *bx, int *by, int *ry, int *xcd, int *nt) {
+  if (!h) return RRMHD_EINVAL;
+  if (bx) *bx = h->shape.bx;
+  if (by) *by = h->shape.by;
+  if (ry) *ry = h->shape.ry;
+  if (xcd) *xcd = h->shape.xcd;
+  if (nt) *nt = h->shape.nt;
   return RRMHD_OK;
 }
 

@@ -29,6 +29,13 @@ struct Entry {
 
 // ---- cache file: {"key": {"bx": 128, "by": 2, "xcd": 2, "grid": 0, "fetch": 0, "nt": 1,
 // "ms": 1.7}, ...}
+// The cache file: the caller's path, else RRMHD_AUTOTUNE_CACHE, else none.
+const char *cache_file(const char *path) {
+  if (path) return path;
+  const char *e = std::getenv("RRMHD_AUTOTUNE_CACHE");
+  return (e && *e) ? e : nullptr;
+}
+
 std::map<std::string, Entry> read_cache(const char *path) {
   std::map<std::string, Entry> m;
   if (!path) return m;
@@ -153,6 +160,7 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
   hipStream_t st = nullptr;
   int rc = rr_handle_info(h, &nx, &ny, &storage, &st, &ready);
   if (rc != RRMHD_OK) return rc;
+  cache_path = cache_file(cache_path);
   auto cache = read_cache(cache_path);
   const bool inplace = rr_handle_inplace(h) != 0;
   const std::string key = key_of(inplace ? "step_inplace" : "step", nx, ny, storage);
@@ -233,6 +241,7 @@ int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials) {
   nys.resize(n);
   rc = rr_batch_domains(b, &n, &storage, nxs.data(), nys.data());
   if (rc != RRMHD_OK) return rc;
+  cache_path = cache_file(cache_path);
   auto cache = read_cache(cache_path);
   // 1) tile width per size class, timed on a standalone grid of that size
   std::map<std::pair<int, int>, int> width;

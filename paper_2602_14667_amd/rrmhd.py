@@ -23,7 +23,7 @@ EXPORTED = [
     "rrmhd_create", "rrmhd_init", "rrmhd_step", "rrmhd_moments",
     "rrmhd_diagnostics", "rrmhd_diagnostics_noalloc", "rrmhd_invariants", "rrmhd_step_count",
     "rrmhd_state_bytes", "rrmhd_save_state", "rrmhd_load_state", "rrmhd_save", "rrmhd_load",
-    "rrmhd_set_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium", "rrmhd_set_graph_chunk",
+    "rrmhd_set_launch", "rrmhd_get_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium", "rrmhd_set_graph_chunk",
     "rrmhd_set_debug_poison",
     "rrmhd_destroy", "rrmhd_strerror",
     "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
@@ -104,6 +104,8 @@ def lib():
         L.rrmhd_set_stream.argtypes = [vp, vp]
         ci = ctypes.c_int
         L.rrmhd_set_launch.argtypes = [vp, ci, ci, ci, ci, ci]
+        ip = ctypes.POINTER(ci)
+        L.rrmhd_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
         L.rrmhd_set_equilibrium.argtypes = [vp, ci]
         L.rrmhd_set_graph_chunk.argtypes = [vp, ci]
         L.rrmhd3d_create.argtypes = [ci, ci, ci, ci, ctypes.c_double, ctypes.c_double, vp,
@@ -449,6 +451,13 @@ class Solver:
         """Read a checkpoint file written by save() into this handle (same
         grid, storage, relaxation times, boundary conditions)."""
         _check(lib().rrmhd_load(self._h, os.fsencode(path)), "rrmhd_load")
+
+    def get_launch(self):
+        """(bx, by, ry, xcd, nt) of the step kernel's current launch shape."""
+        v = [ctypes.c_int() for _ in range(5)]
+        _check(lib().rrmhd_get_launch(self._h, *[ctypes.byref(x) for x in v]),
+               "rrmhd_get_launch")
+        return tuple(x.value for x in v)
 
     def set_launch(self, bx, by, ry=1, xcd=1, nt=0):
         _check(lib().rrmhd_set_launch(self._h, int(bx), int(by), int(ry),

@@ -206,3 +206,35 @@ def test_batch_autotune_preserves_state(tmp_path):
         for g, r in zip(moments_np(b.moments(d)), moments_np(a.moments(d))):
             assert np.array_equal(g, r), d
     a.close(); b.close()
+
+
+def test_environment_overrides(tmp_path, monkeypatch):
+    """RRMHD_TILE replaces the default launch shape at create (results stay
+    bitwise those of the default shape), RRMHD_DEBUG_POISON turns the poison
+    mode on, and RRMHD_AUTOTUNE_CACHE is the cache file of an autotune call
+    that passes none."""
+    rr = R()
+    from test_gpu_parity import dev, gpu_moments
+    note("environment overrides")
+    n = 96
+    u, b = inputs.random_modes(n, n, 0.04, seed=5)
+    ref = rr.Solver(n, n, 0.55, 0.6)
+    default_shape = ref.get_launch()
+    ref.init(dev(u), dev(b))
+    ref.step(12)
+    want = gpu_moments(ref)
+    ref.close()
+    monkeypatch.setenv("RRMHD_TILE", "64x4")
+    monkeypatch.setenv("RRMHD_DEBUG_POISON", "1")
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("RRMHD_AUTOTUNE_CACHE", str(cache))
+    s = rr.Solver(n, n, 0.55, 0.6)
+    assert s.get_launch()[:3] == (64, 4, 1) and s.get_launch() != default_shape
+    s.init(dev(u), dev(b))
+    s.step(12)
+    got = gpu_moments(s)
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k
+    s.autotune(None, trials=2)
+    assert cache.exists() and "step" in cache.read_text()
+    s.close()
