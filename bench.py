@@ -234,9 +234,12 @@ def launch_sweep(torch, rrmhd, inputs, args):
     os.environ.pop("RRMHD_PLANE_PAD_BYTES", None)
 
 
-def batch_bench(torch, rrmhd, inputs, args):
+def time_batch_leg(torch, rrmhd, inputs, steps, autotune, sequential):
     """The 256-domain ensemble (sides 64..1024, tau uniform in [0.501, 0.6]),
-    FP32, autotuned tiles, graph-captured persistent launches."""
+    FP32, graph-captured persistent launches: ms per step over `steps` steps
+    (whole graph chunks of 100), with the library's default launch or
+    autotuned tiles; optionally the same domains stepped one after another
+    as standalone grids, for comparison."""
     doms = inputs.batch_domains(256, seed=0)
     shapes = [(d["side"], d["side"]) for d in doms]
     b = rrmhd.Batch(shapes, [d["tau_f"] for d in doms], [d["tau_m"] for d in doms])
@@ -244,17 +247,17 @@ def batch_bench(torch, rrmhd, inputs, args):
         u, bf = inputs.batch_fields(d)
         b.init(k, torch.from_numpy(u).cuda(), torch.from_numpy(bf).cuda())
     t0 = time.perf_counter()
-    if not args.no_autotune:
+    if autotune:
         b.autotune(None, trials=10)
     tune_s = time.perf_counter() - t0
     chunk = 100
     b.set_graph_chunk(chunk)
-    b.step(args.warmup if args.warmup >= chunk else chunk)
+    b.step(chunk)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    steps = max(chunk, (args.steps // chunk) * chunk)
+    steps = max(chunk, (steps // chunk) * chunk)
     e0.record(st)
     b.step(steps)
     e1.record(st)
@@ -262,41 +265,53 @@ def batch_bench(torch, rrmhd, inputs, args):
     ms = e0.elapsed_time(e1) / steps
     info = b.info()
     nodes = info["nodes"]
-    # sequential standalone launches of the same domains, for comparison
-    seq_ms = 0.0
-    for k, d in enumerate(doms):
-        s = rrmhd.Solver(d["side"], d["side"], d["tau_f"], d["tau_m"])
-        u, bf = inputs.batch_fields(d)
-        s.init(torch.from_numpy(u).cuda(), torch.from_numpy(bf).cuda())
-        s.step(2)
-        f0 = torch.cuda.Event(enable_timing=True)
-        f1 = torch.cuda.Event(enable_timing=True)
-        f0.record(st)
-        s.step(20)
-        f1.record(st)
-        torch.cuda.synchronize()
-        seq_ms += f0.elapsed_time(f1) / 20
-        s.close()
+    seq_ms = None
+    if sequential:
+        seq_ms = 0.0
+        for k, d in enumerate(doms):
+            s = rrmhd.Solver(d["side"], d["side"], d["tau_f"], d["tau_m"])
+            u, bf = inputs.batch_fields(d)
+            s.init(torch.from_numpy(u).cuda(), torch.from_numpy(bf).cuda())
+            s.step(2)
+            f0 = torch.cuda.Event(enable_timing=True)
+            f1 = torch.cuda.Event(enable_timing=True)
+            f0.record(st)
+            s.step(20)
+            f1.record(st)
+            torch.cuda.synchronize()
+            seq_ms += f0.elapsed_time(f1) / 20
+            s.close()
     b.close()
     gbs = 152 * nodes / ms / 1e6
-    print(json.dumps({
-        "metric": "MLUPS & % HBM roofline (batched ensemble step)",
-        "value": round(nodes / ms / 1e3, 1), "unit": "MLUPS", "n_gpus": 1,
-        "steps": steps, "warmup": chunk, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+    return {
+        "value": round(nodes / ms / 1e3, 1), "unit": "MLUPS", "steps": steps,
+        "warmup": chunk, "ms_per_step": round(ms, 4),
         "config": {"workload": "256 periodic domains, sides 64..1024, "
                                "OT or turbulence, tau in [0.501, 0.6]",
                    "nodes": nodes, "tiles": info["tiles"],
                    "workgroups_per_launch": info["grid"],
-                   "graph_chunk": chunk, "autotuned": not args.no_autotune,
+                   "graph_chunk": chunk, "autotuned": autotune,
                    "autotune_s": round(tune_s, 2)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "traffic": batch_traffic() if args.no_autotune else None},
-        "sequential_standalone_ms_per_step": round(seq_ms, 4),
-        "speedup_vs_sequential": round(seq_ms / ms, 3)}), flush=True)
+                     "traffic": None if autotune else batch_traffic()},
+        "sequential_standalone_ms_per_step": None if seq_ms is None else round(seq_ms, 4),
+        "speedup_vs_sequential": None if seq_ms is None else round(seq_ms / ms, 3)}
+
+
+def batch_bench(torch, rrmhd, inputs, args):
+    """The ensemble on its own line, autotuned unless --no-autotune, with the
+    sequential standalone comparison."""
+    leg = time_batch_leg(torch, rrmhd, inputs, args.steps, not args.no_autotune, True)
+    out = {"metric": "MLUPS & % HBM roofline (batched ensemble step)",
+           "value": leg["value"], "unit": "MLUPS", "n_gpus": 1, "steps": leg["steps"],
+           "warmup": leg["warmup"], "ms_per_step": leg["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic"}
+    out.update({k: leg[k] for k in ("config", "roofline", "sequential_standalone_ms_per_step",
+                                    "speedup_vs_sequential")})
+    print(json.dumps(out), flush=True)
 
 
 def hartmann_bench(torch, rrmhd, inputs, args):
@@ -653,6 +668,15 @@ def time_turbulence_leg(torch, rrmhd, args, fields, storage):
             "diagnostics_ms_per_call": round(diag_ms, 4)}
 
 
+def load_config(name):
+    """A configuration file: `name` as a path, else
+    paper_2602_14667_amd/configs/<name>.json."""
+    path = name if os.path.exists(name) else os.path.join(
+        ROOT, "paper_2602_14667_amd", "configs", f"{name}.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -679,6 +703,9 @@ def main():
     ap.add_argument("--no-f16-leg", action="store_true",
                     help="turbulence workload with f32 storage: skip the FP16-storage "
                          "leg timed after it")
+    ap.add_argument("--no-ensemble-leg", action="store_true",
+                    help="turbulence workload: skip the 256-domain ensemble leg "
+                         "(default launch, 1000 steps) timed after it")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch workload: keep the library's default launch "
                          "(one workgroup per 32x8 tile) instead of autotuning")
@@ -697,6 +724,19 @@ def main():
                          "time to steady state of the wall-bounded channel; "
                          "ot64: time per step of the 64^2 Orszag-Tang case")
     ap.add_argument("--closure-scale", choices=["full", "reduced"], default="full")
+    ap.add_argument("--config", default=None,
+                    help="c1..c5 or a path: a JSON file whose 'bench' block sets "
+                         "defaults for these flags (flags given here still win) and "
+                         "whose 'env' block sets RRMHD_* variables not already set")
+    pre, _ = ap.parse_known_args()
+    if pre.config:
+        cfg = load_config(pre.config)
+        unknown = set(cfg.get("bench", {})) - {a.dest for a in ap._actions}
+        if unknown:
+            ap.error(f"config {pre.config}: unknown keys {sorted(unknown)}")
+        ap.set_defaults(**cfg.get("bench", {}))
+        for k, v in cfg.get("env", {}).items():
+            os.environ.setdefault(k, str(v))
     args = ap.parse_args()
     if args.steps is None:
         args.steps = (20 if args.mode != "step" else
@@ -778,6 +818,12 @@ def main():
         out["storage_f16"] = {k: f16[k] for k in ("value", "unit", "ms_per_step", "roofline",
                                                    "launch", "diagnostics_after")}
     del fields
+    # the 256-domain ensemble with the library's default launch, timed in the
+    # same run (its own configuration, reported beside the headline step)
+    if not args.no_ensemble_leg:
+        ens = time_batch_leg(torch, rrmhd, inputs, 1000, False, False)
+        out["ensemble"] = {k: ens[k] for k in ("value", "unit", "steps", "ms_per_step",
+                                               "roofline", "config")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

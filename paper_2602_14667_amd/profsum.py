@@ -89,9 +89,9 @@ def main(prof, out, n):
             "",
             "Commands (from the repository root, on the MI355X host):",
             "```",
-            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline --no-f16-leg",
-            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline --no-f16-leg",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline --no-f16-leg",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_{st} -o run -- python3 bench.py --storage {st} --steps 50 --warmup 5 --no-cpu-baseline --no-f16-leg --no-ensemble-leg",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline --no-f16-leg --no-ensemble-leg",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --steps 5 --warmup 1 --no-cpu-baseline --no-f16-leg --no-ensemble-leg",
             f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/stats_copy -o run -- python3 bench.py --mode copy --steps 20",
             f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/pmc_FETCH_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
             f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/pmc_WRITE_SIZE_copy -o run -- python3 bench.py --mode copy --steps 5 --warmup 1",
