@@ -398,6 +398,25 @@ int rrmhd_closure_gelu_table(uint16_t *out, void *hip_stream);
 int rrmhd_train_samples(const double *rho, const double *u, const double *b,
                         int nf, int factor, double tau_c, double *work,
                         float *x, float *target, void *hip_stream);
+/* The box filter of the training data alone: out [10][Nc] FP64 (device),
+ * Nc = (nf/factor)^2, holds the factor x factor block means of rho, rho u_x,
+ * rho u_y, b_x, b_y, rho u_x u_x, rho u_x u_y, rho u_y u_y, M(b)_xx, M(b)_xy
+ * of the fine moments (layout of rrmhd_moments).  Asynchronous on
+ * hip_stream; EINVAL for null pointers or nf not a multiple of factor. */
+int rrmhd_train_box_filter(const double *rho, const double *u, const double *b,
+                           int nf, int factor, double *out, void *hip_stream);
+/* Replace the fluid populations of a periodic two-buffer handle so that, at
+ * every node, its current state holds the equilibrium of Eq. feq_4th (the
+ * Maxwell stress at second order) for the given density rho [ny][nx],
+ * momentum j [2][ny][nx] and magnetic field b [2][ny][nx] (device FP64, u =
+ * j / rho), with no non-equilibrium part; the magnetic populations are kept.
+ * For the closure protocol's best-velocity bound (a project addition): the
+ * coarse run's velocity is replaced every step by the filtered fine one, b
+ * being the run's own current field.  Asynchronous on the handle's stream;
+ * EINVAL for null pointers, walls or a single-buffer handle, ESTATE before
+ * rrmhd_init. */
+int rrmhd_train_impose_fluid(rrmhd *h, const double *rho, const double *j,
+                             const double *b);
 typedef struct rrmhd_trainer rrmhd_trainer;
 /* Workspace for minibatches of up to max_batch samples. */
 int rrmhd_train_create(int64_t max_batch, void *hip_stream,

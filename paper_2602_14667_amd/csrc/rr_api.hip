@@ -779,6 +779,14 @@ int rrmhd_closure_gelu_table(uint16_t *out, void *hip_stream) {
   return RRMHD_OK;
 }
 
+int rrmhd_train_impose_fluid(rrmhd *h, const double *rho, const double *j, const double *b) {
+  if (!h || !rho || !j || !b || h->D.walls || h->inplace) return RRMHD_EINVAL;
+  if (!h->ready) return RRMHD_ESTATE;
+  const int rc = rr_launch_impose_fluid(h->storage, &h->D, h->buf[h->cur], rho, j, b, h->stream);
+  if (rc != RRMHD_OK) return rr_device_error(hipGetLastError(), "rrmhd_train_impose_fluid");
+  return RRMHD_OK;
+}
+
 int rrmhd_current_vorticity(rrmhd *h, double *jz, double *wz) {
   if (!h) return RRMHD_EINVAL;
   if (!h->ready) return RRMHD_ESTATE;

@@ -51,3 +51,6 @@ extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Doma
                                                      const void *src, double omega_m,
                                                      double *jz, double *wz, double *upl,
                                                      hipStream_t st, int swapped);
+extern "C" RR_HIDDEN int rr_launch_impose_fluid(int storage, const rr::Domain *D, void *dst,
+                                                const double *rho, const double *j,
+                                                const double *b, hipStream_t st);

@@ -33,8 +33,11 @@
 #include <new>
 
 #include "../../include/rrmhd.h"
+#include "rr_internal.h"
+#include "rr_kernels.h"
 #include "rr_mlp.h"
 #include "rr_node.h"
+#include "rr_pull.h"
 
 namespace rr {
 
@@ -555,7 +558,47 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
   p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
+// ---- imposed fluid state (best-velocity bound of the closure protocol) ----
+// Writes the fluid planes of a periodic two-buffer state so that the pulled
+// populations of node X are f_eq(rho(X), j(X) / rho(X), b(X)), FP64
+// evaluated, stored in the handle's codec: the slot of population i at node
+// Y is pulled by Y + c_i, so it receives that node's equilibrium.  The
+// magnetic planes are not touched.
+template <class C>
+__global__ void k_impose_fluid(PlaneGeom G, const double *__restrict__ rho,
+                               const double *__restrict__ j, const double *__restrict__ b,
+                               typename C::T *__restrict__ dst) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= G.nx) return;
+  const int64_t N = (int64_t)G.nx * G.ny;
+  const int64_t o = (int64_t)y * G.nx + x;
+  for (int i = 0; i < 9; ++i) {
+    int tx = x + rr::cx(i), ty = y + rr::cy(i);
+    tx = tx < 0 ? tx + G.nx : (tx >= G.nx ? tx - G.nx : tx);
+    ty = ty < 0 ? ty + G.ny : (ty >= G.ny ? ty - G.ny : ty);
+    const int64_t q = (int64_t)ty * G.nx + tx;
+    const double r = rho[q];
+    const double f = feq64(i, r, j[q] / r, j[N + q] / r, b[q], b[N + q]);
+    dst[(int64_t)i * G.plane + o] = C::enc((float)(f - 1.0 / (double)wdiv(i)), G.s);
+  }
+}
+
 }  // namespace rr
+
+// Launcher used by rrmhd_train_impose_fluid (rr_api.hip).
+extern "C" RR_HIDDEN int rr_launch_impose_fluid(int storage, const rr::Domain *D, void *dst,
+                                                const double *rho, const double *j,
+                                                const double *b, hipStream_t st) {
+  const dim3 block(64), grid((D->nx + 63) / 64, D->ny);
+  const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s};
+  if (storage == rr::kF16)
+    hipLaunchKernelGGL(rr::k_impose_fluid<rr::CodecF16>, grid, block, 0, st, G, rho, j, b,
+                       (uint16_t *)dst);
+  else
+    hipLaunchKernelGGL(rr::k_impose_fluid<rr::CodecF32>, grid, block, 0, st, G, rho, j, b,
+                       (float *)dst);
+  return hipGetLastError() == hipSuccess ? RRMHD_OK : RRMHD_EDEVICE;
+}
 
 // ---------------------------------------------------------------------------
 // C-ABI
@@ -770,6 +813,18 @@ int rrmhd_train_samples(const double *rho, const double *u, const double *b, int
                      work);
   THIP(hipGetLastError());
   hipLaunchKernelGGL(rr::k_samples, dim3(blocks), dim3(256), 0, st, work, nc, tau_c, x, target);
+  THIP(hipGetLastError());
+  return RRMHD_OK;
+}
+
+int rrmhd_train_box_filter(const double *rho, const double *u, const double *b, int nf,
+                           int factor, double *out, void *hip_stream) {
+  if (!rho || !u || !b || !out || factor < 1 || nf < factor || nf % factor != 0)
+    return RRMHD_EINVAL;
+  const int nc = nf / factor;
+  const int64_t Nc = (int64_t)nc * nc;
+  hipLaunchKernelGGL(rr::k_box_filter, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)hip_stream, rho, u, b, nf, factor, out);
   THIP(hipGetLastError());
   return RRMHD_OK;
 }

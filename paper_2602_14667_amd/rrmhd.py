@@ -34,7 +34,8 @@ EXPORTED = [
     "rrmhd_autotune", "rrmhd_batch_autotune",
     "rrmhd_closure_set", "rrmhd_closure_enable", "rrmhd_closure_eval",
     "rrmhd_closure_gelu_table",
-    "rrmhd_train_samples", "rrmhd_train_create", "rrmhd_train_loss_grad",
+    "rrmhd_train_samples", "rrmhd_train_box_filter", "rrmhd_train_impose_fluid",
+    "rrmhd_train_create", "rrmhd_train_loss_grad",
     "rrmhd_train_onestep_samples", "rrmhd_train_onestep_loss_grad",
     "rrmhd_train_adam", "rrmhd_train_destroy", "rrmhd_train_last_error_detail",
     "rrmhd_current_vorticity",
@@ -147,6 +148,8 @@ def lib():
         L.rrmhd_closure_gelu_table.argtypes = [vp, vp]
         L.rrmhd_train_samples.argtypes = [vp, vp, vp, ci, ci, ctypes.c_double,
                                           vp, vp, vp, vp]
+        L.rrmhd_train_box_filter.argtypes = [vp, vp, vp, ci, ci, vp, vp]
+        L.rrmhd_train_impose_fluid.argtypes = [vp, dp, dp, dp]
         L.rrmhd_train_create.argtypes = [i64, vp, ctypes.POINTER(vp)]
         L.rrmhd_train_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.rrmhd_train_onestep_samples.argtypes = [vp, vp, vp, vp, vp, vp, ci, ci,
@@ -337,6 +340,17 @@ class Solver:
             _dev_f64(b, (2, self.ny, self.nx), "b")), "rrmhd_moments")
         _after(self._stream, rho, u, b)
         return rho, u, b
+
+    def impose_fluid(self, rho, j, b):
+        """Replace the fluid populations by the equilibrium of the given FP64
+        device fields rho [ny][nx], momentum j and b [2][ny][nx] (periodic,
+        two buffers); the magnetic populations are kept."""
+        _before(self._stream)
+        _check(lib().rrmhd_train_impose_fluid(
+            self._h, _dev_f64(rho, (self.ny, self.nx), "rho"),
+            _dev_f64(j, (2, self.ny, self.nx), "j"),
+            _dev_f64(b, (2, self.ny, self.nx), "b")), "rrmhd_train_impose_fluid")
+        _after(self._stream, rho, j, b)
 
     def current_vorticity(self):
         """(j_z, w_z) FP64 device tensors [ny][nx]."""
@@ -720,6 +734,22 @@ def train_samples(rho, u, b, factor, tau_c, stream=None):
                                      _stream_handle(stream)),
            "rrmhd_train_samples")
     return x, t
+
+
+def train_box_filter(rho, u, b, factor, out=None, stream=None):
+    """Block means over factor x factor of the fine FP64 device moments:
+    [10][nc][nc] FP64 (rho, rho u_x, rho u_y, b_x, b_y, rho u u (xx, xy,
+    yy), M(b) (xx, xy))."""
+    import torch
+    nf = rho.shape[0]
+    nc = nf // factor
+    if out is None:
+        out = torch.empty((10, nc, nc), dtype=torch.float64, device=rho.device)
+    _dev_f64(out, (10, nc, nc), "out")
+    _check(lib().rrmhd_train_box_filter(_ptr_t(rho), _ptr_t(u), _ptr_t(b), nf, int(factor),
+                                        _ptr_t(out), _stream_handle(stream)),
+           "rrmhd_train_box_filter")
+    return out
 
 
 def train_onestep_samples(m0, m1, factor, tau_c, stream=None):

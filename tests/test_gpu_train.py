@@ -286,3 +286,76 @@ def test_onestep_short_fit_reduces_loss():
         L_or.append(oracle.onestep_objective(m0, m1, fac, tc, d1, q=q)[0] * d[3])
     assert abs(sum(L_or) / D / loss.item() - 1) < 1e-3
     tr.close()
+
+
+def test_box_filter_is_the_block_mean():
+    """rrmhd_train_box_filter: factor x factor block means of rho, rho u, b,
+    rho u u and the Maxwell tensor M(b) = |b|^2 I / 2 - b b, written out
+    here with numpy."""
+    note("box filter 96 -> 24, factor 4")
+    rr = R()
+    n, fac = 96, 4
+    g = np.random.default_rng(3)
+    rho = 1.0 + 0.01 * g.standard_normal((n, n))
+    u = 0.05 * g.standard_normal((2, n, n))
+    b = 0.05 * g.standard_normal((2, n, n))
+    out = rr.train_box_filter(f64(rho), f64(u), f64(b), fac).cpu().numpy()
+    nc = n // fac
+
+    def mean(a):
+        return a.reshape(nc, fac, nc, fac).mean(axis=(1, 3))
+
+    want = [rho, rho * u[0], rho * u[1], b[0], b[1], rho * u[0] * u[0], rho * u[0] * u[1],
+            rho * u[1] * u[1], 0.5 * (b[1] ** 2 - b[0] ** 2), -b[0] * b[1]]
+    for k, w in enumerate(want):
+        assert np.allclose(out[k], mean(w), rtol=1e-13, atol=1e-17), k
+
+
+def test_impose_fluid_vs_oracle():
+    """rrmhd_train_impose_fluid on a ragged 40 x 24 grid after 7 steps: the
+    state's moments are the imposed rho and u = j / rho (FP32 storage
+    accuracy) with b unchanged bitwise; the oracle, its fluid populations set
+    to the equilibrium of the same fields node by node (its own single-node
+    equilibrium) and its magnetic populations kept, then agrees with the GPU
+    run to the FP32 bar over 5 more steps."""
+    note("impose fluid 40 x 24 vs oracle")
+    rr = R()
+    nx, ny, tau = 40, 24, 0.55
+    u0, b0 = inputs.random_modes(nx, ny, 0.04, seed=11)
+    s = rr.Solver(nx, ny, tau, tau)
+    s.init(f64(u0), f64(b0))
+    o = oracle.Oracle(nx, ny, tau, tau)
+    o.init(u0, b0)
+    s.step(7)
+    o.step(7)
+    _, _, b_before = s.moments()
+    g = np.random.default_rng(5)
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    rho = 1.0 + 0.02 * np.sin(2 * np.pi * xx / nx) * np.cos(2 * np.pi * yy / ny)
+    uu, _ = inputs.random_modes(nx, ny, 0.03, seed=12)
+    j = rho[None] * uu
+    bb = b_before.cpu().numpy()
+    s.impose_fluid(f64(rho), f64(j), b_before)
+    r1, u1, b1 = (t.cpu().numpy() for t in s.moments())
+    assert np.array_equal(b1, bb)
+    assert np.max(np.abs(r1 - rho)) < 1e-6
+    assert np.max(np.abs(u1 - uu)) < 1e-6 * np.max(np.abs(uu)) + 1e-7
+    f, gg = o.get_state()
+    for y in range(ny):
+        for x in range(nx):
+            feq, _ = oracle.node_equilibrium(rho[y, x], uu[:, y, x], bb[:, y, x])
+            f[:, y, x] = feq
+    o.set_state(f, gg)
+    s.step(5)
+    o.step(5)
+    rg, ug, bg = (t.cpu().numpy() for t in s.moments())
+    ro, uo, bo = o.moments()
+    for name, a, r in (("rho", rg, ro), ("ux", ug[0], uo[0]), ("uy", ug[1], uo[1]),
+                       ("bx", bg[0], bo[0]), ("by", bg[1], bo[1])):
+        ref = r - 1.0 if name == "rho" else r
+        err = np.linalg.norm(a - r) / np.linalg.norm(ref)
+        note(f"  {name}: rel L2 {err:.2e}")
+        assert err < 1e-6, name
+    with pytest.raises(ValueError):
+        s.impose_fluid(f64(rho), f64(j[:1]), b_before)
+    s.close()
