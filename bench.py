@@ -587,6 +587,19 @@ def closure_bench(args):
                for side in ("plain", "closure")}
     eps_t = {side: {str(t["seed"]): [round(r["eps_spec"], 4) for r in t[side + "_rows"]]
                     for t in tests} for side in ("plain", "closure")}
+    # the best velocity a fluid-only closure could give the coarse run: the
+    # filtered fine velocity imposed after every coarse step
+    n_c = kw["n_f"] // kw["factor"]
+    cks = [r["step"] for r in tests[0]["plain_rows"]]
+    bound = {}
+    for t in tests:
+        run, ref, parts = cp.velocity_bound_run(kw["n_f"], kw["tau_f"], kw["factor"], t["seed"],
+                                                cks)
+        rows, w = cp.judge(run, ref, n_c // 4)
+        bound[str(t["seed"])] = {"eps_spec": [round(r["eps_spec"], 4) for r in rows],
+                                 "magnetic": [round(parts[c]["magnetic"], 4) for c in cks],
+                                 "kinetic_max": max(parts[c]["kinetic"] for c in cks),
+                                 "worst": round(w["eps_spec"], 4)}
     print(json.dumps({
         "metric": "closure-vs-fine wall time at 5% spectral error",
         "value": round(ms["closure_gpu_ms"] / 1e3, 3), "unit": "s (GPU, coarse+closure run)",
@@ -609,7 +622,8 @@ def closure_bench(args):
         "onestep_objective": {"train": res["onestep_objective"],
                               "validation": res["onestep_objective_val"]},
         "alpha": res["alpha"], "calibration": res["calibration"],
-        "fallbacks": [t["fallback_at"] for t in tests]}), flush=True)
+        "fallbacks": [t["fallback_at"] for t in tests],
+        "best_velocity_bound": bound}), flush=True)
 
 
 def time_turbulence_leg(torch, rrmhd, args, fields, storage):

@@ -246,6 +246,54 @@ def fine_reference(n_f, tau_f, factor, seed, coarse_checkpoints):
     return out, gpu_ms
 
 
+def velocity_bound_run(n_f, tau_f, factor, seed, checkpoints):
+    """Best-velocity bound of a fluid-only closure: the fine run and the
+    coarse run advance in lockstep, and after every coarse step the coarse
+    fluid state is replaced by the equilibrium of the box-filtered fine
+    density and momentum (rrmhd_train_impose_fluid, the coarse run's own b
+    kept), so the coarse magnetic field evolves with the filtered fine
+    velocity.  No correction of a_1^(2) can give the coarse run a better
+    velocity than that one; the spectral error left over is the magnetic
+    field's own coarse-grid error.  Returns ({step: (E(k), E_kin, E_mag)} of
+    the coarse run, the same of the filtered fine run, and the per-time
+    kinetic and magnetic spectral errors (eps of E_u(k) and of E_b(k)))."""
+    import torch
+    u, b = fine_fields(n_f, seed)
+    fine = rrmhd.Solver(n_f, n_f, tau_f, tau_f)
+    fine.init(_dev(u), _dev(b))
+    n_c = n_f // factor
+    tc = tau_coarse(tau_f, factor)
+    uc, bc = coarse_fields(n_f, factor, seed)
+    coarse = rrmhd.Solver(n_c, n_c, tc, tc)
+    coarse.init(_dev(uc), _dev(bc))
+    flt = torch.empty((10, n_c, n_c), dtype=torch.float64, device="cuda")
+    kmax = n_c // 4
+    run, ref, parts = {}, {}, {}
+    for c in sorted(checkpoints):
+        while coarse.step_count < c:
+            coarse.step(1)
+            fine.step(factor)
+            rho, uf, bf = fine.moments()
+            rrmhd.train_box_filter(rho, uf, bf, factor, out=flt)
+            _, _, bcur = coarse.moments()
+            coarse.impose_fluid(flt[0], flt[1:3], bcur)
+        _, uu, bb = coarse.moments()
+        uh, bh = uu.cpu().numpy(), bb.cpu().numpy()
+        rho, uf, bf = fine.moments()
+        ufh = spectral.box_filter(uf.cpu().numpy(), factor)
+        bfh = spectral.box_filter(bf.cpu().numpy(), factor)
+        run[c] = (spectral.shell_spectrum(uh, bh), *spectral.energies(uh, bh))
+        ref[c] = (spectral.shell_spectrum(ufh, bfh), *spectral.energies(ufh, bfh))
+        eu, eb = spectral.kinetic_magnetic_spectra(uh, bh)
+        ru, rb = spectral.kinetic_magnetic_spectra(ufh, bfh)
+        parts[c] = dict(kinetic=spectral.eps_spec(eu, ru, kmax),
+                        magnetic=spectral.eps_spec(eb, rb, kmax))
+    torch.cuda.synchronize()
+    fine.close()
+    coarse.close()
+    return run, ref, parts
+
+
 def judge(run, ref, kmax):
     rows = []
     for c in sorted(ref):

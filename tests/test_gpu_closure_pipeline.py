@@ -112,6 +112,43 @@ def test_spectral_error_budget_of_the_plain_coarse_run():
     assert eps[tc] < eps[tc - 0.001] and eps[tc] < eps[tc + 0.001]
 
 
+def test_best_velocity_bound_of_a_fluid_only_closure(capsys):
+    """No correction of the fluid's a_1^(2) brings the coarse run within the
+    5 % spectral bar (full protocol, test seeds 20-23): with the filtered fine
+    velocity imposed after every coarse step (the best velocity any fluid
+    closure could give it), the kinetic spectrum and both energies are
+    reproduced, yet the magnetic field evolved on the coarse grid leaves the
+    worst-time eps_spec above 0.05 on every test seed.  The same bound is
+    below the plain coarse run's worst eps_spec on every seed, so it is the
+    room a fluid-only closure has."""
+    from paper_2602_14667_amd import closure_pipeline as cp, rrmhd
+    rrmhd.lib()
+
+    def log(m):
+        with capsys.disabled():
+            print("[gpu]  ", m, flush=True)
+
+    log("best-velocity bound, full protocol 2048 -> 512, test seeds 20-23")
+    n_f, factor, tau_f = 2048, 4, 0.56
+    n_c = n_f // factor
+    tc = cp.tau_coarse(tau_f, factor)
+    cks = [16000 * (k + 1) // 5 for k in range(5)]
+    kmax = n_c // 4
+    for sd in (20, 21, 22, 23):
+        run, ref, parts = cp.velocity_bound_run(n_f, tau_f, factor, sd, cks)
+        rows, worst = cp.judge(run, ref, kmax)
+        uc, bc = cp.coarse_fields(n_f, factor, sd)
+        plain, _, _ = cp.spectra_run(n_c, tc, uc, bc, cks)
+        _, wp = cp.judge(plain, ref, kmax)
+        log(f"seed {sd}: bound eps_spec {[round(r['eps_spec'], 4) for r in rows]}, magnetic "
+            f"{[round(parts[c]['magnetic'], 4) for c in cks]}, kinetic max "
+            f"{max(parts[c]['kinetic'] for c in cks):.1e}; plain worst {wp['eps_spec']:.4f}")
+        assert max(parts[c]["kinetic"] for c in cks) < 1e-3
+        assert worst["ekin_err"] < 1e-3 and worst["emag_err"] < 5e-3
+        assert worst["eps_spec"] > 0.05
+        assert worst["eps_spec"] < wp["eps_spec"]
+
+
 @pytest.mark.xfail(strict=True, reason=(
     "measured on the full protocol (2048^2 -> 512^2, tau_f 0.56, 16 training seeds, "
     "alpha 0.01 from the validation seeds): the closure lowers the worst-time eps_spec on "
