@@ -68,10 +68,14 @@ class HipBackend:
     name = "hip"
 
     def __init__(self):
+        import ctypes as ct
         import torch
         from paper_2602_14667_amd import rrmhd
         self.torch = torch
-        self.L = _types(rrmhd.lib())
+        rrmhd.lib()  # built and loaded (fails loudly otherwise)
+        # a CDLL object of its own: argument types set here must not replace
+        # the binding's on the shared function objects
+        self.L = _types(ct.CDLL(rrmhd.LIB_PATH))
 
     def put(self, a):
         return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
