@@ -633,8 +633,9 @@ def time_turbulence_leg(torch, rrmhd, args, fields, storage):
     ud, bd = fields
     s = rrmhd.Solver(n, n, args.tau, args.tau, storage=storage,
                      equilibrium=args.equilibrium, inplace=args.inplace)
-    launch = ("library default (f32: 128x2 threads; f16: 128x1 threads, two nodes "
-              "per thread; NT stores)")
+    launch = ("library default (row-interleaved planes, eight neighbouring tiles per "
+              "XCD, NT stores; f32: 128x2 threads, two nodes per thread in 64-bit words; "
+              "f16: 128x1 threads, four nodes per thread in 64-bit words)")
     if args.equilibrium != "algorithm":
         launch = "library default block shape, one node per thread, NT stores"
     if args.inplace:

@@ -28,7 +28,10 @@
  *    RRMHD_DEBUG_POISON = 1 turns on the debug poison mode of two-buffer
  *    handles; RRMHD_AUTOTUNE_CACHE names the autotuner's cache file when the
  *    call passes none; RRMHD_PLANE_PAD_BYTES (a multiple of 256) sets the
- *    gap between population planes.
+ *    gap between population planes of [ny][nx]; RRMHD_LAYOUT = "planar"
+ *    keeps planes of [ny][nx] for every handle; RRMHD_ROW_PAD_BYTES (a
+ *    multiple of 256) sets the gap between row groups of the row-interleaved
+ *    layout.
  */
 #ifndef RRMHD_H
 #define RRMHD_H
@@ -78,6 +81,15 @@ enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
  * graph replay, the learned closure or the equilibrium ablation (EINVAL);
  * the two-node FP16 update is not used. */
 enum { RRMHD_STORE_F16_SR = 2 };
+/* Layout of the populations in device memory (not visible through the API:
+ * moments, diagnostics, rrmhd_save_state and checkpoint files are the same
+ * for either).  Periodic two-buffer handles keep the 19 planes
+ * row-interleaved: each grid row holds its 19 plane rows side by side, each
+ * starting on a 256-byte boundary, and the FP32 step then updates two nodes
+ * per thread with 64-bit words.  Handles with walls or one buffer, or with
+ * RRMHD_STORE_PLANAR OR-ed into rrmhd_grid.storage, keep 19 planes of
+ * [ny][nx].  Results are bitwise the same in both layouts. */
+enum { RRMHD_STORE_PLANAR = 0x200 };
 
 /* Boundary kinds.  PERIODIC: doubly periodic.  WALLS_Y: periodic in x,
  * walls half-way at y = -1/2 and y = ny - 1/2 (half-way bounce-back for f,
@@ -210,10 +222,13 @@ int rrmhd_load(rrmhd *h, const char *path);
  * xcd = 2 so each XCD gets 8 neighbouring tiles out of every 64; nt bit 0
  * writes populations with non-temporal stores, bit 1 reads them with
  * non-temporal loads (periodic grids), bit 2 lets each thread update two
- * neighbouring nodes with 32-bit plane accesses (FP16 storage, periodic
- * grids with even nx; a workgroup then covers 2 bx nodes in x; ignored
- * otherwise).  Results do not depend on the shape (bitwise).  Host-side
- * only. */
+ * neighbouring nodes with one word per plane (FP16 storage: 32-bit words;
+ * FP32 storage on row-interleaved planes: 64-bit words; periodic grids with
+ * even nx), bit 3 four neighbouring nodes with 64-bit words (FP16 storage,
+ * nx a multiple of 4); a workgroup then covers 2 bx or 4 bx nodes in x.  On
+ * row-interleaved planes the multi-node forms need bx a multiple of 64 or
+ * by = 1; where a form does not apply the bit is ignored.  Results do not
+ * depend on the shape (bitwise).  Host-side only. */
 int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt);
 /* The handle's current launch shape (any pointer may be NULL). */
 int rrmhd_get_launch(const rrmhd *h, int *bx, int *by, int *ry, int *xcd, int *nt);

@@ -90,6 +90,7 @@ struct rrmhd {
   int cur = 0;
   int64_t steps = 0;
   bool inplace = false;  // one population buffer (alternating step phases)
+  size_t bytes = 0;      // bytes of one population buffer
   int phase = 0;         // in-place: 0 pull layout, 1 swapped layout
   bool ready = false;
   rr::LaunchShape shape{};
@@ -119,7 +120,7 @@ __global__ void k_poison(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 static hipError_t poison_buffer(const rrmhd *h, void *buf, hipStream_t st) {
-  const int64_t words = (int64_t)h->D.plane * rr::kStatePlanes * h->elem / 4;
+  const int64_t words = (int64_t)(h->bytes / 4);
   const uint32_t nan = h->elem == 4 ? 0x7fc00000u : 0x7e007e00u;
   hipLaunchKernelGGL(k_poison, dim3(2048), dim3(256), 0, st, (uint32_t *)buf, words, nan);
   return hipGetLastError();
@@ -178,7 +179,7 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   const int kind = grid->storage & 0xff, flags = grid->storage & ~0xff;
   if (kind != RRMHD_STORE_F32 && kind != RRMHD_STORE_F16 && kind != RRMHD_STORE_F16_SR)
     return RRMHD_EINVAL;
-  if (flags != 0 && flags != RRMHD_STORE_INPLACE) return RRMHD_EINVAL;
+  if ((flags & ~(RRMHD_STORE_INPLACE | RRMHD_STORE_PLANAR)) != 0) return RRMHD_EINVAL;
   if (!(std::isfinite(tau_f) && std::isfinite(tau_m)) || tau_f <= 0.5 || tau_m <= 0.5)
     return RRMHD_EINVAL;
   rrmhd_bc b{};
@@ -200,7 +201,7 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   if (!h) return RRMHD_ENOMEM;
   // the stochastic-rounding variant is FP16 storage for every read path
   h->storage = kind == RRMHD_STORE_F16_SR ? RRMHD_STORE_F16 : kind;
-  h->inplace = flags == RRMHD_STORE_INPLACE;
+  h->inplace = (flags & RRMHD_STORE_INPLACE) != 0;
   h->elem = kind == RRMHD_STORE_F32 ? 4 : 2;
   h->tau_f = tau_f;
   h->tau_m = tau_m;
@@ -213,13 +214,34 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   // planes (RRMHD_PLANE_PAD_BYTES, a multiple of 256) staggers the plane
   // starts across HBM channels
   const int64_t align = 256 / h->elem;
-  int64_t pad = 256 / h->elem;  // measured best default: 256 B between planes
-  if (const char *e = std::getenv("RRMHD_PLANE_PAD_BYTES")) {
-    long long v = std::atoll(e);
-    if (v >= 0 && v % 256 == 0) pad = v / h->elem;
-  }
-  D.plane = (N + align - 1) / align * align + pad;
   D.walls = b.kind == RRMHD_BC_WALLS_Y;
+  // Layout: periodic two-buffer handles keep the 19 planes row-interleaved
+  // (each grid row holds its 19 plane rows side by side, each starting on a
+  // 256-byte boundary), which streams faster than whole planes; walls and
+  // single-buffer handles, or RRMHD_STORE_PLANAR (or RRMHD_LAYOUT=planar),
+  // keep planes of [ny][nx].
+  bool rows = !D.walls && !h->inplace && !(flags & RRMHD_STORE_PLANAR);
+  if (const char *e = std::getenv("RRMHD_LAYOUT"))
+    if (std::strcmp(e, "planar") == 0) rows = false;
+  if (rows) {
+    int64_t pad = 0;  // extra gap between row groups
+    if (const char *e = std::getenv("RRMHD_ROW_PAD_BYTES")) {
+      long long v = std::atoll(e);
+      if (v >= 0 && v % 256 == 0) pad = v / h->elem;
+    }
+    D.plane = ((int64_t)grid->nx + align - 1) / align * align;
+    D.row = rr::kStatePlanes * D.plane + pad;
+    h->bytes = (size_t)D.row * grid->ny * h->elem;
+  } else {
+    int64_t pad = 256 / h->elem;  // measured best default: 256 B between planes
+    if (const char *e = std::getenv("RRMHD_PLANE_PAD_BYTES")) {
+      long long v = std::atoll(e);
+      if (v >= 0 && v % 256 == 0) pad = v / h->elem;
+    }
+    D.plane = (N + align - 1) / align * align + pad;
+    D.row = grid->nx;
+    h->bytes = (size_t)D.plane * rr::kStatePlanes * h->elem;
+  }
   const double om = 1.0 / tau_f, omm = 1.0 / tau_m;
   D.om_c = (float)(1.0 - om);
   D.omm_c = (float)(1.0 - omm);
@@ -257,7 +279,7 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   }
   if (const char *e = std::getenv("RRMHD_DEBUG_POISON"))
     h->poison = !h->inplace && std::atoi(e) != 0;
-  const size_t bytes = (size_t)D.plane * rr::kStatePlanes * h->elem;
+  const size_t bytes = h->bytes;
   int rc = RRMHD_OK;
   for (int k = 0; k < (h->inplace ? 1 : 2) && rc == RRMHD_OK; ++k) {
     hipError_t e = hipMalloc(&h->buf[k], bytes);
@@ -290,7 +312,7 @@ int rrmhd_set_launch(rrmhd *h, int bx, int by, int ry, int xcd, int nt) {
   h->shape.by = by;
   h->shape.ry = ry;
   h->shape.xcd = (xcd >= 0 && xcd <= 2) ? xcd : 0;
-  h->shape.nt = nt & 7;
+  h->shape.nt = nt & 15;
   return RRMHD_OK;
 }
 
@@ -499,6 +521,36 @@ int rrmhd_step_count(const rrmhd *h, int64_t *out) {
   return RRMHD_OK;
 }
 
+}  // extern "C"
+
+// Copy between a population buffer and the dense state of 19 planes of
+// [ny][nx] (device to device, on the handle's stream); to_buf selects the
+// direction.
+static hipError_t copy_planes(const rrmhd *h, void *dense, const void *buf_in, bool to_buf) {
+  // to_buf: dense -> buf_in (the buffer is then written); else buf_in -> dense
+  const size_t plane_bytes = (size_t)h->D.nx * h->D.ny * h->elem;
+  const size_t width = (size_t)h->D.nx * h->elem, rstride = (size_t)h->D.row * h->elem;
+  if (h->D.row == h->D.nx) {
+    const size_t pitch = (size_t)h->D.plane * h->elem;
+    return to_buf ? hipMemcpy2DAsync((void *)buf_in, pitch, dense, plane_bytes, plane_bytes,
+                                     rr::kStatePlanes, hipMemcpyDeviceToDevice, h->stream)
+                  : hipMemcpy2DAsync(dense, plane_bytes, buf_in, pitch, plane_bytes,
+                                     rr::kStatePlanes, hipMemcpyDeviceToDevice, h->stream);
+  }
+  for (int p = 0; p < rr::kStatePlanes; ++p) {
+    char *d = (char *)dense + p * plane_bytes;
+    char *b = (char *)buf_in + (size_t)p * h->D.plane * h->elem;
+    hipError_t e = to_buf ? hipMemcpy2DAsync(b, rstride, d, width, width, h->D.ny,
+                                             hipMemcpyDeviceToDevice, h->stream)
+                          : hipMemcpy2DAsync(d, width, b, rstride, width, h->D.ny,
+                                             hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+extern "C" {
+
 int64_t rrmhd_state_bytes(const rrmhd *h) {
   if (!h) return RRMHD_EINVAL;
   return (int64_t)h->D.nx * h->D.ny * rr::kStatePlanes * h->elem;
@@ -511,19 +563,13 @@ int rrmhd_save_state(rrmhd *h, void *dst, int64_t bytes) {
     HIP_OR_RETURN(rr::launch_swapped_to_pull(h->storage, h->D, h->buf[0], dst, h->stream));
     return RRMHD_OK;
   }
-  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
-  const size_t pitch = (size_t)h->D.plane * h->elem;
-  HIP_OR_RETURN(hipMemcpy2DAsync(dst, row, h->buf[h->cur], pitch, row, rr::kStatePlanes,
-                                 hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_RETURN(copy_planes(h, dst, (const char *)h->buf[h->cur], false));
   return RRMHD_OK;
 }
 
 int rrmhd_load_state(rrmhd *h, const void *src, int64_t bytes, int64_t step_count) {
   if (!h || !src || bytes < rrmhd_state_bytes(h) || step_count < 0) return RRMHD_EINVAL;
-  const size_t row = (size_t)h->D.nx * h->D.ny * h->elem;
-  const size_t pitch = (size_t)h->D.plane * h->elem;
-  HIP_OR_RETURN(hipMemcpy2DAsync(h->buf[0], pitch, src, row, row, rr::kStatePlanes,
-                                 hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_RETURN(copy_planes(h, const_cast<void *>(src), h->buf[0], true));
   h->cur = 0;
   h->phase = 0;
   h->steps = step_count;
@@ -587,7 +633,7 @@ int rr_ck_mismatch(const char *field) {
 }
 
 int rr_ck_write(const char *path, const void *hdr, size_t hdr_bytes, const char *base,
-                size_t pitch, size_t row, int planes) {
+                size_t pitch, size_t row, int planes, size_t rstride, int nrows) {
   char *host = new (std::nothrow) char[row];
   if (!host) return RRMHD_ENOMEM;
   int rc = RRMHD_OK;
@@ -595,7 +641,10 @@ int rr_ck_write(const char *path, const void *hdr, size_t hdr_bytes, const char 
   if (!f) rc = io_err("cannot open", path);
   if (rc == RRMHD_OK && std::fwrite(hdr, hdr_bytes, 1, f) != 1) rc = io_err("cannot write", path);
   for (int p = 0; p < planes && rc == RRMHD_OK; ++p) {
-    hipError_t e = hipMemcpy(host, base + (size_t)p * pitch, row, hipMemcpyDeviceToHost);
+    hipError_t e =
+        nrows > 1 ? hipMemcpy2D(host, row / nrows, base + (size_t)p * pitch, rstride, row / nrows,
+                                nrows, hipMemcpyDeviceToHost)
+                  : hipMemcpy(host, base + (size_t)p * pitch, row, hipMemcpyDeviceToHost);
     if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
     else if (std::fwrite(host, 1, row, f) != row) rc = io_err("cannot write", path);
   }
@@ -617,7 +666,7 @@ int rr_ck_open(const char *path, void *hdr, size_t hdr_bytes, FILE **out) {
 }
 
 int rr_ck_read_planes(FILE *f, const char *path, size_t hdr_bytes, char *base, size_t pitch,
-                      size_t row, int planes, bool *touched) {
+                      size_t row, int planes, bool *touched, size_t rstride, int nrows) {
   *touched = false;
   // the whole payload must be in the file before the device state is
   // touched, so a short file leaves the handle unchanged
@@ -635,7 +684,10 @@ int rr_ck_read_planes(FILE *f, const char *path, size_t hdr_bytes, char *base, s
       break;
     }
     *touched = true;
-    hipError_t e = hipMemcpy(base + (size_t)p * pitch, host, row, hipMemcpyHostToDevice);
+    hipError_t e =
+        nrows > 1 ? hipMemcpy2D(base + (size_t)p * pitch, rstride, host, row / nrows, row / nrows,
+                                nrows, hipMemcpyHostToDevice)
+                  : hipMemcpy(base + (size_t)p * pitch, host, row, hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = dev_err(e, "hipMemcpy(checkpoint plane)");
   }
   delete[] host;
@@ -652,6 +704,12 @@ int rrmhd_save(rrmhd *h, const char *path) {
   void *tmp = nullptr;
   const char *base = (const char *)h->buf[h->cur];
   size_t pitch = (size_t)h->D.plane * h->elem;
+  size_t rstride = 0;
+  int nrows = 1;
+  if (h->D.row != h->D.nx) {  // row-interleaved: each plane gathered row by row
+    rstride = (size_t)h->D.row * h->elem;
+    nrows = h->D.ny;
+  }
   if (h->inplace && h->phase) {
     // between the two step forms: gather the swapped layout first
     HIP_OR_RETURN(hipMalloc(&tmp, row * rr::kStatePlanes));
@@ -665,7 +723,8 @@ int rrmhd_save(rrmhd *h, const char *path) {
   }
   hipError_t e = hipStreamSynchronize(h->stream);
   int rc = e != hipSuccess ? dev_err(e, "hipStreamSynchronize")
-                           : rr_ck_write(path, &hd, sizeof hd, base, pitch, row, rr::kStatePlanes);
+                           : rr_ck_write(path, &hd, sizeof hd, base, pitch, row, rr::kStatePlanes,
+                                         rstride, nrows);
   if (tmp) (void)hipFree(tmp);
   return rc;
 }
@@ -697,7 +756,9 @@ int rrmhd_load(rrmhd *h, const char *path) {
   bool touched = false;
   if (rc == RRMHD_OK)
     rc = rr_ck_read_planes(f, path, sizeof hd, (char *)h->buf[0], (size_t)h->D.plane * h->elem,
-                           (size_t)h->D.nx * h->D.ny * h->elem, rr::kStatePlanes, &touched);
+                           (size_t)h->D.nx * h->D.ny * h->elem, rr::kStatePlanes, &touched,
+                           h->D.row != h->D.nx ? (size_t)h->D.row * h->elem : 0,
+                           h->D.row != h->D.nx ? h->D.ny : 1);
   std::fclose(f);
   if (rc != RRMHD_OK) {
     if (touched) h->ready = false;  // part of the state was overwritten
@@ -724,6 +785,8 @@ int rr_handle_info(const rrmhd *h, int *nx, int *ny, int *storage, hipStream_t *
 int rr_handle_walls(const rrmhd *h) { return h && h->D.walls ? 1 : 0; }
 
 int rr_handle_inplace(const rrmhd *h) { return h && h->inplace ? 1 : 0; }
+
+int rr_handle_rows(const rrmhd *h) { return h && h->D.row != h->D.nx ? 1 : 0; }
 
 void rr_handle_set_ready(rrmhd *h, int ready) {
   if (h) h->ready = ready != 0;

@@ -70,7 +70,7 @@ __device__ __forceinline__ void batch_tile(const BatchDom *__restrict__ doms,
     P.Gx = 0.0f;
     P.Gy = 0.0f;
     P.src_c = 0.0f;
-    const PlaneGeom G{D.plane, D.nx, D.ny, s, inv_s};
+    const PlaneGeom G{D.plane, D.nx, D.ny, s, inv_s, 0u, (int64_t)D.nx};  // planes of [ny][nx]
     update_periodic<C, false, NT, false>(G, src + D.base, dst + D.base, x, y, P);
   }
 }
@@ -239,6 +239,7 @@ static rr::Domain domain_of(const rrmhd_batch *b, int d) {
   D.nx = B.nx;
   D.ny = B.ny;
   D.plane = B.plane;
+  D.row = B.nx;  // planes of [ny][nx]
   D.walls = 0;
   D.om_c = B.om_c;
   D.omm_c = B.omm_c;

@@ -110,57 +110,30 @@ __global__ __launch_bounds__(1024) void k_mlp_eval(const MlpDev *__restrict__ g,
 // wave w of the block takes row 16 ty + w, lanes take 64 consecutive x.  The
 // grid is persistent (one 1024-thread block per CU, the LDS holding the
 // parameters and the GELU table) so the parameters are staged once per block.
-template <class C, bool NT>
+template <class C, bool NT, int RM>
 __global__ __launch_bounds__(1024) void k_step_closure(PlaneGeom G, CollideParams P,
                                                        const MlpDev *__restrict__ g,
                                                        int tiles_x, int ntiles,
                                                        const typename C::T *__restrict__ src,
                                                        typename C::T *__restrict__ dst) {
-  using T = typename C::T;
   __shared__ MlpDev W;
   mlp_to_lds(g, &W);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const ClosureHook hook{&W};
-  constexpr uint32_t E = sizeof(T);
-  const uint32_t pitch = G.nx * E;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     // keep the weights in LDS: without this the compiler hoists their loads
     // out of the tile loop and the register file overflows
     asm volatile("" ::: "memory");
     const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int y = ty * 16 + wave;
+    const int y = ty * 16 + wave;  // one row per wavefront
     if (y >= G.ny) continue;  // whole wave idle (wave-uniform)
     const int xr = tx * 64 + lane;
     const bool active = xr < G.nx;
     const int x = active ? xr : G.nx - 1;  // idle lanes still join the MLP
-    const uint32_t x0 = x * E;
-    const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
-    const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
-    const uint32_t b0 = y * pitch;
-    const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
-    const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
     float d[kQ], gg[2 * kQm];
-    d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    gg[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    pull_node_per<C, false>(G, row_addr<RM>(G, src, y), x, d, gg);
     collide<false>(d, gg, P, hook);
-    if (active) store_planes<C, NT>(G, dst, b0 + x0, d, gg);
+    if (active) store_node<C, NT, RM>(G, dst, x, y, d, gg);
   }
 }
 
@@ -186,6 +159,21 @@ hipError_t launch_mlp_eval(const MlpDev *mlp, const float *x, float *y, int64_t 
   return hipGetLastError();
 }
 
+template <int RM>
+static void closure_t(int storage, const Domain &D, const PlaneGeom &G, const CollideParams &P,
+                      const MlpDev *mlp, int tiles_x, int ntiles, int grid, const void *src,
+                      void *dst, hipStream_t st) {
+  if (storage == kF16 && D.s == 1.0f)
+    hipLaunchKernelGGL((k_step_closure<CodecF16U, true, RM>), dim3(grid), dim3(1024), 0, st, G, P,
+                       mlp, tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
+  else if (storage == kF16)
+    hipLaunchKernelGGL((k_step_closure<CodecF16, true, RM>), dim3(grid), dim3(1024), 0, st, G, P,
+                       mlp, tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
+  else
+    hipLaunchKernelGGL((k_step_closure<CodecF32, true, RM>), dim3(grid), dim3(1024), 0, st, G, P,
+                       mlp, tiles_x, ntiles, (const float *)src, (float *)dst);
+}
+
 hipError_t launch_step_closure(int storage, const Domain &D, const MlpDev *mlp,
                                const void *src, void *dst, int grid_blocks, hipStream_t st) {
   const int tiles_x = (D.nx + 63) / 64, tiles_y = (D.ny + 15) / 16;
@@ -198,16 +186,11 @@ hipError_t launch_step_closure(int storage, const Domain &D, const MlpDev *mlp,
   P.Gx = 0.0f;
   P.Gy = 0.0f;
   P.src_c = 0.0f;
-  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
-  if (storage == kF16 && D.s == 1.0f)
-    hipLaunchKernelGGL((k_step_closure<CodecF16U, true>), dim3(grid), dim3(1024), 0, st, G, P, mlp,
-                       tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
-  else if (storage == kF16)
-    hipLaunchKernelGGL((k_step_closure<CodecF16, true>), dim3(grid), dim3(1024), 0, st, G, P, mlp,
-                       tiles_x, ntiles, (const uint16_t *)src, (uint16_t *)dst);
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, 0u, D.row};
+  if (D.row == D.nx)
+    closure_t<RM_OFFSET>(storage, D, G, P, mlp, tiles_x, ntiles, grid, src, dst, st);
   else
-    hipLaunchKernelGGL((k_step_closure<CodecF32, true>), dim3(grid), dim3(1024), 0, st, G, P, mlp,
-                       tiles_x, ntiles, (const float *)src, (float *)dst);
+    closure_t<RM_UNIFORM>(storage, D, G, P, mlp, tiles_x, ntiles, grid, src, dst, st);
   return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ namespace rr {
 
 // SWAPPED: the layout a single-buffer handle holds after an odd number of
 // steps, f_i(x) in slot opp(i) of x itself.
-template <class C, bool SWAPPED>
+// One row per workgroup (blockIdx.y), so RM_UNIFORM applies to any layout.
+template <class C, bool SWAPPED, int RM>
 __global__ void k_current(PlaneGeom G, const typename C::T *__restrict__ src, double omega_m,
                           double Gx, double Gy, double *__restrict__ jz,
                           double *__restrict__ upl) {
@@ -22,42 +23,21 @@ __global__ void k_current(PlaneGeom G, const typename C::T *__restrict__ src, do
   if (x >= G.nx) return;
   using T = typename C::T;
   constexpr uint32_t E = sizeof(T);
-  const uint32_t pitch = G.nx * E, x0 = x * E;
-  const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E, xp = (x == G.nx - 1 ? 0 : x + 1) * E;
-  const uint32_t b0 = y * pitch, bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
-  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
+  const RowAddr<T> A = row_addr<RM>(G, src, y);
   float d[kQ], g[2 * kQm];
   if constexpr (SWAPPED) {
-    const uint32_t o = b0 + x0;
+    const uint32_t o = A.oz + x * E;
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      d[i] = C::dec(ld_at<T, false>(plane_ptr(src, opp_f(i), G.plane), o), G.inv_s);
+      d[i] = C::dec(ld_at<T, false>(plane_ptr(A.z, opp_f(i), G.plane), o), G.inv_s);
 #pragma unroll
     for (int j = 0; j < kQm; ++j)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
         g[2 * j + c] =
-            C::dec(ld_at<T, false>(plane_ptr(src, gplane(opp_g(j), c), G.plane), o), G.inv_s);
+            C::dec(ld_at<T, false>(plane_ptr(A.z, gplane(opp_g(j), c), G.plane), o), G.inv_s);
   } else {
-    d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
-    d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-    g[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+    pull_node_per<C, false>(G, A, x, d, g);
   }
   double dr = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
 #pragma unroll
@@ -114,20 +94,26 @@ extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Doma
                                            double omega_m, double *jz, double *wz,
                                            double *upl, hipStream_t st, int swapped) {
   const dim3 block(64), grid((D->nx + 63) / 64, D->ny);
-  const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s};
+  const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s, 0u, D->row};
   const double gx = D->Gx, gy = D->Gy;
   auto s16 = (const uint16_t *)src;
   auto s32 = (const float *)src;
+  // single-buffer handles (swapped) keep planes of [ny][nx]
+  const bool rows = D->row != D->nx;
   if (storage == rr::kF16) {
     if (swapped)
-      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, true>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, true, rr::RM_OFFSET>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
+    else if (rows)
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, false, rr::RM_UNIFORM>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
     else
-      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, false>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, false, rr::RM_OFFSET>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
   } else {
     if (swapped)
-      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, true>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, true, rr::RM_OFFSET>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
+    else if (rows)
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, false, rr::RM_UNIFORM>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
     else
-      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, false>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, false, rr::RM_OFFSET>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
   }
   if (hipGetLastError() != hipSuccess) return RRMHD_EDEVICE;
   if (wz) {

@@ -11,7 +11,10 @@ constexpr int kStatePlanes = 19;  // 9 fluid + 5 x 2 magnetic planes
 // Geometry and physics of one domain, as the kernels see it.
 struct Domain {
   int nx, ny;
-  int64_t plane;  // elements between consecutive planes of one buffer
+  int64_t plane;  // elements between consecutive planes of one buffer (of one row)
+  int64_t row;    // elements between consecutive rows of one plane: nx for
+                  // planes of [ny][nx]; kStatePlanes * plane for the
+                  // row-interleaved layout, [ny][plane][x]
   int walls;      // 0 periodic, 1 walls in y
   float om_c, omm_c, src_c;
   float Gx, Gy;
@@ -29,7 +32,8 @@ struct LaunchShape {
   int ry;      // rows per thread (block covers by * ry rows)
   int xcd;     // 1: XCD-aware block order
   int nt;      // bit 0: non-temporal stores, bit 1: non-temporal loads,
-               // bit 2: FP16 storage, periodic, even nx: two nodes per thread
+               // bit 2: two nodes per thread, bit 3: four (periodic grids;
+               // see multi_nodes)
 };
 
 hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,

@@ -1,10 +1,12 @@
 // rr_kernels.hip -- single-domain kernels: the fused stream-and-collide step,
 // equilibrium initialisation, moments and FP64 diagnostics.
 //
-// Layout in HBM: structure of arrays, 19 planes per buffer (f_0..f_8, then
-// g_0x, g_0y, ..., g_4x, g_4y), each plane [ny][nx] with x fastest and
-// `plane` elements between plane starts.  Two buffers (A/B) alternate: a
-// step pulls from one and writes the other.  A stored value is the
+// Layout in HBM: 19 planes per buffer (f_0..f_8, then g_0x, g_0y, ...,
+// g_4x, g_4y), x fastest; element (p, y, x) at p * plane + y * row + x.
+// Planes of [ny][nx] (row = nx, `plane` elements between plane starts) or
+// row-interleaved (the 19 plane rows of one grid row side by side: plane =
+// the row's width, row = 19 plane).  Two buffers (A/B) alternate: a step
+// pulls from one and writes the other.  A stored value is the
 // post-collision population of the previous step at its source node, so the
 // pull f_i(x) = f*_i(x - c_i) is task 6 of the algorithm fused into the
 // loads of the next step.
@@ -23,8 +25,8 @@ namespace rr {
 // wall term: g_j = -g*_opp(j) + 2 psi_j b_wall.
 // ---------------------------------------------------------------------------
 struct Rows {
-  int xm, xp;        // x - 1, x + 1 (periodic)
-  int rm, r0, rp;    // row offsets of y - 1, y, y + 1
+  int xm, xp;                // x - 1, x + 1 (periodic)
+  int64_t rm, r0, rp;        // element offsets of the rows y - 1, y, y + 1
   bool lo, hi;       // wall below (y == 0) / above (y == ny - 1)
 };
 
@@ -35,9 +37,9 @@ __device__ __forceinline__ Rows rows_of(const Domain &D, int x, int y) {
   R.xp = x == D.nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? D.ny - 1 : y - 1;
   const int yp = y == D.ny - 1 ? 0 : y + 1;
-  R.rm = ym * D.nx;
-  R.r0 = y * D.nx;
-  R.rp = yp * D.nx;
+  R.rm = (int64_t)ym * D.row;
+  R.r0 = (int64_t)y * D.row;
+  R.rp = (int64_t)yp * D.row;
   R.lo = WALLS && y == 0;
   R.hi = WALLS && y == D.ny - 1;
   return R;
@@ -50,7 +52,7 @@ __device__ __forceinline__ float pull_f(const Domain &D,
                                         const Rows &R, int x) {
   constexpr int CX = cx(I), CY = cy(I);
   const int sx = CX == 0 ? x : (CX > 0 ? R.xm : R.xp);
-  int off = (CY == 0 ? R.r0 : (CY > 0 ? R.rm : R.rp)) + sx;
+  int64_t off = (CY == 0 ? R.r0 : (CY > 0 ? R.rm : R.rp)) + sx;
   int plane = I;
   if constexpr (WALLS && CY != 0) {
     const bool wall = CY > 0 ? R.lo : R.hi;
@@ -69,7 +71,7 @@ __device__ __forceinline__ void pull_g(const Domain &D,
                                        float &gy) {
   constexpr int EX = ex(J), EY = ey(J);
   const int sx = EX == 0 ? x : (EX > 0 ? R.xm : R.xp);
-  int off = (EY == 0 ? R.r0 : (EY > 0 ? R.rm : R.rp)) + sx;
+  int64_t off = (EY == 0 ? R.r0 : (EY > 0 ? R.rm : R.rp)) + sx;
   int j = J;
   bool wall = false;
   if constexpr (WALLS && EY != 0) {
@@ -135,7 +137,8 @@ __device__ __forceinline__ int xcd_local(int L, int n) {
 // 1-D grid of tiles; a tile is blockDim.x nodes of ry consecutive rows,
 // blockDim.y tiles high.
 // ---------------------------------------------------------------------------
-template <class C, bool WALLS, bool FORCED, bool NT, bool NTL, bool FULLM = false>
+template <class C, bool WALLS, bool FORCED, bool NT, bool NTL, bool FULLM = false,
+          int RM = RM_OFFSET>
 __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
                                               int xcd,
                                               const typename C::T *__restrict__ src,
@@ -160,10 +163,10 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
       float d[kQ], g[2 * kQm];
       pull_node<C, true>(D, src, x, y, d, g);
       collide<FORCED, NoCorrection, FULLM>(d, g, P);
-      const int o = y * D.nx + x;
+      const int64_t o = (int64_t)y * D.row + x;
       uint32_t seed = 0;
       if constexpr (codec_sr<C>::value)
-        seed = sr_seed(D.sr_key, (uint32_t)o * (uint32_t)sizeof(typename C::T));
+        seed = sr_seed(D.sr_key, (uint32_t)(y * D.nx + x) * (uint32_t)sizeof(typename C::T));
       auto enc = [&](float v, int p) {
         if constexpr (codec_sr<C>::value)
           return C::enc_sr(v, D.s, sr_plane(seed, p));
@@ -175,8 +178,8 @@ __global__ __launch_bounds__(256) void k_step(Domain D, int tiles_x, int ry,
 #pragma unroll
       for (int k = 0; k < 2 * kQm; ++k) dst[(int64_t)(kQ + k) * D.plane + o] = enc(g[k], kQ + k);
     } else {
-      const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key};
-      update_periodic<C, FORCED, NT, NTL, FULLM>(G, src, dst, x, y, P);
+      const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key, D.row};
+      update_periodic<C, FORCED, NT, NTL, FULLM, RM>(G, src, dst, x, y, P);
     }
   }
 }
@@ -203,12 +206,12 @@ __device__ __forceinline__ void update_walled_push(const Domain &D, typename C::
   pull_node<C, true>(D, buf, x, y, d, g);
   collide<FORCED>(d, g, P);
   const Rows R = rows_of<true>(D, x, y);
-  const int own = R.r0 + x;
+  const int64_t own = R.r0 + x;
   // stochastic rounding: the bits of this node and of the population's own
   // plane, as in the two-buffer step
   uint32_t seed = 0;
   if constexpr (codec_sr<C>::value)
-    seed = sr_seed(D.sr_key, (uint32_t)own * (uint32_t)sizeof(typename C::T));
+    seed = sr_seed(D.sr_key, (uint32_t)(y * D.nx + x) * (uint32_t)sizeof(typename C::T));
   auto enc = [&](float v, int p) {
     if constexpr (codec_sr<C>::value)
       return C::enc_sr(v, D.s, sr_plane(seed, p));
@@ -219,18 +222,18 @@ __device__ __forceinline__ void update_walled_push(const Domain &D, typename C::
   for (int i = 0; i < kQ; ++i) {
     const bool out = (cy(i) > 0 && R.hi) || (cy(i) < 0 && R.lo);
     const int tx = cx(i) == 0 ? x : (cx(i) > 0 ? R.xp : R.xm);
-    const int trow = cy(i) == 0 ? R.r0 : (cy(i) > 0 ? R.rp : R.rm);
+    const int64_t trow = cy(i) == 0 ? R.r0 : (cy(i) > 0 ? R.rp : R.rm);
     const int plane = out ? i : opp_f(i);
-    const int off = out ? own : trow + tx;
+    const int64_t off = out ? own : trow + tx;
     st_el<typename C::T, NT>(&buf[(int64_t)plane * D.plane + off], enc(d[i], i));
   }
 #pragma unroll
   for (int j = 0; j < kQm; ++j) {
     const bool out = (ey(j) > 0 && R.hi) || (ey(j) < 0 && R.lo);
     const int tx = ex(j) == 0 ? x : (ex(j) > 0 ? R.xp : R.xm);
-    const int trow = ey(j) == 0 ? R.r0 : (ey(j) > 0 ? R.rp : R.rm);
+    const int64_t trow = ey(j) == 0 ? R.r0 : (ey(j) > 0 ? R.rp : R.rm);
     const int jj = out ? j : opp_g(j);
-    const int off = out ? own : trow + tx;
+    const int64_t off = out ? own : trow + tx;
     st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 0) * D.plane + off],
                              enc(g[2 * j], gplane(j, 0)));
     st_el<typename C::T, NT>(&buf[(int64_t)gplane(jj, 1) * D.plane + off],
@@ -244,7 +247,7 @@ __device__ __forceinline__ void update_walled_push(const Domain &D, typename C::
 template <class C, bool WALLS>
 __device__ __forceinline__ void own_node(const Domain &D, const typename C::T *buf, int x, int y,
                                          float (&d)[kQ], float (&g)[2 * kQm]) {
-  const int64_t o = (int64_t)y * D.nx + x;
+  const int64_t o = (int64_t)y * D.row + x;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) d[i] = C::dec(buf[(int64_t)opp_f(i) * D.plane + o], D.inv_s);
 #pragma unroll
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
-  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key};
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key, D.row};
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
@@ -293,10 +296,10 @@ __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int
         float d[kQ], g[2 * kQm];
         own_node<C, true>(D, buf, x, y, d, g);
         collide<FORCED>(d, g, P);
-        const int o = y * D.nx + x;
+        const int64_t o = (int64_t)y * D.row + x;
         uint32_t seed = 0;
         if constexpr (codec_sr<C>::value)
-          seed = sr_seed(D.sr_key, (uint32_t)o * (uint32_t)sizeof(typename C::T));
+          seed = sr_seed(D.sr_key, (uint32_t)(y * D.nx + x) * (uint32_t)sizeof(typename C::T));
         auto enc = [&](float v, int p) {
           if constexpr (codec_sr<C>::value)
             return C::enc_sr(v, D.s, sr_plane(seed, p));
@@ -324,12 +327,13 @@ __global__ void k_swapped_to_pull(Domain D, const T *__restrict__ buf, T *__rest
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= D.nx) return;
   const int64_t N = (int64_t)D.nx * D.ny, o = (int64_t)y * D.nx + x;
+  const int64_t ob = (int64_t)y * D.row + x;
   auto src_of = [&](int p, int op, int cxv, int cyv) -> T {
     int tx = x + cxv, ty = y + cyv;
     tx = tx < 0 ? tx + D.nx : (tx >= D.nx ? tx - D.nx : tx);
-    if (D.walls && (ty < 0 || ty >= D.ny)) return buf[(int64_t)p * D.plane + o];
+    if (D.walls && (ty < 0 || ty >= D.ny)) return buf[(int64_t)p * D.plane + ob];
     ty = ty < 0 ? ty + D.ny : (ty >= D.ny ? ty - D.ny : ty);
-    return buf[(int64_t)op * D.plane + (int64_t)ty * D.nx + tx];
+    return buf[(int64_t)op * D.plane + (int64_t)ty * D.row + tx];
   };
   for (int i = 0; i < kQ; ++i) dst[(int64_t)i * N + o] = src_of(i, opp_f(i), cx(i), cy(i));
   for (int j = 0; j < kQm; ++j)
@@ -383,7 +387,7 @@ __global__ void k_init(Domain D, const double *__restrict__ u,
   const int y = blockIdx.y;
   if (x >= D.nx) return;
   const int64_t N = (int64_t)D.nx * D.ny;
-  const int o = y * D.nx + x;
+  const int64_t o = (int64_t)y * D.row + x;  // stored state
   auto fld = [&](const double *a, int comp, int xx, int yy) {
     return a[comp * N + (int64_t)yy * D.nx + xx];
   };
@@ -649,18 +653,18 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_final(
   if (threadIdx.x == 0) out[2] = r;
 }
 
-// FP16 storage, periodic grid with even nx: each thread updates the node pair
-// (x, x + 1) with 32-bit plane accesses (update_periodic_pair); a workgroup
-// of bx x by threads covers 2 bx x by ry nodes.
-template <class C, bool FORCED, bool NT, bool NTL>
-__global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry, int xcd,
-                                                   const uint16_t *__restrict__ src,
-                                                   uint16_t *__restrict__ dst) {
+// Periodic grid with nx a multiple of K: each thread updates the nodes x ..
+// x + K - 1 with one word per plane (update_periodic_multi); a workgroup of
+// bx x by threads covers K bx x by ry nodes.
+template <class C, int K, bool FORCED, bool NT, bool NTL, int RM>
+__global__ __launch_bounds__(256) void k_step_multi(Domain D, int tiles_x, int ry, int xcd,
+                                                   const typename C::T *__restrict__ src,
+                                                   typename C::T *__restrict__ dst) {
   const int ntiles = gridDim.x;
   const int L = xcd == 1 ? xcd_remap(blockIdx.x, ntiles)
                          : (xcd == 2 ? xcd_local(blockIdx.x, ntiles) : (int)blockIdx.x);
   const int tx = L % tiles_x, ty = L / tiles_x;
-  const int x = 2 * (tx * blockDim.x + threadIdx.x);
+  const int x = K * (tx * blockDim.x + threadIdx.x);
   const int y0 = (ty * blockDim.y + threadIdx.y) * ry;
   if (x >= D.nx) return;
   CollideParams P;
@@ -669,11 +673,11 @@ __global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
-  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s};
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, 0u, D.row};
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
-    update_periodic_pair<C, FORCED, NT, NTL>(G, src, dst, x, y, P);
+    update_periodic_multi<C, K, FORCED, NT, NTL, RM>(G, src, dst, x, y, P);
   }
 }
 
@@ -681,16 +685,30 @@ __global__ __launch_bounds__(256) void k_step_pair(Domain D, int tiles_x, int ry
 // Host launchers
 // ---------------------------------------------------------------------------
 LaunchShape default_shape(const Domain &D) {
-  // Measured on MI355X at 8192^2 (planes 256 B apart beyond alignment):
-  // 128 x 2 for FP32 storage; for FP16 storage 128 x 1 threads with two nodes
-  // per thread on periodic grids of even width (2-4 % faster than one node
-  // per thread in the same run), else 256 x 1; plain block order,
-  // non-temporal stores.
+  // Measured on MI355X at 8192^2.  Row-interleaved planes: FP32 storage two
+  // nodes per thread (64-bit words), 128 x 2 threads; FP16 storage four nodes
+  // per thread (64-bit words), 128 x 1; both with eight neighbouring tiles
+  // per XCD (xcd = 2).  Planes of [ny][nx] (planes 256 B apart beyond
+  // alignment): 128 x 2 for FP32; for FP16 128 x 1 threads with two nodes per
+  // thread on periodic grids of even width (2-4 % faster than one node per
+  // thread in the same run), else 256 x 1; plain block order.  Non-temporal
+  // stores throughout.
   LaunchShape L;
   L.ry = 1;
   L.xcd = 0;
   L.nt = 1;
-  if (D.elem == 2 && !D.walls && D.nx % 2 == 0 && D.nx >= 512) {
+  const bool rows = D.row != D.nx && !D.walls && D.nx >= 512;
+  if (rows && D.elem == 2 && D.nx % 4 == 0) {
+    L.bx = 128;
+    L.by = 1;
+    L.xcd = 2;
+    L.nt = 9;
+  } else if (rows && D.elem == 4 && D.nx % 2 == 0) {
+    L.bx = 128;
+    L.by = 2;
+    L.xcd = 2;
+    L.nt = 5;
+  } else if (D.elem == 2 && !D.walls && D.nx % 2 == 0 && D.nx >= 512) {
     L.bx = 128;
     L.by = 1;
     L.nt = 5;
@@ -703,6 +721,34 @@ LaunchShape default_shape(const Domain &D) {
     L.by = 256 / L.bx;
   }
   return L;
+}
+
+// Every lane of a wavefront updates the same row when the workgroup's rows
+// are whole wavefronts wide or the workgroup is one row.
+static bool uniform_rows(const LaunchShape &L) { return L.bx % 64 == 0 || L.by == 1; }
+
+// Row addressing of a periodic launch: 32-bit row offsets for planes of
+// [ny][nx]; row base pointers for the row-interleaved layout, scalar when
+// every wavefront updates one row.
+static int row_mode(const Domain &D, const LaunchShape &L) {
+  if (D.row == D.nx) return RM_OFFSET;
+  return uniform_rows(L) ? RM_UNIFORM : RM_LANE;
+}
+
+template <class C, bool FORCED, bool NT, bool NTL, bool FULLM>
+static void launch_periodic(const Domain &D, const typename C::T *s, typename C::T *d,
+                            const LaunchShape &L, dim3 grid, dim3 block, int tiles_x,
+                            hipStream_t st) {
+  switch (row_mode(D, L)) {
+    case RM_OFFSET:
+      hipLaunchKernelGGL((k_step<C, false, FORCED, NT, NTL, FULLM, RM_OFFSET>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      break;
+    case RM_UNIFORM:
+      hipLaunchKernelGGL((k_step<C, false, FORCED, NT, NTL, FULLM, RM_UNIFORM>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step<C, false, FORCED, NT, NTL, FULLM, RM_LANE>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  }
 }
 
 template <class C, bool NT, bool NTL>
@@ -722,9 +768,9 @@ static void step_nt(const Domain &D, const void *src, void *dst, const LaunchSha
       hipLaunchKernelGGL((k_step<C, true, false, NT, false>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
   } else {
     if (forced)
-      hipLaunchKernelGGL((k_step<C, false, true, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      launch_periodic<C, true, NT, NTL, false>(D, s, d, L, grid, block, tiles_x, st);
     else
-      hipLaunchKernelGGL((k_step<C, false, false, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      launch_periodic<C, false, NT, NTL, false>(D, s, d, L, grid, block, tiles_x, st);
   }
 }
 
@@ -747,25 +793,69 @@ static void step_fullm(const Domain &D, const void *src, void *dst, const Launch
       hipLaunchKernelGGL((k_step<C, true, false, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
   } else {
     if (forced)
-      hipLaunchKernelGGL((k_step<C, false, true, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      launch_periodic<C, true, true, false, true>(D, s, d, L, grid, block, tiles_x, st);
     else
-      hipLaunchKernelGGL((k_step<C, false, false, true, false, true>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+      launch_periodic<C, false, true, false, true>(D, s, d, L, grid, block, tiles_x, st);
   }
 }
 
-template <class C, bool NT, bool NTL>
-static void step_pair_nt(const Domain &D, const void *src, void *dst, const LaunchShape &L,
-                         hipStream_t st) {
-  const int tiles_x = (D.nx / 2 + L.bx - 1) / L.bx;
+template <class C, int K, bool NT, bool NTL>
+static void step_multi_nt(const Domain &D, const void *src, void *dst, const LaunchShape &L,
+                          hipStream_t st) {
+  const int tiles_x = (D.nx / K + L.bx - 1) / L.bx;
   const int rows_per_tile = L.by * L.ry;
   const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
   const dim3 grid(tiles_x * tiles_y), block(L.bx, L.by);
-  auto s = (const uint16_t *)src;
-  auto d = (uint16_t *)dst;
-  if (D.Gx != 0.0f || D.Gy != 0.0f)
-    hipLaunchKernelGGL((k_step_pair<C, true, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  auto s = (const typename C::T *)src;
+  auto d = (typename C::T *)dst;
+  const bool forced = D.Gx != 0.0f || D.Gy != 0.0f;
+  // multi-node launches on row-interleaved planes require whole-row
+  // wavefronts (multi_nodes), so the modes here are RM_OFFSET and RM_UNIFORM
+  if (D.row == D.nx) {
+    if (forced)
+      hipLaunchKernelGGL((k_step_multi<C, K, true, NT, NTL, RM_OFFSET>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    else
+      hipLaunchKernelGGL((k_step_multi<C, K, false, NT, NTL, RM_OFFSET>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  } else {
+    if (forced)
+      hipLaunchKernelGGL((k_step_multi<C, K, true, NT, NTL, RM_UNIFORM>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    else
+      hipLaunchKernelGGL((k_step_multi<C, K, false, NT, NTL, RM_UNIFORM>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+  }
+}
+
+template <class C, int K>
+static void step_multi(const Domain &D, const void *src, void *dst, const LaunchShape &L,
+                       hipStream_t st) {
+  const bool nts = L.nt & 1, ntl = (L.nt & 2) != 0;
+  if (nts && ntl)
+    step_multi_nt<C, K, true, true>(D, src, dst, L, st);
+  else if (nts)
+    step_multi_nt<C, K, true, false>(D, src, dst, L, st);
+  else if (ntl)
+    step_multi_nt<C, K, false, true>(D, src, dst, L, st);
   else
-    hipLaunchKernelGGL((k_step_pair<C, false, NT, NTL>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, s, d);
+    step_multi_nt<C, K, false, false>(D, src, dst, L, st);
+}
+
+// Nodes per thread of a periodic launch (1 when no multi-node form applies).
+// nt bit 2: two nodes (FP16 storage on either layout; FP32 storage on
+// row-interleaved planes: on planes of [ny][nx] its 64-bit words measured
+// slower than one node per thread); nt bit 3: four nodes (FP16 storage, 64-bit
+// words).  Round-to-nearest codecs only, nx a multiple of the count, and on
+// row-interleaved planes whole-row wavefronts.
+template <class C>
+static int multi_nodes(const Domain &D, const LaunchShape &L) {
+  if constexpr (codec_sr<C>::value) {
+    return 1;
+  } else {
+    if (!(L.nt & 12) || D.walls) return 1;
+    const bool rows = D.row != D.nx;
+    if (rows && !uniform_rows(L)) return 1;
+    if (sizeof(typename C::T) == 2 && (L.nt & 8) && D.nx % 4 == 0) return 4;
+    if ((L.nt & 4) && D.nx % 2 == 0 && (sizeof(typename C::T) == 2 || rows)) return 2;
+    return 1;
+  }
 }
 
 template <class C>
@@ -776,17 +866,17 @@ static hipError_t step_t(const Domain &D, const void *src, void *dst,
     step_fullm<C>(D, src, dst, L, st);
     return hipGetLastError();
   }
-  if constexpr (sizeof(typename C::T) == 2 && !codec_sr<C>::value) {
-    if ((L.nt & 4) && !D.walls && D.nx % 2 == 0) {
-      if (nts && ntl)
-        step_pair_nt<C, true, true>(D, src, dst, L, st);
-      else if (nts)
-        step_pair_nt<C, true, false>(D, src, dst, L, st);
-      else if (ntl)
-        step_pair_nt<C, false, true>(D, src, dst, L, st);
-      else
-        step_pair_nt<C, false, false>(D, src, dst, L, st);
+  if constexpr (!codec_sr<C>::value) {
+    const int k = multi_nodes<C>(D, L);
+    if (k == 2) {
+      step_multi<C, 2>(D, src, dst, L, st);
       return hipGetLastError();
+    }
+    if constexpr (sizeof(typename C::T) == 2) {
+      if (k == 4) {
+        step_multi<C, 4>(D, src, dst, L, st);
+        return hipGetLastError();
+      }
     }
   }
   if (nts && ntl)
@@ -803,8 +893,9 @@ static hipError_t step_t(const Domain &D, const void *src, void *dst,
 hipError_t launch_step(int storage, const Domain &D, const void *src, void *dst,
                        const LaunchShape &L, hipStream_t st) {
   if (L.bx <= 0 || L.by <= 0 || L.bx * L.by > 256 || L.ry <= 0) return hipErrorInvalidValue;
-  // byte offsets inside one plane are 32-bit
-  if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
+  // planes of [ny][nx]: byte offsets inside one plane are 32-bit (the
+  // row-interleaved layout addresses rows through 64-bit bases)
+  if (D.row == D.nx && (int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
     return hipErrorInvalidValue;
   if (storage == kF16 && D.sr) return step_t<CodecF16SR>(D, src, dst, L, st);
   if (storage == kF16)  // S = 1 (the default) needs no scaling of the stored values

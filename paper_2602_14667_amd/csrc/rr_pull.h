@@ -5,6 +5,7 @@
 // wave-uniform (scalar registers) and the in-plane position is a 32-bit byte
 // offset, so each access is one global load/store with a scalar base.
 #pragma once
+#include <type_traits>
 #include <utility>
 
 #include "rr_node.h"
@@ -12,10 +13,11 @@
 namespace rr {
 
 struct PlaneGeom {
-  int64_t plane;  // elements between plane starts
+  int64_t plane;  // elements between plane starts (within one row)
   int nx, ny;
   float s, inv_s;  // storage scale
   uint32_t sr_key = 0;  // per-step key of the stochastic-rounding codec
+  int64_t row = 0;      // elements between row starts of one plane
 };
 
 template <class T>
@@ -42,33 +44,111 @@ __device__ __forceinline__ void st_at(T *__restrict__ base, uint32_t byte_off, T
     *p = v;
 }
 
+// Row addressing of a node update (rows y - 1, y, y + 1 of a periodic grid).
+//  RM_OFFSET: one base per plane, the row as a 32-bit byte offset; for
+//    layouts whose rows all lie within 4 GiB of a plane's start (planes of
+//    [ny][nx] below 4 GiB).
+//  RM_UNIFORM: a base pointer per row with the row index wave-uniform (the
+//    caller guarantees that every lane of a wavefront updates the same row),
+//    so the bases stay in scalar registers; any layout and size.
+//  RM_LANE: a base pointer per row and lane; any layout, size and tile.
+// In every mode the in-row position is a 32-bit byte offset.
+enum { RM_OFFSET = 0, RM_UNIFORM = 1, RM_LANE = 2 };
+
+template <class T>
+struct RowAddr {
+  const T *m, *z, *p;   // plane-0 bases for the rows y - 1, y, y + 1
+  uint32_t om, oz, op;  // byte offsets added to them
+};
+
+template <int RM, class T>
+__device__ __forceinline__ RowAddr<T> row_addr(const PlaneGeom &G, const T *s, int y) {
+  if constexpr (RM == RM_UNIFORM) y = __builtin_amdgcn_readfirstlane(y);
+  const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y == G.ny - 1 ? 0 : y + 1;
+  RowAddr<T> A;
+  if constexpr (RM == RM_OFFSET) {
+    const uint32_t pitch = (uint32_t)G.row * (uint32_t)sizeof(T);
+    A.m = A.z = A.p = s;
+    A.om = ym * pitch;
+    A.oz = y * pitch;
+    A.op = yp * pitch;
+  } else {
+    A.m = s + (int64_t)ym * G.row;
+    A.z = s + (int64_t)y * G.row;
+    A.p = s + (int64_t)yp * G.row;
+    A.om = A.oz = A.op = 0;
+  }
+  return A;
+}
+
+// Where a store to row y goes: base pointer and byte offset of the row.
+template <int RM, class T>
+__device__ __forceinline__ T *row_dst(const PlaneGeom &G, T *d, int y, uint32_t &off) {
+  if constexpr (RM == RM_UNIFORM) y = __builtin_amdgcn_readfirstlane(y);
+  if constexpr (RM == RM_OFFSET) {
+    off = (uint32_t)y * (uint32_t)G.row * (uint32_t)sizeof(T);
+    return d;
+  } else {
+    off = 0;
+    return d + (int64_t)y * G.row;
+  }
+}
+
 // Population I of node (x, y) comes from (x - c_Ix, y - c_Iy).
 template <class C, int I, bool NTL>
-__device__ __forceinline__ float pull_f_per(const PlaneGeom &G,
-                                            const typename C::T *__restrict__ s,
-                                            uint32_t bm, uint32_t b0, uint32_t bp,
+__device__ __forceinline__ float pull_f_per(const PlaneGeom &G, const RowAddr<typename C::T> &A,
                                             uint32_t xm, uint32_t x0, uint32_t xp) {
   constexpr int CX = cx(I), CY = cy(I);
-  const uint32_t row = CY == 0 ? b0 : (CY > 0 ? bm : bp);
+  const typename C::T *base = CY == 0 ? A.z : (CY > 0 ? A.m : A.p);
+  const uint32_t row = CY == 0 ? A.oz : (CY > 0 ? A.om : A.op);
   const uint32_t col = CX == 0 ? x0 : (CX > 0 ? xm : xp);
-  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(s, I, G.plane), row + col), G.inv_s);
+  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(base, I, G.plane), row + col), G.inv_s);
 }
 
 template <class C, int J, int COMP, bool NTL>
-__device__ __forceinline__ float pull_g_per(const PlaneGeom &G,
-                                            const typename C::T *__restrict__ s,
-                                            uint32_t bm, uint32_t b0, uint32_t bp,
+__device__ __forceinline__ float pull_g_per(const PlaneGeom &G, const RowAddr<typename C::T> &A,
                                             uint32_t xm, uint32_t x0, uint32_t xp) {
   constexpr int EX = ex(J), EY = ey(J);
-  const uint32_t row = EY == 0 ? b0 : (EY > 0 ? bm : bp);
+  const typename C::T *base = EY == 0 ? A.z : (EY > 0 ? A.m : A.p);
+  const uint32_t row = EY == 0 ? A.oz : (EY > 0 ? A.om : A.op);
   const uint32_t col = EX == 0 ? x0 : (EX > 0 ? xm : xp);
-  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(s, gplane(J, COMP), G.plane), row + col),
+  return C::dec(ld_at<typename C::T, NTL>(plane_ptr(base, gplane(J, COMP), G.plane), row + col),
                 G.inv_s);
+}
+
+// The 19 populations of node (x, y) through the pull (periodic).
+template <class C, bool NTL>
+__device__ __forceinline__ void pull_node_per(const PlaneGeom &G, const RowAddr<typename C::T> &A,
+                                              int x, float (&d)[kQ], float (&g)[2 * kQm]) {
+  constexpr uint32_t E = sizeof(typename C::T);
+  const uint32_t x0 = x * E;
+  const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
+  const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
+  d[0] = pull_f_per<C, 0, NTL>(G, A, xm, x0, xp);
+  d[1] = pull_f_per<C, 1, NTL>(G, A, xm, x0, xp);
+  d[2] = pull_f_per<C, 2, NTL>(G, A, xm, x0, xp);
+  d[3] = pull_f_per<C, 3, NTL>(G, A, xm, x0, xp);
+  d[4] = pull_f_per<C, 4, NTL>(G, A, xm, x0, xp);
+  d[5] = pull_f_per<C, 5, NTL>(G, A, xm, x0, xp);
+  d[6] = pull_f_per<C, 6, NTL>(G, A, xm, x0, xp);
+  d[7] = pull_f_per<C, 7, NTL>(G, A, xm, x0, xp);
+  d[8] = pull_f_per<C, 8, NTL>(G, A, xm, x0, xp);
+  g[0] = pull_g_per<C, 0, 0, NTL>(G, A, xm, x0, xp);
+  g[1] = pull_g_per<C, 0, 1, NTL>(G, A, xm, x0, xp);
+  g[2] = pull_g_per<C, 1, 0, NTL>(G, A, xm, x0, xp);
+  g[3] = pull_g_per<C, 1, 1, NTL>(G, A, xm, x0, xp);
+  g[4] = pull_g_per<C, 2, 0, NTL>(G, A, xm, x0, xp);
+  g[5] = pull_g_per<C, 2, 1, NTL>(G, A, xm, x0, xp);
+  g[6] = pull_g_per<C, 3, 0, NTL>(G, A, xm, x0, xp);
+  g[7] = pull_g_per<C, 3, 1, NTL>(G, A, xm, x0, xp);
+  g[8] = pull_g_per<C, 4, 0, NTL>(G, A, xm, x0, xp);
+  g[9] = pull_g_per<C, 4, 1, NTL>(G, A, xm, x0, xp);
 }
 
 // Store the post-collision populations of one node at byte offset o of
 // every plane.  Written plane by plane (not as a loop over a running
 // pointer) so each store keeps a scalar plane base and the 32-bit offset.
+// seed: the stochastic-rounding bits of the node (unused otherwise).
 template <class C, bool NT, int P>
 __device__ __forceinline__ void store_plane(const PlaneGeom &G, typename C::T *__restrict__ dst,
                                             uint32_t o, uint32_t seed, const float *d,
@@ -86,52 +166,37 @@ __device__ __forceinline__ void store_planes_seq(const PlaneGeom &G,
                                                  std::integer_sequence<int, P...>) {
   (store_plane<C, NT, P>(G, dst, o, seed, d, g), ...);
 }
-template <class C, bool NT>
-__device__ __forceinline__ void store_planes(const PlaneGeom &G, typename C::T *__restrict__ dst,
-                                             uint32_t o, const float *d, const float *g) {
-  uint32_t seed = 0;
-  if constexpr (codec_sr<C>::value) seed = sr_seed(G.sr_key, o);
-  store_planes_seq<C, NT>(G, dst, o, seed, d, g, std::make_integer_sequence<int, kPlanes>{});
+// The random bits of the stochastic-rounding codec are keyed by the node's
+// position (y nx + x) in bytes of the stored type, whatever the layout.
+template <class C>
+__device__ __forceinline__ uint32_t node_seed(const PlaneGeom &G, int x, int y) {
+  if constexpr (codec_sr<C>::value)
+    return sr_seed(G.sr_key, ((uint32_t)y * (uint32_t)G.nx + (uint32_t)x) *
+                                 (uint32_t)sizeof(typename C::T));
+  else
+    return 0;
+}
+template <class C, bool NT, int RM>
+__device__ __forceinline__ void store_node(const PlaneGeom &G, typename C::T *__restrict__ dst,
+                                           int x, int y, const float *d, const float *g) {
+  uint32_t off;
+  typename C::T *base = row_dst<RM>(G, dst, y, off);
+  store_planes_seq<C, NT>(G, base, off + (uint32_t)x * (uint32_t)sizeof(typename C::T),
+                          node_seed<C>(G, x, y), d, g,
+                          std::make_integer_sequence<int, kPlanes>{});
 }
 
 // Pull, collide and store one node of a doubly periodic domain.  src/dst
 // point at plane 0 of the domain's two buffers.
-template <class C, bool FORCED, bool NT, bool NTL, bool FULLM = false>
+template <class C, bool FORCED, bool NT, bool NTL, bool FULLM = false, int RM = RM_OFFSET>
 __device__ __forceinline__ void update_periodic(const PlaneGeom &G,
                                                 const typename C::T *__restrict__ src,
                                                 typename C::T *__restrict__ dst, int x,
                                                 int y, const CollideParams &P) {
-  using T = typename C::T;
-  constexpr uint32_t E = sizeof(T);
-  const uint32_t pitch = G.nx * E;
-  const uint32_t x0 = x * E;
-  const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
-  const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
-  const uint32_t b0 = y * pitch;
-  const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
-  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
   float d[kQ], g[2 * kQm];
-  d[0] = pull_f_per<C, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[1] = pull_f_per<C, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[2] = pull_f_per<C, 2, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[3] = pull_f_per<C, 3, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[4] = pull_f_per<C, 4, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[5] = pull_f_per<C, 5, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[6] = pull_f_per<C, 6, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[7] = pull_f_per<C, 7, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  d[8] = pull_f_per<C, 8, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[0] = pull_g_per<C, 0, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[1] = pull_g_per<C, 0, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[2] = pull_g_per<C, 1, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[3] = pull_g_per<C, 1, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[4] = pull_g_per<C, 2, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[5] = pull_g_per<C, 2, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[6] = pull_g_per<C, 3, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[7] = pull_g_per<C, 3, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[8] = pull_g_per<C, 4, 0, NTL>(G, src, bm, b0, bp, xm, x0, xp);
-  g[9] = pull_g_per<C, 4, 1, NTL>(G, src, bm, b0, bp, xm, x0, xp);
+  pull_node_per<C, NTL>(G, row_addr<RM>(G, src, y), x, d, g);
   collide<FORCED, NoCorrection, FULLM>(d, g, P);
-  store_planes<C, NT>(G, dst, b0 + x0, d, g);
+  store_node<C, NT, RM>(G, dst, x, y, d, g);
 }
 
 // ---- single-buffer (in-place) streaming --------------------------------------
@@ -165,34 +230,14 @@ __device__ __forceinline__ void update_periodic_push(const PlaneGeom &G, typenam
                                                      int x, int y, const CollideParams &P) {
   using T = typename C::T;
   constexpr uint32_t E = sizeof(T);
-  const uint32_t pitch = G.nx * E;
+  // single-buffer handles keep planes of [ny][nx] (row == nx), below 4 GiB
+  const RowAddr<T> A = row_addr<RM_OFFSET>(G, (const T *)buf, y);
+  const uint32_t b0 = A.oz, bm = A.om, bp = A.op;
   const uint32_t x0 = x * E;
   const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
   const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
-  const uint32_t b0 = y * pitch;
-  const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
-  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
-  const T *src = buf;
   float d[kQ], g[2 * kQm];
-  d[0] = pull_f_per<C, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[1] = pull_f_per<C, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[2] = pull_f_per<C, 2, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[3] = pull_f_per<C, 3, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[4] = pull_f_per<C, 4, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[5] = pull_f_per<C, 5, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[6] = pull_f_per<C, 6, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[7] = pull_f_per<C, 7, false>(G, src, bm, b0, bp, xm, x0, xp);
-  d[8] = pull_f_per<C, 8, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[0] = pull_g_per<C, 0, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[1] = pull_g_per<C, 0, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[2] = pull_g_per<C, 1, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[3] = pull_g_per<C, 1, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[4] = pull_g_per<C, 2, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[5] = pull_g_per<C, 2, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[6] = pull_g_per<C, 3, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[7] = pull_g_per<C, 3, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[8] = pull_g_per<C, 4, 0, false>(G, src, bm, b0, bp, xm, x0, xp);
-  g[9] = pull_g_per<C, 4, 1, false>(G, src, bm, b0, bp, xm, x0, xp);
+  pull_node_per<C, false>(G, A, x, d, g);
   collide<FORCED>(d, g, P);
   // f*_i(x) -> buf[opp(i)][x + c_i]: the slot read for direction opp(i)
   auto at = [&](int cxv, int cyv) {
@@ -241,7 +286,7 @@ template <class C, bool FORCED, bool NT>
 __device__ __forceinline__ void update_periodic_own(const PlaneGeom &G, typename C::T *buf,
                                                     int x, int y, const CollideParams &P) {
   constexpr uint32_t E = sizeof(typename C::T);
-  const uint32_t o = y * (G.nx * E) + x * E;
+  const uint32_t o = y * ((uint32_t)G.row * E) + x * E;  // row == nx (planes of [ny][nx])
   const typename C::T *src = buf;
   float d[kQ], g[2 * kQm];
   d[0] = ld_own<C, opp_f(0)>(G, src, o);
@@ -264,90 +309,119 @@ __device__ __forceinline__ void update_periodic_own(const PlaneGeom &G, typename
   g[8] = ld_own<C, gplane(opp_g(4), 0)>(G, src, o);
   g[9] = ld_own<C, gplane(opp_g(4), 1)>(G, src, o);
   collide<FORCED>(d, g, P);
-  store_planes<C, NT>(G, buf, o, d, g);
+  store_node<C, NT, RM_OFFSET>(G, buf, x, y, d, g);
 }
 
-// ---- 16-bit storage, two neighbouring nodes per thread -----------------------
-// Nodes (x, x + 1), x even, nx even: every plane moves as one 32-bit word per
-// thread (low half node x, high half node x + 1), which halves the memory
-// instructions per byte of the 2-byte codec.  The planes shifted by +-1 in x
-// read the word at an odd 16-bit position (gfx950 loads unaligned global
-// words natively); at the periodic seam (x = 0 for c_x = +1, x = nx - 2 for
-// c_x = -1) the two halves come from opposite ends of the row and are read
-// separately.
-template <int CX, bool NTL>
-__device__ __forceinline__ uint32_t ld_pair(const uint16_t *__restrict__ plane, uint32_t row,
-                                            int x, int nx) {
-  if (CX == 0) return ld_at<uint32_t, NTL>((const uint32_t *)plane, row + 2u * x);
+// ---- K neighbouring nodes per thread -------------------------------------------
+// Nodes x .. x + K - 1 (x a multiple of K, nx a multiple of K): every plane
+// moves as one word of K stored values per thread (element k: node x + k) --
+// two 16-bit values in a 32-bit word or four in a 64-bit word for FP16
+// storage, two FP32 values in a 64-bit word -- which divides the memory
+// instructions per byte by K.  The planes shifted by +-1 in x read the word
+// at an odd element position (gfx950 loads unaligned global words natively);
+// at the periodic seam (x = 0 for c_x = +1, x = nx - K for c_x = -1) the
+// word's elements come from both ends of the row and are read one by one.
+// Each node's post-collision values replace its own elements of the loaded
+// words, so the per-node arithmetic and results are those of one node per
+// thread.
+template <class T, int K>
+struct NodeWord {
+  static_assert(K * sizeof(T) == 4 || K * sizeof(T) == 8, "32- or 64-bit words");
+  using W = std::conditional_t<K * sizeof(T) == 4, uint32_t, uint64_t>;
+  using U = std::conditional_t<sizeof(T) == 2, uint16_t, uint32_t>;
+  static constexpr int kBits = 8 * sizeof(T);
+  __device__ __forceinline__ static T get(W w, int k) { return bits((U)(w >> (k * kBits))); }
+  __device__ __forceinline__ static W put(W w, int k, T t) {
+    const W m = (W)(U)~(U)0 << (k * kBits);
+    return (w & ~m) | ((W)ubits(t) << (k * kBits));
+  }
+  __device__ __forceinline__ static T bits(U u) {
+    T t;
+    __builtin_memcpy(&t, &u, sizeof(T));
+    return t;
+  }
+  __device__ __forceinline__ static U ubits(T t) {
+    U u;
+    __builtin_memcpy(&u, &t, sizeof(T));
+    return u;
+  }
+};
+
+template <int CX, bool NTL, int K, class T>
+__device__ __forceinline__ typename NodeWord<T, K>::W ld_word(const T *__restrict__ plane,
+                                                              uint32_t row, int x, int nx) {
+  using NW = NodeWord<T, K>;
+  using W = typename NW::W;
+  constexpr uint32_t E = sizeof(T);
+  if (CX == 0) return ld_at<W, NTL>((const W *)plane, row + E * x);
+  const bool seam = CX > 0 ? x == 0 : x == nx - K;
   // first source node, kept inside the row so the word is always in bounds
-  const int xs = CX > 0 ? (x > 0 ? x - 1 : 0) : (x + 1 < nx - 1 ? x + 1 : nx - 2);
-  uint32_t w = ld_at<uint32_t, NTL>((const uint32_t *)plane, row + 2u * xs);
-  if (CX > 0 ? x == 0 : x == nx - 2) {
-    // the pair straddles the seam: (nx - 1, 0) in both cases
-    const uint32_t lo = ld_at<uint16_t, NTL>(plane, row + 2u * (nx - 1));
-    const uint32_t hi = ld_at<uint16_t, NTL>(plane, row);
-    w = lo | (hi << 16);
+  const int xs = CX > 0 ? (seam ? 0 : x - 1) : (seam ? nx - K : x + 1);
+  W w = ld_at<W, NTL>((const W *)plane, row + E * xs);
+  if (seam) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      int xx = x - CX + k;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      w = NW::put(w, k, ld_at<T, NTL>(plane, row + E * xx));
+    }
   }
   return w;
 }
 
-// Store plane P's word: node x's value (the low half already encoded in
-// lo[P]) and node x + 1's from its post-collision arrays.
-template <class C, bool NT, int P>
-__device__ __forceinline__ void store_pair_plane(const PlaneGeom &G, uint16_t *__restrict__ dst,
-                                                 uint32_t o, const uint16_t *lo, const float *d,
-                                                 const float *g) {
-  const float v = P < kQ ? d[P] : g[P - kQ];
-  st_at<uint32_t, NT>((uint32_t *)(dst + (int64_t)P * G.plane), o,
-                      (uint32_t)lo[P] | ((uint32_t)C::enc(v, G.s) << 16));
+template <class C, bool NT, int K, int P>
+__device__ __forceinline__ void store_word(const PlaneGeom &G, typename C::T *__restrict__ dst,
+                                           uint32_t o, const typename NodeWord<typename C::T, K>::W *w) {
+  using W = typename NodeWord<typename C::T, K>::W;
+  st_at<W, NT>((W *)(dst + (int64_t)P * G.plane), o, w[P]);
 }
-template <class C, bool NT, int... P>
-__device__ __forceinline__ void store_pair_planes(const PlaneGeom &G, uint16_t *__restrict__ dst,
-                                                  uint32_t o, const uint16_t *lo, const float *d,
-                                                  const float *g,
-                                                  std::integer_sequence<int, P...>) {
-  (store_pair_plane<C, NT, P>(G, dst, o, lo, d, g), ...);
+template <class C, bool NT, int K, int... P>
+__device__ __forceinline__ void store_words(const PlaneGeom &G, typename C::T *__restrict__ dst,
+                                            uint32_t o,
+                                            const typename NodeWord<typename C::T, K>::W *w,
+                                            std::integer_sequence<int, P...>) {
+  (store_word<C, NT, K, P>(G, dst, o, w), ...);
 }
 
-// C: a 16-bit codec (CodecF16 or CodecF16U).
-template <class C, bool FORCED, bool NT, bool NTL>
-__device__ __forceinline__ void update_periodic_pair(const PlaneGeom &G,
-                                                     const uint16_t *__restrict__ src,
-                                                     uint16_t *__restrict__ dst, int x, int y,
-                                                     const CollideParams &P) {
-  const uint32_t pitch = G.nx * 2u;
-  const uint32_t b0 = y * pitch;
-  const uint32_t bm = (y == 0 ? G.ny - 1 : y - 1) * pitch;
-  const uint32_t bp = (y == G.ny - 1 ? 0 : y + 1) * pitch;
-  uint32_t w[kPlanes];
-  auto rowf = [&](int cyv) { return cyv == 0 ? b0 : (cyv > 0 ? bm : bp); };
-#define RR_LDF(I) w[I] = ld_pair<cx(I), NTL>(plane_ptr(src, I, G.plane), rowf(cy(I)), x, G.nx)
-#define RR_LDG(J, K) \
-  w[gplane(J, K)] = ld_pair<ex(J), NTL>(plane_ptr(src, gplane(J, K), G.plane), rowf(ey(J)), x, G.nx)
+// C: a codec without stochastic rounding (FP32, CodecF16 or CodecF16U).
+template <class C, int K, bool FORCED, bool NT, bool NTL, int RM = RM_OFFSET>
+__device__ __forceinline__ void update_periodic_multi(const PlaneGeom &G,
+                                                      const typename C::T *__restrict__ src,
+                                                      typename C::T *__restrict__ dst, int x,
+                                                      int y, const CollideParams &P) {
+  using T = typename C::T;
+  using NW = NodeWord<T, K>;
+  const RowAddr<T> A = row_addr<RM>(G, src, y);
+  typename NW::W w[kPlanes];
+  auto base = [&](int cyv) { return cyv == 0 ? A.z : (cyv > 0 ? A.m : A.p); };
+  auto rowf = [&](int cyv) { return cyv == 0 ? A.oz : (cyv > 0 ? A.om : A.op); };
+#define RR_LDF(I) \
+  w[I] = ld_word<cx(I), NTL, K>(plane_ptr(base(cy(I)), I, G.plane), rowf(cy(I)), x, G.nx)
+#define RR_LDG(J, K2)                                                                    \
+  w[gplane(J, K2)] = ld_word<ex(J), NTL, K>(plane_ptr(base(ey(J)), gplane(J, K2), G.plane), \
+                                            rowf(ey(J)), x, G.nx)
   RR_LDF(0); RR_LDF(1); RR_LDF(2); RR_LDF(3); RR_LDF(4); RR_LDF(5); RR_LDF(6); RR_LDF(7); RR_LDF(8);
   RR_LDG(0, 0); RR_LDG(0, 1); RR_LDG(1, 0); RR_LDG(1, 1); RR_LDG(2, 0); RR_LDG(2, 1);
   RR_LDG(3, 0); RR_LDG(3, 1); RR_LDG(4, 0); RR_LDG(4, 1);
 #undef RR_LDF
 #undef RR_LDG
-  // node x (low halves), then node x + 1 (high halves)
-  float d[kQ], g[2 * kQm];
-  uint16_t lo[kPlanes];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) d[i] = C::dec((uint16_t)(w[i] & 0xffffu), G.inv_s);
+  for (int k = 0; k < K; ++k) {
+    float d[kQ], g[2 * kQm];
 #pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k) g[k] = C::dec((uint16_t)(w[kQ + k] & 0xffffu), G.inv_s);
-  collide<FORCED>(d, g, P);
+    for (int i = 0; i < kQ; ++i) d[i] = C::dec(NW::get(w[i], k), G.inv_s);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) lo[i] = C::enc(d[i], G.s);
+    for (int m = 0; m < 2 * kQm; ++m) g[m] = C::dec(NW::get(w[kQ + m], k), G.inv_s);
+    collide<FORCED>(d, g, P);
 #pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k) lo[kQ + k] = C::enc(g[k], G.s);
+    for (int i = 0; i < kQ; ++i) w[i] = NW::put(w[i], k, C::enc(d[i], G.s));
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) d[i] = C::dec((uint16_t)(w[i] >> 16), G.inv_s);
-#pragma unroll
-  for (int k = 0; k < 2 * kQm; ++k) g[k] = C::dec((uint16_t)(w[kQ + k] >> 16), G.inv_s);
-  collide<FORCED>(d, g, P);
-  store_pair_planes<C, NT>(G, dst, b0 + 2u * x, lo, d, g,
-                           std::make_integer_sequence<int, kPlanes>{});
+    for (int m = 0; m < 2 * kQm; ++m) w[kQ + m] = NW::put(w[kQ + m], k, C::enc(g[m], G.s));
+  }
+  uint32_t off;
+  T *out = row_dst<RM>(G, dst, y, off);
+  store_words<C, NT, K>(G, out, off + (uint32_t)sizeof(T) * x, w,
+                        std::make_integer_sequence<int, kPlanes>{});
 }
 
 }  // namespace rr

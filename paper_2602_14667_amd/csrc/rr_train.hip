@@ -571,7 +571,7 @@ __global__ void k_impose_fluid(PlaneGeom G, const double *__restrict__ rho,
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= G.nx) return;
   const int64_t N = (int64_t)G.nx * G.ny;
-  const int64_t o = (int64_t)y * G.nx + x;
+  const int64_t o = (int64_t)y * G.row + x;  // stored state
   for (int i = 0; i < 9; ++i) {
     int tx = x + rr::cx(i), ty = y + rr::cy(i);
     tx = tx < 0 ? tx + G.nx : (tx >= G.nx ? tx - G.nx : tx);
@@ -590,7 +590,7 @@ extern "C" RR_HIDDEN int rr_launch_impose_fluid(int storage, const rr::Domain *D
                                                 const double *rho, const double *j,
                                                 const double *b, hipStream_t st) {
   const dim3 block(64), grid((D->nx + 63) / 64, D->ny);
-  const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s};
+  const rr::PlaneGeom G{D->plane, D->nx, D->ny, D->s, D->inv_s, 0u, D->row};
   if (storage == rr::kF16)
     hipLaunchKernelGGL(rr::k_impose_fluid<rr::CodecF16>, grid, block, 0, st, G, rho, j, b,
                        (uint16_t *)dst);

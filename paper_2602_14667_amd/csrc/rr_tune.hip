@@ -163,7 +163,9 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
   cache_path = cache_file(cache_path);
   auto cache = read_cache(cache_path);
   const bool inplace = rr_handle_inplace(h) != 0;
-  const std::string key = key_of(inplace ? "step_inplace" : "step", nx, ny, storage);
+  const bool rows = rr_handle_rows(h) != 0;  // row-interleaved planes
+  const std::string key =
+      key_of(inplace ? "step_inplace" : (rows ? "step_rows" : "step"), nx, ny, storage);
   Entry best;
   auto it = cache.find(key);
   if (it != cache.end()) {
@@ -184,19 +186,25 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
     } else {
       rc = rrmhd_load_state(h, save, nb, 0);
     }
-    // nt = 5: non-temporal stores and, for FP16 storage on periodic grids
-    // with even nx, two nodes per thread
+    // nt = 5: non-temporal stores and, on periodic grids with even nx, two
+    // nodes per thread (FP16 storage; FP32 storage on row-interleaved planes)
+    // nt = 9: non-temporal stores and four nodes per thread (FP16 storage,
+    // nx a multiple of 4)
     const Shape cands[] = {{256, 1, 0, 1}, {128, 2, 0, 1}, {64, 4, 0, 1}, {128, 1, 0, 1},
                            {64, 1, 0, 1},  {32, 8, 0, 1},  {256, 1, 2, 1}, {128, 2, 2, 1},
                            {64, 4, 2, 1},  {128, 1, 0, 5}, {128, 2, 0, 5}, {64, 4, 0, 5},
-                           {256, 1, 0, 5}, {64, 2, 0, 5}};
-    const bool pair_ok =
-        storage == RRMHD_STORE_F16 && nx % 2 == 0 && !rr_handle_walls(h) && !inplace;
+                           {256, 1, 0, 5}, {64, 2, 0, 5},  {128, 2, 2, 5}, {64, 4, 2, 5},
+                           {128, 1, 0, 9}, {128, 1, 2, 9}, {256, 1, 0, 9}, {128, 2, 0, 9}};
+    const bool pair_ok = (storage == RRMHD_STORE_F16 || rows) && nx % 2 == 0 &&
+                         !rr_handle_walls(h) && !inplace;
+    const bool quad_ok =
+        storage == RRMHD_STORE_F16 && nx % 4 == 0 && !rr_handle_walls(h) && !inplace;
     best.ms = 1e30;
     for (const Shape &c : cands) {
       if (rc != RRMHD_OK) break;
       if ((c.nt & 4) && !pair_ok) continue;
-      const int span = (c.nt & 4) ? 2 * c.bx : c.bx;  // nodes per workgroup row
+      if ((c.nt & 8) && !quad_ok) continue;
+      const int span = (c.nt & 8) ? 4 * c.bx : ((c.nt & 4) ? 2 * c.bx : c.bx);  // nodes per row
       if (span > 64 && span / 2 >= nx) continue;      // mostly idle lanes
       rc = rrmhd_set_launch(h, c.bx, c.by, 1, c.xcd, c.nt);
       if (rc != RRMHD_OK) break;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librrmhd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6
-STORE_F32, STORE_F16, STORE_INPLACE = 0, 1, 0x100
+STORE_F32, STORE_F16, STORE_INPLACE, STORE_PLANAR = 0, 1, 0x100, 0x200
 STORE_F16_SR = 2
 BC_PERIODIC, BC_WALLS_Y = 0, 1
 FEQ_ALGORITHM, FEQ_FULL_MAXWELL = 0, 1
@@ -272,18 +272,22 @@ class Solver:
     equilibrium: "algorithm" (the method's) or "full_maxwell" (ablation with
     the u.M cross terms of the third and fourth orders).
     inplace: one population buffer instead of two (single-buffer streaming).
+    layout: "default" (row-interleaved planes for periodic two-buffer
+    handles) or "planar" (planes of [ny][nx]); results are the same.
     """
 
     def __init__(self, nx, ny, tau_f, tau_m, storage="f32", walls=False,
                  force=(0.0, 0.0), b_wall=(0.0, 0.0), codec_scale=0.0,
-                 stream=None, equilibrium="algorithm", inplace=False):
+                 stream=None, equilibrium="algorithm", inplace=False, layout="default"):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.storage = storage
         self._stream = _own_stream(stream)
         kind = {"f32": STORE_F32, "f16": STORE_F16, "f16sr": STORE_F16_SR}[storage]
-        g = Grid(self.nx, self.ny, kind | (STORE_INPLACE if inplace else 0),
-                 float(codec_scale))
+        if layout not in ("default", "planar"):
+            raise ValueError(f"layout must be 'default' or 'planar', not {layout!r}")
+        flags = (STORE_INPLACE if inplace else 0) | (STORE_PLANAR if layout == "planar" else 0)
+        g = Grid(self.nx, self.ny, kind | flags, float(codec_scale))
         bc = BC(BC_WALLS_Y if walls else BC_PERIODIC,
                 (ctypes.c_double * 2)(*force), (ctypes.c_double * 2)(*b_wall))
         h = ctypes.c_void_p()

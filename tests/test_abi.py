@@ -111,7 +111,7 @@ def test_null_handle_calls_are_rejected():
 
 def test_create_rejects_unknown_storage_flags():
     L = rrmhd.lib()
-    for storage in (0x200, 0x101 | 0x400, 3, 0x104):  # 0x104: unknown kind with one buffer
+    for storage in (0x400, 0x101 | 0x400, 3, 0x104, 0x800 | 0x200):  # 0x104: unknown kind with one buffer
         g = rrmhd.Grid(4, 4, storage, 0.0)
         h = ctypes.c_void_p()
         assert L.rrmhd_create(ctypes.byref(g), 0.6, 0.6, None, None,

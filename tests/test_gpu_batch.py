@@ -180,7 +180,8 @@ def test_autotune_preserves_state_and_caches(tmp_path):
     import json
     with open(cache) as fh:
         entries = json.load(fh)
-    assert any(k.endswith(f"/step/{n}x{n}/f32") for k in entries)
+    # periodic two-buffer handles keep row-interleaved planes: their own key
+    assert any(k.endswith(f"/step_rows/{n}x{n}/f32") for k in entries)
     # a second handle takes the cached entry
     again = c.autotune(cache, trials=5)
     assert (again["bx"], again["by"], again["xcd"]) == (best["bx"], best["by"],
