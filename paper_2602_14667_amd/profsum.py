@@ -144,9 +144,9 @@ def inplace_summary(prof, out, n):
             "Commands (from the repository root, on the MI355X host; calibration runs as for the "
             "two-buffer step summaries):",
             "```",
-            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/ip_stats_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 50 --warmup 6 --no-cpu-baseline",
-            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/ip_pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 6 --warmup 2 --no-cpu-baseline",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/ip_pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 6 --warmup 2 --no-cpu-baseline",
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d {prof}/ip_stats_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 50 --warmup 6 --no-cpu-baseline --no-f16-leg --no-ensemble-leg",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {prof}/ip_pmc_FETCH_SIZE_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 6 --warmup 2 --no-cpu-baseline --no-f16-leg --no-ensemble-leg",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {prof}/ip_pmc_WRITE_SIZE_{st} -o run -- python3 bench.py --storage {st} --inplace --steps 6 --warmup 2 --no-cpu-baseline --no-f16-leg --no-ensemble-leg",
             f"python -m paper_2602_14667_amd.profsum inplace {prof} profiles {n}",
             "```",
             "",
