@@ -256,14 +256,16 @@ def closure_summary(prof, out, n):
     fac = _calibration(prof)
     stats = kernel_stats(os.path.join(prof, "cl_stats"))
     cl = [k for k in stats if "k_step_closure" in k][0]
-    pl = [k for k in stats if "k_step<" in k][0]
+    # the plain step: one node per thread or the multi-node form
+    pl = [k for k in stats if "k_step<" in k or "k_step_multi<" in k][0]
+    m_pl = "k_step_multi<" if "k_step_multi<" in pl else "k_step<"
     t_cl, t_pl = stats[cl]["avg_ns"], stats[pl]["avg_ns"]
     rd = counter_mean(os.path.join(prof, "cl_pmc_FETCH_SIZE"), "k_step_closure") * 1024 * fac["FETCH_SIZE"]
     wr = counter_mean(os.path.join(prof, "cl_pmc_WRITE_SIZE"), "k_step_closure") * 1024 * fac["WRITE_SIZE"]
     sq = os.path.join(prof, "cl_pmc_sq")
     ctr = {}
     for kern, tag in ((cl, "closure"), (pl, "plain")):
-        m = "k_step_closure" if tag == "closure" else "k_step<"
+        m = "k_step_closure" if tag == "closure" else m_pl
         ctr[tag] = {c: counter_mean_named(sq, m, c) for c in (
             "SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU",
             "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT",
@@ -320,11 +322,11 @@ def closure_summary(prof, out, n):
         c = ctr[tag]
         if None in c.values():
             continue
-        per = 64 / nodes  # wave instructions -> instructions per lane (one node per lane)
+        per = 64 / nodes  # wave instructions -> lane instructions per node
         simd_cyc = simds * t * 1e-9 * clk
         cu_cyc = cus * t * 1e-9 * clk
         lines.append(
-            f"* {tag}: per lane (each lane updates one node) {c['SQ_INSTS_VALU'] * per:.0f} VALU, "
+            f"* {tag}: per node {c['SQ_INSTS_VALU'] * per:.0f} VALU, "
             f"{c['SQ_INSTS_MFMA'] * per:.1f} MFMA and {c['SQ_INSTS_LDS'] * per:.0f} LDS instructions "
             f"({c['SQ_WAVES']:.0f} waves); VALU busy {100 * 4 * c['SQ_ACTIVE_INST_VALU'] / simd_cyc:.0f} %, "
             f"MFMA busy {100 * c['SQ_VALU_MFMA_BUSY_CYCLES'] / simd_cyc:.0f} %, LDS active "
