@@ -69,8 +69,10 @@ enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
 /* RRMHD_STORE_F16_SR: FP16 storage whose step stores round stochastically
  * (each value goes to one of its two FP16 neighbours, away from zero with
  * probability equal to its distance from the neighbour toward zero in units
- * of the gap, exactly for magnitudes >= 2^-32; smaller ones store zero, and
- * results beyond the FP16 range, NaN included, store infinity),
+ * of the gap -- exactly in FP16's normal range, to 2^-13 of the gap for
+ * subnormal results, magnitudes below 2^-37 storing zero -- results beyond
+ * the FP16 range store infinity and NaN a quiet NaN; the rule is written
+ * out at rrmhd_sr_encode),
  * with random bits from a counter-based hash of the step count, the node
  * and the plane, so runs are reproducible and independent of the launch
  * shape.  An optional variant of the prescribed round-to-nearest-even
@@ -513,6 +515,17 @@ int rrmhd_batch_autotune(rrmhd_batch *b, const char *cache_path, int trials);
  * and to calibrate memory-traffic counters against a known byte count. */
 int rrmhd_bandwidth_probe(void *dst, const void *src, int64_t bytes,
                           void *hip_stream);
+
+/* The encode of RRMHD_STORE_F16_SR on arrays (device memory, codec scale 1):
+ * out[i] = the FP16 bit pattern of x[i] rounded stochastically with the 32
+ * random bits r[i] -- with e the biased FP32 exponent of x and m its 24-bit
+ * significand, d = max(126 - e, 13) dropped bits, the dropped fraction kept
+ * to 13 bits, t = floor(m 2^(13-d)), and the kept integer k = floor((t + r_13)
+ * 2^-13) with r_13 the top 13 bits of r; past the largest finite value
+ * infinity, NaN a quiet NaN of its sign and the top ten payload bits.  For callers that check the codec (tests).  n >= 0;
+ * asynchronous on hip_stream. */
+int rrmhd_sr_encode(const float *x, const uint32_t *r, uint16_t *out, int64_t n,
+                    void *hip_stream);
 
 const char *rrmhd_strerror(int code);
 const char *rrmhd_last_error_detail(void);

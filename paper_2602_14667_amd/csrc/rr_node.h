@@ -111,18 +111,20 @@ struct CodecF16U {
 // (a counter-based hash of step, node and plane).  Decoding and the plain
 // encode (used at initialisation) are those of CodecF16.
 //
-// The rounding is done on the FP32 bit pattern, where magnitudes are ordered
-// as integers.  With e the biased FP32 exponent and m the significand with
-// its leading one, the FP16 grid below |x| has spacing 2^(e-150+d) where
-// d = max(126 - e, 13) bits of m are dropped (13 in FP16's normal range,
-// more below 2^-14 where the grid is 2^-24).  Adding d random bits before the
-// shift carries into the kept part with probability (dropped bits) / 2^d,
-// the exact probability.  The kept integer k is the FP16 pattern less the
-// exponent field ((e - 113) << 10 for normal values, nothing for subnormals:
-// 1024 <= k <= 2048 in the normal range, and k = 1024 is the smallest normal
-// 2^-14 where a subnormal rounds up).  d is clamped at 31: magnitudes below
-// 2^-32 give zero.  Results past the largest finite value, and NaN, saturate
-// to infinity.
+// With e the biased FP32 exponent of x = v s and m its significand with the
+// leading one (24 bits), the FP16 grid below |x| has spacing 2^(e-150+d)
+// where d = max(126 - e, 13) bits of m are dropped (13 in FP16's normal
+// range, more below 2^-14 where the grid is 2^-24).  The dropped fraction is
+// kept to 13 bits, t = floor(m 2^(13-d)), and the kept integer is
+// k = floor((t + r_13) 2^-13) with r_13 the top 13 of the 32 random bits: the
+// carry happens with probability equal to the dropped fraction -- exactly in
+// FP16's normal range, to 2^-13 of the 2^-24 grid below (toward zero), and
+// magnitudes below 2^-37 store zero.  k is the FP16 pattern less the
+// exponent field ((e - 113) << 10 for normal values, nothing for
+// subnormals).  Results past the largest finite value store infinity; NaN
+// stores a quiet NaN of the same sign and the top ten payload bits.  gfx950
+// performs this conversion in one instruction (v_cvt_sr_f16_f32); a GPU test
+// compares the library's encode with this rule written out value by value.
 struct CodecF16SR {
   using T = uint16_t;
   static constexpr bool kSR = true;
@@ -133,14 +135,13 @@ struct CodecF16SR {
     return __half_as_ushort(__float2half_rn(v * s));
   }
   __device__ __forceinline__ static T enc_sr(float v, float s, uint32_t r) {
-    const uint32_t b = __float_as_uint(v * s);
-    const uint32_t a = b & 0x7fffffffu;
-    const int e = (int)(a >> 23);
-    const uint32_t d = (uint32_t)min(max(126 - e, 13), 31);
-    const uint32_t m = e > 94 ? ((a & 0x7fffffu) | 0x800000u) : 0u;
-    const uint32_t k = (m + (r & ((1u << d) - 1u))) >> d;
-    const uint32_t h = min(((uint32_t)(max(e, 113) - 113) << 10) + k, 0x7c00u);
-    return (T)(((b >> 16) & 0x8000u) | h);
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    h2 z = {0, 0};
+    z = __builtin_amdgcn_cvt_sr_f16_f32(z, v * s, r, false);
+    const _Float16 lo = z[0];
+    T u;
+    __builtin_memcpy(&u, &lo, sizeof u);
+    return u;
   }
 };
 

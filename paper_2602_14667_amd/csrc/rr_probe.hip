@@ -1,9 +1,11 @@
 // rr_probe.hip -- plain device copy used as the measured bandwidth reference
-// (and to calibrate memory-traffic counters against a known byte count).
+// (and to calibrate memory-traffic counters against a known byte count), and
+// the stochastically rounding FP16 encode of the storage codec on arrays.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/rrmhd.h"
+#include "rr_node.h"
 
 namespace {
 
@@ -16,7 +18,26 @@ __global__ __launch_bounds__(256) void k_copy16(const v4f *__restrict__ src,
     __builtin_nontemporal_store(src[i], dst + i);
 }
 
+__global__ __launch_bounds__(256) void k_sr_encode(const float *__restrict__ x,
+                                                   const uint32_t *__restrict__ r,
+                                                   uint16_t *__restrict__ out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = rr::CodecF16SR::enc_sr(x[i], 1.0f, r[i]);
+}
+
 }  // namespace
+
+extern "C" int rrmhd_sr_encode(const float *x, const uint32_t *r, uint16_t *out, int64_t n,
+                               void *hip_stream) {
+  if (!x || !r || !out || n < 0) return RRMHD_EINVAL;
+  if (n == 0) return RRMHD_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL(k_sr_encode, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                     x, r, out, n);
+  return hipGetLastError() == hipSuccess ? RRMHD_OK : RRMHD_EDEVICE;
+}
 
 extern "C" int rrmhd_bandwidth_probe(void *dst, const void *src, int64_t bytes,
                                      void *hip_stream) {

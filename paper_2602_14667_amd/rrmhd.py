@@ -26,7 +26,7 @@ EXPORTED = [
     "rrmhd_set_launch", "rrmhd_get_launch", "rrmhd_set_stream", "rrmhd_set_equilibrium", "rrmhd_set_graph_chunk",
     "rrmhd_set_debug_poison",
     "rrmhd_destroy", "rrmhd_strerror",
-    "rrmhd_last_error_detail", "rrmhd_bandwidth_probe",
+    "rrmhd_last_error_detail", "rrmhd_bandwidth_probe", "rrmhd_sr_encode",
     "rrmhd_batch_create", "rrmhd_batch_init", "rrmhd_batch_step",
     "rrmhd_batch_set_graph_chunk", "rrmhd_batch_set_shape", "rrmhd_batch_set_fetch",
     "rrmhd_batch_moments", "rrmhd_batch_diagnostics", "rrmhd_batch_info",
@@ -123,6 +123,7 @@ def lib():
         L.rrmhd3d_destroy.argtypes = [vp]
         L.rrmhd_destroy.argtypes = [vp]
         L.rrmhd_bandwidth_probe.argtypes = [vp, vp, i64, vp]
+        L.rrmhd_sr_encode.argtypes = [vp, vp, vp, i64, vp]
         dbl = ctypes.POINTER(ctypes.c_double)
         L.rrmhd_batch_create.argtypes = [ci, ctypes.POINTER(Grid), dbl, dbl, ci,
                                          vp, ctypes.POINTER(vp)]
@@ -604,6 +605,22 @@ class Solver3D:
     def set_debug_poison(self, on=True):
         """NaN-fill the destination buffer before every step (debug)."""
         _check(lib().rrmhd3d_set_debug_poison(self._h, int(bool(on))), "rrmhd3d_set_debug_poison")
+
+
+def sr_encode(x, r, stream=None):
+    """The stochastically rounding FP16 encode of the storage codec: x float32
+    and r uint32 (as int32 bits) device tensors of one shape; returns the FP16
+    bit patterns as an int16 tensor."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous float32 device tensor")
+    if not (r.is_cuda and r.dtype == torch.int32 and r.is_contiguous() and r.shape == x.shape):
+        raise ValueError("r must be a contiguous int32 device tensor shaped like x")
+    out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _check(lib().rrmhd_sr_encode(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), x.numel(),
+                                 _stream_handle(stream)), "rrmhd_sr_encode")
+    return out
 
 
 def bandwidth_probe(dst, src, stream=None):
