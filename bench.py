@@ -639,8 +639,10 @@ def time_turbulence_leg(torch, rrmhd, args, fields, storage):
     if args.equilibrium != "algorithm":
         launch = "library default block shape, one node per thread, NT stores"
     if args.inplace:
-        launch = ("library default for one buffer (f32: 64x1, f16: 128x1 threads, XCD-local "
-                  "order, NT stores); steps alternate pull+push and own-slot forms")
+        launch = ("library default for one buffer (row-interleaved planes, XCD-local order, "
+                  "NT stores; f32: 128x1 threads, one node per thread; f16: 64x2 threads, two "
+                  "nodes per thread in 32-bit words); steps alternate pull+push and own-slot "
+                  "forms")
     s.init(ud, bd)
     s.step(args.warmup)
     torch.cuda.synchronize()

@@ -64,7 +64,9 @@ enum {
  * bit for bit as a two-buffer one; moments, diagnostics, fields and
  * rrmhd_save_state read either layout (save returns the usual one).  Not
  * with the learned closure or the equilibrium ablation (EINVAL); of the
- * launch shape's nt bits only bit 0 (non-temporal stores) applies. */
+ * launch shape's nt bits, bit 1 (non-temporal loads) does not apply, and
+ * bits 2 and 3 (two or four nodes per thread) apply, on periodic grids, only
+ * together with bit 0. */
 enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
 /* RRMHD_STORE_F16_SR: FP16 storage whose step stores round stochastically
  * (each value goes to one of its two FP16 neighbours, away from zero with
@@ -85,10 +87,10 @@ enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
 enum { RRMHD_STORE_F16_SR = 2 };
 /* Layout of the populations in device memory (not visible through the API:
  * moments, diagnostics, rrmhd_save_state and checkpoint files are the same
- * for either).  Periodic two-buffer handles keep the 19 planes
+ * for either).  Periodic handles (one or two buffers) keep the 19 planes
  * row-interleaved: each grid row holds its 19 plane rows side by side, each
  * starting on a 256-byte boundary, and the FP32 step then updates two nodes
- * per thread with 64-bit words.  Handles with walls or one buffer, or with
+ * per thread with 64-bit words.  Handles with walls, or with
  * RRMHD_STORE_PLANAR OR-ed into rrmhd_grid.storage, keep 19 planes of
  * [ny][nx].  Results are bitwise the same in both layouts. */
 enum { RRMHD_STORE_PLANAR = 0x200 };

@@ -215,12 +215,11 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   // starts across HBM channels
   const int64_t align = 256 / h->elem;
   D.walls = b.kind == RRMHD_BC_WALLS_Y;
-  // Layout: periodic two-buffer handles keep the 19 planes row-interleaved
-  // (each grid row holds its 19 plane rows side by side, each starting on a
-  // 256-byte boundary), which streams faster than whole planes; walls and
-  // single-buffer handles, or RRMHD_STORE_PLANAR (or RRMHD_LAYOUT=planar),
-  // keep planes of [ny][nx].
-  bool rows = !D.walls && !h->inplace && !(flags & RRMHD_STORE_PLANAR);
+  // Layout: periodic handles keep the 19 planes row-interleaved (each grid
+  // row holds its 19 plane rows side by side, each starting on a 256-byte
+  // boundary), which streams faster than whole planes; walls, or
+  // RRMHD_STORE_PLANAR (or RRMHD_LAYOUT=planar), keep planes of [ny][nx].
+  bool rows = !D.walls && !(flags & RRMHD_STORE_PLANAR);
   if (const char *e = std::getenv("RRMHD_LAYOUT"))
     if (std::strcmp(e, "planar") == 0) rows = false;
   if (rows) {
@@ -256,13 +255,24 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   D.elem = (int)h->elem;
   h->shape = rr::default_shape(D);
   if (h->inplace) {
-    // measured best for the alternating single-buffer steps at 8192^2: one
-    // row per workgroup, eight neighbouring tiles per XCD
-    h->shape.bx = h->elem == 2 ? 128 : 64;
-    h->shape.by = 1;
+    // measured best for the alternating single-buffer steps at 8192^2, with
+    // eight neighbouring tiles per XCD and non-temporal stores: FP16 storage
+    // on row-interleaved planes 64 x 2 threads with two nodes per thread;
+    // otherwise one node per thread and one row per workgroup, 128 wide (FP16
+    // storage, or FP32 on row-interleaved planes) or 64 wide (FP32 on planes
+    // of [ny][nx])
+    const bool rows_wide = D.row != D.nx && D.nx >= 512;
     h->shape.ry = 1;
     h->shape.xcd = 2;
-    h->shape.nt = 1;
+    if (rows_wide && h->elem == 2 && D.nx % 2 == 0) {
+      h->shape.bx = 64;
+      h->shape.by = 2;
+      h->shape.nt = 5;
+    } else {
+      h->shape.bx = (h->elem == 2 || rows_wide) ? 128 : 64;
+      h->shape.by = 1;
+      h->shape.nt = 1;
+    }
   }
 
   // environment overrides of the launch shape ("BXxBY" or "BXxBYxRY") and of
@@ -720,6 +730,8 @@ int rrmhd_save(rrmhd *h, const char *path) {
     }
     base = (const char *)tmp;
     pitch = row;
+    rstride = 0;  // the gathered copy is dense
+    nrows = 1;
   }
   hipError_t e = hipStreamSynchronize(h->stream);
   int rc = e != hipSuccess ? dev_err(e, "hipStreamSynchronize")

@@ -98,17 +98,20 @@ extern "C" RR_HIDDEN int rr_launch_current_vorticity(int storage, const rr::Doma
   const double gx = D->Gx, gy = D->Gy;
   auto s16 = (const uint16_t *)src;
   auto s32 = (const float *)src;
-  // single-buffer handles (swapped) keep planes of [ny][nx]
   const bool rows = D->row != D->nx;
   if (storage == rr::kF16) {
-    if (swapped)
+    if (swapped && rows)
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF16, true, rr::RM_UNIFORM>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
+    else if (swapped)
       hipLaunchKernelGGL((rr::k_current<rr::CodecF16, true, rr::RM_OFFSET>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
     else if (rows)
       hipLaunchKernelGGL((rr::k_current<rr::CodecF16, false, rr::RM_UNIFORM>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
     else
       hipLaunchKernelGGL((rr::k_current<rr::CodecF16, false, rr::RM_OFFSET>), grid, block, 0, st, G, s16, omega_m, gx, gy, jz, upl);
   } else {
-    if (swapped)
+    if (swapped && rows)
+      hipLaunchKernelGGL((rr::k_current<rr::CodecF32, true, rr::RM_UNIFORM>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
+    else if (swapped)
       hipLaunchKernelGGL((rr::k_current<rr::CodecF32, true, rr::RM_OFFSET>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);
     else if (rows)
       hipLaunchKernelGGL((rr::k_current<rr::CodecF32, false, rr::RM_UNIFORM>), grid, block, 0, st, G, s32, omega_m, gx, gy, jz, upl);

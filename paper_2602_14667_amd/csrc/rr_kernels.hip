@@ -266,7 +266,7 @@ __device__ __forceinline__ void own_node(const Domain &D, const typename C::T *b
   }
 }
 
-template <class C, bool WALLS, bool FORCED, int PHASE, bool NT>
+template <class C, bool WALLS, bool FORCED, int PHASE, bool NT, int RM = RM_OFFSET>
 __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int ry, int xcd,
                                                       typename C::T *buf) {
   const int ntiles = gridDim.x;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int
       if constexpr (WALLS)
         update_walled_push<C, FORCED, NT>(D, buf, x, y, P);
       else
-        update_periodic_push<C, FORCED, NT>(G, buf, x, y, P);
+        update_periodic_push<C, FORCED, NT, RM>(G, buf, x, y, P);
     } else {
       if constexpr (WALLS) {
         float d[kQ], g[2 * kQm];
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_step_inplace(Domain D, int tiles_x, int
         for (int k = 0; k < 2 * kQm; ++k)
           st_el<typename C::T, NT>(&buf[(int64_t)(kQ + k) * D.plane + o], enc(g[k], kQ + k));
       } else {
-        update_periodic_own<C, FORCED, NT>(G, buf, x, y, P);
+        update_periodic_own<C, FORCED, NT, RM>(G, buf, x, y, P);
       }
     }
   }
@@ -681,6 +681,36 @@ __global__ __launch_bounds__(256) void k_step_multi(Domain D, int tiles_x, int r
   }
 }
 
+// Single-buffer step on a periodic grid with nx a multiple of K: each thread
+// takes the nodes x .. x + K - 1 with one word per plane in either phase
+// (update_periodic_push_multi / update_periodic_own_multi).
+template <class C, int K, bool FORCED, int PHASE, int RM>
+__global__ __launch_bounds__(256) void k_step_inplace_multi(Domain D, int tiles_x, int ry, int xcd,
+                                                            typename C::T *buf) {
+  const int ntiles = gridDim.x;
+  const int L = xcd == 1 ? xcd_remap(blockIdx.x, ntiles)
+                         : (xcd == 2 ? xcd_local(blockIdx.x, ntiles) : (int)blockIdx.x);
+  const int tx = L % tiles_x, ty = L / tiles_x;
+  const int x = K * (tx * blockDim.x + threadIdx.x);
+  const int y0 = (ty * blockDim.y + threadIdx.y) * ry;
+  if (x >= D.nx) return;
+  CollideParams P;
+  P.om_c = D.om_c;
+  P.omm_c = D.omm_c;
+  P.Gx = D.Gx;
+  P.Gy = D.Gy;
+  P.src_c = D.src_c;
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, 0u, D.row};
+  for (int r = 0; r < ry; ++r) {
+    const int y = y0 + r;
+    if (y >= D.ny) return;
+    if constexpr (PHASE == 0)
+      update_periodic_push_multi<C, K, FORCED, true, RM>(G, buf, x, y, P);
+    else
+      update_periodic_own_multi<C, K, FORCED, true, RM>(G, buf, x, y, P);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -941,6 +971,21 @@ hipError_t launch_moments(int storage, const Domain &D, const void *src,
   return hipGetLastError();
 }
 
+template <class C, bool FORCED, int PHASE, bool NT>
+static void inplace_periodic(const Domain &D, typename C::T *b, const LaunchShape &L, dim3 grid,
+                             dim3 block, int tiles_x, hipStream_t st) {
+  switch (row_mode(D, L)) {
+    case RM_OFFSET:
+      hipLaunchKernelGGL((k_step_inplace<C, false, FORCED, PHASE, NT, RM_OFFSET>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+      break;
+    case RM_UNIFORM:
+      hipLaunchKernelGGL((k_step_inplace<C, false, FORCED, PHASE, NT, RM_UNIFORM>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step_inplace<C, false, FORCED, PHASE, NT, RM_LANE>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+  }
+}
+
 template <class C, int PHASE, bool NT>
 static void inplace_t(const Domain &D, void *buf, const LaunchShape &L, hipStream_t st) {
   const int tiles_x = (D.nx + L.bx - 1) / L.bx;
@@ -956,16 +1001,54 @@ static void inplace_t(const Domain &D, void *buf, const LaunchShape &L, hipStrea
       hipLaunchKernelGGL((k_step_inplace<C, true, false, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
   } else {
     if (forced)
-      hipLaunchKernelGGL((k_step_inplace<C, false, true, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+      inplace_periodic<C, true, PHASE, NT>(D, b, L, grid, block, tiles_x, st);
     else
-      hipLaunchKernelGGL((k_step_inplace<C, false, false, PHASE, NT>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+      inplace_periodic<C, false, PHASE, NT>(D, b, L, grid, block, tiles_x, st);
   }
 }
 
+// K nodes per thread, non-temporal stores; as for the two-buffer multi-node
+// update, row-interleaved planes come with whole-row wavefronts (RM_UNIFORM).
+template <class C, int K, int PHASE>
+static void inplace_multi_t(const Domain &D, void *buf, const LaunchShape &L, hipStream_t st) {
+  const int tiles_x = (D.nx / K + L.bx - 1) / L.bx;
+  const int rows_per_tile = L.by * L.ry;
+  const int tiles_y = (D.ny + rows_per_tile - 1) / rows_per_tile;
+  const dim3 grid(tiles_x * tiles_y), block(L.bx, L.by);
+  const bool forced = D.Gx != 0.0f || D.Gy != 0.0f;
+  auto b = (typename C::T *)buf;
+  if (D.row == D.nx) {
+    if (forced)
+      hipLaunchKernelGGL((k_step_inplace_multi<C, K, true, PHASE, RM_OFFSET>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+    else
+      hipLaunchKernelGGL((k_step_inplace_multi<C, K, false, PHASE, RM_OFFSET>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+  } else {
+    if (forced)
+      hipLaunchKernelGGL((k_step_inplace_multi<C, K, true, PHASE, RM_UNIFORM>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+    else
+      hipLaunchKernelGGL((k_step_inplace_multi<C, K, false, PHASE, RM_UNIFORM>), grid, block, 0, st, D, tiles_x, L.ry, L.xcd, b);
+  }
+}
+
+// The multi-node forms take the nodes-per-thread rule of the two-buffer
+// step (multi_nodes) and need non-temporal stores (nt bit 0).
 template <class C>
 static void inplace_phase(const Domain &D, void *buf, int phase, const LaunchShape &L,
                           hipStream_t st) {
   const bool nt = L.nt & 1;
+  if constexpr (!codec_sr<C>::value) {
+    const int k = nt ? multi_nodes<C>(D, L) : 1;
+    if (k == 2) {
+      phase ? inplace_multi_t<C, 2, 1>(D, buf, L, st) : inplace_multi_t<C, 2, 0>(D, buf, L, st);
+      return;
+    }
+    if constexpr (sizeof(typename C::T) == 2) {
+      if (k == 4) {
+        phase ? inplace_multi_t<C, 4, 1>(D, buf, L, st) : inplace_multi_t<C, 4, 0>(D, buf, L, st);
+        return;
+      }
+    }
+  }
   if (phase)
     nt ? inplace_t<C, 1, true>(D, buf, L, st) : inplace_t<C, 1, false>(D, buf, L, st);
   else
@@ -975,7 +1058,8 @@ static void inplace_phase(const Domain &D, void *buf, int phase, const LaunchSha
 hipError_t launch_step_inplace(int storage, const Domain &D, void *buf, int phase,
                                const LaunchShape &L, hipStream_t st) {
   if (L.bx <= 0 || L.by <= 0 || L.bx * L.by > 256 || L.ry <= 0) return hipErrorInvalidValue;
-  if ((int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
+  // as for the two-buffer step: 32-bit offsets inside planes of [ny][nx]
+  if (D.row == D.nx && (int64_t)D.nx * D.ny * (storage == kF16 ? 2 : 4) >= ((int64_t)1 << 32))
     return hipErrorInvalidValue;
   if (storage == kF16 && D.sr)
     inplace_phase<CodecF16SR>(D, buf, phase, L, st);

@@ -75,6 +75,18 @@ __device__ __forceinline__ float rdiv(float a, float b, float rb) {
 // ---- storage codecs ------------------------------------------------------
 // Stored value for the fluid plane i: S (f_i - w_i); for a magnetic plane:
 // S g.  F32 keeps S = 1.  F16 converts with round-to-nearest-even.
+//
+// The FP16 encodes round the FP32 value as computed.  Left to itself the
+// compiler may fold the last FMA of the collision and the conversion into one
+// mixed-precision instruction that rounds the exact result once, and it
+// makes that choice kernel by kernel, so two kernels would then differ by one
+// FP16 unit where the FP32 value sits on a rounding tie.  An empty asm
+// statement hides where the value came from, which keeps every kernel's
+// stores identical.
+__device__ __forceinline__ float f32_as_computed(float v) {
+  asm("" : "+v"(v));
+  return v;
+}
 struct CodecF32 {
   using T = float;
   __device__ __forceinline__ static float dec(T v, float) { return v; }
@@ -86,21 +98,19 @@ struct CodecF16 {
     return __half2float(__ushort_as_half(v)) * inv_s;
   }
   __device__ __forceinline__ static T enc(float v, float s) {
-    return __half_as_ushort(__float2half_rn(v * s));
+    return __half_as_ushort(__float2half_rn(f32_as_computed(v * s)));
   }
 };
 // The F16 codec at S = 1 (the default), used by every kernel that writes
-// populations when S = 1: no multiply by 1 on decoded values, and a plain
-// round-to-nearest-even conversion on encode (CodecF16's scaled encode is
-// fused into one mixed-precision FMA, which returns +0 for -0 and so is not
-// bit-identical at S = 1).
+// populations when S = 1: the same stored bits as CodecF16 at S = 1 without
+// the multiplies by 1 on decode and encode.
 struct CodecF16U {
   using T = uint16_t;
   __device__ __forceinline__ static float dec(T v, float) {
     return __half2float(__ushort_as_half(v));
   }
   __device__ __forceinline__ static T enc(float v, float) {
-    return __half_as_ushort(__float2half_rn(v));
+    return __half_as_ushort(__float2half_rn(f32_as_computed(v)));
   }
 };
 

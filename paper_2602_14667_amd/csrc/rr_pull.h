@@ -225,14 +225,12 @@ __device__ __forceinline__ void store_plane_at(const PlaneGeom &G, typename C::T
     st_at<typename C::T, NT>(buf + (int64_t)P * G.plane, o, C::enc(v, G.s));
 }
 
-template <class C, bool FORCED, bool NT>
+template <class C, bool FORCED, bool NT, int RM = RM_OFFSET>
 __device__ __forceinline__ void update_periodic_push(const PlaneGeom &G, typename C::T *buf,
                                                      int x, int y, const CollideParams &P) {
   using T = typename C::T;
   constexpr uint32_t E = sizeof(T);
-  // single-buffer handles keep planes of [ny][nx] (row == nx), below 4 GiB
-  const RowAddr<T> A = row_addr<RM_OFFSET>(G, (const T *)buf, y);
-  const uint32_t b0 = A.oz, bm = A.om, bp = A.op;
+  const RowAddr<T> A = row_addr<RM>(G, (const T *)buf, y);
   const uint32_t x0 = x * E;
   const uint32_t xm = (x == 0 ? G.nx - 1 : x - 1) * E;
   const uint32_t xp = (x == G.nx - 1 ? 0 : x + 1) * E;
@@ -240,40 +238,22 @@ __device__ __forceinline__ void update_periodic_push(const PlaneGeom &G, typenam
   pull_node_per<C, false>(G, A, x, d, g);
   collide<FORCED>(d, g, P);
   // f*_i(x) -> buf[opp(i)][x + c_i]: the slot read for direction opp(i)
+  auto base = [&](int cyv) { return (T *)(cyv == 0 ? A.z : (cyv > 0 ? A.p : A.m)); };
   auto at = [&](int cxv, int cyv) {
-    return (cyv == 0 ? b0 : (cyv > 0 ? bp : bm)) + (cxv == 0 ? x0 : (cxv > 0 ? xp : xm));
+    return (cyv == 0 ? A.oz : (cyv > 0 ? A.op : A.om)) + (cxv == 0 ? x0 : (cxv > 0 ? xp : xm));
   };
-  uint32_t seed = 0;
-  if constexpr (codec_sr<C>::value) seed = sr_seed(G.sr_key, b0 + x0);
-  store_plane_at<C, opp_f(0), NT>(G, buf, at(cx(0), cy(0)), d[0], seed, 0);
-  store_plane_at<C, opp_f(1), NT>(G, buf, at(cx(1), cy(1)), d[1], seed, 1);
-  store_plane_at<C, opp_f(2), NT>(G, buf, at(cx(2), cy(2)), d[2], seed, 2);
-  store_plane_at<C, opp_f(3), NT>(G, buf, at(cx(3), cy(3)), d[3], seed, 3);
-  store_plane_at<C, opp_f(4), NT>(G, buf, at(cx(4), cy(4)), d[4], seed, 4);
-  store_plane_at<C, opp_f(5), NT>(G, buf, at(cx(5), cy(5)), d[5], seed, 5);
-  store_plane_at<C, opp_f(6), NT>(G, buf, at(cx(6), cy(6)), d[6], seed, 6);
-  store_plane_at<C, opp_f(7), NT>(G, buf, at(cx(7), cy(7)), d[7], seed, 7);
-  store_plane_at<C, opp_f(8), NT>(G, buf, at(cx(8), cy(8)), d[8], seed, 8);
-  store_plane_at<C, gplane(opp_g(0), 0), NT>(G, buf, at(ex(0), ey(0)), g[0], seed,
-                                             gplane(0, 0));
-  store_plane_at<C, gplane(opp_g(0), 1), NT>(G, buf, at(ex(0), ey(0)), g[1], seed,
-                                             gplane(0, 1));
-  store_plane_at<C, gplane(opp_g(1), 0), NT>(G, buf, at(ex(1), ey(1)), g[2], seed,
-                                             gplane(1, 0));
-  store_plane_at<C, gplane(opp_g(1), 1), NT>(G, buf, at(ex(1), ey(1)), g[3], seed,
-                                             gplane(1, 1));
-  store_plane_at<C, gplane(opp_g(2), 0), NT>(G, buf, at(ex(2), ey(2)), g[4], seed,
-                                             gplane(2, 0));
-  store_plane_at<C, gplane(opp_g(2), 1), NT>(G, buf, at(ex(2), ey(2)), g[5], seed,
-                                             gplane(2, 1));
-  store_plane_at<C, gplane(opp_g(3), 0), NT>(G, buf, at(ex(3), ey(3)), g[6], seed,
-                                             gplane(3, 0));
-  store_plane_at<C, gplane(opp_g(3), 1), NT>(G, buf, at(ex(3), ey(3)), g[7], seed,
-                                             gplane(3, 1));
-  store_plane_at<C, gplane(opp_g(4), 0), NT>(G, buf, at(ex(4), ey(4)), g[8], seed,
-                                             gplane(4, 0));
-  store_plane_at<C, gplane(opp_g(4), 1), NT>(G, buf, at(ex(4), ey(4)), g[9], seed,
-                                             gplane(4, 1));
+  const uint32_t seed = node_seed<C>(G, x, y);
+#define RR_PUSHF(I) \
+  store_plane_at<C, opp_f(I), NT>(G, base(cy(I)), at(cx(I), cy(I)), d[I], seed, I)
+#define RR_PUSHG(J, K2)                                                                  \
+  store_plane_at<C, gplane(opp_g(J), K2), NT>(G, base(ey(J)), at(ex(J), ey(J)), g[2 * J + K2], \
+                                              seed, gplane(J, K2))
+  RR_PUSHF(0); RR_PUSHF(1); RR_PUSHF(2); RR_PUSHF(3); RR_PUSHF(4); RR_PUSHF(5); RR_PUSHF(6);
+  RR_PUSHF(7); RR_PUSHF(8);
+  RR_PUSHG(0, 0); RR_PUSHG(0, 1); RR_PUSHG(1, 0); RR_PUSHG(1, 1); RR_PUSHG(2, 0);
+  RR_PUSHG(2, 1); RR_PUSHG(3, 0); RR_PUSHG(3, 1); RR_PUSHG(4, 0); RR_PUSHG(4, 1);
+#undef RR_PUSHF
+#undef RR_PUSHG
 }
 
 template <class C, int P>
@@ -282,12 +262,13 @@ __device__ __forceinline__ float ld_own(const PlaneGeom &G, const typename C::T 
   return C::dec(ld_at<typename C::T, false>(plane_ptr(buf, P, G.plane), o), G.inv_s);
 }
 
-template <class C, bool FORCED, bool NT>
+template <class C, bool FORCED, bool NT, int RM = RM_OFFSET>
 __device__ __forceinline__ void update_periodic_own(const PlaneGeom &G, typename C::T *buf,
                                                     int x, int y, const CollideParams &P) {
   constexpr uint32_t E = sizeof(typename C::T);
-  const uint32_t o = y * ((uint32_t)G.row * E) + x * E;  // row == nx (planes of [ny][nx])
-  const typename C::T *src = buf;
+  uint32_t off;
+  const typename C::T *src = row_dst<RM>(G, buf, y, off);
+  const uint32_t o = off + x * E;
   float d[kQ], g[2 * kQm];
   d[0] = ld_own<C, opp_f(0)>(G, src, o);
   d[1] = ld_own<C, opp_f(1)>(G, src, o);
@@ -309,7 +290,7 @@ __device__ __forceinline__ void update_periodic_own(const PlaneGeom &G, typename
   g[8] = ld_own<C, gplane(opp_g(4), 0)>(G, src, o);
   g[9] = ld_own<C, gplane(opp_g(4), 1)>(G, src, o);
   collide<FORCED>(d, g, P);
-  store_node<C, NT, RM_OFFSET>(G, buf, x, y, d, g);
+  store_node<C, NT, RM>(G, buf, x, y, d, g);
 }
 
 // ---- K neighbouring nodes per thread -------------------------------------------
@@ -422,6 +403,123 @@ __device__ __forceinline__ void update_periodic_multi(const PlaneGeom &G,
   T *out = row_dst<RM>(G, dst, y, off);
   store_words<C, NT, K>(G, out, off + (uint32_t)sizeof(T) * x, w,
                         std::make_integer_sequence<int, kPlanes>{});
+}
+
+
+// ---- single-buffer streaming with K nodes per thread ---------------------------
+// The two phases of the alternating update with one word per plane.  Phase 0
+// writes each updated word back over the K slots that its own load read
+// (element by element at the periodic seam, where the load was assembled
+// element by element), phase 1 reads and writes the node's own aligned
+// words, so every slot is still read and written by one thread only.
+template <int CX, bool NT, int K, class T>
+__device__ __forceinline__ void st_word(T *__restrict__ plane, uint32_t row, int x, int nx,
+                                        typename NodeWord<T, K>::W w) {
+  using NW = NodeWord<T, K>;
+  using W = typename NW::W;
+  constexpr uint32_t E = sizeof(T);
+  if (CX == 0) {
+    st_at<W, NT>((W *)plane, row + E * x, w);
+    return;
+  }
+  const bool seam = CX > 0 ? x == 0 : x == nx - K;
+  if (!seam) {
+    st_at<W, NT>((W *)plane, row + E * (x - CX), w);
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int xx = x - CX + k;
+    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+    st_at<T, NT>(plane, row + E * xx, NW::get(w, k));
+  }
+}
+
+// Phase 0: pull as update_periodic_multi does, collide, and put f*_i of node
+// x + k into element k of the word just read for the opposite direction
+// (the slot buf[opp(i)][x + k + c_i]); every word returns to where it came
+// from.  C: a codec without stochastic rounding.
+template <class C, int K, bool FORCED, bool NT, int RM>
+__device__ __forceinline__ void update_periodic_push_multi(const PlaneGeom &G,
+                                                           typename C::T *buf, int x, int y,
+                                                           const CollideParams &P) {
+  using T = typename C::T;
+  using NW = NodeWord<T, K>;
+  const RowAddr<T> A = row_addr<RM>(G, (const T *)buf, y);
+  typename NW::W w[kPlanes];
+  auto base = [&](int cyv) { return (T *)(cyv == 0 ? A.z : (cyv > 0 ? A.m : A.p)); };
+  auto rowf = [&](int cyv) { return cyv == 0 ? A.oz : (cyv > 0 ? A.om : A.op); };
+#define RR_LDF(I) \
+  w[I] = ld_word<cx(I), false, K>(plane_ptr((const T *)base(cy(I)), I, G.plane), rowf(cy(I)), x, G.nx)
+#define RR_LDG(J, K2)                                                                      \
+  w[gplane(J, K2)] = ld_word<ex(J), false, K>(                                            \
+      plane_ptr((const T *)base(ey(J)), gplane(J, K2), G.plane), rowf(ey(J)), x, G.nx)
+  RR_LDF(0); RR_LDF(1); RR_LDF(2); RR_LDF(3); RR_LDF(4); RR_LDF(5); RR_LDF(6); RR_LDF(7); RR_LDF(8);
+  RR_LDG(0, 0); RR_LDG(0, 1); RR_LDG(1, 0); RR_LDG(1, 1); RR_LDG(2, 0); RR_LDG(2, 1);
+  RR_LDG(3, 0); RR_LDG(3, 1); RR_LDG(4, 0); RR_LDG(4, 1);
+#undef RR_LDF
+#undef RR_LDG
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float d[kQ], g[2 * kQm];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) d[i] = C::dec(NW::get(w[i], k), G.inv_s);
+#pragma unroll
+    for (int m = 0; m < 2 * kQm; ++m) g[m] = C::dec(NW::get(w[kQ + m], k), G.inv_s);
+    collide<FORCED>(d, g, P);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) w[opp_f(i)] = NW::put(w[opp_f(i)], k, C::enc(d[i], G.s));
+#pragma unroll
+    for (int j = 0; j < kQm; ++j) {
+      w[gplane(opp_g(j), 0)] = NW::put(w[gplane(opp_g(j), 0)], k, C::enc(g[2 * j], G.s));
+      w[gplane(opp_g(j), 1)] = NW::put(w[gplane(opp_g(j), 1)], k, C::enc(g[2 * j + 1], G.s));
+    }
+  }
+#define RR_STF(I) \
+  st_word<cx(I), NT, K>(base(cy(I)) + (int64_t)(I) * G.plane, rowf(cy(I)), x, G.nx, w[I])
+#define RR_STG(J, K2)                                                                     \
+  st_word<ex(J), NT, K>(base(ey(J)) + (int64_t)gplane(J, K2) * G.plane, rowf(ey(J)), x, G.nx, \
+                        w[gplane(J, K2)])
+  RR_STF(0); RR_STF(1); RR_STF(2); RR_STF(3); RR_STF(4); RR_STF(5); RR_STF(6); RR_STF(7); RR_STF(8);
+  RR_STG(0, 0); RR_STG(0, 1); RR_STG(1, 0); RR_STG(1, 1); RR_STG(2, 0); RR_STG(2, 1);
+  RR_STG(3, 0); RR_STG(3, 1); RR_STG(4, 0); RR_STG(4, 1);
+#undef RR_STF
+#undef RR_STG
+}
+
+// Phase 1: the node's own aligned words in the swapped layout (population i
+// of node x + k is element k of plane opp(i)), collide, store in the pull
+// layout at the same words.
+template <class C, int K, bool FORCED, bool NT, int RM>
+__device__ __forceinline__ void update_periodic_own_multi(const PlaneGeom &G,
+                                                          typename C::T *buf, int x, int y,
+                                                          const CollideParams &P) {
+  using T = typename C::T;
+  using NW = NodeWord<T, K>;
+  using W = typename NW::W;
+  uint32_t off;
+  T *row = row_dst<RM>(G, buf, y, off);
+  const uint32_t o = off + (uint32_t)sizeof(T) * x;
+  W w[kPlanes];
+#pragma unroll
+  for (int p = 0; p < kPlanes; ++p) w[p] = ld_at<W, false>((const W *)(row + (int64_t)p * G.plane), o);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float d[kQ], g[2 * kQm];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) d[i] = C::dec(NW::get(w[opp_f(i)], k), G.inv_s);
+#pragma unroll
+    for (int j = 0; j < kQm; ++j) {
+      g[2 * j] = C::dec(NW::get(w[gplane(opp_g(j), 0)], k), G.inv_s);
+      g[2 * j + 1] = C::dec(NW::get(w[gplane(opp_g(j), 1)], k), G.inv_s);
+    }
+    collide<FORCED>(d, g, P);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) w[i] = NW::put(w[i], k, C::enc(d[i], G.s));
+#pragma unroll
+    for (int m = 0; m < 2 * kQm; ++m) w[kQ + m] = NW::put(w[kQ + m], k, C::enc(g[m], G.s));
+  }
+  store_words<C, NT, K>(G, row, o, w, std::make_integer_sequence<int, kPlanes>{});
 }
 
 }  // namespace rr

@@ -195,10 +195,9 @@ int rrmhd_autotune(rrmhd *h, const char *cache_path, int trials, int *out_bx,
                            {64, 4, 2, 1},  {128, 1, 0, 5}, {128, 2, 0, 5}, {64, 4, 0, 5},
                            {256, 1, 0, 5}, {64, 2, 0, 5},  {128, 2, 2, 5}, {64, 4, 2, 5},
                            {128, 1, 0, 9}, {128, 1, 2, 9}, {256, 1, 0, 9}, {128, 2, 0, 9}};
-    const bool pair_ok = (storage == RRMHD_STORE_F16 || rows) && nx % 2 == 0 &&
-                         !rr_handle_walls(h) && !inplace;
-    const bool quad_ok =
-        storage == RRMHD_STORE_F16 && nx % 4 == 0 && !rr_handle_walls(h) && !inplace;
+    const bool pair_ok =
+        (storage == RRMHD_STORE_F16 || rows) && nx % 2 == 0 && !rr_handle_walls(h);
+    const bool quad_ok = storage == RRMHD_STORE_F16 && nx % 4 == 0 && !rr_handle_walls(h);
     best.ms = 1e30;
     for (const Shape &c : cands) {
       if (rc != RRMHD_OK) break;

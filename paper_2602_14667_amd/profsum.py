@@ -159,8 +159,10 @@ def inplace_summary(prof, out, n):
         lines.append("")
         tot = 0.0
         for ph in (0, 1):
-            # k_step_inplace<codec, walls, forced, phase, nt>
-            pat = re.compile(r"k_step_inplace<[^,<>]+, \w+, \w+, %d," % ph)
+            # k_step_inplace<codec, walls, forced, phase, nt, row mode> or
+            # k_step_inplace_multi<codec, nodes per thread, forced, phase, row mode>
+            pat = re.compile(r"k_step_inplace<[^,<>]+, \w+, \w+, %d,|"
+                             r"k_step_inplace_multi<[^,<>]+, \d+, \w+, %d," % (ph, ph))
             name = [k for k in stats if pat.search(k)][0]
             avg = stats[name]["avg_ns"]
             tot += avg

@@ -273,8 +273,8 @@ class Solver:
     equilibrium: "algorithm" (the method's) or "full_maxwell" (ablation with
     the u.M cross terms of the third and fourth orders).
     inplace: one population buffer instead of two (single-buffer streaming).
-    layout: "default" (row-interleaved planes for periodic two-buffer
-    handles) or "planar" (planes of [ny][nx]); results are the same.
+    layout: "default" (row-interleaved planes for periodic handles) or
+    "planar" (planes of [ny][nx]); results are the same.
     """
 
     def __init__(self, nx, ny, tau_f, tau_m, storage="f32", walls=False,

@@ -3,7 +3,8 @@ RRMHD_STORE_INPLACE holds one population buffer and alternates two step
 forms (pull + push into the opposite slots; own swapped slots + local
 store).  The per-node arithmetic is that of the two-buffer step, so the two
 are compared bit for bit, at odd and even step counts (the two layouts), with
-walls and forcing, across launch shapes, through save/resume and the
+walls and forcing, across launch shapes (one, two and four nodes per
+thread, both layouts), through save/resume, checkpoint files and the
 autotuner; plus the per-field bar against the FP64 oracle and the memory
 held."""
 import numpy as np
@@ -161,6 +162,87 @@ def test_inplace_launch_shapes_bitwise(storage):
         s.close()
         for k in FIELDS:
             assert np.array_equal(g[k], r[k]), (bx, by, ry, xcd, nt, k)
+
+
+MULTI_SHAPES = [(128, 2, 1, 2, 5), (128, 1, 1, 2, 9), (64, 4, 1, 0, 5), (32, 8, 1, 0, 5),
+                (16, 16, 1, 0, 9), (64, 1, 2, 1, 13), (128, 1, 1, 0, 4)]
+
+
+@pytest.mark.parametrize("layout", ["default", "planar"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
+@pytest.mark.parametrize("size", [(4, 5), (8, 3), (12, 7), (2, 3), (130, 66), (520, 18), (67, 9)])
+def test_inplace_multi_node_bitwise(layout, storage, size):
+    """Single-buffer steps with two or four nodes per thread (whole-row
+    wavefronts), one node per thread in mixed-row wavefronts and plain
+    stores, on both layouts: the two-buffer state bit for bit at odd and even
+    step counts; sizes with the periodic seam in the first and last word."""
+    nx, ny = size
+    note(f"in-place multi-node {nx}x{ny} {storage} {layout}")
+    R = rrmhd()
+    u, b = inputs.random_modes(nx, ny, 0.05, seed=5 * nx + ny)
+    ref = R.Solver(nx, ny, 0.53, 0.57, storage=storage)
+    ref.init(dev(u), dev(b))
+    for shape in MULTI_SHAPES:
+        s = R.Solver(nx, ny, 0.53, 0.57, storage=storage, inplace=True, layout=layout)
+        s.set_launch(*shape)
+        s.init(dev(u), dev(b))
+        if ref.step_count:
+            ref.close()
+            ref = R.Solver(nx, ny, 0.53, 0.57, storage=storage)
+            ref.init(dev(u), dev(b))
+        for k in (1, 2, 5, 6):
+            ref.step(k - ref.step_count)
+            s.step(k - s.step_count)
+            assert_same(ref, s, (shape, k))
+        s.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_inplace_multi_forcing_and_default_shape(storage):
+    """Forcing on the multi-node single-buffer path at 1024 x 512 (the
+    default launch shape for FP16 storage, a two-node shape for FP32): 21
+    steps equal the two-buffer run."""
+    n, m = 1024, 512
+    note(f"in-place multi-node default shape, forcing, {storage}")
+    u, b = inputs.random_modes(n, m, 0.04, seed=21)
+    two, one = pair(n, m, 0.52, 0.55, storage, force=(1e-5, -2e-6))
+    if storage == "f32":  # one node per thread by default
+        assert one.get_launch() == (128, 1, 1, 2, 1)
+        one.set_launch(64, 4, 1, 2, 5)
+    else:
+        assert one.get_launch() == (64, 2, 1, 2, 5)
+    for s in (two, one):
+        s.init(dev(u), dev(b))
+        s.step(21)
+    assert_same(two, one, "forced")
+    two.close(); one.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
+def test_inplace_rows_checkpoint_at_odd_step(storage, tmp_path):
+    """A row-interleaved single-buffer handle saved to a file between the two
+    step forms (odd step count) and resumed on a two-buffer handle and on
+    planar handles continues bit for bit."""
+    note(f"in-place rows checkpoint at odd step {storage}")
+    R = rrmhd()
+    nx, ny = 88, 30
+    u, b = inputs.random_modes(nx, ny, 0.05, seed=17)
+    ref = R.Solver(nx, ny, 0.53, 0.56, storage=storage)
+    one = R.Solver(nx, ny, 0.53, 0.56, storage=storage, inplace=True)
+    for s in (ref, one):
+        s.init(dev(u), dev(b))
+        s.step(7)
+    path = str(tmp_path / "odd.rrmhd")
+    one.save(path)
+    ref.step(6)
+    for kw in (dict(), dict(layout="planar"), dict(inplace=True, layout="planar")):
+        c = R.Solver(nx, ny, 0.53, 0.56, storage=storage, **kw)
+        c.load(path)
+        c.step(6)
+        assert_same(ref, c, ("odd-step file", kw))
+        c.close()
+    ref.close(); one.close()
 
 
 def test_inplace_autotune_keeps_state(tmp_path):

@@ -36,7 +36,7 @@ SHAPES = [(128, 2, 1, 0, 5), (128, 1, 1, 0, 5), (64, 4, 1, 2, 5), (32, 8, 1, 0, 
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "f16sr"])
-@pytest.mark.parametrize("size", [(130, 67), (64, 48), (2, 3), (1, 1), (520, 18), (67, 2)])
+@pytest.mark.parametrize("size", [(130, 67), (64, 48), (2, 3), (1, 1), (520, 18), (67, 2), (4, 5), (8, 3), (12, 7)])
 def test_layouts_bitwise_across_shapes(storage, size):
     nx, ny = size
     note(f"layouts {nx}x{ny} {storage}")
