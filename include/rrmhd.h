@@ -160,7 +160,7 @@ int rrmhd_diagnostics(rrmhd *h, double *E_kin, double *E_mag,
  * per-workgroup partial sums and its eight results) is a static device array
  * of 72 KiB that each GPU the library runs on holds until the process ends;
  * its device address is looked up once per device at rrmhd_create.  The
- * workspace the pass needs does not grow with the grid (1024 persistent
+ * workspace the pass needs does not grow with the grid (768 persistent
  * workgroups at most); a build whose pass would need more than the array
  * holds returns RRMHD_EINVAL (rrmhd_last_error_detail gives the sizes)
  * before anything is launched.  Every call on one GPU shares that GPU's

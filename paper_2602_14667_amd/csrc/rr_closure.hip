@@ -120,19 +120,9 @@ __global__ __launch_bounds__(1024) void k_step_closure(PlaneGeom G, CollideParam
   mlp_to_lds(g, &W);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const ClosureHook hook{&W};
-  // Tile order: the hardware deals workgroups to the eight XCDs in turn, so
-  // with a grid that is a multiple of 8 each XCD takes one contiguous band of
-  // tiles, its workgroups side by side: neighbouring tiles, which share the
-  // cache lines of their +-1 pulls, then meet in one L2.
-  int t0 = blockIdx.x, t_end = ntiles, stride = gridDim.x;
-  if ((gridDim.x & 7) == 0 && ntiles >= (int)gridDim.x) {
-    const int per_xcd = gridDim.x >> 3, band = (ntiles + 7) >> 3;
-    const int xcd = blockIdx.x & 7;
-    t0 = xcd * band + (blockIdx.x >> 3);
-    t_end = min(ntiles, (xcd + 1) * band);
-    stride = per_xcd;
-  }
-  for (int t = t0; t < t_end; t += stride) {
+  // one band of tiles per XCD (tile_band)
+  const TileBand B = tile_band(ntiles);
+  for (int t = B.first; t < B.end; t += B.stride) {
     // keep the weights in LDS: without this the compiler hoists their loads
     // out of the tile loop and the register file overflows
     asm volatile("" ::: "memory");

@@ -433,15 +433,31 @@ struct MomD {
   double rho, jx, jy, ux, uy, bx, by;
 };
 
-template <class C, bool WALLS, bool SWAPPED = false>
-__device__ __forceinline__ MomD moments_d(const Domain &D,
-                                          const typename C::T *__restrict__ s,
-                                          int x, int y) {
-  float d[kQ], g[2 * kQm];
+// The populations of node (x, y): pulled, or read from the node's own slots
+// in the swapped layout.
+template <class C, bool WALLS, bool SWAPPED>
+__device__ __forceinline__ void load_node(const Domain &D, const typename C::T *__restrict__ s,
+                                          int x, int y, float (&d)[kQ], float (&g)[2 * kQm]) {
   if constexpr (SWAPPED)
     own_node<C, WALLS>(D, s, x, y, d, g);
   else
     pull_node<C, WALLS>(D, s, x, y, d, g);
+}
+
+// b = sum_j g_j in FP64.
+__device__ __forceinline__ double2 b_of(const float (&g)[2 * kQm]) {
+  double bx = 0.0, by = 0.0;
+#pragma unroll
+  for (int j = 0; j < kQm; ++j) {
+    bx += (double)g[2 * j];
+    by += (double)g[2 * j + 1];
+  }
+  return make_double2(bx, by);
+}
+
+// The moments of one node's populations in FP64.
+__device__ __forceinline__ MomD moments_of(const Domain &D, const float (&d)[kQ],
+                                           const float (&g)[2 * kQm]) {
   MomD m;
   double dr = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
@@ -455,15 +471,19 @@ __device__ __forceinline__ MomD moments_d(const Domain &D,
   m.jy = jy;
   m.ux = (jx + 0.5 * m.rho * (double)D.Gx) / m.rho;
   m.uy = (jy + 0.5 * m.rho * (double)D.Gy) / m.rho;
-  double bx = 0.0, by = 0.0;
-#pragma unroll
-  for (int j = 0; j < kQm; ++j) {
-    bx += (double)g[2 * j];
-    by += (double)g[2 * j + 1];
-  }
-  m.bx = bx;
-  m.by = by;
+  const double2 b = b_of(g);
+  m.bx = b.x;
+  m.by = b.y;
   return m;
+}
+
+template <class C, bool WALLS, bool SWAPPED = false>
+__device__ __forceinline__ MomD moments_d(const Domain &D,
+                                          const typename C::T *__restrict__ s,
+                                          int x, int y) {
+  float d[kQ], g[2 * kQm];
+  load_node<C, WALLS, SWAPPED>(D, s, x, y, d, g);
+  return moments_of(D, d, g);
 }
 
 template <class C, bool WALLS, bool SWAPPED>
@@ -492,7 +512,9 @@ __global__ void k_moments(Domain D, const typename C::T *__restrict__ src,
 // d_a phi = 3 sum_i w_i phi(x + c_i) c_ia.
 // ---------------------------------------------------------------------------
 constexpr int kDiagBlock = 256;
-constexpr int kDiagGrid = 1024;  // persistent workgroups of the diagnostics (2048-8192 equal)
+// persistent workgroups of the diagnostics: every one resident at once on
+// MI355X (256 CUs x 3 workgroups of 4 waves at the kernel's 146-156 VGPRs)
+constexpr int kDiagGrid = 768;
 constexpr int kSums = 7;  // |u|^2, |b|^2, rho, j_x, j_y, b_x, b_y
 
 __device__ __forceinline__ double nanmax(double a, double b) {
@@ -521,11 +543,11 @@ __device__ double block_reduce(double v, double *lds) {
   return r;
 }
 
-// b = sum_j g_j of node (x, y) in FP64, summed as moments_d sums it.
+// The magnetic populations of node (x, y) (b = b_of(g), summed as
+// moments_of sums it).
 template <class C, bool WALLS, bool SWAPPED>
-__device__ __forceinline__ void b_at(const Domain &D, const typename C::T *__restrict__ s,
-                                     int x, int y, double &bx, double &by) {
-  float g[2 * kQm];
+__device__ __forceinline__ void g_at(const Domain &D, const typename C::T *__restrict__ s, int x,
+                                     int y, float (&g)[2 * kQm]) {
   if constexpr (SWAPPED) {
     float d[kQ];
     own_node<C, WALLS>(D, s, x, y, d, g);  // the fluid loads are dead code
@@ -536,13 +558,6 @@ __device__ __forceinline__ void b_at(const Domain &D, const typename C::T *__res
     pull_g<C, WALLS, 2>(D, s, R, x, g[4], g[5]);
     pull_g<C, WALLS, 3>(D, s, R, x, g[6], g[7]);
     pull_g<C, WALLS, 4>(D, s, R, x, g[8], g[9]);
-  }
-  bx = 0.0;
-  by = 0.0;
-#pragma unroll
-  for (int j = 0; j < kQm; ++j) {
-    bx += (double)g[2 * j];
-    by += (double)g[2 * j + 1];
   }
 }
 
@@ -568,30 +583,29 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_tile(Domain D,
   auto wrap = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
   double acc[kSums] = {0, 0, 0, 0, 0, 0, 0};
   double mx = 0.0;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  constexpr int kWaves = kDiagBlock / 64, kRows = kDTY / kWaves;
+  static_assert(kDTY % kWaves == 0 && kRing <= kDiagBlock, "one ring cell per thread");
+  const TileBand B = tile_band(ntiles);  // one band of tiles per XCD
+  for (int t = B.first; t < B.end; t += B.stride) {
     const int x0 = (t % tiles_x) * kDTX, y0 = (t / tiles_x) * kDTY;
-    // tile cells: moments of the real nodes, b of every cell
-    for (int r = wave; r < kDTY; r += kDiagBlock / 64) {
-      const int x = x0 + lane, y = y0 + r;
-      double2 bv = make_double2(0.0, 0.0);
-      if (x < D.nx && y < D.ny) {
-        const MomD m = moments_d<C, WALLS, SWAPPED>(D, src, x, y);
-        acc[0] += m.ux * m.ux + m.uy * m.uy;
-        acc[1] += m.bx * m.bx + m.by * m.by;
-        acc[2] += m.rho;
-        acc[3] += m.jx;
-        acc[4] += m.jy;
-        acc[5] += m.bx;
-        acc[6] += m.by;
-        bv = make_double2(m.bx, m.by);
-      } else if (!(WALLS && y >= D.ny)) {
-        b_at<C, WALLS, SWAPPED>(D, src, wrap(x, D.nx), wrap(y, D.ny), bv.x, bv.y);
-      }
-      bt[r + 1][lane + 1] = bv;
+    const int x = x0 + lane;
+    // Every load of the tile is issued before any arithmetic: the wave's
+    // rows (all populations of the real nodes, g of the cells past a ragged
+    // edge), then one cell of the ring per thread (its g).
+    float d[kRows][kQ], g[kRows][2 * kQm];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int y = y0 + wave + kWaves * k;
+      if (x < D.nx && y < D.ny)
+        load_node<C, WALLS, SWAPPED>(D, src, x, y, d[k], g[k]);
+      else if (!(WALLS && y >= D.ny))
+        g_at<C, WALLS, SWAPPED>(D, src, wrap(x, D.nx), wrap(y, D.ny), g[k]);
     }
-    // the ring
-    for (int h = threadIdx.x; h < kRing; h += kDiagBlock) {
-      int lx, ly;
+    int lx = 0, ly = 0;
+    bool ring_live = false;
+    float gr[2 * kQm];
+    if (threadIdx.x < kRing) {
+      const int h = threadIdx.x;
       if (h < kDTX + 2) {
         lx = h - 1;
         ly = -1;
@@ -604,14 +618,34 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_tile(Domain D,
         ly = k % kDTY;
       }
       const int y = y0 + ly;
-      double2 bv = make_double2(0.0, 0.0);
-      if (!(WALLS && (y < 0 || y >= D.ny)))
-        b_at<C, WALLS, SWAPPED>(D, src, wrap(x0 + lx, D.nx), wrap(y, D.ny), bv.x, bv.y);
-      bt[ly + 1][lx + 1] = bv;
+      ring_live = !(WALLS && (y < 0 || y >= D.ny));
+      if (ring_live) g_at<C, WALLS, SWAPPED>(D, src, wrap(x0 + lx, D.nx), wrap(y, D.ny), gr);
     }
+    // tile cells: moments of the real nodes, b of every cell
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int r = wave + kWaves * k, y = y0 + r;
+      double2 bv = make_double2(0.0, 0.0);
+      if (x < D.nx && y < D.ny) {
+        const MomD m = moments_of(D, d[k], g[k]);
+        acc[0] += m.ux * m.ux + m.uy * m.uy;
+        acc[1] += m.bx * m.bx + m.by * m.by;
+        acc[2] += m.rho;
+        acc[3] += m.jx;
+        acc[4] += m.jy;
+        acc[5] += m.bx;
+        acc[6] += m.by;
+        bv = make_double2(m.bx, m.by);
+      } else if (!(WALLS && y >= D.ny)) {
+        bv = b_of(g[k]);
+      }
+      bt[r + 1][lane + 1] = bv;
+    }
+    // the ring (zero beyond a wall)
+    if (threadIdx.x < kRing) bt[ly + 1][lx + 1] = ring_live ? b_of(gr) : make_double2(0.0, 0.0);
     __syncthreads();
-    for (int r = wave; r < kDTY; r += kDiagBlock / 64) {
-      const int x = x0 + lane, y = y0 + r;
+    for (int r = wave; r < kDTY; r += kWaves) {
+      const int y = y0 + r;
       if (x >= D.nx || y >= D.ny) continue;
       if (WALLS && (y < 1 || y > D.ny - 2)) continue;
       double sum = 0.0;
@@ -1083,6 +1117,9 @@ hipError_t launch_swapped_to_pull(int storage, const Domain &D, const void *buf,
   return hipGetLastError();
 }
 
+// Workgroups of a diagnostics launch: a fixed count, so the order of the
+// FP64 sums depends on the grid size only (not on a kernel's register
+// allocation); at most one per tile.
 static int diag_grid(const Domain &D) {
   const int64_t tiles = (int64_t)((D.nx + kDTX - 1) / kDTX) * ((D.ny + kDTY - 1) / kDTY);
   return (int)(tiles < kDiagGrid ? tiles : kDiagGrid);
@@ -1093,13 +1130,14 @@ size_t diag_work_bytes(const Domain &) {
 }
 
 template <class C, bool SW>
-static void diag_t(const Domain &D, const void *src, double *ps, double *pm, int nb,
-                   hipStream_t st) {
+static int diag_t(const Domain &D, const void *src, double *ps, double *pm, hipStream_t st) {
   auto s = (const typename C::T *)src;
+  const int nb = diag_grid(D);
   if (D.walls)
     hipLaunchKernelGGL((k_diag_tile<C, true, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, ps, pm);
   else
     hipLaunchKernelGGL((k_diag_tile<C, false, SW>), dim3(nb), dim3(kDiagBlock), 0, st, D, s, ps, pm);
+  return nb;
 }
 
 hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
@@ -1107,13 +1145,13 @@ hipError_t launch_diagnostics(int storage, const Domain &D, const void *src,
   const int64_t N = (int64_t)D.nx * D.ny;
   double *ps = (double *)work;
   double *pm = ps + kDiagGrid * kSums;
-  const int nb = diag_grid(D);
+  int nb;
   if (storage == kF16)
-    swapped ? diag_t<CodecF16, true>(D, src, ps, pm, nb, st)
-            : diag_t<CodecF16, false>(D, src, ps, pm, nb, st);
+    nb = swapped ? diag_t<CodecF16, true>(D, src, ps, pm, st)
+                 : diag_t<CodecF16, false>(D, src, ps, pm, st);
   else
-    swapped ? diag_t<CodecF32, true>(D, src, ps, pm, nb, st)
-            : diag_t<CodecF32, false>(D, src, ps, pm, nb, st);
+    nb = swapped ? diag_t<CodecF32, true>(D, src, ps, pm, st)
+                 : diag_t<CodecF32, false>(D, src, ps, pm, st);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, st, ps, nb, pm, nb,
                      1.0 / (2.0 * (double)N), out_dev);
   return hipGetLastError();

@@ -20,6 +20,26 @@ struct PlaneGeom {
   int64_t row = 0;      // elements between row starts of one plane
 };
 
+// Tile order of a persistent grid: the hardware deals workgroups to the
+// eight XCDs in turn, so with a grid that is a multiple of 8 (and no larger
+// than the tile count) each XCD takes one contiguous band of tiles, its
+// workgroups side by side.  Neighbouring tiles, which share the cache lines
+// of their halos, then meet in one L2.  Workgroup b visits tiles first,
+// first + stride, ... below end.
+struct TileBand {
+  int first, end, stride;
+};
+__device__ __forceinline__ TileBand tile_band(int ntiles) {
+  TileBand B{(int)blockIdx.x, ntiles, (int)gridDim.x};
+  if ((gridDim.x & 7) == 0 && ntiles >= (int)gridDim.x) {
+    const int band = (ntiles + 7) >> 3, xcd = blockIdx.x & 7;
+    B.first = xcd * band + (blockIdx.x >> 3);
+    B.end = min(ntiles, (xcd + 1) * band);
+    B.stride = gridDim.x >> 3;
+  }
+  return B;
+}
+
 template <class T>
 __device__ __forceinline__ const T *plane_ptr(const T *__restrict__ s, int p,
                                               int64_t plane) {
