@@ -636,9 +636,16 @@ def time_turbulence_leg(torch, rrmhd, args, fields, storage):
     launch = ("library default (row-interleaved planes, eight neighbouring tiles per "
               "XCD, NT stores; f32: 128x2 threads, two nodes per thread in 64-bit words; "
               "f16: 128x1 threads, four nodes per thread in 64-bit words)")
+    if storage == "f16sr":
+        launch = ("library default (row-interleaved planes, eight neighbouring tiles per XCD, "
+                  "NT stores, 128x1 threads, one node per thread)")
     if args.equilibrium != "algorithm":
         launch = "library default block shape, one node per thread, NT stores"
-    if args.inplace:
+    if args.inplace and storage == "f16sr":
+        launch = ("library default for one buffer (row-interleaved planes, XCD-local order, "
+                  "NT stores, 128x1 threads, one node per thread); steps alternate pull+push "
+                  "and own-slot forms")
+    elif args.inplace:
         launch = ("library default for one buffer (row-interleaved planes, XCD-local order, "
                   "NT stores; f32: 128x1 threads, one node per thread; f16: 64x2 threads, two "
                   "nodes per thread in 32-bit words); steps alternate pull+push and own-slot "

@@ -81,9 +81,9 @@ enum { RRMHD_STORE_F32 = 0, RRMHD_STORE_F16 = 1, RRMHD_STORE_INPLACE = 0x100 };
  * codec, reported separately; initialisation still rounds to nearest.  It
  * combines with RRMHD_STORE_INPLACE (each value draws the bits of the node
  * that computes it and of its own plane, whichever slot receives it, so the
- * single-buffer handle stays bitwise equal to the two-buffer one); not with
- * graph replay, the learned closure or the equilibrium ablation (EINVAL);
- * the two-node FP16 update is not used. */
+ * single-buffer handle stays bitwise equal to the two-buffer one, and the
+ * two- and four-node updates equal one node per thread); not with graph
+ * replay, the learned closure or the equilibrium ablation (EINVAL). */
 enum { RRMHD_STORE_F16_SR = 2 };
 /* Layout of the populations in device memory (not visible through the API:
  * moments, diagnostics, rrmhd_save_state and checkpoint files are the same

@@ -257,14 +257,14 @@ int rrmhd_create(const rrmhd_grid *grid, double tau_f, double tau_m,
   if (h->inplace) {
     // measured best for the alternating single-buffer steps at 8192^2, with
     // eight neighbouring tiles per XCD and non-temporal stores: FP16 storage
-    // on row-interleaved planes 64 x 2 threads with two nodes per thread;
-    // otherwise one node per thread and one row per workgroup, 128 wide (FP16
-    // storage, or FP32 on row-interleaved planes) or 64 wide (FP32 on planes
-    // of [ny][nx])
+    // (round to nearest) on row-interleaved planes 64 x 2 threads with two
+    // nodes per thread; otherwise one node per thread and one row per
+    // workgroup, 128 wide (FP16 storage, or FP32 on row-interleaved planes)
+    // or 64 wide (FP32 on planes of [ny][nx])
     const bool rows_wide = D.row != D.nx && D.nx >= 512;
     h->shape.ry = 1;
     h->shape.xcd = 2;
-    if (rows_wide && h->elem == 2 && D.nx % 2 == 0) {
+    if (rows_wide && h->elem == 2 && D.nx % 2 == 0 && !D.sr) {
       h->shape.bx = 64;
       h->shape.by = 2;
       h->shape.nt = 5;

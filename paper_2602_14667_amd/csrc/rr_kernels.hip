@@ -707,7 +707,7 @@ __global__ __launch_bounds__(256) void k_step_multi(Domain D, int tiles_x, int r
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
-  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, 0u, D.row};
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key, D.row};
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void k_step_inplace_multi(Domain D, int tiles_
   P.Gx = D.Gx;
   P.Gy = D.Gy;
   P.src_c = D.src_c;
-  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, 0u, D.row};
+  const PlaneGeom G{D.plane, D.nx, D.ny, D.s, D.inv_s, D.sr_key, D.row};
   for (int r = 0; r < ry; ++r) {
     const int y = y0 + r;
     if (y >= D.ny) return;
@@ -762,7 +762,13 @@ LaunchShape default_shape(const Domain &D) {
   L.xcd = 0;
   L.nt = 1;
   const bool rows = D.row != D.nx && !D.walls && D.nx >= 512;
-  if (rows && D.elem == 2 && D.nx % 4 == 0) {
+  if (D.sr && !D.walls && D.nx >= 512) {
+    // stochastic rounding is ALU-bound (a hash per value): more nodes per
+    // thread measured no faster (two 67.8 %, four 64-66 %, one 67.1 %)
+    L.bx = 128;
+    L.by = 1;
+    L.xcd = rows ? 2 : 0;
+  } else if (rows && D.elem == 2 && D.nx % 4 == 0) {
     L.bx = 128;
     L.by = 1;
     L.xcd = 2;
@@ -906,20 +912,16 @@ static void step_multi(const Domain &D, const void *src, void *dst, const Launch
 // nt bit 2: two nodes (FP16 storage on either layout; FP32 storage on
 // row-interleaved planes: on planes of [ny][nx] its 64-bit words measured
 // slower than one node per thread); nt bit 3: four nodes (FP16 storage, 64-bit
-// words).  Round-to-nearest codecs only, nx a multiple of the count, and on
-// row-interleaved planes whole-row wavefronts.
+// words).  nx a multiple of the count, and on row-interleaved planes
+// whole-row wavefronts.
 template <class C>
 static int multi_nodes(const Domain &D, const LaunchShape &L) {
-  if constexpr (codec_sr<C>::value) {
-    return 1;
-  } else {
-    if (!(L.nt & 12) || D.walls) return 1;
-    const bool rows = D.row != D.nx;
-    if (rows && !uniform_rows(L)) return 1;
-    if (sizeof(typename C::T) == 2 && (L.nt & 8) && D.nx % 4 == 0) return 4;
-    if ((L.nt & 4) && D.nx % 2 == 0 && (sizeof(typename C::T) == 2 || rows)) return 2;
-    return 1;
-  }
+  if (!(L.nt & 12) || D.walls) return 1;
+  const bool rows = D.row != D.nx;
+  if (rows && !uniform_rows(L)) return 1;
+  if (sizeof(typename C::T) == 2 && (L.nt & 8) && D.nx % 4 == 0) return 4;
+  if ((L.nt & 4) && D.nx % 2 == 0 && (sizeof(typename C::T) == 2 || rows)) return 2;
+  return 1;
 }
 
 template <class C>
@@ -930,7 +932,7 @@ static hipError_t step_t(const Domain &D, const void *src, void *dst,
     step_fullm<C>(D, src, dst, L, st);
     return hipGetLastError();
   }
-  if constexpr (!codec_sr<C>::value) {
+  {
     const int k = multi_nodes<C>(D, L);
     if (k == 2) {
       step_multi<C, 2>(D, src, dst, L, st);
@@ -1070,7 +1072,7 @@ template <class C>
 static void inplace_phase(const Domain &D, void *buf, int phase, const LaunchShape &L,
                           hipStream_t st) {
   const bool nt = L.nt & 1;
-  if constexpr (!codec_sr<C>::value) {
+  {
     const int k = nt ? multi_nodes<C>(D, L) : 1;
     if (k == 2) {
       phase ? inplace_multi_t<C, 2, 1>(D, buf, L, st) : inplace_multi_t<C, 2, 0>(D, buf, L, st);

@@ -196,6 +196,17 @@ __device__ __forceinline__ uint32_t node_seed(const PlaneGeom &G, int x, int y) 
   else
     return 0;
 }
+// The stored value of population plane p computed by the node with random
+// bits `seed` (stochastic rounding), or the codec's plain encode.
+template <class C>
+__device__ __forceinline__ typename C::T enc_node(const PlaneGeom &G, float v, uint32_t seed,
+                                                  int p) {
+  if constexpr (codec_sr<C>::value)
+    return C::enc_sr(v, G.s, sr_plane(seed, p));
+  else
+    return C::enc(v, G.s);
+}
+
 template <class C, bool NT, int RM>
 __device__ __forceinline__ void store_node(const PlaneGeom &G, typename C::T *__restrict__ dst,
                                            int x, int y, const float *d, const float *g) {
@@ -384,7 +395,8 @@ __device__ __forceinline__ void store_words(const PlaneGeom &G, typename C::T *_
   (store_word<C, NT, K, P>(G, dst, o, w), ...);
 }
 
-// C: a codec without stochastic rounding (FP32, CodecF16 or CodecF16U).
+// With stochastic rounding each element draws the bits of its own node, as
+// one node per thread does.
 template <class C, int K, bool FORCED, bool NT, bool NTL, int RM = RM_OFFSET>
 __device__ __forceinline__ void update_periodic_multi(const PlaneGeom &G,
                                                       const typename C::T *__restrict__ src,
@@ -414,10 +426,12 @@ __device__ __forceinline__ void update_periodic_multi(const PlaneGeom &G,
 #pragma unroll
     for (int m = 0; m < 2 * kQm; ++m) g[m] = C::dec(NW::get(w[kQ + m], k), G.inv_s);
     collide<FORCED>(d, g, P);
+    const uint32_t seed = node_seed<C>(G, x + k, y);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) w[i] = NW::put(w[i], k, C::enc(d[i], G.s));
+    for (int i = 0; i < kQ; ++i) w[i] = NW::put(w[i], k, enc_node<C>(G, d[i], seed, i));
 #pragma unroll
-    for (int m = 0; m < 2 * kQm; ++m) w[kQ + m] = NW::put(w[kQ + m], k, C::enc(g[m], G.s));
+    for (int m = 0; m < 2 * kQm; ++m)
+      w[kQ + m] = NW::put(w[kQ + m], k, enc_node<C>(G, g[m], seed, kQ + m));
   }
   uint32_t off;
   T *out = row_dst<RM>(G, dst, y, off);
@@ -458,7 +472,8 @@ __device__ __forceinline__ void st_word(T *__restrict__ plane, uint32_t row, int
 // Phase 0: pull as update_periodic_multi does, collide, and put f*_i of node
 // x + k into element k of the word just read for the opposite direction
 // (the slot buf[opp(i)][x + k + c_i]); every word returns to where it came
-// from.  C: a codec without stochastic rounding.
+// from.  Stochastic rounding draws the bits of node x + k and of the
+// population's own plane, as store_plane_at does.
 template <class C, int K, bool FORCED, bool NT, int RM>
 __device__ __forceinline__ void update_periodic_push_multi(const PlaneGeom &G,
                                                            typename C::T *buf, int x, int y,
@@ -487,12 +502,16 @@ __device__ __forceinline__ void update_periodic_push_multi(const PlaneGeom &G,
 #pragma unroll
     for (int m = 0; m < 2 * kQm; ++m) g[m] = C::dec(NW::get(w[kQ + m], k), G.inv_s);
     collide<FORCED>(d, g, P);
+    const uint32_t seed = node_seed<C>(G, x + k, y);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) w[opp_f(i)] = NW::put(w[opp_f(i)], k, C::enc(d[i], G.s));
+    for (int i = 0; i < kQ; ++i)
+      w[opp_f(i)] = NW::put(w[opp_f(i)], k, enc_node<C>(G, d[i], seed, i));
 #pragma unroll
     for (int j = 0; j < kQm; ++j) {
-      w[gplane(opp_g(j), 0)] = NW::put(w[gplane(opp_g(j), 0)], k, C::enc(g[2 * j], G.s));
-      w[gplane(opp_g(j), 1)] = NW::put(w[gplane(opp_g(j), 1)], k, C::enc(g[2 * j + 1], G.s));
+      w[gplane(opp_g(j), 0)] =
+          NW::put(w[gplane(opp_g(j), 0)], k, enc_node<C>(G, g[2 * j], seed, gplane(j, 0)));
+      w[gplane(opp_g(j), 1)] =
+          NW::put(w[gplane(opp_g(j), 1)], k, enc_node<C>(G, g[2 * j + 1], seed, gplane(j, 1)));
     }
   }
 #define RR_STF(I) \
@@ -534,10 +553,12 @@ __device__ __forceinline__ void update_periodic_own_multi(const PlaneGeom &G,
       g[2 * j + 1] = C::dec(NW::get(w[gplane(opp_g(j), 1)], k), G.inv_s);
     }
     collide<FORCED>(d, g, P);
+    const uint32_t seed = node_seed<C>(G, x + k, y);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) w[i] = NW::put(w[i], k, C::enc(d[i], G.s));
+    for (int i = 0; i < kQ; ++i) w[i] = NW::put(w[i], k, enc_node<C>(G, d[i], seed, i));
 #pragma unroll
-    for (int m = 0; m < 2 * kQm; ++m) w[kQ + m] = NW::put(w[kQ + m], k, C::enc(g[m], G.s));
+    for (int m = 0; m < 2 * kQm; ++m)
+      w[kQ + m] = NW::put(w[kQ + m], k, enc_node<C>(G, g[m], seed, kQ + m));
   }
   store_words<C, NT, K>(G, row, o, w, std::make_integer_sequence<int, kPlanes>{});
 }

@@ -688,18 +688,21 @@ def test_c1_fp16_stochastic_rounding_per_field():
     assert worst(sr, ("ux", "uy", "bx", "by")) < worst(rne, ("ux", "uy", "bx", "by"))
 
 
-@pytest.mark.parametrize("shape", [(130, 66), (129, 40)])
+@pytest.mark.parametrize("shape", [(130, 66), (129, 40), (132, 40), (4, 5), (520, 12)])
 def test_stochastic_rounding_is_reproducible_and_shape_independent(shape):
     """The random bits are a hash of (step, node, plane): two runs, and runs
-    with other launch shapes, give the same state bit for bit; walls and
-    forcing included."""
+    with other launch shapes (one, two and four nodes per thread) and either
+    layout, give the same state bit for bit."""
     nx, ny = shape
     R = rrmhd()
     u, b = inputs.random_modes(nx, ny, 0.03, seed=11)
     ref = None
-    for bx, by, ry, xcd, nt in ((0, 0, 0, 0, 0), (64, 4, 1, 0, 0), (32, 2, 3, 1, 1),
-                                (256, 1, 1, 2, 3), (0, 0, 0, 0, 0)):
-        s = R.Solver(nx, ny, 0.53, 0.57, storage="f16sr")
+    for bx, by, ry, xcd, nt, layout in (
+            (0, 0, 0, 0, 0, "default"), (64, 4, 1, 0, 0, "default"), (32, 2, 3, 1, 1, "default"),
+            (256, 1, 1, 2, 3, "default"), (128, 1, 1, 2, 9, "default"), (64, 2, 1, 2, 5, "default"),
+            (64, 4, 1, 0, 13, "default"), (32, 8, 1, 0, 9, "default"), (128, 1, 1, 0, 9, "planar"),
+            (64, 2, 1, 2, 5, "planar"), (0, 0, 0, 0, 0, "default")):
+        s = R.Solver(nx, ny, 0.53, 0.57, storage="f16sr", layout=layout)
         if bx:
             s.set_launch(bx, by, ry, xcd, nt)
         s.init(dev(u), dev(b))
@@ -709,7 +712,7 @@ def test_stochastic_rounding_is_reproducible_and_shape_independent(shape):
         if ref is None:
             ref = g
         for k in FIELDS:
-            assert np.array_equal(g[k], ref[k]), (bx, by, k)
+            assert np.array_equal(g[k], ref[k]), (bx, by, nt, layout, k)
     # the rounding is not round-to-nearest: the result differs from the codec
     s = R.Solver(nx, ny, 0.53, 0.57, storage="f16")
     s.init(dev(u), dev(b))
