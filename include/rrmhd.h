@@ -308,9 +308,12 @@ int rrmhd3d_step_count(const rrmhd3d *h, int64_t *out);
 int rrmhd3d_moments(rrmhd3d *h, double *rho, double *u, double *b);
 int rrmhd3d_diagnostics(rrmhd3d *h, double *E_kin, double *E_mag, double *max_div_b);
 int rrmhd3d_invariants(rrmhd3d *h, double out[7]);
-/* bx x by threads per workgroup over x and y (bx * by <= 256); results do
- * not depend on it.  Host-side only. */
-int rrmhd3d_set_launch(rrmhd3d *h, int bx, int by);
+/* bx x by threads per workgroup over x and y (bx * by <= 256); xcd = 1
+ * hands each XCD 8 neighbouring row tiles out of every 64 workgroups, 0 keeps
+ * the plain order, -1 leaves the current setting (default: 1 for FP16
+ * storage or one buffer, 0 for FP32 with two).  Results do not depend on
+ * the shape or the order.  Host-side only. */
+int rrmhd3d_set_launch(rrmhd3d *h, int bx, int by, int xcd);
 int rrmhd3d_destroy(rrmhd3d *h);
 /* Checkpoint files of the 3D handle, as rrmhd_save / rrmhd_load: a 64-byte
  * header (magic "RRMHD3C1", int32 version 1, nx, ny, nz, storage kind,

@@ -33,6 +33,8 @@
 // then g_0x, g_0y, g_0z, ..., g_6z (48 planes), each [nz][ny][nx].
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <cmath>
 #include <new>
 #include <utility>
@@ -306,14 +308,33 @@ __device__ __forceinline__ Src3 sources(const Dom3 &D, int x, int y, int z, uint
   return S;
 }
 
+// Tile of a workgroup: the grid is (row tiles of a z plane, nz) and the
+// hardware deals workgroups to the eight XCDs in turn in linear order.  With
+// xcd set, within each run of 64 consecutive workgroups XCD k takes tiles
+// 8k .. 8k + 7 of the run (neighbouring rows), so their y halos meet in one
+// L2.
+struct Tile3 {
+  int t, z;
+};
+__device__ __forceinline__ Tile3 tile3(int xcd) {
+  const int n = gridDim.x * gridDim.y;
+  int L = blockIdx.x + gridDim.x * blockIdx.y;
+  if (xcd) {
+    const int g = L >> 6, j = L & 63;
+    if ((g + 1) * 64 <= n) L = (g << 6) + ((j & 7) << 3) + (j >> 3);
+  }
+  return Tile3{L % (int)gridDim.x, L / (int)gridDim.x};
+}
+
 template <class C>
-__global__ __launch_bounds__(256) void k_step3(Dom3 D, int tiles_x,
+__global__ __launch_bounds__(256) void k_step3(Dom3 D, int tiles_x, int xcd,
                                                const typename C::T *__restrict__ src,
                                                typename C::T *__restrict__ dst) {
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const Tile3 T = tile3(xcd);
+  const int tx = T.t % tiles_x, ty = T.t / tiles_x;
   const int x = tx * blockDim.x + threadIdx.x;
   const int y = ty * blockDim.y + threadIdx.y;
-  const int z = blockIdx.y;
+  const int z = T.z;
   if (x >= D.nx || y >= D.ny) return;
   constexpr uint32_t E = sizeof(typename C::T);
   const Src3 S = sources(D, x, y, z, E);
@@ -373,11 +394,13 @@ __device__ __forceinline__ void load_own(const typename C::T *buf, const Dom3 &D
 }
 
 template <class C, int PHASE>
-__global__ __launch_bounds__(256) void k_step3_inplace(Dom3 D, int tiles_x, typename C::T *buf) {
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+__global__ __launch_bounds__(256) void k_step3_inplace(Dom3 D, int tiles_x, int xcd,
+                                                       typename C::T *buf) {
+  const Tile3 T = tile3(xcd);
+  const int tx = T.t % tiles_x, ty = T.t / tiles_x;
   const int x = tx * blockDim.x + threadIdx.x;
   const int y = ty * blockDim.y + threadIdx.y;
-  const int z = blockIdx.y;
+  const int z = T.z;
   if (x >= D.nx || y >= D.ny) return;
   constexpr uint32_t E = sizeof(typename C::T);
   const Src3 S = sources(D, x, y, z, E);
@@ -647,6 +670,7 @@ struct rrmhd3d {
   int phase = 0;         // in-place: 0 pull layout, 1 swapped layout
   bool poison = false;   // debug: NaN-fill the destination buffer before each step
   int bx = 64, by = 4;
+  int xcd = 0;  // XCD-local tile order
   double *diag_work = nullptr;
   double *diag_out = nullptr;
   double *diag_host = nullptr;
@@ -662,9 +686,9 @@ template <class C>
 static void launch_inplace3(rrmhd3d *h, dim3 grid, dim3 block, int tiles_x) {
   auto b = (typename C::T *)h->buf[0];
   if (h->phase == 0)
-    hipLaunchKernelGGL((rr3::k_step3_inplace<C, 0>), grid, block, 0, h->stream, h->D, tiles_x, b);
+    hipLaunchKernelGGL((rr3::k_step3_inplace<C, 0>), grid, block, 0, h->stream, h->D, tiles_x, h->xcd, b);
   else
-    hipLaunchKernelGGL((rr3::k_step3_inplace<C, 1>), grid, block, 0, h->stream, h->D, tiles_x, b);
+    hipLaunchKernelGGL((rr3::k_step3_inplace<C, 1>), grid, block, 0, h->stream, h->D, tiles_x, h->xcd, b);
 }
 
 template <class C>
@@ -742,6 +766,11 @@ int rrmhd3d_create(int32_t nx, int32_t ny, int32_t nz, int32_t storage, double t
     h->bx = 256;
     h->by = 1;
   }
+  // measured at 256^3: the XCD-local order gains about one point of 8 TB/s
+  // for FP16 storage (67.6 % against 66.7 %) and for one buffer (FP32 61.5 %
+  // against 60.5 %, FP16 65.2 % against 64.2 %); FP32 with two buffers is the
+  // same either way and keeps the plain order
+  h->xcd = (h->storage == RRMHD_STORE_F16 || h->inplace) ? 1 : 0;
   const size_t bytes = (size_t)h->D.plane * rr3::kPlanes * elem;
   int rc = RRMHD_OK;
   for (int k = 0; k < (h->inplace ? 1 : 2) && rc == RRMHD_OK; ++k)
@@ -759,10 +788,11 @@ int rrmhd3d_create(int32_t nx, int32_t ny, int32_t nz, int32_t storage, double t
   return RRMHD_OK;
 }
 
-int rrmhd3d_set_launch(rrmhd3d *h, int bx, int by) {
-  if (!h || bx < 1 || by < 1 || bx * by > 256) return RRMHD_EINVAL;
+int rrmhd3d_set_launch(rrmhd3d *h, int bx, int by, int xcd) {
+  if (!h || bx < 1 || by < 1 || bx * by > 256 || xcd < -1 || xcd > 1) return RRMHD_EINVAL;
   h->bx = bx;
   h->by = by;
+  if (xcd >= 0) h->xcd = xcd;
   return RRMHD_OK;
 }
 
@@ -808,10 +838,10 @@ int rrmhd3d_step(rrmhd3d *h, int64_t n) {
     }
     if (h->storage == RRMHD_STORE_F16)
       hipLaunchKernelGGL(rr3::k_step3<rr3::CodecF16U>, grid, block, 0, h->stream, h->D, tiles_x,
-                         (const uint16_t *)s, (uint16_t *)d);
+                         h->xcd, (const uint16_t *)s, (uint16_t *)d);
     else
       hipLaunchKernelGGL(rr3::k_step3<rr3::CodecF32>, grid, block, 0, h->stream, h->D, tiles_x,
-                         (const float *)s, (float *)d);
+                         h->xcd, (const float *)s, (float *)d);
     HIP3(hipGetLastError());
     h->cur ^= 1;
     h->steps++;

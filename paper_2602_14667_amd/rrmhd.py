@@ -119,7 +119,7 @@ def lib():
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
         L.rrmhd3d_invariants.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
-        L.rrmhd3d_set_launch.argtypes = [vp, ci, ci]
+        L.rrmhd3d_set_launch.argtypes = [vp, ci, ci, ci]
         L.rrmhd3d_destroy.argtypes = [vp]
         L.rrmhd_destroy.argtypes = [vp]
         L.rrmhd_bandwidth_probe.argtypes = [vp, vp, i64, vp]
@@ -591,8 +591,11 @@ class Solver3D:
         _check(lib().rrmhd3d_invariants(self._h, out), "rrmhd3d_invariants")
         return list(out)
 
-    def set_launch(self, bx, by):
-        _check(lib().rrmhd3d_set_launch(self._h, int(bx), int(by)), "rrmhd3d_set_launch")
+    def set_launch(self, bx, by, xcd=-1):
+        """bx x by threads per workgroup; xcd 1 / 0: XCD-local or plain tile
+        order, -1 keeps the current one."""
+        _check(lib().rrmhd3d_set_launch(self._h, int(bx), int(by), int(xcd)),
+               "rrmhd3d_set_launch")
 
     def save(self, path):
         """Write a checkpoint file (header + state); synchronous."""

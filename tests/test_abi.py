@@ -145,5 +145,5 @@ def test_null_3d_handle_calls_are_rejected():
     assert L.rrmhd3d_step(None, 1) == rrmhd.EINVAL
     assert L.rrmhd3d_init(None, None, None) == rrmhd.EINVAL
     assert L.rrmhd3d_moments(None, None, None, None) == rrmhd.EINVAL
-    assert L.rrmhd3d_set_launch(None, 64, 4) == rrmhd.EINVAL
+    assert L.rrmhd3d_set_launch(None, 64, 4, 0) == rrmhd.EINVAL
     assert L.rrmhd3d_destroy(None) == rrmhd.OK

@@ -116,17 +116,22 @@ def test_3d_diagnostics_and_invariants():
     s.close()
 
 
+@pytest.mark.parametrize("inplace", [False, True])
+@pytest.mark.parametrize("shape", [(37, 11, 5), (40, 70, 9)])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_3d_launch_shapes_bitwise(storage):
-    note(f"3D launch shapes {storage}")
+def test_3d_launch_shapes_bitwise(storage, shape, inplace):
+    """Launch shapes and both tile orders (the XCD-local one reorders every
+    full run of 64 workgroups: the 40 x 70 x 9 box has several) give the same
+    state bit for bit, with one buffer or two."""
+    note(f"3D launch shapes {storage} {shape} inplace={inplace}")
     R = rrmhd()
-    shape = (37, 11, 5)
     u, b = inputs.random_modes3d(*shape, 0.03, seed=9)
     out = []
-    for bx, by in ((0, 0), (64, 4), (32, 8), (16, 16), (128, 2), (1, 1), (256, 1)):
-        s = R.Solver3D(*shape, 0.54, 0.58, storage=storage)
+    for bx, by, xcd in ((0, 0, -1), (64, 4, 0), (64, 4, 1), (32, 8, 1), (16, 16, 0), (16, 16, 1),
+                        (128, 2, 1), (1, 1, 0), (256, 1, 1)):
+        s = R.Solver3D(*shape, 0.54, 0.58, storage=storage, inplace=inplace)
         if bx:
-            s.set_launch(bx, by)
+            s.set_launch(bx, by, xcd)
         s.init(dev(u), dev(b))
         s.step(7)
         out.append(gpu_fields(s))
