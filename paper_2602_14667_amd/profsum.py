@@ -114,6 +114,21 @@ def main(prof, out, n):
             f"* calibration: plain copy of {COPY_BYTES} B reads as FETCH_SIZE x {fac['FETCH_SIZE']:.4f}, "
             f"WRITE_SIZE x {fac['WRITE_SIZE']:.4f}; copy kernel {2 * COPY_BYTES / copy_ns:.1f} GB/s",
         ]
+        # the diagnostics pass (energies, max |div b|) of the same runs: it
+        # reads the state once, half the step's bytes per node
+        diag = [k for k in stats if "k_diag_tile" in k]
+        if diag:
+            davg = stats[diag[0]]["avg_ns"]
+            dalg = alg / 2
+            drd = counter_mean(os.path.join(prof, f"pmc_FETCH_SIZE_{st}"), "k_diag_tile")
+            line = (f"* diagnostics pass (`k_diag_tile`, every K steps; reads the state once, "
+                    f"{bpn // 2} B/node): average {davg / 1e3:.1f} us -> {dalg / davg:.1f} GB/s "
+                    f"algorithmic = {dalg / davg / 8000 * 100:.1f} % of 8 TB/s")
+            if drd is not None:
+                drd *= 1024 * fac["FETCH_SIZE"]
+                line += (f"; HBM reads (PMC, calibrated) {drd / 1e9:.3f} GB "
+                         f"({drd / dalg:.3f}x algorithmic, the tile rings included)")
+            lines.append(line)
         with open(os.path.join(out, f"step_{st}_{n}.md"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
     print("ok")
